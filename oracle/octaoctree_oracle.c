@@ -1,0 +1,615 @@
+/*
+ * FP64 CPU oracle for the OctaOctree query and the neural-radiosity residual
+ * step. TEST INFRASTRUCTURE ONLY: see octaoctree_oracle.h.
+ *
+ * Each function follows the paper's steps in order, one query at a time, in
+ * double precision, with no blocking or fusion. Where the paper is silent the
+ * readings are stated at the function (they are the same readings the GPU
+ * library is held to):
+ *  - spatial lookup uses the containing node at every level (the paper's
+ *    "no octree interpolation" variant, Sec. 4.4) instead of the 8-cell
+ *    trilinear blend of Sec. 3.4;
+ *  - directional lookup is a texel-centred bilinear fetch on an R x R map
+ *    with the octahedral seam identification, in place of the barycentric
+ *    vertex lookup of Sec. 3.3;
+ *  - the decoder reads the concatenated levels h only (no G-buffer inputs);
+ *  - the BSDF is Lambert + GGX (Smith separable, Schlick Fresnel).
+ *
+ * Parity pins (tests/test_oracle_*.py): brute-force containment for the
+ * descent, closed-form octahedral vectors and the decode round trip, bilinear
+ * weight / reproduction / seam-continuity properties, dense-layer products,
+ * BSDF special cases, the constant-radiance residual closed form, and FP64
+ * central finite differences for the adjoint.
+ */
+#include "octaoctree_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------ */
+/* Spatial: quantisation and octree (Sec. 3.4 sparse octree; Sec. 4.1)       */
+/* ------------------------------------------------------------------------ */
+
+/* Cell coordinate along one axis at depth D: floor(x * 2^D) clamped to the
+ * cube. Cells are half-open, so x == 1 lands in the last cell. The scaling by
+ * a power of two is exact in floating point. */
+static int64_t quant_axis(float xa, int32_t D) {
+  double v = floor((double)xa * ldexp(1.0, D));
+  int64_t maxq = ((int64_t)1 << D) - 1;
+  if (!(v >= 0.0)) return 0; /* negative, or NaN (unspecified, clamped) */
+  if (v > (double)maxq) return maxq;
+  return (int64_t)v;
+}
+
+void ora_quantize(const float* x, int64_t B, int32_t D, int64_t* q_out) {
+  for (int64_t b = 0; b < B; ++b)
+    for (int a = 0; a < 3; ++a) q_out[3 * b + a] = quant_axis(x[3 * b + a], D);
+}
+
+/* Octant of the child at level l + 1 that contains cell q (finest-level
+ * coordinates): bit a of the octant is bit (D - l - 1) of q_a. */
+static int child_octant(const int64_t q[3], int32_t shift) {
+  int bx = (int)((q[0] >> shift) & 1);
+  int by = (int)((q[1] >> shift) & 1);
+  int bz = (int)((q[2] >> shift) & 1);
+  return bx | (by << 1) | (bz << 2);
+}
+
+typedef struct {
+  int64_t* start;
+  int64_t* count;
+  uint32_t* mask;
+  int64_t* first_child;
+  int64_t n, cap;
+} node_list;
+
+static int node_push(node_list* L, int64_t start, int64_t count) {
+  if (L->n == L->cap) {
+    int64_t nc = L->cap ? 2 * L->cap : 1024;
+    int64_t* s = (int64_t*)realloc(L->start, nc * sizeof(int64_t));
+    if (!s) return -1;
+    L->start = s;
+    int64_t* c = (int64_t*)realloc(L->count, nc * sizeof(int64_t));
+    if (!c) return -1;
+    L->count = c;
+    uint32_t* m = (uint32_t*)realloc(L->mask, nc * sizeof(uint32_t));
+    if (!m) return -1;
+    L->mask = m;
+    int64_t* f = (int64_t*)realloc(L->first_child, nc * sizeof(int64_t));
+    if (!f) return -1;
+    L->first_child = f;
+    L->cap = nc;
+  }
+  L->start[L->n] = start;
+  L->count[L->n] = count;
+  L->mask[L->n] = 0;
+  L->first_child[L->n] = 0;
+  L->n++;
+  return 0;
+}
+
+/* Builds the tree top-down. The root always exists. Every node at level
+ * l < D holding more than tau samples is refined, and only its non-empty
+ * children are created ("every non-empty cell stores a map", Sec. 3.4).
+ * Nodes are numbered breadth first; within a level by parent, then octant.
+ * Each node owns a contiguous run of a sample permutation, which a stable
+ * counting split by octant divides among its children. */
+int ora_build_octree(const float* samples, int64_t n, int32_t D, int32_t tau,
+                     uint32_t* nodes_out, int64_t capacity,
+                     int64_t* level_offset_out, int64_t* n_nodes_out) {
+  if (n < 0 || D < 0 || D > ORA_MAX_LEVELS - 1 || tau < 0) return -1;
+  if ((n > 0 && !samples) || !level_offset_out || !n_nodes_out) return -1;
+
+  int64_t* q = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * 3 * sizeof(int64_t));
+  int64_t* perm = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+  int64_t* tmp = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+  node_list L;
+  memset(&L, 0, sizeof(L));
+  int rc = 0;
+  if (!q || !perm || !tmp) { rc = -5; goto done; }
+  ora_quantize(samples, n, D, q);
+  for (int64_t i = 0; i < n; ++i) perm[i] = i;
+
+  int64_t level_offset[ORA_MAX_LEVELS + 2];
+  level_offset[0] = 0;
+  if (node_push(&L, 0, n)) { rc = -5; goto done; }
+  level_offset[1] = 1;
+
+  for (int32_t l = 0; l < D; ++l) {
+    int32_t shift = D - l - 1;
+    for (int64_t v = level_offset[l]; v < level_offset[l + 1]; ++v) {
+      int64_t s0 = L.start[v], cnt = L.count[v];
+      if (cnt <= tau) continue; /* leaf */
+      int64_t bucket[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      for (int64_t s = s0; s < s0 + cnt; ++s) bucket[child_octant(&q[3 * perm[s]], shift)]++;
+      int64_t pos[8];
+      pos[0] = s0;
+      for (int o = 1; o < 8; ++o) pos[o] = pos[o - 1] + bucket[o - 1];
+      for (int64_t s = s0; s < s0 + cnt; ++s) {
+        int o = child_octant(&q[3 * perm[s]], shift);
+        tmp[pos[o]++] = perm[s];
+      }
+      memcpy(&perm[s0], &tmp[s0], (size_t)cnt * sizeof(int64_t));
+      int64_t first = L.n, run = s0;
+      uint32_t mask = 0;
+      for (int o = 0; o < 8; ++o) {
+        if (bucket[o] > 0) {
+          if (node_push(&L, run, bucket[o])) { rc = -5; goto done; }
+          mask |= 1u << o;
+        }
+        run += bucket[o];
+      }
+      L.mask[v] = mask;
+      L.first_child[v] = first;
+    }
+    level_offset[l + 2] = L.n;
+  }
+
+  for (int32_t l = 0; l <= D + 1; ++l) level_offset_out[l] = level_offset[l];
+  *n_nodes_out = L.n;
+  if (L.n > ((int64_t)1 << 24)) { rc = -4; goto done; } /* first_child needs 24 bits */
+  if (!nodes_out) goto done;
+  if (capacity < L.n) { rc = -2; goto done; }
+  for (int64_t v = 0; v < L.n; ++v)
+    nodes_out[v] = L.mask[v] ? (((uint32_t)L.first_child[v] << 8) | L.mask[v]) : 0u;
+
+done:
+  free(q);
+  free(perm);
+  free(tmp);
+  free(L.start);
+  free(L.count);
+  free(L.mask);
+  free(L.first_child);
+  return rc;
+}
+
+static int popcount8(uint32_t m) {
+  int c = 0;
+  for (int i = 0; i < 8; ++i) c += (int)((m >> i) & 1u);
+  return c;
+}
+
+/* Containing node at every level: start at the root; at level l the child
+ * octant of the query's cell selects a child of the level-(l-1) node, whose
+ * index is first_child plus the number of existing children with a smaller
+ * octant. A missing child ends the descent (index -1 below). */
+static void descend_one(const ora_tree* t, const float* x3, int32_t* idx) {
+  int32_t D = t->n_levels - 1;
+  int64_t q[3];
+  for (int a = 0; a < 3; ++a) q[a] = quant_axis(x3[a], D);
+  int64_t cur = 0;
+  idx[0] = 0;
+  for (int32_t l = 1; l <= D; ++l) {
+    if (cur >= 0) {
+      uint32_t word = t->nodes[cur];
+      uint32_t mask = word & 0xffu;
+      int64_t first = (int64_t)(word >> 8);
+      int o = child_octant(q, D - l);
+      if ((mask >> o) & 1u)
+        cur = first + popcount8(mask & ((1u << o) - 1u));
+      else
+        cur = -1;
+    }
+    idx[l] = (int32_t)cur;
+  }
+}
+
+void ora_descend(const ora_tree* t, const float* x, int64_t B, int32_t* idx_out) {
+  for (int64_t b = 0; b < B; ++b) descend_one(t, &x[3 * b], &idx_out[(int64_t)t->n_levels * b]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Directional: octahedral map (Sec. 3.3) and bilinear taps                  */
+/* ------------------------------------------------------------------------ */
+
+static double sign_pos(double v) { return v < 0.0 ? -1.0 : 1.0; } /* sign(0) = +1 */
+
+/* u = (wx, wy) / (|wx| + |wy| + |wz|); for wz < 0 the lower hemisphere is
+ * folded with both new coordinates computed from the unfolded u; then
+ * (s, t) = (u + 1) / 2. The zero vector maps to the map centre. */
+static void octa_one(const float* d, double* st) {
+  double dx = d[0], dy = d[1], dz = d[2];
+  double S = fabs(dx) + fabs(dy) + fabs(dz);
+  double ux = 0.0, uy = 0.0;
+  if (S > 0.0) {
+    ux = dx / S;
+    uy = dy / S;
+  }
+  if (dz < 0.0) {
+    double fx = (1.0 - fabs(uy)) * sign_pos(ux);
+    double fy = (1.0 - fabs(ux)) * sign_pos(uy);
+    ux = fx;
+    uy = fy;
+  }
+  st[0] = 0.5 * (ux + 1.0);
+  st[1] = 0.5 * (uy + 1.0);
+}
+
+void ora_octa(const float* dir, int64_t B, double* st_out) {
+  for (int64_t b = 0; b < B; ++b) octa_one(&dir[3 * b], &st_out[2 * b]);
+}
+
+/* Inverse map: a point of the unfolded square inside the diamond
+ * |u| + |v| <= 1 is on the upper hemisphere with z = 1 - |u| - |v|; a point
+ * outside it is unfolded first. */
+void ora_octa_decode(const double* st, int64_t B, double* dir_out) {
+  for (int64_t b = 0; b < B; ++b) {
+    double u = 2.0 * st[2 * b] - 1.0, v = 2.0 * st[2 * b + 1] - 1.0;
+    double z = 1.0 - fabs(u) - fabs(v);
+    if (z < 0.0) {
+      double nu = (1.0 - fabs(v)) * sign_pos(u);
+      double nv = (1.0 - fabs(u)) * sign_pos(v);
+      u = nu;
+      v = nv;
+    }
+    double len = sqrt(u * u + v * v + z * z);
+    dir_out[3 * b] = u / len;
+    dir_out[3 * b + 1] = v / len;
+    dir_out[3 * b + 2] = z / len;
+  }
+}
+
+/* Texel (i, j) has its centre at ((i + 0.5) / R, (j + 0.5) / R). The four
+ * texels around (s, t) get the usual bilinear weights. A tap outside the map
+ * is moved to the texel it touches across the octahedral seam: the edges
+ * s = 0 and s = 1 are each glued to themselves with t mirrored, and the edges
+ * t = 0 and t = 1 with s mirrored. Column wrap is applied first, then row
+ * wrap, so a corner tap lands on the diagonally opposite map corner. */
+static void taps_one(double s, double t, int32_t R, int32_t ij[8], double w[4]) {
+  double pu = s * R - 0.5, pv = t * R - 0.5;
+  double fi = floor(pu), fj = floor(pv);
+  double fu = pu - fi, fv = pv - fj;
+  int32_t i0 = (int32_t)fi, j0 = (int32_t)fj;
+  for (int k = 0; k < 4; ++k) {
+    int a = k & 1, bb = k >> 1;
+    int32_t i = i0 + a, j = j0 + bb;
+    w[k] = (a ? fu : 1.0 - fu) * (bb ? fv : 1.0 - fv);
+    if (i < 0) {
+      i = -1 - i;
+      j = R - 1 - j;
+    } else if (i >= R) {
+      i = 2 * R - 1 - i;
+      j = R - 1 - j;
+    }
+    if (j < 0) {
+      i = R - 1 - i;
+      j = -1 - j;
+    } else if (j >= R) {
+      i = R - 1 - i;
+      j = 2 * R - 1 - j;
+    }
+    ij[2 * k] = i;
+    ij[2 * k + 1] = j;
+  }
+}
+
+void ora_taps(const double* st, int64_t B, int32_t R, int32_t* ij_out, double* w_out) {
+  for (int64_t b = 0; b < B; ++b) taps_one(st[2 * b], st[2 * b + 1], R, &ij_out[8 * b], &w_out[4 * b]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Encoding: per-level features, concatenated level by level (Sec. 3.4)      */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int32_t idx[ORA_MAX_LEVELS];
+  int32_t ij[ORA_MAX_LEVELS][8];
+  double w[ORA_MAX_LEVELS][4];
+} query_taps;
+
+static void query_locate(const ora_tree* t, const float* x3, const float* d3, query_taps* qt) {
+  double st[2];
+  descend_one(t, x3, qt->idx);
+  octa_one(d3, st);
+  for (int32_t l = 0; l < t->n_levels; ++l) taps_one(st[0], st[1], t->res[l], qt->ij[l], qt->w[l]);
+}
+
+/* Offset of texel (i, j) of node idx at level l in that level's table. */
+static int64_t texel_base(const ora_tree* t, int32_t l, int32_t idx, int32_t i, int32_t j) {
+  int64_t R = t->res[l];
+  int64_t local = (int64_t)idx - t->level_offset[l];
+  return ((local * R + j) * R + i) * t->C;
+}
+
+/* h_l = sum over taps of w * T_l[node][j][i][:]; a level without a node
+ * contributes zeros. */
+static void encode_from_taps(const ora_tree* t, const query_taps* qt, double* h) {
+  int32_t C = t->C;
+  for (int32_t l = 0; l < t->n_levels; ++l) {
+    for (int32_t c = 0; c < C; ++c) h[l * C + c] = 0.0;
+    if (qt->idx[l] < 0) continue;
+    for (int k = 0; k < 4; ++k) {
+      int64_t base = texel_base(t, l, qt->idx[l], qt->ij[l][2 * k], qt->ij[l][2 * k + 1]);
+      for (int32_t c = 0; c < C; ++c) h[l * C + c] += qt->w[l][k] * (double)t->feat[l][base + c];
+    }
+  }
+}
+
+void ora_encode(const ora_tree* t, const float* x, const float* dir, int64_t B, double* h_out,
+                int32_t* idx_out) {
+  int64_t HC = (int64_t)t->n_levels * t->C;
+  for (int64_t b = 0; b < B; ++b) {
+    query_taps qt;
+    query_locate(t, &x[3 * b], &dir[3 * b], &qt);
+    encode_from_taps(t, &qt, &h_out[HC * b]);
+    if (idx_out)
+      for (int32_t l = 0; l < t->n_levels; ++l) idx_out[(int64_t)t->n_levels * b + l] = qt.idx[l];
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Decoder MLP (Sec. 3.5): ReLU hidden layers, linear output                 */
+/* ------------------------------------------------------------------------ */
+
+#define ORA_MAX_WIDTH 256
+
+/* Forward pass of one row. act[i] receives the input of layer i (act[0] = h)
+ * and pre[i] the pre-activation of layer i. */
+static void mlp_row(const ora_mlp* m, const double* h, double act[][ORA_MAX_WIDTH],
+                    double pre[][ORA_MAX_WIDTH], double* out) {
+  for (int32_t k = 0; k < m->dims[0]; ++k) act[0][k] = h[k];
+  for (int32_t i = 0; i < m->n_layers; ++i) {
+    int32_t fin = m->dims[i], fout = m->dims[i + 1];
+    for (int32_t o = 0; o < fout; ++o) {
+      double z = (double)m->b[i][o];
+      for (int32_t k = 0; k < fin; ++k) z += (double)m->W[i][(int64_t)o * fin + k] * act[i][k];
+      pre[i][o] = z;
+      if (i + 1 < m->n_layers)
+        act[i + 1][o] = z > 0.0 ? z : 0.0;
+      else
+        out[o] = z;
+    }
+  }
+}
+
+void ora_mlp_fwd(const ora_mlp* m, const double* h, int64_t B, double* out) {
+  static __thread double act[ORA_MAX_LAYERS + 1][ORA_MAX_WIDTH];
+  static __thread double pre[ORA_MAX_LAYERS][ORA_MAX_WIDTH];
+  int32_t din = m->dims[0], dout = m->dims[m->n_layers];
+  for (int64_t b = 0; b < B; ++b) mlp_row(m, &h[din * b], act, pre, &out[dout * b]);
+}
+
+void ora_query_fwd(const ora_tree* t, const ora_mlp* m, const float* x, const float* dir,
+                   int64_t B, double* rgb_out, int32_t nthreads) {
+  int32_t dout = m->dims[m->n_layers];
+#ifdef _OPENMP
+  int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#pragma omp parallel for schedule(static) num_threads(nt)
+#endif
+  for (int64_t b = 0; b < B; ++b) {
+    double h[ORA_MAX_LEVELS * 16];
+    double act[ORA_MAX_LAYERS + 1][ORA_MAX_WIDTH];
+    double pre[ORA_MAX_LAYERS][ORA_MAX_WIDTH];
+    query_taps qt;
+    query_locate(t, &x[3 * b], &dir[3 * b], &qt);
+    encode_from_taps(t, &qt, h);
+    mlp_row(m, h, act, pre, &rgb_out[dout * b]);
+  }
+  (void)nthreads;
+}
+
+/* ------------------------------------------------------------------------ */
+/* BSDF weight (rendering equation, Sec. 3.2)                                */
+/* ------------------------------------------------------------------------ */
+
+static double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* f_r = albedo / pi + D G F / (4 cos_i cos_o) with the GGX distribution
+ * D = a^2 / (pi ((n.h)^2 (a^2 - 1) + 1)^2), the separable Smith term
+ * G1(c) = 2c / (c + sqrt(a^2 + (1 - a^2) c^2)), Schlick's Fresnel
+ * F = F0 + (1 - F0)(1 - wi.h)^5, and a = roughness. The sample weight is
+ * f_r |n . wi| / pdf; directions below either horizon weigh zero. */
+static void bsdf_one(const float* n3, const float* wo3, const float* wi3, const float* alb3,
+                     double alpha, double F0, double pdf, double w[3]) {
+  double n[3], wo[3], wi[3];
+  for (int a = 0; a < 3; ++a) {
+    n[a] = n3[a];
+    wo[a] = wo3[a];
+    wi[a] = wi3[a];
+  }
+  double ci = dot3(n, wi), co = dot3(n, wo);
+  if (ci <= 0.0 || co <= 0.0) {
+    w[0] = w[1] = w[2] = 0.0;
+    return;
+  }
+  double hv[3] = {wi[0] + wo[0], wi[1] + wo[1], wi[2] + wo[2]};
+  double hl = sqrt(dot3(hv, hv));
+  for (int a = 0; a < 3; ++a) hv[a] /= hl;
+  double nh = dot3(n, hv);
+  double a2 = alpha * alpha;
+  double den = nh * nh * (a2 - 1.0) + 1.0;
+  double Dm = a2 / (PI * den * den);
+  double g1i = 2.0 * ci / (ci + sqrt(a2 + (1.0 - a2) * ci * ci));
+  double g1o = 2.0 * co / (co + sqrt(a2 + (1.0 - a2) * co * co));
+  double F = F0 + (1.0 - F0) * pow(1.0 - dot3(wi, hv), 5.0);
+  double spec = Dm * g1i * g1o * F / (4.0 * ci * co);
+  for (int c = 0; c < 3; ++c) w[c] = ((double)alb3[c] / PI + spec) * fabs(ci) / pdf;
+}
+
+void ora_bsdf_weight(const ora_batch* bt, double* w_out) {
+  for (int64_t b = 0; b < bt->B; ++b)
+    for (int32_t k = 0; k < bt->N; ++k) {
+      int64_t bk = b * bt->N + k;
+      double p = bt->pdf ? (double)bt->pdf[bk] : 1.0;
+      bsdf_one(&bt->n[3 * b], &bt->wo[3 * b], &bt->wi[3 * bk], &bt->albedo[3 * b],
+               (double)bt->rough[b], bt->F0, p, &w_out[3 * bk]);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Residual step (Sec. 3.2 Monte-Carlo target, Sec. 3.6 loss)                */
+/* ------------------------------------------------------------------------ */
+
+/* LHS radiance at (x, d), RHS target T = L_e + (1/N) sum_k w_k * L(x'_k, d'_k)
+ * (or the override), and the residual r = LHS - T. */
+static int residual_parts(const ora_tree* t, const ora_mlp* m, const ora_batch* bt, double* lhs,
+                          double* T, double* r, int32_t nthreads) {
+  int64_t B = bt->B;
+  int32_t N = bt->N;
+  ora_query_fwd(t, m, bt->x, bt->dir, B, lhs, nthreads);
+  if (bt->target_override) {
+    for (int64_t i = 0; i < 3 * B; ++i) T[i] = (double)bt->target_override[i];
+  } else {
+    for (int64_t i = 0; i < 3 * B; ++i) T[i] = (double)bt->Le[i];
+    if (N > 0) {
+      double* rhsq = (double*)malloc((size_t)(B * N * 3) * sizeof(double));
+      double* w = (double*)malloc((size_t)(B * N * 3) * sizeof(double));
+      if (!rhsq || !w) {
+        free(rhsq);
+        free(w);
+        return -5;
+      }
+      ora_query_fwd(t, m, bt->x2, bt->dir2, B * N, rhsq, nthreads);
+      ora_bsdf_weight(bt, w);
+      for (int64_t b = 0; b < B; ++b)
+        for (int c = 0; c < 3; ++c) {
+          double acc = 0.0;
+          for (int32_t k = 0; k < N; ++k) acc += w[3 * (b * N + k) + c] * rhsq[3 * (b * N + k) + c];
+          T[3 * b + c] += acc / (double)N;
+        }
+      free(rhsq);
+      free(w);
+    }
+  }
+  for (int64_t i = 0; i < 3 * B; ++i) r[i] = lhs[i] - T[i];
+  return 0;
+}
+
+/* Normaliser of the relative loss, treated as a constant: the sum of
+ * prediction and target, clamped at zero, plus eps. */
+static double rel_norm(double lhs, double T, double eps) {
+  double s = lhs + T;
+  return (s > 0.0 ? s : 0.0) + eps;
+}
+
+static int check_inputs(const ora_tree* t, const ora_mlp* m, const ora_batch* bt) {
+  if (!t || !m || !bt || bt->B < 0 || bt->N < 0) return -1;
+  if (t->n_levels < 1 || t->n_levels > ORA_MAX_LEVELS) return -1;
+  if (m->n_layers < 1 || m->n_layers > ORA_MAX_LAYERS) return -1;
+  if (m->dims[0] != t->n_levels * t->C || m->dims[m->n_layers] != 3) return -1;
+  for (int32_t i = 0; i <= m->n_layers; ++i)
+    if (m->dims[i] < 1 || m->dims[i] > ORA_MAX_WIDTH) return -1;
+  if (t->n_levels * t->C > ORA_MAX_LEVELS * 16) return -1;
+  return 0;
+}
+
+int ora_residual_fwd(const ora_tree* t, const ora_mlp* m, const ora_batch* bt, double* lhs_out,
+                     double* rhs_out, double* resid_out, double* loss_out, int32_t nthreads) {
+  int rc = check_inputs(t, m, bt);
+  if (rc) return rc;
+  int64_t B = bt->B;
+  rc = residual_parts(t, m, bt, lhs_out, rhs_out, resid_out, nthreads);
+  if (rc) return rc;
+  double acc = 0.0;
+  for (int64_t i = 0; i < 3 * B; ++i) {
+    double r = resid_out[i];
+    if (bt->loss_kind == 1) r /= rel_norm(lhs_out[i], rhs_out[i], bt->eps);
+    acc += r * r;
+  }
+  *loss_out = B > 0 ? acc / (3.0 * (double)B) : 0.0;
+  return 0;
+}
+
+/* Reverse pass of one query for the radiance seed g: the dense-layer
+ * gradients (ReLU'(0) = 0), then dh = W_1^T delta_1, then each tap's share
+ * w_tap * dh_l added to the texel it read. */
+static void backprop_query(const ora_tree* t, const ora_mlp* m, const float* x3, const float* d3,
+                           const double g[3], double* const* dfeat, double* const* dW,
+                           double* const* db) {
+  double h[ORA_MAX_LEVELS * 16];
+  double act[ORA_MAX_LAYERS + 1][ORA_MAX_WIDTH];
+  double pre[ORA_MAX_LAYERS][ORA_MAX_WIDTH];
+  double out[ORA_MAX_WIDTH];
+  double delta[ORA_MAX_WIDTH], prev[ORA_MAX_WIDTH];
+  query_taps qt;
+  query_locate(t, x3, d3, &qt);
+  encode_from_taps(t, &qt, h);
+  mlp_row(m, h, act, pre, out);
+
+  int32_t nl = m->n_layers;
+  for (int32_t o = 0; o < m->dims[nl]; ++o) delta[o] = g[o];
+  for (int32_t i = nl - 1; i >= 0; --i) {
+    int32_t fin = m->dims[i], fout = m->dims[i + 1];
+    for (int32_t o = 0; o < fout; ++o) {
+      db[i][o] += delta[o];
+      for (int32_t k = 0; k < fin; ++k) dW[i][(int64_t)o * fin + k] += delta[o] * act[i][k];
+    }
+    for (int32_t k = 0; k < fin; ++k) {
+      double s = 0.0;
+      for (int32_t o = 0; o < fout; ++o) s += (double)m->W[i][(int64_t)o * fin + k] * delta[o];
+      if (i > 0 && !(pre[i - 1][k] > 0.0)) s = 0.0;
+      prev[k] = s;
+    }
+    for (int32_t k = 0; k < fin; ++k) delta[k] = prev[k];
+  }
+  /* delta now holds dL/dh. */
+  int32_t C = t->C;
+  for (int32_t l = 0; l < t->n_levels; ++l) {
+    if (qt.idx[l] < 0) continue;
+    for (int k = 0; k < 4; ++k) {
+      int64_t base = texel_base(t, l, qt.idx[l], qt.ij[l][2 * k], qt.ij[l][2 * k + 1]);
+      for (int32_t c = 0; c < C; ++c) dfeat[l][base + c] += qt.w[l][k] * delta[l * C + c];
+    }
+  }
+}
+
+/* Gradient of the loss scaled by grad_loss. With the target detached (the
+ * paper's choice) only the LHS query receives the seed
+ * 2 r grad_loss / (3B) (divided by the squared normaliser for the relative
+ * loss). With grad_through_rhs each RHS query (b, k) also receives
+ * -seed_b * w_bk / N. */
+int ora_residual_bwd(const ora_tree* t, const ora_mlp* m, const ora_batch* bt, double grad_loss,
+                     double* const* dfeat, double* const* dW, double* const* db,
+                     int32_t nthreads) {
+  int rc = check_inputs(t, m, bt);
+  if (rc) return rc;
+  int64_t B = bt->B;
+  int32_t N = bt->N;
+  if (B == 0) return 0;
+  double* lhs = (double*)malloc((size_t)(3 * B) * sizeof(double));
+  double* T = (double*)malloc((size_t)(3 * B) * sizeof(double));
+  double* r = (double*)malloc((size_t)(3 * B) * sizeof(double));
+  double* w = NULL;
+  if (!lhs || !T || !r) { rc = -5; goto done; }
+  rc = residual_parts(t, m, bt, lhs, T, r, nthreads);
+  if (rc) goto done;
+  int full = bt->grad_through_rhs && !bt->target_override && N > 0;
+  if (full) {
+    w = (double*)malloc((size_t)(3 * B * N) * sizeof(double));
+    if (!w) { rc = -5; goto done; }
+    ora_bsdf_weight(bt, w);
+  }
+  for (int64_t b = 0; b < B; ++b) {
+    double g[3];
+    for (int c = 0; c < 3; ++c) {
+      double gc = 2.0 * r[3 * b + c] * grad_loss / (3.0 * (double)B);
+      if (bt->loss_kind == 1) {
+        double rho = rel_norm(lhs[3 * b + c], T[3 * b + c], bt->eps);
+        gc /= rho * rho;
+      }
+      g[c] = gc;
+    }
+    backprop_query(t, m, &bt->x[3 * b], &bt->dir[3 * b], g, dfeat, dW, db);
+    if (full) {
+      for (int32_t k = 0; k < N; ++k) {
+        int64_t bk = b * N + k;
+        double gk[3];
+        for (int c = 0; c < 3; ++c) gk[c] = -g[c] * w[3 * bk + c] / (double)N;
+        backprop_query(t, m, &bt->x2[3 * bk], &bt->dir2[3 * bk], gk, dfeat, dW, db);
+      }
+    }
+  }
+done:
+  free(lhs);
+  free(T);
+  free(r);
+  free(w);
+  return rc;
+}

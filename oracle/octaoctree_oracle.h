@@ -1,0 +1,114 @@
+/*
+ * FP64 CPU oracle for the OctaOctree query and the neural-radiosity residual
+ * step (OctaOctree Neural Radiosity, Sec. 3.2-3.6).
+ *
+ * TEST INFRASTRUCTURE ONLY. This library exists to check the HIP library
+ * against a plain, slow, obviously correct implementation. Only the test
+ * suite, the smoke check and the benchmark's CPU-baseline leg may load it.
+ * It shares no source, header, table or helper with the HIP library.
+ *
+ * Conventions
+ *  - Every FP32 input is widened exactly to double; all arithmetic is FP64.
+ *  - Feature tables are the FP32 master copies, laid out per level as
+ *    [n_l][R_l][R_l][C] (row = t direction, column = s direction).
+ *  - Node words: (first_child << 8) | child_mask, first_child a global node
+ *    index, child octant o = bx | by << 1 | bz << 2. Leaves hold 0.
+ *  - Levels 0..D; level 0 is the root.
+ *  - Functions that can fail return 0 on success, a negative code otherwise.
+ *
+ * Parity status per function is listed in the comment above each one.
+ */
+#ifndef OCTAOCTREE_ORACLE_H
+#define OCTAOCTREE_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORA_MAX_LEVELS 16
+#define ORA_MAX_LAYERS 7
+
+typedef struct {
+  int32_t n_levels;                          /* L = D + 1 */
+  int32_t C;                                 /* features per texel */
+  int32_t res[ORA_MAX_LEVELS];               /* R_l texels per side */
+  int64_t level_offset[ORA_MAX_LEVELS + 1];  /* level l = [off_l, off_{l+1}) */
+  const uint32_t* nodes;
+  const float* feat[ORA_MAX_LEVELS];         /* FP32 masters */
+} ora_tree;
+
+typedef struct {
+  int32_t n_layers;                          /* number of Linear layers */
+  int32_t dims[ORA_MAX_LAYERS + 1];          /* dims[0] = L*C, dims[n_layers] = 3 */
+  const float* W[ORA_MAX_LAYERS];            /* [dims[i+1]][dims[i]] row-major */
+  const float* b[ORA_MAX_LAYERS];            /* [dims[i+1]] */
+} ora_mlp;
+
+typedef struct {
+  int64_t B;
+  int32_t N;
+  const float *x, *dir, *n, *wo, *albedo, *Le; /* [B][3] */
+  const float* rough;                          /* [B] GGX alpha */
+  const float *x2, *dir2, *wi;                 /* [B][N][3] */
+  const float* pdf;                            /* [B][N] or NULL (== 1) */
+  const float* target_override;                /* [B][3] or NULL */
+  double F0;
+  int32_t loss_kind;                           /* 0 mean L2, 1 relative L2 */
+  double eps;
+  int32_t grad_through_rhs;                    /* 0 detached target, 1 full */
+} ora_batch;
+
+/* Octree construction from surface samples (refinement rule: a node at level
+ * l < D holding more than tau samples gets its non-empty children). */
+int ora_build_octree(const float* samples, int64_t n, int32_t D, int32_t tau,
+                     uint32_t* nodes_out, int64_t capacity,
+                     int64_t* level_offset_out, int64_t* n_nodes_out);
+
+/* Integer cell coordinates of x at the finest level D, clamped. [B][3]. */
+void ora_quantize(const float* x, int64_t B, int32_t D, int64_t* q_out);
+
+/* Node containing x at every level, -1 where the tree has no node. [B][L]. */
+void ora_descend(const ora_tree* t, const float* x, int64_t B, int32_t* idx_out);
+
+/* Octahedral projection and fold (Sec. 3.3), remapped to [0,1]^2. [B][2]. */
+void ora_octa(const float* dir, int64_t B, double* st_out);
+
+/* Inverse of ora_octa: unit direction for a map coordinate. [B][3]. */
+void ora_octa_decode(const double* st, int64_t B, double* dir_out);
+
+/* Four bilinear taps at resolution R: texel (i, j) pairs [B][4][2] and
+ * weights [B][4]. */
+void ora_taps(const double* st, int64_t B, int32_t R, int32_t* ij_out, double* w_out);
+
+/* Concatenated per-level features h [B][L*C] and node indices [B][L]
+ * (idx_out may be NULL). */
+void ora_encode(const ora_tree* t, const float* x, const float* dir, int64_t B,
+                double* h_out, int32_t* idx_out);
+
+/* Decoder MLP on FP64 inputs h [B][dims[0]] -> out [B][dims[n_layers]]. */
+void ora_mlp_fwd(const ora_mlp* m, const double* h, int64_t B, double* out);
+
+/* Encode + MLP, queries processed in parallel over nthreads (<= 0: all). */
+void ora_query_fwd(const ora_tree* t, const ora_mlp* m, const float* x, const float* dir,
+                   int64_t B, double* rgb_out, int32_t nthreads);
+
+/* BSDF sample weight f_r * |n . wi| / pdf for every (b, k): [B][N][3]. */
+void ora_bsdf_weight(const ora_batch* bt, double* w_out);
+
+/* Residual forward: LHS radiance, RHS target, residual [B][3] and loss. */
+int ora_residual_fwd(const ora_tree* t, const ora_mlp* m, const ora_batch* bt,
+                     double* lhs_out, double* rhs_out, double* resid_out, double* loss_out,
+                     int32_t nthreads);
+
+/* Residual backward for upstream gradient grad_loss. Gradients accumulate
+ * (+=) into dfeat[l] ([n_l][R_l][R_l][C]), dW[i], db[i], all FP64. */
+int ora_residual_bwd(const ora_tree* t, const ora_mlp* m, const ora_batch* bt, double grad_loss,
+                     double* const* dfeat, double* const* dW, double* const* db,
+                     int32_t nthreads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
