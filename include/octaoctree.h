@@ -1,0 +1,242 @@
+/*
+ * liboctaoctree: the OctaOctree query and neural-radiosity residual step on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: OctaOctree Neural Radiosity for Real-time Glossy Material Rendering.
+ *  - Sec. 3.3: a direction is projected onto the octahedron, its lower
+ *    hemisphere folded, and the result remapped to [0,1]^2.
+ *  - Sec. 3.4: an adaptive octree over the scene; every non-empty cell at
+ *    every level holds a C-channel octahedral feature map; the per-level
+ *    features are concatenated into h (dimension levels * C).
+ *  - Sec. 3.5: a small MLP decodes h into RGB radiance.
+ *  - Sec. 3.2: the residual step compares the prediction at (x, w_o) with a
+ *    Monte-Carlo estimate of the rendering equation's right-hand side built
+ *    from predictions at secondary hits.
+ *  - Sec. 3.6: the target is detached from the gradient.
+ *
+ * Where the paper leaves a choice open, this library takes these readings:
+ *  - Each level reads the node that contains x (no 8-cell trilinear blend).
+ *  - Each map has R x R texels, read by a bilinear fetch at texel centres.
+ *    The octahedral seams are glued: the edges s = 0 and s = 1 each meet
+ *    themselves with t mirrored, and the edges t = 0 and t = 1 with s
+ *    mirrored. The barycentric vertex lookup is not used.
+ *  - The decoder reads h only.
+ *  - The BSDF is Lambert plus GGX.
+ *
+ * Conventions for every entry point:
+ *  - Return value: OO_OK (0) or a negative status. oo_last_error() holds a
+ *    message for the calling thread.
+ *  - Array pointers are DEVICE pointers owned by the caller unless marked
+ *    "host". The library allocates no device memory. Scratch memory comes
+ *    from a caller-provided workspace.
+ *  - Device work is enqueued asynchronously on the given hipStream_t (NULL
+ *    is the default stream). Device faults surface at the caller's next
+ *    synchronisation. oo_build_octree runs on the host and is synchronous.
+ *  - B = 0 (no queries) is a valid no-op.
+ *  - Gradient outputs accumulate (+=). The caller zeroes them.
+ *  - Inputs are FP32 unless a dtype field says otherwise. FP32 arrays need
+ *    4-byte alignment. Feature tables need 16-byte alignment.
+ *  - Points are expected in the unit cube. Coordinates outside it are
+ *    clamped to the boundary cells. NaN inputs give unspecified results.
+ */
+#ifndef OCTAOCTREE_H
+#define OCTAOCTREE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OO_MAX_LEVELS 16
+#define OO_MAX_LAYERS 7
+
+/* Status codes. */
+#define OO_OK 0
+#define OO_EINVAL (-1)        /* invalid argument (shape, pointer, alignment) */
+#define OO_ECAPACITY (-2)     /* output capacity too small; needed size written */
+#define OO_EHIP (-3)          /* a HIP runtime call failed */
+#define OO_EUNSUPPORTED (-4)  /* valid but not implemented (e.g. a layer width) */
+
+typedef enum { OO_F32 = 0, OO_F16 = 1, OO_BF16 = 2 } oo_dtype;
+
+/*
+ * The octree and its feature maps (Sec. 3.4). All pointers are device
+ * pointers.
+ *  - n_levels: L = D + 1 levels, 0 (root) ..= D, with 1 <= L <= 16.
+ *  - C: channels per texel, 4 or 8.
+ *  - res[l]: the level-l map is res[l] x res[l] texels. A power of two in
+ *    [2, 64].
+ *  - level_offset: the nodes of level l have global indices
+ *    [level_offset[l], level_offset[l+1]).
+ *  - nodes: one 32-bit word per node, breadth first; within a level, nodes
+ *    are ordered by parent, then octant.
+ *    word = (first_child << 8) | child_mask. Bit o of the mask is set when
+ *    the child in octant o = bx | by << 1 | bz << 2 exists. first_child is
+ *    the global index of the lowest existing child. A leaf's word is 0.
+ *  - feat[l]: level-l table [n_l][res][res][C] of feat_dtype. Row index is
+ *    t (v), column index is s (u), channels contiguous. 16-byte aligned.
+ */
+typedef struct {
+  int32_t n_levels;
+  int32_t C;
+  int32_t res[OO_MAX_LEVELS];
+  int64_t level_offset[OO_MAX_LEVELS + 1];
+  const uint32_t* nodes;
+  oo_dtype feat_dtype;
+  const void* feat[OO_MAX_LEVELS];
+} oo_tree;
+
+/*
+ * The decoder MLP (Sec. 3.5). Hidden layers use ReLU; the output layer is
+ * linear.
+ *  - n_layers: number of Linear layers, 2..5.
+ *  - dims[0] = n_levels * C (at most 128). dims[n_layers] = 3. Every hidden
+ *    width is the same: 64 or 128.
+ *  - W[i]: [dims[i+1]][dims[i]] row-major in `dtype`. Also the operand type
+ *    of the matrix cores. Accumulation is always FP32.
+ *  - b[i]: [dims[i+1]] FP32.
+ */
+typedef struct {
+  int32_t n_layers;
+  int32_t dims[OO_MAX_LAYERS + 1];
+  oo_dtype dtype;
+  const void* W[OO_MAX_LAYERS];
+  const float* b[OO_MAX_LAYERS];
+} oo_mlp;
+
+/*
+ * Octree construction on the host (Sec. 3.4 sparse octree of non-empty cells;
+ * Sec. 4.1 o-cnn-style structure).
+ *  - Refinement rule: the root always exists. A node at level l < max_depth
+ *    holding MORE than split_threshold samples gets every child octant that
+ *    holds at least one sample.
+ *  - samples_xyz_host: host [n][3] FP32 points in the unit cube.
+ *  - Size query: call with nodes_out_host == NULL. Then only
+ *    *n_nodes_out_host and level_offset_out_host are written.
+ *  - capacity: size of nodes_out_host in words. If it is too small the call
+ *    returns OO_ECAPACITY and still writes the needed count.
+ *  - level_offset_out_host: host [max_depth + 2].
+ *  - Returns OO_EUNSUPPORTED if the tree needs more than 2^24 nodes.
+ */
+int oo_build_octree(const float* samples_xyz_host, int64_t n, int32_t max_depth,
+                    int32_t split_threshold, uint32_t* nodes_out_host, int64_t capacity,
+                    int64_t* level_offset_out_host, int64_t* n_nodes_out_host);
+
+/*
+ * Encoding query: the node containing x at every level, the octahedral
+ * coordinate of dir, and a bilinear fetch per level (Sec. 3.3-3.4).
+ *  - x, dir: [B][3] FP32.
+ *  - h_out: [B][n_levels * C] in h_dtype. Level-major, channels contiguous.
+ *    A level without a node contributes zeros.
+ *  - node_idx_out: [B][n_levels] global node index per level, -1 where the
+ *    tree has no node. May be NULL.
+ */
+int oo_encode_query(const oo_tree* tree, const float* x, const float* dir, int64_t B, void* h_out,
+                    oo_dtype h_dtype, int32_t* node_idx_out, hipStream_t stream);
+
+/*
+ * Decoder forward on materialised features (Sec. 3.5).
+ *  - h: [B][dims[0]] in h_dtype. h_dtype must equal mlp->dtype.
+ *  - rgb_out: [B][3] FP32.
+ */
+int oo_mlp_fwd(const oo_mlp* mlp, const void* h, oo_dtype h_dtype, int64_t B, float* rgb_out,
+               hipStream_t stream);
+
+/*
+ * Fused query forward: encode + decode in one kernel. h stays on chip
+ * (Sec. 3.6, rendering: one query and one decoder evaluation per visible
+ * point).
+ *  - x, dir: [B][3] FP32. rgb_out: [B][3] FP32.
+ *  - Supported type pairs (tree->feat_dtype, mlp->dtype): (F32, F32),
+ *    (F16, F16), (BF16, BF16).
+ */
+int oo_query_fwd(const oo_tree* tree, const oo_mlp* mlp, const float* x, const float* dir, int64_t B,
+                 float* rgb_out, hipStream_t stream);
+
+/*
+ * One batch of the neural-radiosity residual (Sec. 3.2 Monte-Carlo RHS;
+ * Sec. 3.6 loss). All pointers are device pointers.
+ *  - B: number of LHS points. N: secondary samples per point, N >= 0.
+ *  - Per point, [B][3] FP32: x, dir (lookup direction of the LHS query),
+ *    n (normal), wo (outgoing direction), albedo, Le (emission).
+ *  - rough: [B] FP32, the GGX alpha.
+ *  - Per sample, [B][N][3] FP32: x2 (secondary hit), dir2 (lookup
+ *    direction at the hit), wi (sampled incident direction).
+ *  - pdf: [B][N] FP32, or NULL for 1.
+ *  - target_override: [B][3] FP32. When set, it replaces the RHS estimate
+ *    and no RHS query is made. Finite-difference checks use this to freeze
+ *    the target.
+ *  - F0: Schlick reflectance at normal incidence.
+ *  - loss_kind: 0 = mean L2 over the 3B entries. 1 = relative L2 with the
+ *    detached normaliser max(LHS + T, 0) + eps (Sec. 3.6).
+ *  - grad_through_rhs: 0 = target detached (the paper's choice). 1 = the
+ *    gradient also flows into the RHS queries.
+ *  - BSDF: f = albedo/pi + D G F / (4 cos_i cos_o) with GGX D, Smith's
+ *    separable G, Schlick's F. Sample weight: f |n . wi| / pdf. n, wo and wi
+ *    are normalised first. A direction below either horizon weighs 0.
+ */
+typedef struct {
+  int64_t B;
+  int32_t N;
+  const float *x, *dir, *n, *wo, *albedo, *Le;
+  const float* rough;
+  const float *x2, *dir2, *wi;
+  const float* pdf;
+  const float* target_override;
+  float F0;
+  int32_t loss_kind;
+  float eps;
+  int32_t grad_through_rhs;
+} oo_residual_batch;
+
+/* Workspace size in bytes that the residual forward and backward need for
+ * this problem. The same workspace serves both calls. */
+int oo_residual_workspace_bytes(const oo_tree* tree, const oo_mlp* mlp,
+                                const oo_residual_batch* batch, size_t* bytes);
+
+/*
+ * Residual forward.
+ *  - Outputs, each [B][3] FP32: lhs_out = L(x, dir);
+ *    rhs_out = T = Le + (1/N) sum_k w_k * L(x2_k, dir2_k), or the override;
+ *    resid_out = lhs - T.
+ *  - loss_out: device FP64 scalar, sum over entries of r^2 / (3B). The
+ *    relative loss divides each r by its normaliser first.
+ *  - The loss reduction runs in FP64 in a fixed order, so repeated calls
+ *    give identical bits.
+ */
+int oo_radiosity_residual_fwd(const oo_tree* tree, const oo_mlp* mlp, const oo_residual_batch* batch,
+                              float* lhs_out, float* rhs_out, float* resid_out, double* loss_out,
+                              void* workspace, hipStream_t stream);
+
+/*
+ * Residual backward. The encoding is recomputed, not stored.
+ *  - resid, rhs: the forward's outputs for the same batch and parameters.
+ *  - grad_loss: device FP64 scalar, dLoss_total/dloss.
+ *  - dfeat[l]: FP32 [n_l][res][res][C]. Receives += the feature gradient by
+ *    atomic scatter; the summation order is not fixed.
+ *  - dW[i], db[i]: FP32, shaped like the layer. Receive += the reduced
+ *    gradient; the reduction order is fixed.
+ *  - Gradients are for the tables and weights the forward read. In
+ *    mixed-precision runs those are the FP16/BF16 working copies, and the
+ *    gradient is applied to the FP32 masters.
+ */
+int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_residual_batch* batch,
+                              const float* resid, const float* rhs, const double* grad_loss,
+                              float* const* dfeat, float* const* dW, float* const* db, void* workspace,
+                              hipStream_t stream);
+
+/* FP32 -> FP16/BF16 (round to nearest even) or FP32 copy, n elements. Used
+ * to refresh working copies from FP32 masters. */
+int oo_cast_params(const float* src_fp32, void* dst, oo_dtype dst_dtype, int64_t n, hipStream_t stream);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char* oo_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OCTAOCTREE_H */

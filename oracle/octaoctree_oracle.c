@@ -406,6 +406,12 @@ static double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1]
  * G1(c) = 2c / (c + sqrt(a^2 + (1 - a^2) c^2)), Schlick's Fresnel
  * F = F0 + (1 - F0)(1 - wi.h)^5, and a = roughness. The sample weight is
  * f_r |n . wi| / pdf; directions below either horizon weigh zero. */
+static void normalize3(double* v) {
+  double l = sqrt(dot3(v, v));
+  if (l > 0.0)
+    for (int a = 0; a < 3; ++a) v[a] /= l;
+}
+
 static void bsdf_one(const float* n3, const float* wo3, const float* wi3, const float* alb3,
                      double alpha, double F0, double pdf, double w[3]) {
   double n[3], wo[3], wi[3];
@@ -414,6 +420,10 @@ static void bsdf_one(const float* n3, const float* wo3, const float* wi3, const 
     wo[a] = wo3[a];
     wi[a] = wi3[a];
   }
+  /* directions are unit vectors: FP32 inputs are normalised first */
+  normalize3(n);
+  normalize3(wo);
+  normalize3(wi);
   double ci = dot3(n, wi), co = dot3(n, wo);
   if (ci <= 0.0 || co <= 0.0) {
     w[0] = w[1] = w[2] = 0.0;

@@ -39,7 +39,8 @@ def test_alpha_one_closed_form_any_angle():
         wi, wo = unit(g.normal(size=3)), unit(g.normal(size=3))
         wi[2], wo[2] = abs(wi[2]), abs(wo[2])
         n = np.array([0, 0, 1], np.float32)
-        ci, co = float(wi[2]), float(wo[2])
+        ci = float(wi[2]) / np.linalg.norm(wi.astype(np.float64))
+        co = float(wo[2]) / np.linalg.norm(wo.astype(np.float64))
         w = one_sample(n, wo, wi, [0, 0, 0], 1.0, F0=1.0)
         np.testing.assert_allclose(w, ci / (math.pi * (ci + 1) * (co + 1)), rtol=1e-11)
 
@@ -55,10 +56,11 @@ def test_reciprocity_horizon_albedo_and_pdf():
             wo = -wo
         a = float(g.uniform(0.02, 1))
         alb = g.uniform(0, 1, 3).astype(np.float32)
-        ci, co = float(np.dot(wi.astype(np.float64), n)), float(np.dot(wo.astype(np.float64), n))
+        un = lambda v: v.astype(np.float64) / np.linalg.norm(v.astype(np.float64))
+        ci, co = float(np.dot(un(wi), un(n))), float(np.dot(un(wo), un(n)))
         f_io = one_sample(n, wo, wi, alb, a) / ci
         f_oi = one_sample(n, wi, wo, alb, a) / co
-        np.testing.assert_allclose(f_io, f_oi, rtol=2e-6)  # reciprocity (FP32-unit inputs)
+        np.testing.assert_allclose(f_io, f_oi, rtol=1e-12)  # reciprocity
         diff = one_sample(n, wo, wi, alb, a) - one_sample(n, wo, wi, [0, 0, 0], a)
         np.testing.assert_allclose(diff, alb.astype(np.float64) / math.pi * ci, rtol=1e-10, atol=1e-15)
         np.testing.assert_allclose(one_sample(n, wo, wi, alb, a, pdf=0.25),
@@ -246,10 +248,10 @@ def test_scatter_conservation_uniform_shift():
     every query with a node there (weights sum to 1), so the sum of the
     level's feature gradient equals the derivative of that shift."""
     tree, mlp, batch = tiny_problem(seed=12, N=2, B=32, bias_scale=0.1)
-    # tables on a 2^-20 grid so that a shift by 2^-20 is exact in FP32
+    # tables on a 2^-20 grid so that a shift by 2^-16 is exact in FP32
     q = [np.round(f * 2.0 ** 20).astype(np.float32) / np.float32(2.0 ** 20) for f in tree.feat]
     tree = oracle.Tree(tree.nodes, tree.level_offset, tree.res, tree.C, q)
-    e = 2.0 ** -20
+    e = 2.0 ** -16  # loss is piecewise quadratic in a shift: central differences are exact off kinks
     fb = _frozen(tree, mlp, batch)
     dfeat, _, _ = oracle.residual_bwd(tree, mlp, fb)
     for l in range(tree.n_levels):
@@ -260,4 +262,4 @@ def test_scatter_conservation_uniform_shift():
                 return _loss(oracle.Tree(tree.nodes, tree.level_offset, tree.res, tree.C, feat), mlp, fb)
             fd = (at(np.float32(e)) - at(np.float32(-e))) / (2 * e)
             s = dfeat[l][..., c].sum()
-            assert abs(s - fd) <= 1e-6 * max(1e-3, abs(fd)), (l, c, s, fd)
+            assert abs(s - fd) <= 2e-6 * max(1e-3, abs(fd)), (l, c, s, fd)
