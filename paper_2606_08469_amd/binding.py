@@ -1,0 +1,343 @@
+"""Python binding of liboctaoctree (ctypes + torch for device memory/streams).
+
+Argument marshalling only: every step runs in the library's HIP kernels. There
+is no CPU fallback; a missing library or a failing call raises.
+
+Entry points mirror include/octaoctree.h: build_octree, encode_query,
+mlp_fwd, query_fwd, residual_workspace_bytes, residual_fwd, residual_bwd,
+cast_params. ``OctaOctree`` bundles an octree, its FP32 master tables and MLP
+(plus 16-bit working copies), and ``RadiosityResidual`` is the
+torch.autograd.Function of the residual step (Sec. 3.2 / 3.6: the target is
+detached).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+MAX_LEVELS = 16
+MAX_LAYERS = 7
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboctaoctree.so")
+
+F32, F16, BF16 = 0, 1, 2
+DTYPE_CODE = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
+CODE_DTYPE = {v: k for k, v in DTYPE_CODE.items()}
+
+
+class OOError(RuntimeError):
+    pass
+
+
+class _Tree(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("C", C.c_int32), ("res", C.c_int32 * MAX_LEVELS),
+                ("level_offset", C.c_int64 * (MAX_LEVELS + 1)), ("nodes", C.c_void_p),
+                ("feat_dtype", C.c_int32), ("feat", C.c_void_p * MAX_LEVELS)]
+
+
+class _MLP(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("dims", C.c_int32 * (MAX_LAYERS + 1)), ("dtype", C.c_int32),
+                ("W", C.c_void_p * MAX_LAYERS), ("b", C.c_void_p * MAX_LAYERS)]
+
+
+class _Batch(C.Structure):
+    _fields_ = [("B", C.c_int64), ("N", C.c_int32),
+                ("x", C.c_void_p), ("dir", C.c_void_p), ("n", C.c_void_p), ("wo", C.c_void_p),
+                ("albedo", C.c_void_p), ("Le", C.c_void_p), ("rough", C.c_void_p),
+                ("x2", C.c_void_p), ("dir2", C.c_void_p), ("wi", C.c_void_p), ("pdf", C.c_void_p),
+                ("target_override", C.c_void_p), ("F0", C.c_float), ("loss_kind", C.c_int32),
+                ("eps", C.c_float), ("grad_through_rhs", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise OOError(f"liboctaoctree.so not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+        L.oo_build_octree.argtypes = [vp, i64, i32, i32, vp, i64, vp, vp]
+        L.oo_encode_query.argtypes = [vp, vp, vp, i64, vp, i32, vp, vp]
+        L.oo_mlp_fwd.argtypes = [vp, vp, i32, i64, vp, vp]
+        L.oo_query_fwd.argtypes = [vp, vp, vp, vp, i64, vp, vp]
+        L.oo_residual_workspace_bytes.argtypes = [vp, vp, vp, C.POINTER(C.c_size_t)]
+        L.oo_radiosity_residual_fwd.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.oo_radiosity_residual_bwd.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.oo_cast_params.argtypes = [vp, vp, i32, i64, vp]
+        L.oo_last_error.restype = C.c_char_p
+        for f in ("oo_build_octree", "oo_encode_query", "oo_mlp_fwd", "oo_query_fwd",
+                  "oo_residual_workspace_bytes", "oo_radiosity_residual_fwd", "oo_radiosity_residual_bwd",
+                  "oo_cast_params"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise OOError(f"{what} failed ({rc}): {lib().oo_last_error().decode()}")
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev(t, dtype=torch.float32):
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        t = torch.from_numpy(np.ascontiguousarray(t))
+    return t.to(device="cuda", dtype=dtype).contiguous()
+
+
+# ---------------------------------------------------------------------------
+# Host octree construction
+# ---------------------------------------------------------------------------
+
+def build_octree(samples, max_depth: int, split_threshold: int):
+    """Sparse octree from FP32 surface samples (host, synchronous).
+    Returns (nodes uint32 [n_nodes], level_offset int64 [max_depth + 2])."""
+    s = np.ascontiguousarray(samples, dtype=np.float32).reshape(-1, 3)
+    lo = np.zeros(max_depth + 2, np.int64)
+    nn = np.zeros(1, np.int64)
+    L = lib()
+    _check(L.oo_build_octree(s.ctypes.data, s.shape[0], max_depth, split_threshold, None, 0,
+                             lo.ctypes.data, nn.ctypes.data), "oo_build_octree (size)")
+    nodes = np.zeros(int(nn[0]), np.uint32)
+    _check(L.oo_build_octree(s.ctypes.data, s.shape[0], max_depth, split_threshold, nodes.ctypes.data,
+                             nodes.size, lo.ctypes.data, nn.ctypes.data), "oo_build_octree")
+    return nodes, lo
+
+
+# ---------------------------------------------------------------------------
+# Device-side descriptions
+# ---------------------------------------------------------------------------
+
+class Tree:
+    """Octree on the device plus one feature table per level."""
+
+    def __init__(self, nodes, level_offset, res, C_, feat):
+        self.nodes = torch.from_numpy(np.asarray(nodes, np.uint32).view(np.int32)).cuda()
+        self.level_offset = [int(v) for v in level_offset]
+        self.res = [int(r) for r in res]
+        self.C = int(C_)
+        self.feat = [f if isinstance(f, torch.Tensor) else _dev(f) for f in feat]
+
+    @property
+    def n_levels(self):
+        return len(self.res)
+
+    def struct(self, feat=None):
+        feat = self.feat if feat is None else feat
+        t = _Tree()
+        t.n_levels = self.n_levels
+        t.C = self.C
+        for l, R in enumerate(self.res):
+            t.res[l] = R
+        for l in range(self.n_levels + 1):
+            t.level_offset[l] = self.level_offset[l]
+        t.nodes = self.nodes.data_ptr()
+        t.feat_dtype = DTYPE_CODE[feat[0].dtype]
+        for l, f in enumerate(feat):
+            t.feat[l] = f.data_ptr() if f.numel() else None
+        return t
+
+
+class MLP:
+    def __init__(self, W, b):
+        self.W = [w if isinstance(w, torch.Tensor) else _dev(w) for w in W]
+        self.b = [v if isinstance(v, torch.Tensor) else _dev(v) for v in b]
+
+    def struct(self, W=None):
+        W = self.W if W is None else W
+        m = _MLP()
+        m.n_layers = len(W)
+        m.dims[0] = W[0].shape[1]
+        for i, w in enumerate(W):
+            m.dims[i + 1] = w.shape[0]
+            m.W[i] = w.data_ptr()
+            m.b[i] = self.b[i].data_ptr()
+        m.dtype = DTYPE_CODE[W[0].dtype]
+        return m
+
+
+_BATCH_ARRAYS = ("x", "dir", "n", "wo", "albedo", "Le", "rough", "x2", "dir2", "wi", "pdf", "target_override")
+
+
+def device_batch(batch: dict) -> dict:
+    """Copies a host batch (numpy arrays + scalars) to device FP32 tensors."""
+    out = {k: v for k, v in batch.items() if k not in _BATCH_ARRAYS}
+    for k in _BATCH_ARRAYS:
+        out[k] = _dev(batch.get(k))
+    return out
+
+
+def batch_struct(b: dict):
+    s = _Batch()
+    s.B = int(b["x"].shape[0])
+    s.N = int(b.get("N", 0))
+    for k in _BATCH_ARRAYS:
+        setattr(s, k, _ptr(b.get(k)))
+    s.F0 = float(b.get("F0", 0.04))
+    s.loss_kind = int(b.get("loss_kind", 0))
+    s.eps = float(b.get("eps", 1e-2))
+    s.grad_through_rhs = int(b.get("grad_through_rhs", 0))
+    return s
+
+
+# ---------------------------------------------------------------------------
+# Entry points
+# ---------------------------------------------------------------------------
+
+def encode_query(tree: Tree, x, d, h_dtype=torch.float32, with_idx=True, feat=None):
+    B = x.shape[0]
+    h = torch.empty((B, tree.n_levels * tree.C), dtype=h_dtype, device="cuda")
+    idx = torch.empty((B, tree.n_levels), dtype=torch.int32, device="cuda") if with_idx else None
+    ts = tree.struct(feat)
+    _check(lib().oo_encode_query(C.byref(ts), _ptr(x), _ptr(d), B, _ptr(h), DTYPE_CODE[h_dtype], _ptr(idx),
+                                 _stream()), "oo_encode_query")
+    return h, idx
+
+
+def mlp_fwd(mlp: MLP, h, W=None):
+    B = h.shape[0]
+    rgb = torch.empty((B, 3), dtype=torch.float32, device="cuda")
+    ms = mlp.struct(W)
+    _check(lib().oo_mlp_fwd(C.byref(ms), _ptr(h), DTYPE_CODE[h.dtype], B, _ptr(rgb), _stream()), "oo_mlp_fwd")
+    return rgb
+
+
+def query_fwd(tree: Tree, mlp: MLP, x, d, feat=None, W=None, out=None):
+    B = x.shape[0]
+    rgb = torch.empty((B, 3), dtype=torch.float32, device="cuda") if out is None else out
+    ts, ms = tree.struct(feat), mlp.struct(W)
+    _check(lib().oo_query_fwd(C.byref(ts), C.byref(ms), _ptr(x), _ptr(d), B, _ptr(rgb), _stream()),
+           "oo_query_fwd")
+    return rgb
+
+
+def residual_workspace_bytes(tree: Tree, mlp: MLP, batch: dict, feat=None, W=None) -> int:
+    ts, ms, bs = tree.struct(feat), mlp.struct(W), batch_struct(batch)
+    n = C.c_size_t(0)
+    _check(lib().oo_residual_workspace_bytes(C.byref(ts), C.byref(ms), C.byref(bs), C.byref(n)),
+           "oo_residual_workspace_bytes")
+    return int(n.value)
+
+
+def residual_fwd(tree: Tree, mlp: MLP, batch: dict, workspace, feat=None, W=None, outs=None):
+    """Returns (lhs, rhs, resid) [B][3] FP32 and the loss (0-dim FP64 device tensor)."""
+    B = batch["x"].shape[0]
+    if outs is None:
+        outs = tuple(torch.empty((B, 3), dtype=torch.float32, device="cuda") for _ in range(3)) + (
+            torch.empty((), dtype=torch.float64, device="cuda"),)
+    lhs, rhs, res, loss = outs
+    ts, ms, bs = tree.struct(feat), mlp.struct(W), batch_struct(batch)
+    _check(lib().oo_radiosity_residual_fwd(C.byref(ts), C.byref(ms), C.byref(bs), _ptr(lhs), _ptr(rhs), _ptr(res),
+                                           _ptr(loss), _ptr(workspace), _stream()), "oo_radiosity_residual_fwd")
+    return lhs, rhs, res, loss
+
+
+def residual_bwd(tree: Tree, mlp: MLP, batch: dict, resid, rhs, grad_loss, dfeat, dW, db, workspace, feat=None,
+                 W=None):
+    """Accumulates (+=) FP32 gradients into dfeat / dW / db."""
+    ts, ms, bs = tree.struct(feat), mlp.struct(W), batch_struct(batch)
+    arr = lambda ts_: (C.c_void_p * max(1, len(ts_)))(*[t.data_ptr() if t.numel() else None for t in ts_])
+    g = grad_loss.to(device="cuda", dtype=torch.float64).contiguous().reshape(())
+    _check(lib().oo_radiosity_residual_bwd(C.byref(ts), C.byref(ms), C.byref(bs), _ptr(resid), _ptr(rhs), _ptr(g),
+                                           arr(dfeat), arr(dW), arr(db), _ptr(workspace), _stream()),
+           "oo_radiosity_residual_bwd")
+
+
+def cast_params(src, dst):
+    assert src.dtype == torch.float32 and src.numel() == dst.numel()
+    _check(lib().oo_cast_params(_ptr(src), _ptr(dst), DTYPE_CODE[dst.dtype], src.numel(), _stream()),
+           "oo_cast_params")
+    return dst
+
+
+# ---------------------------------------------------------------------------
+# Module and autograd
+# ---------------------------------------------------------------------------
+
+class OctaOctree(torch.nn.Module):
+    """FP32 master feature tables and MLP weights as Parameters, with 16-bit
+    working copies (refreshed by ``refresh()``) when ``dtype`` is FP16/BF16."""
+
+    def __init__(self, nodes, level_offset, res, C_, feat, W, b, dtype=torch.float32):
+        super().__init__()
+        self.dtype = dtype
+        self.feat = torch.nn.ParameterList([torch.nn.Parameter(_dev(f)) for f in feat])
+        self.W = torch.nn.ParameterList([torch.nn.Parameter(_dev(w)) for w in W])
+        self.b = torch.nn.ParameterList([torch.nn.Parameter(_dev(v)) for v in b])
+        self.tree = Tree(nodes, level_offset, res, C_, list(self.feat))
+        self.mlp = MLP(list(self.W), list(self.b))
+        self._ws = None
+        self.work_feat, self.work_W = None, None
+        self.refresh()
+
+    def refresh(self):
+        """Re-derive the working copies from the FP32 masters."""
+        with torch.no_grad():
+            if self.dtype == torch.float32:
+                self.work_feat, self.work_W = list(self.feat), list(self.W)
+            else:
+                if self.work_feat is None:
+                    self.work_feat = [torch.empty_like(f, dtype=self.dtype) for f in self.feat]
+                    self.work_W = [torch.empty_like(w, dtype=self.dtype) for w in self.W]
+                for src, dst in zip(list(self.feat) + list(self.W), self.work_feat + self.work_W):
+                    if src.numel():
+                        cast_params(src.detach(), dst)
+
+    def forward(self, x, d):
+        """Radiance at (x, d) [B][3] (inference; no autograd)."""
+        return query_fwd(self.tree, self.mlp, x, d, feat=self.work_feat, W=self.work_W)
+
+    def workspace(self, batch):
+        n = residual_workspace_bytes(self.tree, self.mlp, batch, feat=self.work_feat, W=self.work_W)
+        if self._ws is None or self._ws.numel() < n:
+            self._ws = torch.empty(max(n, 256), dtype=torch.uint8, device="cuda")
+        return self._ws
+
+    def residual(self, batch):
+        """Loss of the residual step (0-dim FP64) with autograd to the masters."""
+        return RadiosityResidual.apply(self, batch, *self.feat, *self.W, *self.b)
+
+
+class RadiosityResidual(torch.autograd.Function):
+    """Neural-radiosity residual loss. Forward evaluates LHS and RHS queries
+    and the FP64 loss; backward recomputes the LHS encoding, runs the decoder
+    backward on matrix cores and scatters feature gradients with FP32
+    atomics. Gradients w.r.t. the 16-bit working copies are returned for the
+    FP32 masters."""
+
+    @staticmethod
+    def forward(ctx, model: OctaOctree, batch: dict, *params):
+        ws = model.workspace(batch)
+        lhs, rhs, res, loss = residual_fwd(model.tree, model.mlp, batch, ws, feat=model.work_feat,
+                                           W=model.work_W)
+        ctx.model, ctx.batch = model, batch
+        ctx.save_for_backward(res, rhs)
+        ctx.lhs = lhs
+        return loss
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        model, batch = ctx.model, ctx.batch
+        res, rhs = ctx.saved_tensors
+        dfeat = [torch.zeros(f.shape, dtype=torch.float32, device="cuda") for f in model.feat]
+        dW = [torch.zeros(w.shape, dtype=torch.float32, device="cuda") for w in model.W]
+        db = [torch.zeros(v.shape, dtype=torch.float32, device="cuda") for v in model.b]
+        ws = model.workspace(batch)
+        residual_bwd(model.tree, model.mlp, batch, res, rhs, grad_loss, dfeat, dW, db, ws,
+                     feat=model.work_feat, W=model.work_W)
+        return (None, None, *dfeat, *dW, *db)

@@ -1,0 +1,411 @@
+// C-ABI of liboctaoctree: argument validation, host octree construction,
+// workspace layout and kernel dispatch. Declarations and their contracts are
+// in include/octaoctree.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "octaoctree.h"
+#include "oo_internal.h"
+
+using namespace oo;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int hip_status(hipError_t e, const char* what) {
+  if (e == hipSuccess) return OO_OK;
+  return fail(OO_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+
+int check_tree(const oo_tree* t, TreeArgs& A) {
+  if (!t) return fail(OO_EINVAL, "tree is NULL");
+  if (t->n_levels < 1 || t->n_levels > OO_MAX_LEVELS)
+    return fail(OO_EINVAL, "n_levels must be in [1, %d], got %d", OO_MAX_LEVELS, t->n_levels);
+  if (t->C != 4 && t->C != 8) return fail(OO_EINVAL, "C must be 4 or 8, got %d", t->C);
+  if (t->feat_dtype != OO_F32 && t->feat_dtype != OO_F16 && t->feat_dtype != OO_BF16)
+    return fail(OO_EINVAL, "unknown feat_dtype %d", (int)t->feat_dtype);
+  if (!t->nodes) return fail(OO_EINVAL, "nodes is NULL");
+  if (t->level_offset[0] != 0 || t->level_offset[1] != 1)
+    return fail(OO_EINVAL, "level_offset must start 0, 1 (one root node)");
+  A.L = t->n_levels;
+  A.C = t->C;
+  A.D = t->n_levels - 1;
+  A.nodes = t->nodes;
+  for (int l = 0; l < OO_MAX_LEVELS; ++l) {
+    A.res[l] = 2;
+    A.feat[l] = nullptr;
+  }
+  for (int l = 0; l <= OO_MAX_LEVELS; ++l) A.off[l] = l <= t->n_levels ? t->level_offset[l] : t->level_offset[t->n_levels];
+  for (int l = 0; l < t->n_levels; ++l) {
+    if (!pow2_in(t->res[l], 2, 64)) return fail(OO_EINVAL, "res[%d] = %d is not a power of two in [2, 64]", l, t->res[l]);
+    if (t->level_offset[l + 1] < t->level_offset[l]) return fail(OO_EINVAL, "level_offset must be non-decreasing");
+    A.res[l] = t->res[l];
+    const bool has_nodes = t->level_offset[l + 1] > t->level_offset[l];
+    if (has_nodes) {
+      if (!t->feat[l]) return fail(OO_EINVAL, "feat[%d] is NULL", l);
+      if (reinterpret_cast<uintptr_t>(t->feat[l]) % 16) return fail(OO_EINVAL, "feat[%d] is not 16-byte aligned", l);
+      A.feat[l] = t->feat[l];
+    }
+  }
+  if (t->level_offset[t->n_levels] > (int64_t(1) << 24))
+    return fail(OO_EUNSUPPORTED, "more than 2^24 nodes");
+  // Levels without nodes are never read with a non-zero weight; point them at
+  // level 0 so that the kernels' predicated loads stay in bounds.
+  for (int l = 0; l < t->n_levels; ++l)
+    if (!A.feat[l]) A.feat[l] = A.feat[0];
+  return OO_OK;
+}
+
+int check_mlp(const oo_mlp* m, int K0, MlpArgs& A) {
+  if (!m) return fail(OO_EINVAL, "mlp is NULL");
+  if (m->n_layers < 2 || m->n_layers > 5) return fail(OO_EUNSUPPORTED, "n_layers must be in [2, 5], got %d", m->n_layers);
+  if (m->dtype != OO_F32 && m->dtype != OO_F16 && m->dtype != OO_BF16)
+    return fail(OO_EINVAL, "unknown mlp dtype %d", (int)m->dtype);
+  if (m->dims[0] != K0) return fail(OO_EINVAL, "dims[0] = %d must equal n_levels * C = %d", m->dims[0], K0);
+  if (K0 > 128) return fail(OO_EUNSUPPORTED, "input width %d > 128", K0);
+  if (m->dims[m->n_layers] != 3) return fail(OO_EINVAL, "last dim must be 3, got %d", m->dims[m->n_layers]);
+  const int H = m->dims[1];
+  for (int i = 1; i < m->n_layers; ++i)
+    if (m->dims[i] != H) return fail(OO_EUNSUPPORTED, "hidden widths must all be equal");
+  if (H != 64 && H != 128) return fail(OO_EUNSUPPORTED, "hidden width must be 64 or 128, got %d", H);
+  if (H == 128 && m->n_layers > 3) return fail(OO_EUNSUPPORTED, "width 128 supports at most 2 hidden layers");
+  for (int i = 0; i < m->n_layers; ++i)
+    if (!m->W[i] || !m->b[i]) return fail(OO_EINVAL, "W[%d] or b[%d] is NULL", i, i);
+  A.n_layers = m->n_layers;
+  A.K0 = K0;
+  A.H = H;
+  for (int i = 0; i < OO_MAX_LAYERS; ++i) {
+    A.W[i] = i < m->n_layers ? m->W[i] : nullptr;
+    A.b[i] = i < m->n_layers ? m->b[i] : nullptr;
+  }
+  return OO_OK;
+}
+
+int check_pair(const oo_tree* t, const oo_mlp* m) {
+  if (t->feat_dtype != m->dtype)
+    return fail(OO_EUNSUPPORTED, "feature dtype %d and MLP dtype %d must match", (int)t->feat_dtype, (int)m->dtype);
+  if (t->feat_dtype != OO_F32 && t->C != 8) return fail(OO_EUNSUPPORTED, "16-bit tables need C = 8");
+  return OO_OK;
+}
+
+int check_batch(const oo_residual_batch* b, ResidualArgs& A) {
+  if (!b) return fail(OO_EINVAL, "batch is NULL");
+  if (b->B < 0 || b->N < 0) return fail(OO_EINVAL, "B and N must be >= 0");
+  if (b->loss_kind != 0 && b->loss_kind != 1) return fail(OO_EINVAL, "loss_kind must be 0 or 1");
+  if (b->B > 0) {
+    if (!b->x || !b->dir) return fail(OO_EINVAL, "x and dir are required");
+    if (!b->target_override) {
+      if (!b->Le) return fail(OO_EINVAL, "Le is required without target_override");
+      if (b->N > 0 && (!b->n || !b->wo || !b->albedo || !b->rough || !b->x2 || !b->dir2 || !b->wi))
+        return fail(OO_EINVAL, "n, wo, albedo, rough, x2, dir2 and wi are required when N > 0");
+    }
+  }
+  A.B = b->B;
+  A.N = b->target_override ? 0 : b->N;
+  A.n = b->n;
+  A.wo = b->wo;
+  A.albedo = b->albedo;
+  A.Le = b->Le;
+  A.rough = b->rough;
+  A.wi = b->wi;
+  A.pdf = b->pdf;
+  A.target_override = b->target_override;
+  A.F0 = b->F0;
+  A.loss_kind = b->loss_kind;
+  A.eps = b->eps;
+  return OO_OK;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct Workspace {
+  size_t Lq, lossp, seeds, wt[OO_MAX_LAYERS], dwp, total;
+  int grid;
+  ParamLayout PL;
+};
+
+void param_layout(const MlpArgs& M, ParamLayout& PL) {
+  PL.n_layers = M.n_layers;
+  int64_t off = 0;
+  for (int i = 0; i < M.n_layers; ++i) {
+    PL.n_in[i] = i == 0 ? M.K0 : M.H;
+    PL.n_out[i] = i == M.n_layers - 1 ? 3 : M.H;
+    PL.w_off[i] = off;
+    off += (int64_t)PL.n_in[i] * PL.n_out[i];
+    PL.b_off[i] = off;
+    off += PL.n_out[i];
+  }
+  PL.P = off;
+}
+
+Workspace workspace_layout(const MlpArgs& M, oo_dtype md, const oo_residual_batch* b) {
+  Workspace w;
+  const int64_t B = b->B;
+  const int N = b->target_override ? 0 : b->N;
+  const int64_t Qf = B * (1 + N);
+  const bool full = b->grad_through_rhs && !b->target_override && N > 0;
+  const int64_t Qb = full ? Qf : B;
+  param_layout(M, w.PL);
+  w.grid = bwd_grid(M, Qb);
+  size_t o = 0;
+  w.Lq = o;
+  o = align256(o + (size_t)Qf * 3 * sizeof(float));
+  w.lossp = o;
+  o = align256(o + (size_t)(combine_blocks(B) + 1) * sizeof(double));
+  w.seeds = o;
+  o = align256(o + (size_t)Qb * 3 * sizeof(float));
+  const size_t esz = md == OO_F32 ? 4 : 2;
+  for (int i = 0; i < M.n_layers; ++i) {
+    w.wt[i] = o;
+    o = align256(o + (size_t)w.PL.n_in[i] * ((w.PL.n_out[i] + 3) & ~3) * esz);
+  }
+  w.dwp = o;
+  o = align256(o + (size_t)w.grid * w.PL.P * sizeof(float));
+  w.total = o;
+  return w;
+}
+
+// --- host octree construction ---------------------------------------------
+// Morton codes of the samples' finest cells, sorted once: every node is then
+// a contiguous run of the sorted codes sharing a prefix, and its children are
+// the sub-runs split by the next octant digit, already in octant order.
+
+inline int64_t quant_host(float v, int D) {
+  const float scale = (float)(1u << D);
+  float f = std::floor(v * scale);
+  if (!(f >= 0.0f)) f = 0.0f;
+  if (f > scale - 1.0f) f = scale - 1.0f;
+  return (int64_t)f;
+}
+
+inline uint64_t morton3(uint64_t x, uint64_t y, uint64_t z, int D) {
+  uint64_t code = 0;
+  for (int bit = 0; bit < D; ++bit) {
+    code |= ((x >> bit) & 1ull) << (3 * bit);
+    code |= ((y >> bit) & 1ull) << (3 * bit + 1);
+    code |= ((z >> bit) & 1ull) << (3 * bit + 2);
+  }
+  return code;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* oo_last_error(void) { return g_err; }
+
+int oo_build_octree(const float* samples, int64_t n, int32_t max_depth, int32_t split_threshold, uint32_t* nodes_out,
+                    int64_t capacity, int64_t* level_offset_out, int64_t* n_nodes_out) {
+  g_err[0] = 0;
+  if (n < 0) return fail(OO_EINVAL, "n must be >= 0");
+  if (max_depth < 0 || max_depth > OO_MAX_LEVELS - 1) return fail(OO_EINVAL, "max_depth must be in [0, %d]", OO_MAX_LEVELS - 1);
+  if (split_threshold < 0) return fail(OO_EINVAL, "split_threshold must be >= 0");
+  if ((n > 0 && !samples) || !level_offset_out || !n_nodes_out) return fail(OO_EINVAL, "NULL argument");
+  const int D = max_depth;
+  std::vector<uint64_t> code((size_t)n);
+  for (int64_t i = 0; i < n; ++i)
+    code[i] = morton3(quant_host(samples[3 * i], D), quant_host(samples[3 * i + 1], D),
+                      quant_host(samples[3 * i + 2], D), D);
+  std::sort(code.begin(), code.end());
+
+  struct Node {
+    int64_t lo, hi;
+    uint32_t word;
+  };
+  std::vector<Node> nodes;
+  nodes.push_back({0, n, 0u});
+  std::vector<int64_t> lo(D + 2, 0);
+  lo[0] = 0;
+  lo[1] = 1;
+  for (int l = 0; l < D; ++l) {
+    const int shift = 3 * (D - l - 1);
+    for (int64_t v = lo[l]; v < lo[l + 1]; ++v) {
+      const int64_t a = nodes[v].lo, b = nodes[v].hi;
+      if (b - a <= split_threshold) continue;
+      const int64_t first = (int64_t)nodes.size();
+      uint32_t mask = 0;
+      int64_t s = a;
+      while (s < b) {
+        const unsigned o = (unsigned)((code[s] >> shift) & 7ull);
+        const uint64_t key = code[s] >> shift;
+        int64_t e = s;
+        while (e < b && (code[e] >> shift) == key) ++e;
+        mask |= 1u << o;
+        nodes.push_back({s, e, 0u});
+        s = e;
+      }
+      nodes[v].word = ((uint32_t)first << 8) | mask;
+    }
+    lo[l + 2] = (int64_t)nodes.size();
+  }
+  const int64_t total = (int64_t)nodes.size();
+  for (int l = 0; l <= D + 1; ++l) level_offset_out[l] = lo[l];
+  *n_nodes_out = total;
+  if (total > (int64_t(1) << 24)) return fail(OO_EUNSUPPORTED, "tree needs %lld nodes (> 2^24)", (long long)total);
+  if (!nodes_out) return OO_OK;
+  if (capacity < total) return fail(OO_ECAPACITY, "capacity %lld < %lld nodes", (long long)capacity, (long long)total);
+  for (int64_t v = 0; v < total; ++v) nodes_out[v] = nodes[v].word;
+  return OO_OK;
+}
+
+int oo_encode_query(const oo_tree* tree, const float* x, const float* dir, int64_t B, void* h_out, oo_dtype h_dtype,
+                    int32_t* node_idx_out, hipStream_t stream) {
+  g_err[0] = 0;
+  TreeArgs T;
+  int rc = check_tree(tree, T);
+  if (rc) return rc;
+  if (B < 0) return fail(OO_EINVAL, "B must be >= 0");
+  if (h_dtype != OO_F32 && h_dtype != OO_F16 && h_dtype != OO_BF16) return fail(OO_EINVAL, "unknown h_dtype");
+  if (B == 0) return OO_OK;
+  if (!x || !dir || !h_out) return fail(OO_EINVAL, "x, dir and h_out are required");
+  return hip_status(launch_encode(T, tree->feat_dtype, x, dir, B, h_out, h_dtype, node_idx_out, stream),
+                    "encode_query launch");
+}
+
+int oo_mlp_fwd(const oo_mlp* mlp, const void* h, oo_dtype h_dtype, int64_t B, float* rgb_out, hipStream_t stream) {
+  g_err[0] = 0;
+  if (!mlp) return fail(OO_EINVAL, "mlp is NULL");
+  MlpArgs M;
+  int rc = check_mlp(mlp, mlp->dims[0], M);
+  if (rc) return rc;
+  if (h_dtype != mlp->dtype) return fail(OO_EINVAL, "h_dtype must equal mlp->dtype");
+  if (mlp->dims[0] % 4) return fail(OO_EUNSUPPORTED, "input width must be a multiple of 4");
+  if (B < 0) return fail(OO_EINVAL, "B must be >= 0");
+  if (B == 0) return OO_OK;
+  if (!h || !rgb_out) return fail(OO_EINVAL, "h and rgb_out are required");
+  return hip_status(launch_mlp(M, mlp->dtype, h, B, rgb_out, stream), "mlp_fwd launch");
+}
+
+int oo_query_fwd(const oo_tree* tree, const oo_mlp* mlp, const float* x, const float* dir, int64_t B, float* rgb_out,
+                 hipStream_t stream) {
+  g_err[0] = 0;
+  TreeArgs T;
+  MlpArgs M;
+  int rc = check_tree(tree, T);
+  if (rc) return rc;
+  if ((rc = check_mlp(mlp, tree->n_levels * tree->C, M))) return rc;
+  if ((rc = check_pair(tree, mlp))) return rc;
+  if (B < 0) return fail(OO_EINVAL, "B must be >= 0");
+  if (B == 0) return OO_OK;
+  if (!x || !dir || !rgb_out) return fail(OO_EINVAL, "x, dir and rgb_out are required");
+  QuerySrc src{x, dir, B, x, dir};
+  return hip_status(launch_query(T, tree->feat_dtype, M, mlp->dtype, src, B, rgb_out, stream), "query_fwd launch");
+}
+
+int oo_residual_workspace_bytes(const oo_tree* tree, const oo_mlp* mlp, const oo_residual_batch* batch, size_t* bytes) {
+  g_err[0] = 0;
+  TreeArgs T;
+  MlpArgs M;
+  ResidualArgs A;
+  int rc = check_tree(tree, T);
+  if (rc) return rc;
+  if ((rc = check_mlp(mlp, tree->n_levels * tree->C, M))) return rc;
+  if ((rc = check_pair(tree, mlp))) return rc;
+  if ((rc = check_batch(batch, A))) return rc;
+  if (!bytes) return fail(OO_EINVAL, "bytes is NULL");
+  *bytes = workspace_layout(M, mlp->dtype, batch).total;
+  return OO_OK;
+}
+
+int oo_radiosity_residual_fwd(const oo_tree* tree, const oo_mlp* mlp, const oo_residual_batch* batch, float* lhs_out,
+                              float* rhs_out, float* resid_out, double* loss_out, void* workspace, hipStream_t stream) {
+  g_err[0] = 0;
+  TreeArgs T;
+  MlpArgs M;
+  ResidualArgs A;
+  int rc = check_tree(tree, T);
+  if (rc) return rc;
+  if ((rc = check_mlp(mlp, tree->n_levels * tree->C, M))) return rc;
+  if ((rc = check_pair(tree, mlp))) return rc;
+  if ((rc = check_batch(batch, A))) return rc;
+  if (!loss_out || !workspace) return fail(OO_EINVAL, "loss_out and workspace are required");
+  if (A.B > 0 && (!lhs_out || !rhs_out || !resid_out)) return fail(OO_EINVAL, "lhs_out, rhs_out, resid_out are required");
+  const Workspace w = workspace_layout(M, mlp->dtype, batch);
+  char* ws = static_cast<char*>(workspace);
+  float* Lq = reinterpret_cast<float*>(ws + w.Lq);
+  double* lossp = reinterpret_cast<double*>(ws + w.lossp);
+  const int64_t Q = A.B * (1 + A.N);
+  QuerySrc src{batch->x, batch->dir, A.B, A.N > 0 ? batch->x2 : batch->x, A.N > 0 ? batch->dir2 : batch->dir};
+  hipError_t e = launch_query(T, tree->feat_dtype, M, mlp->dtype, src, Q, Lq, stream);
+  if (e != hipSuccess) return hip_status(e, "residual query launch");
+  return hip_status(launch_combine(A, Lq, lhs_out, rhs_out, resid_out, lossp, loss_out, stream), "combine launch");
+}
+
+int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_residual_batch* batch,
+                              const float* resid, const float* rhs, const double* grad_loss, float* const* dfeat,
+                              float* const* dW, float* const* db, void* workspace, hipStream_t stream) {
+  g_err[0] = 0;
+  TreeArgs T;
+  MlpArgs M;
+  ResidualArgs A;
+  int rc = check_tree(tree, T);
+  if (rc) return rc;
+  if ((rc = check_mlp(mlp, tree->n_levels * tree->C, M))) return rc;
+  if ((rc = check_pair(tree, mlp))) return rc;
+  if ((rc = check_batch(batch, A))) return rc;
+  if (!grad_loss || !dfeat || !dW || !db || !workspace) return fail(OO_EINVAL, "NULL argument");
+  if (A.B == 0) return OO_OK;
+  if (!resid || !rhs) return fail(OO_EINVAL, "resid and rhs are required");
+  GradArgs G;
+  for (int l = 0; l < OO_MAX_LEVELS; ++l) G.dfeat[l] = nullptr;
+  for (int l = 0; l < tree->n_levels; ++l) {
+    const bool has_nodes = tree->level_offset[l + 1] > tree->level_offset[l];
+    if (has_nodes && !dfeat[l]) return fail(OO_EINVAL, "dfeat[%d] is NULL", l);
+    G.dfeat[l] = dfeat[l];
+  }
+  for (int i = 0; i < mlp->n_layers; ++i)
+    if (!dW[i] || !db[i]) return fail(OO_EINVAL, "dW[%d] or db[%d] is NULL", i, i);
+  const Workspace w = workspace_layout(M, mlp->dtype, batch);
+  char* ws = static_cast<char*>(workspace);
+  float* seeds = reinterpret_cast<float*>(ws + w.seeds);
+  float* partials = reinterpret_cast<float*>(ws + w.dwp);
+  void* Wt[OO_MAX_LAYERS];
+  for (int i = 0; i < mlp->n_layers; ++i) Wt[i] = ws + w.wt[i];
+  const bool full = batch->grad_through_rhs && !batch->target_override && batch->N > 0;
+  const int64_t Qb = full ? A.B * (1 + A.N) : A.B;
+  const float post_scale = (float)(1.0 / (3.0 * (double)A.B));
+  hipError_t e = launch_seeds(A, resid, rhs, grad_loss, full ? 1 : 0, seeds, stream);
+  if (e != hipSuccess) return hip_status(e, "seed launch");
+  e = launch_transpose_weights(M, mlp->dtype, Wt, stream);
+  if (e != hipSuccess) return hip_status(e, "transpose launch");
+  QuerySrc src{batch->x, batch->dir, A.B, full ? batch->x2 : batch->x, full ? batch->dir2 : batch->dir};
+  e = launch_bwd(T, tree->feat_dtype, M, mlp->dtype, Wt, src, Qb, seeds, post_scale, G, w.PL, partials, w.grid, stream);
+  if (e != hipSuccess) return hip_status(e, "backward launch");
+  ReduceDst D;
+  D.n_seg = 2 * mlp->n_layers;
+  for (int i = 0; i < mlp->n_layers; ++i) {
+    D.start[2 * i] = w.PL.w_off[i];
+    D.dst[2 * i] = dW[i];
+    D.start[2 * i + 1] = w.PL.b_off[i];
+    D.dst[2 * i + 1] = db[i];
+  }
+  D.start[D.n_seg] = w.PL.P;
+  return hip_status(launch_dw_reduce(partials, w.grid, w.PL, D, post_scale, stream), "dW reduce launch");
+}
+
+int oo_cast_params(const float* src, void* dst, oo_dtype dst_dtype, int64_t n, hipStream_t stream) {
+  g_err[0] = 0;
+  if (n < 0) return fail(OO_EINVAL, "n must be >= 0");
+  if (dst_dtype != OO_F32 && dst_dtype != OO_F16 && dst_dtype != OO_BF16) return fail(OO_EINVAL, "unknown dtype");
+  if (n == 0) return OO_OK;
+  if (!src || !dst) return fail(OO_EINVAL, "src and dst are required");
+  return hip_status(launch_cast(src, dst, dst_dtype, n, stream), "cast launch");
+}
+
+}  // extern "C"

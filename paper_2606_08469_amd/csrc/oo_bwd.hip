@@ -1,0 +1,602 @@
+// Backward of the residual step: seeds, the fused recompute + decoder
+// backward + feature scatter kernel, and the fixed-order dW/db reduction.
+//
+// One workgroup (8 waves) handles 64 queries at a time:
+//  1. encode: 8 lanes per query, each gathering whole texels of every eighth
+//     level; h written to an LDS fragment tile and, transposed, to the
+//     layer-0 activation buffer;
+//  2. forward recompute of the hidden layers on matrix cores, activations
+//     kept in LDS as [neuron][query];
+//  3. backward: delta chained through W^T on matrix cores; dW of every layer
+//     contracted over the workgroup's 64 queries, each wave owning an eighth
+//     of the dW tiles in registers for the whole kernel; dh for every query;
+//  4. scatter: lanes grouped by channel add w_tap * dh into the FP32 feature
+//     gradient tables with hardware float atomics.
+// dW/db leave as one partial per workgroup, reduced in a fixed order later.
+#include <hip/hip_runtime.h>
+
+#include "oo_device.h"
+#include "oo_internal.h"
+
+namespace oo {
+
+constexpr int kQW = 64;  // queries per workgroup tile
+
+struct BwdLayout {
+  int KB0, R0;
+  size_t htile, act0, act1, delta, dh, qidx, qst, total;
+};
+
+__host__ __device__ inline BwdLayout bwd_layout(int K0, int H, int n_layers, int L, int msz) {
+  BwdLayout b;
+  b.KB0 = (K0 + 31) / 32;
+  b.R0 = (K0 + 15) / 16 * 16;
+  size_t o = 0;
+  b.htile = o;
+  const size_t hbytes = (size_t)4 * b.KB0 * kWave * 8 * msz;
+  o += hbytes;
+  b.act0 = o;
+  o += (size_t)b.R0 * kQW * msz;
+  b.act1 = o;  // hidden-layer activations a_1 .. a_{n_layers-1}, H rows each
+  o += (size_t)(n_layers - 1) * H * kQW * msz;
+  b.delta = o;
+  o += (size_t)H * kQW * msz;
+  const size_t dbytes = (size_t)kQW * b.R0 * 4;
+  if (dbytes <= hbytes) {
+    b.dh = b.htile;  // h is dead once the forward recompute is done
+  } else {
+    b.dh = o;
+    o += dbytes;
+  }
+  b.qidx = o;
+  o += (size_t)kQW * L * 4;
+  b.qst = o;
+  o += (size_t)kQW * 2 * 4;
+  b.total = o;
+  return b;
+}
+
+// [row][query] buffer of 64 queries, 16-byte chunks XOR-swizzled by row so
+// that 16 lanes reading 16 rows at one query offset hit distinct banks.
+__device__ inline int tq_index(int row, int q) { return row * kQW + ((((q >> 3) ^ (row & 7))) << 3) + (q & 7); }
+
+template <class MT>
+__device__ inline typename FragT<MT>::type tq_frag(const MT* buf, int row, int chunk) {
+  return *reinterpret_cast<const typename FragT<MT>::type*>(buf + row * kQW + ((chunk ^ (row & 7)) << 3));
+}
+
+// Single-element write into the fragment tile (q, k).
+template <class MT>
+__device__ inline void htile_put1(MT* tile, int KB, int q, int k, float v) {
+  tile[htile_index<MT>(q, k, KB)] = from_f32<MT>(v);
+}
+
+// Waves per workgroup. 4 waves give each wave 512 registers (one wave per
+// SIMD), enough for the dW accumulators of a 128-wide MLP without spilling.
+constexpr int kBwdWaves = 4;
+constexpr int kMSplit = kBwdWaves / 4;           // waves sharing one query column block
+constexpr int kLanesPerQuery = 64 * kBwdWaves / kQW;
+
+// dW tiles of one layer owned by this wave: tile tau = wave + 8u.
+template <class MT, int U>
+__device__ inline void dw_layer(f32x4 (&acc)[U], const MT* dT, const MT* act, int n_out, int n_in, int wave, int lane) {
+  const int MM = (n_out + 15) / 16, NK = (n_in + 15) / 16;
+  const int r16 = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int tau = wave + kBwdWaves * u;
+    if (tau < MM * NK) {
+      const int mm = tau / NK, nk = tau % NK;
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk) {
+        const auto a = tq_frag<MT>(dT, 16 * mm + r16, 4 * kk + g);
+        const auto b = tq_frag<MT>(act, 16 * nk + r16, 4 * kk + g);
+        acc[u] = mma(a, b, acc[u]);
+      }
+    }
+    // keep the scheduler from hoisting every tile's LDS reads at once
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <int U>
+__device__ inline void dw_store(const f32x4 (&acc)[U], float* part, int64_t off, int n_out, int n_in, int wave,
+                                int lane) {
+  const int MM = (n_out + 15) / 16, NK = (n_in + 15) / 16;
+  const int r16 = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int tau = wave + kBwdWaves * u;
+    if (tau < MM * NK) {
+      const int mm = tau / NK, nk = tau % NK;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n = 16 * mm + 4 * g + j, k = 16 * nk + r16;
+        if (n < n_out && k < n_in) part[off + (int64_t)n * n_in + k] = acc[u][j];
+      }
+    }
+  }
+}
+
+// B-operand chunk kb for query column col, read from a [row][query] buffer:
+// slot i holds row nu(kb, g, i); rows >= n_rows read as zero.
+template <class MT>
+__device__ inline typename FragT<MT>::type tq_bfrag(const MT* buf, int kb, int g, int col, int n_rows) {
+  typename FragT<MT>::type b;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int row = nu(kb, g, i);
+    b[i] = row < n_rows ? buf[tq_index(row, col)] : from_f32<MT>(0.0f);
+  }
+  return b;
+}
+
+// Writes this wave's output tiles (M-tiles m0 .. m0+MT2-1 of query columns
+// 16 nt .. 16 nt + 15) into a [row][query] buffer, rows >= n_rows as zeros.
+template <class MT, int MT2>
+__device__ inline void store_tq(MT* buf, const f32x4 (&acc)[MT2], int m0, int n_tiles, int n_rows, int nt, int lane,
+                                bool relu) {
+  const int col = 16 * nt + (lane & 15), g = lane >> 4;
+#pragma unroll
+  for (int mi = 0; mi < MT2; ++mi) {
+    const int m = m0 + mi;
+    if (m < n_tiles) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = 16 * m + 4 * g + j;
+        float v = row < n_rows ? acc[mi][j] : 0.0f;
+        if (relu) v = fmaxf(v, 0.0f);
+        buf[tq_index(row, col)] = from_f32<MT>(v);
+      }
+    }
+  }
+}
+
+// Workgroup of kBwdWaves waves on 64 queries. In the layer chains wave w
+// works on query columns 16 (w % 4) .. +15 and on the share w / 4 of the
+// output rows; the layers exchange activations and deltas through the
+// [row][query] buffers.
+template <class TT, class MT, int C, int H>
+__global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, const MlpArgs M, const MlpArgs Mt,
+                                                  const QuerySrc src, int64_t Q, const float* __restrict__ seeds,
+                                                  float post_scale, const GradArgs G, const ParamLayout PL,
+                                                  float* __restrict__ partials) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  typedef typename FragT<MT>::type frag;
+  constexpr int MH = H / 16, MH2 = MH / kMSplit;
+  constexpr int U0 = (MH * 8 + kBwdWaves - 1) / kBwdWaves, UH = (MH * MH + kBwdWaves - 1) / kBwdWaves;
+  constexpr int UO = (MH + kBwdWaves - 1) / kBwdWaves;
+  constexpr int NHH = H == 128 ? 1 : 3;  // hidden-to-hidden layers supported
+  const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, r16 = lane & 15;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: scalar branches
+  const int nt = wave & 3, mh = wave >> 2, col = 16 * nt + r16;  // mh = 0 with 4 waves
+  const int K0 = M.K0, NL = M.n_layers, L = T.L;
+  const BwdLayout lay = bwd_layout(K0, H, NL, L, (int)sizeof(MT));
+  const int KB0 = lay.KB0, R0 = lay.R0;
+  MT* htile = reinterpret_cast<MT*>(smem + lay.htile);
+  MT* const act0 = reinterpret_cast<MT*>(smem + lay.act0);
+  MT* const act1 = reinterpret_cast<MT*>(smem + lay.act1);
+  // input activation buffer of layer i: a_0 = h, a_i = ReLU(z_{i-1})
+  auto act = [&](int i) { return i == 0 ? act0 : act1 + (size_t)(i - 1) * H * kQW; };
+  MT* dT = reinterpret_cast<MT*>(smem + lay.delta);
+  float* dh = reinterpret_cast<float*>(smem + lay.dh);
+  int* qidx = reinterpret_cast<int*>(smem + lay.qidx);
+  float* qst = reinterpret_cast<float*>(smem + lay.qst);
+
+  f32x4 acc0[U0], accH[NHH][UH], accO[UO];
+  const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int u = 0; u < U0; ++u) acc0[u] = z4;
+#pragma unroll
+  for (int h = 0; h < NHH; ++h)
+#pragma unroll
+    for (int u = 0; u < UH; ++u) accH[h][u] = z4;
+#pragma unroll
+  for (int u = 0; u < UO; ++u) accO[u] = z4;
+  float dbacc[kMaxLayers];
+#pragma unroll
+  for (int i = 0; i < kMaxLayers; ++i) dbacc[i] = 0.0f;
+
+  // Zero paddings once: h tile inputs [K0, 32 KB0) and layer-0 rows [K0, R0).
+  for (int e = tid; e < kQW * (32 * KB0 - K0); e += blockDim.x) {
+    const int q = e % kQW, k = K0 + e / kQW;
+    htile_put1<MT>(htile, KB0, q, k, 0.0f);
+  }
+  for (int e = tid; e < (R0 - K0) * kQW; e += blockDim.x) act0[tq_index(K0 + e / kQW, e % kQW)] = from_f32<MT>(0.0f);
+  __syncthreads();
+
+  const int64_t n_tiles = (Q + kQW - 1) / kQW;
+  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const int64_t qbase = tile * kQW;
+    // ---- 1. encode: kLanesPerQuery lanes per query, one level each -----
+    {
+      const int ql = tid / kLanesPerQuery, part = tid % kLanesPerQuery;
+      const int64_t q = qbase + ql;
+      const bool valid = q < Q;
+      float x[3] = {0.f, 0.f, 0.f}, d[3] = {0.f, 0.f, 1.f};
+      if (valid) load_query(src, q, x, d);
+      {
+        int idx[kMaxLevels];
+        descend(T, valid, x, idx);
+        float s, t;
+        octa(d, s, t);
+        if (part == 0) {
+          qst[2 * ql] = s;
+          qst[2 * ql + 1] = t;
+#pragma unroll
+          for (int l = 0; l < kMaxLevels; ++l)
+            if (l < L) qidx[ql * L + l] = idx[l];
+        }
+      }
+      wave_lds_sync();  // the lanes of a query are in one wave
+      const float s = qst[2 * ql], t = qst[2 * ql + 1];
+#pragma unroll
+      for (int l0 = 0; l0 < kMaxLevels; l0 += kLanesPerQuery) {
+        const int l = l0 + part;
+        if (l < L) {
+          float h[C];
+          gather_level<TT, C>(T, l, qidx[ql * L + l], s, t, h);
+#pragma unroll
+          for (int c = 0; c < C; c += 4) htile_put4<MT>(htile, KB0, ql, l * C + c, &h[c]);
+#pragma unroll
+          for (int c = 0; c < C; ++c) act0[tq_index(l * C + c, ql)] = from_f32<MT>(h[c]);
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- 2. forward recompute of the hidden layers ------------------------
+    {
+      f32x4 acc[MH2];
+      const MT* W0 = launder_ptr(reinterpret_cast<const MT*>(M.W[0]));
+      const float* b0 = launder_ptr(M.b[0]);
+#pragma unroll
+      for (int mi = 0; mi < MH2; ++mi)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[mi][j] = b0[16 * (mh * MH2 + mi) + 4 * g + j];
+      for (int kb = 0; kb < KB0; ++kb) {
+        const frag b = htile_get<MT>(htile, KB0, nt, kb, lane);
+#pragma unroll
+        for (int mi = 0; mi < MH2; ++mi) acc[mi] = mma(wfrag_global<MT>(W0, H, K0, K0, mh * MH2 + mi, kb, lane), b, acc[mi]);
+      }
+      store_tq<MT, MH2>(act(1), acc, mh * MH2, MH, H, nt, lane, true);
+      for (int layer = 1; layer < NL - 1; ++layer) {
+        __syncthreads();  // a_layer complete
+        const MT* Wl = launder_ptr(reinterpret_cast<const MT*>(M.W[layer]));
+        const float* bl = launder_ptr(M.b[layer]);
+        const MT* a = act(layer);
+#pragma unroll
+        for (int mi = 0; mi < MH2; ++mi)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[mi][j] = bl[16 * (mh * MH2 + mi) + 4 * g + j];
+#pragma unroll
+        for (int kb = 0; kb < H / 32; ++kb) {
+          const frag b = tq_bfrag<MT>(a, kb, g, col, H);
+#pragma unroll
+          for (int mi = 0; mi < MH2; ++mi) acc[mi] = mma(wfrag_global<MT>(Wl, H, H, H, mh * MH2 + mi, kb, lane), b, acc[mi]);
+        }
+        store_tq<MT, MH2>(act(layer + 1), acc, mh * MH2, MH, H, nt, lane, true);
+      }
+    }
+
+    // ---- 3. backward ------------------------------------------------------
+    if (mh == 0) {  // seeds of the output layer into the delta buffer, rows 0..15
+      const int64_t q = qbase + col;
+      f32x4 so[1];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = 4 * g + j;
+        so[0][j] = (row < 3 && q < Q) ? seeds[3 * q + row] : 0.0f;
+      }
+      store_tq<MT, 1>(dT, so, 0, 1, 3, nt, lane, false);
+    }
+    for (int i = NL - 1; i >= 0; --i) {
+      const int n_out = i == NL - 1 ? 3 : H, n_in = i == 0 ? K0 : H;
+      __syncthreads();  // delta_i and the activations are complete
+      if (i == NL - 1)
+        dw_layer<MT, UO>(accO, dT, act(i), n_out, n_in, wave, lane);
+      else if (i == 0)
+        dw_layer<MT, U0>(acc0, dT, act0, n_out, n_in, wave, lane);
+      else {
+#pragma unroll
+        for (int hh = 0; hh < NHH; ++hh)
+          if (hh == i - 1) dw_layer<MT, UH>(accH[hh], dT, act(i), n_out, n_in, wave, lane);
+      }
+      if (tid < n_out) {
+        float sum = 0.0f;
+#pragma unroll
+        for (int c = 0; c < kQW / 8; ++c) {
+          const auto v = tq_frag<MT>(dT, tid, c);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) sum += to_f32(v[e]);
+        }
+#pragma unroll
+        for (int ii = 0; ii < kMaxLayers; ++ii)
+          if (ii == i) dbacc[ii] += sum;
+      }
+      const MT* Wt = launder_ptr(reinterpret_cast<const MT*>(Mt.W[i]));  // [n_in][ldt], ldt = n_out rounded up to 4
+      const int ldt = (n_out + 3) & ~3;
+      const int KBo = (n_out + 31) / 32;
+      if (i > 0) {
+        f32x4 dacc[MH2];
+#pragma unroll
+        for (int mi = 0; mi < MH2; ++mi) dacc[mi] = z4;
+        for (int kb = 0; kb < KBo; ++kb) {
+          const frag b = tq_bfrag<MT>(dT, kb, g, col, n_out);
+#pragma unroll
+          for (int mi = 0; mi < MH2; ++mi) dacc[mi] = mma(wfrag_global<MT>(Wt, H, n_out, ldt, mh * MH2 + mi, kb, lane), b, dacc[mi]);
+        }
+        // ReLU'(z) = 1 where the layer-i input activation is positive
+        const MT* a = act(i);
+#pragma unroll
+        for (int mi = 0; mi < MH2; ++mi)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int n = 16 * (mh * MH2 + mi) + 4 * g + j;
+            if (!(to_f32(a[tq_index(n, col)]) > 0.0f)) dacc[mi][j] = 0.0f;
+          }
+        __syncthreads();  // every wave has read delta_i
+        store_tq<MT, MH2>(dT, dacc, mh * MH2, MH, H, nt, lane, false);
+      } else {
+        constexpr int MK2 = 8 / kMSplit;  // up to 8 row tiles of dh (K0 <= 128)
+        const int MK = (K0 + 15) / 16;
+        f32x4 dacc[MK2];
+#pragma unroll
+        for (int mi = 0; mi < MK2; ++mi) dacc[mi] = z4;
+        for (int kb = 0; kb < KBo; ++kb) {
+          const frag b = tq_bfrag<MT>(dT, kb, g, col, n_out);
+#pragma unroll
+          for (int mi = 0; mi < MK2; ++mi)
+            if (mh * MK2 + mi < MK) dacc[mi] = mma(wfrag_global<MT>(Wt, K0, n_out, ldt, mh * MK2 + mi, kb, lane), b, dacc[mi]);
+        }
+        __syncthreads();  // dh may alias the h tile; all reads of it are done
+#pragma unroll
+        for (int mi = 0; mi < MK2; ++mi)
+          if (mh * MK2 + mi < MK)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int k = 16 * (mh * MK2 + mi) + 4 * g + j;
+              if (k < K0) dh[col * R0 + k] = dacc[mi][j];
+            }
+      }
+    }
+    __syncthreads();
+
+    // ---- 4. scatter into the feature gradient tables ---------------------
+    {
+      const int c = tid % C;
+      for (int p = tid / C; p < kQW * L; p += blockDim.x / C) {
+        const int ql = p / L, l = p % L;
+        const int id = qidx[ql * L + l];
+        if (id < 0) continue;
+        const int R = T.res[l];
+        int tx[4];
+        float w[4];
+        taps(qst[2 * ql], qst[2 * ql + 1], R, tx, w);
+        const float gv = dh[ql * R0 + l * C + c] * post_scale;
+        float* base = G.dfeat[l] + ((int64_t)(id - T.off[l]) * R * R) * C + c;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) unsafeAtomicAdd(base + (int64_t)tx[k] * C, w[k] * gv);
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- partials ------------------------------------------------------------
+  float* part = partials + (int64_t)blockIdx.x * PL.P;
+  for (int i = 0; i < NL; ++i) {
+    const int n_out = PL.n_out[i], n_in = PL.n_in[i];
+    if (i == NL - 1)
+      dw_store<UO>(accO, part, PL.w_off[i], n_out, n_in, wave, lane);
+    else if (i == 0)
+      dw_store<U0>(acc0, part, PL.w_off[i], n_out, n_in, wave, lane);
+    else {
+#pragma unroll
+      for (int hh = 0; hh < NHH; ++hh)
+        if (hh == i - 1) dw_store<UH>(accH[hh], part, PL.w_off[i], n_out, n_in, wave, lane);
+    }
+#pragma unroll
+    for (int ii = 0; ii < kMaxLayers; ++ii)
+      if (ii == i && tid < n_out) part[PL.b_off[i] + tid] = dbacc[ii];
+  }
+}
+
+// Seeds of the backward: LHS point b gets 2 r_b grad_loss (divided by the
+// squared detached normaliser for the relative loss); with the gradient
+// through the target, secondary query (b, k) gets -seed_b * w_bk / N. The
+// 1 / (3B) mean factor is applied later in FP32, so that 16-bit matrix-core
+// operands stay far from underflow.
+__device__ inline void bsdf_weight_b(const ResidualArgs& A, int64_t b, int k, float w[3]);
+
+__global__ __launch_bounds__(256) void seed_kernel(const ResidualArgs A, const float* __restrict__ resid,
+                                                   const float* __restrict__ rhs, const double* __restrict__ grad_loss,
+                                                   int full, float* __restrict__ seeds) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= A.B) return;
+  const float gam = (float)(*grad_loss);
+  float sd[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float r = resid[3 * b + c];
+    float v = 2.0f * r * gam;
+    if (A.loss_kind == 1) {
+      const float T = rhs[3 * b + c], Lh = r + T;
+      const float rho = fmaxf(Lh + T, 0.0f) + A.eps;
+      v /= rho * rho;
+    }
+    sd[c] = v;
+    seeds[3 * b + c] = v;
+  }
+  if (full && A.N > 0) {
+    const float invN = 1.0f / (float)A.N;
+    for (int k = 0; k < A.N; ++k) {
+      float w[3];
+      bsdf_weight_b(A, b, k, w);
+      const int64_t q = A.B + b * A.N + k;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) seeds[3 * q + c] = -sd[c] * w[c] * invN;
+    }
+  }
+}
+
+// Wt[i][o] = W[o][i], rows of Wt padded with zeros to ld = n_out rounded up
+// to a multiple of 4.
+__global__ __launch_bounds__(256) void transpose_kernel(const void* __restrict__ W, void* __restrict__ Wt, int n_out,
+                                                        int n_in, int esz) {
+  const int ld = (n_out + 3) & ~3;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ld * n_in) return;
+  const int i = e / ld, o = e % ld;
+  if (esz == 4)
+    reinterpret_cast<float*>(Wt)[e] = o < n_out ? reinterpret_cast<const float*>(W)[o * n_in + i] : 0.0f;
+  else
+    reinterpret_cast<uint16_t*>(Wt)[e] = o < n_out ? reinterpret_cast<const uint16_t*>(W)[o * n_in + i] : (uint16_t)0;
+}
+
+// dst[p] += scale * sum over workgroups of partial[g][p], summed in FP64 in
+// workgroup order.
+__global__ __launch_bounds__(256) void dw_reduce_kernel(const float* __restrict__ partials, int grid, int64_t P,
+                                                        const ReduceDst D, float scale) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  double s = 0.0;
+  for (int g = 0; g < grid; ++g) s += (double)partials[(int64_t)g * P + p];
+  int seg = 0;
+  while (seg + 1 < D.n_seg && p >= D.start[seg + 1]) ++seg;
+  D.dst[seg][p - D.start[seg]] += (float)(s * (double)scale);
+}
+
+// ---------------------------------------------------------------------------
+// BSDF weight (same formula as the forward residual assembly).
+// ---------------------------------------------------------------------------
+__device__ inline void unit3(const float* p, float v[3]) {
+  v[0] = p[0];
+  v[1] = p[1];
+  v[2] = p[2];
+  const float l = sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  if (l > 0.0f) {
+    v[0] /= l;
+    v[1] /= l;
+    v[2] /= l;
+  }
+}
+
+__device__ inline void bsdf_weight_b(const ResidualArgs& A, int64_t b, int k, float w[3]) {
+  const int64_t bk = b * A.N + k;
+  float n[3], wo[3], wi[3];
+  unit3(A.n + 3 * b, n);
+  unit3(A.wo + 3 * b, wo);
+  unit3(A.wi + 3 * bk, wi);
+  const float alpha = A.rough[b];
+  const float pdf = A.pdf ? A.pdf[bk] : 1.0f;
+  const float ci = n[0] * wi[0] + n[1] * wi[1] + n[2] * wi[2];
+  const float co = n[0] * wo[0] + n[1] * wo[1] + n[2] * wo[2];
+  if (!(ci > 0.0f) || !(co > 0.0f)) {
+    w[0] = w[1] = w[2] = 0.0f;
+    return;
+  }
+  float h[3] = {wi[0] + wo[0], wi[1] + wo[1], wi[2] + wo[2]};
+  const float hl = sqrtf(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
+  h[0] /= hl;
+  h[1] /= hl;
+  h[2] /= hl;
+  const float nh = n[0] * h[0] + n[1] * h[1] + n[2] * h[2];
+  const float cx = n[1] * h[2] - n[2] * h[1], cy = n[2] * h[0] - n[0] * h[2], cz = n[0] * h[1] - n[1] * h[0];
+  const float a2 = alpha * alpha;
+  const float den = a2 * nh * nh + (cx * cx + cy * cy + cz * cz);
+  const float Dm = a2 / (3.14159265358979f * den * den);
+  const float g1i = 2.0f * ci / (ci + sqrtf(a2 + (1.0f - a2) * ci * ci));
+  const float g1o = 2.0f * co / (co + sqrtf(a2 + (1.0f - a2) * co * co));
+  const float vh = 1.0f - (wi[0] * h[0] + wi[1] * h[1] + wi[2] * h[2]);
+  const float vh2 = vh * vh;
+  const float F = A.F0 + (1.0f - A.F0) * (vh2 * vh2 * vh);
+  const float spec = Dm * g1i * g1o * F / (4.0f * ci * co);
+  const float sc = ci / pdf;
+  for (int c = 0; c < 3; ++c) w[c] = (A.albedo[3 * b + c] * (1.0f / 3.14159265358979f) + spec) * sc;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+static int cu_count() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (cus <= 0) cus = 256;
+  }
+  return cus;
+}
+
+size_t bwd_lds_bytes(const MlpArgs& M, oo_dtype md, int L) {
+  return bwd_layout(M.K0, M.H, M.n_layers, L, md == OO_F32 ? 4 : 2).total;
+}
+
+int bwd_grid(const MlpArgs& M, int64_t Q) {
+  const int64_t n_tiles = (Q + kQW - 1) / kQW;
+  int64_t g = (int64_t)cu_count() * 2;
+  if (g > n_tiles) g = n_tiles;
+  return (int)(g > 0 ? g : 1);
+  (void)M;
+}
+
+hipError_t launch_seeds(const ResidualArgs& A, const float* resid, const float* rhs, const double* grad_loss,
+                        int full, float* seeds, hipStream_t st) {
+  if (A.B == 0) return hipSuccess;
+  hipLaunchKernelGGL(seed_kernel, dim3((unsigned)((A.B + 255) / 256)), dim3(256), 0, st, A, resid, rhs, grad_loss,
+                     full, seeds);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_weights(const MlpArgs& M, oo_dtype md, void* const* Wt, hipStream_t st) {
+  const int esz = md == OO_F32 ? 4 : 2;
+  for (int i = 0; i < M.n_layers; ++i) {
+    const int n_in = i == 0 ? M.K0 : M.H, n_out = i == M.n_layers - 1 ? 3 : M.H;
+    const int n = n_in * ((n_out + 3) & ~3);
+    hipLaunchKernelGGL(transpose_kernel, dim3((n + 255) / 256), dim3(256), 0, st, M.W[i], Wt[i], n_out, n_in, esz);
+  }
+  return hipGetLastError();
+}
+
+template <class TT, class MT, int C, int H>
+static hipError_t launch_bwd_t(const TreeArgs& T, const MlpArgs& M, const MlpArgs& Mt, const QuerySrc& src,
+                               int64_t Q, const float* seeds, float post_scale, const GradArgs& G,
+                               const ParamLayout& PL, float* partials, int grid, hipStream_t st) {
+  const size_t lds = bwd_layout(M.K0, H, M.n_layers, T.L, (int)sizeof(MT)).total;
+  auto k = bwd_kernel<TT, MT, C, H>;
+  hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * kBwdWaves), lds, st, T, M, Mt, src, Q, seeds, post_scale, G, PL, partials);
+  return hipGetLastError();
+}
+
+template <class TT, class MT, int C>
+static hipError_t launch_bwd_c(const TreeArgs& T, const MlpArgs& M, const MlpArgs& Mt, const QuerySrc& src,
+                               int64_t Q, const float* seeds, float post_scale, const GradArgs& G,
+                               const ParamLayout& PL, float* partials, int grid, hipStream_t st) {
+  return M.H == 64 ? launch_bwd_t<TT, MT, C, 64>(T, M, Mt, src, Q, seeds, post_scale, G, PL, partials, grid, st)
+                   : launch_bwd_t<TT, MT, C, 128>(T, M, Mt, src, Q, seeds, post_scale, G, PL, partials, grid, st);
+}
+
+hipError_t launch_bwd(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, void* const* Wt,
+                      const QuerySrc& src, int64_t Q, const float* seeds, float post_scale, const GradArgs& G,
+                      const ParamLayout& PL, float* partials, int grid, hipStream_t st) {
+  MlpArgs Mt = M;
+  for (int i = 0; i < M.n_layers; ++i) Mt.W[i] = Wt[i];
+  if (td == OO_F32)
+    return T.C == 4 ? launch_bwd_c<float, float, 4>(T, M, Mt, src, Q, seeds, post_scale, G, PL, partials, grid, st)
+                    : launch_bwd_c<float, float, 8>(T, M, Mt, src, Q, seeds, post_scale, G, PL, partials, grid, st);
+  if (td == OO_F16) return launch_bwd_c<f16, f16, 8>(T, M, Mt, src, Q, seeds, post_scale, G, PL, partials, grid, st);
+  return launch_bwd_c<bf16, bf16, 8>(T, M, Mt, src, Q, seeds, post_scale, G, PL, partials, grid, st);
+  (void)md;
+}
+
+hipError_t launch_dw_reduce(const float* partials, int grid, const ParamLayout& PL, const ReduceDst& D, float scale,
+                            hipStream_t st) {
+  const int64_t blocks = (PL.P + 255) / 256;
+  hipLaunchKernelGGL(dw_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, st, partials, grid, PL.P, D, scale);
+  return hipGetLastError();
+}
+
+}  // namespace oo

@@ -1,0 +1,405 @@
+// Device-side building blocks shared by the forward and backward kernels:
+// octree descent, octahedral map, bilinear taps, texel gathers, and the
+// matrix-core fragment conventions used by the decoder MLP.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "octaoctree.h"
+
+namespace oo {
+
+constexpr int kMaxLevels = OO_MAX_LEVELS;
+constexpr int kMaxLayers = OO_MAX_LAYERS;
+constexpr int kWave = 64;
+
+// Kernel-argument copy of oo_tree (levels with no node point at level 0's
+// table so that predicated dummy loads stay in bounds).
+struct TreeArgs {
+  int32_t L, C, D;
+  int32_t res[kMaxLevels];
+  int64_t off[kMaxLevels + 1];
+  const uint32_t* nodes;
+  const void* feat[kMaxLevels];
+};
+
+// Kernel-argument copy of oo_mlp.
+struct MlpArgs {
+  int32_t n_layers;  // Linear layers; n_layers - 1 hidden layers of width H
+  int32_t K0;        // input width (levels * C)
+  int32_t H;
+  const void* W[kMaxLayers];  // [out][in] row-major, MT
+  const float* b[kMaxLayers];
+};
+
+// Two query sources concatenated: q < nA reads (xA, dA)[q], else
+// (xB, dB)[q - nA]. The residual step lists LHS points first, then the
+// secondary hits.
+struct QuerySrc {
+  const float* xA;
+  const float* dA;
+  int64_t nA;
+  const float* xB;
+  const float* dB;
+};
+
+__device__ inline void load_query(const QuerySrc& s, int64_t q, float x[3], float d[3]) {
+  const float* xp = q < s.nA ? s.xA + 3 * q : s.xB + 3 * (q - s.nA);
+  const float* dp = q < s.nA ? s.dA + 3 * q : s.dB + 3 * (q - s.nA);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    x[a] = xp[a];
+    d[a] = dp[a];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Spatial: quantisation and descent (containing node at every level)
+// ---------------------------------------------------------------------------
+
+// floor(x * 2^D) clamped to [0, 2^D - 1]; exact because the scale is a power
+// of two. fmaxf maps NaN to 0.
+__device__ inline int quant_axis(float xa, int D) {
+  const float scale = (float)(1u << D);
+  float v = floorf(xa * scale);
+  v = fminf(fmaxf(v, 0.0f), scale - 1.0f);
+  return (int)v;
+}
+
+// idx[l] = global index of the level-l node containing x, or -1. Level 0 is
+// the root. The walk stops for the whole wave once no lane has a node left.
+__device__ inline void descend(const TreeArgs& T, bool valid, const float x[3], int idx[kMaxLevels]) {
+  const int D = T.D;
+  const int qx = quant_axis(x[0], D), qy = quant_axis(x[1], D), qz = quant_axis(x[2], D);
+  int cur = valid ? 0 : -1;
+#pragma unroll
+  for (int l = 0; l < kMaxLevels; ++l) idx[l] = -1;
+  idx[0] = cur;
+#pragma unroll
+  for (int l = 1; l < kMaxLevels; ++l) {
+    if (l > D || !__any(cur >= 0)) break;
+    int nxt = -1;
+    if (cur >= 0) {
+      const uint32_t w = T.nodes[cur];
+      const int sh = D - l;
+      const int o = ((qx >> sh) & 1) | (((qy >> sh) & 1) << 1) | (((qz >> sh) & 1) << 2);
+      const uint32_t m = w & 0xffu;
+      nxt = ((m >> o) & 1u) ? (int)(w >> 8) + __popc(m & ((1u << o) - 1u)) : -1;
+    }
+    cur = nxt;
+    idx[l] = cur;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Directional: octahedral map and bilinear taps
+// ---------------------------------------------------------------------------
+
+// u = (dx, dy) / (|dx| + |dy| + |dz|), lower hemisphere folded from the
+// unfolded coordinates, (s, t) = (u + 1) / 2. sign(0) = +1.
+__device__ inline void octa(const float d[3], float& s, float& t) {
+  const float S = fabsf(d[0]) + fabsf(d[1]) + fabsf(d[2]);
+  float ux = 0.0f, uy = 0.0f;
+  if (S > 0.0f) {
+    ux = d[0] / S;
+    uy = d[1] / S;
+  }
+  if (d[2] < 0.0f) {
+    const float fx = (1.0f - fabsf(uy)) * (ux < 0.0f ? -1.0f : 1.0f);
+    const float fy = (1.0f - fabsf(ux)) * (uy < 0.0f ? -1.0f : 1.0f);
+    ux = fx;
+    uy = fy;
+  }
+  s = 0.5f * (ux + 1.0f);
+  t = 0.5f * (uy + 1.0f);
+}
+
+// Four texel-centred bilinear taps at resolution R. A tap beyond the map is
+// moved across the octahedral seam: columns first (edges s = 0 and s = 1 meet
+// themselves with t mirrored), then rows (edges t = 0 and t = 1 meet
+// themselves with s mirrored). texel[k] = j * R + i.
+__device__ inline void taps(float s, float t, int R, int texel[4], float w[4]) {
+  const float pu = s * (float)R - 0.5f, pv = t * (float)R - 0.5f;
+  const float fi = floorf(pu), fj = floorf(pv);
+  const float fu = pu - fi, fv = pv - fj;
+  const int i0 = (int)fi, j0 = (int)fj;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int a = k & 1, b = k >> 1;
+    int i = i0 + a, j = j0 + b;
+    w[k] = (a ? fu : 1.0f - fu) * (b ? fv : 1.0f - fv);
+    if (i < 0) {
+      i = -1 - i;
+      j = R - 1 - j;
+    } else if (i >= R) {
+      i = 2 * R - 1 - i;
+      j = R - 1 - j;
+    }
+    if (j < 0) {
+      i = R - 1 - i;
+      j = -1 - j;
+    } else if (j >= R) {
+      i = R - 1 - i;
+      j = 2 * R - 1 - j;
+    }
+    texel[k] = j * R + i;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Element types
+// ---------------------------------------------------------------------------
+
+typedef _Float16 f16;
+typedef __bf16 bf16;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline float to_f32(float v) { return v; }
+__device__ inline float to_f32(f16 v) { return (float)v; }
+__device__ inline float to_f32(bf16 v) { return (float)v; }
+
+template <class T>
+__device__ inline T from_f32(float v);
+template <>
+__device__ inline float from_f32<float>(float v) { return v; }
+template <>
+__device__ inline f16 from_f32<f16>(float v) { return (f16)v; }
+template <>
+__device__ inline bf16 from_f32<bf16>(float v) { return (bf16)v; }
+
+// Texel gather: acc[c] += w * table[texel][c] for C channels, read as one or
+// two 16-byte (or one 8-byte) vector loads.
+template <class TT, int C>
+struct Texel;
+
+template <int C>
+struct Texel<float, C> {
+  static_assert(C == 4 || C == 8, "C");
+  typedef float4 raw[C / 4];
+  __device__ static inline void load(const float* p, raw& r) {
+#pragma unroll
+    for (int v = 0; v < C / 4; ++v) r[v] = reinterpret_cast<const float4*>(p)[v];
+  }
+  __device__ static inline void acc(const raw& r, float w, float* a) {
+#pragma unroll
+    for (int v = 0; v < C / 4; ++v) {
+      a[4 * v + 0] += w * r[v].x;
+      a[4 * v + 1] += w * r[v].y;
+      a[4 * v + 2] += w * r[v].z;
+      a[4 * v + 3] += w * r[v].w;
+    }
+  }
+};
+
+template <class H16, int C>
+struct Texel16 {
+  static_assert(C == 4 || C == 8, "C");
+  typedef H16 vec __attribute__((ext_vector_type(C)));
+  typedef vec raw;
+  __device__ static inline void load(const H16* p, raw& r) { r = *reinterpret_cast<const vec*>(p); }
+  __device__ static inline void acc(const raw& r, float w, float* a) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) a[c] += w * (float)r[c];
+  }
+};
+template <int C>
+struct Texel<f16, C> : Texel16<f16, C> {};
+template <int C>
+struct Texel<bf16, C> : Texel16<bf16, C> {};
+
+// Per-level feature h_l of one query: the 4 taps of the level-l map of node
+// idx (zeros when idx < 0). Loads are issued branch-free (a missing level
+// reads texel 0 of the level table with weight 0) so that all levels' loads
+// can be in flight together.
+template <class TT, int C>
+__device__ inline void gather_level(const TreeArgs& T, int l, int idx, float s, float t, float* h) {
+  const int R = T.res[l];
+  int tx[4];
+  float w[4];
+  taps(s, t, R, tx, w);
+  const bool ok = idx >= 0;
+  const int64_t node = ok ? (int64_t)idx - T.off[l] : 0;
+  const TT* base = reinterpret_cast<const TT*>(T.feat[l]);
+  typename Texel<TT, C>::raw r[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t e = ok ? ((node * R * R) + tx[k]) * C : 0;
+    Texel<TT, C>::load(base + e, r[k]);
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) h[c] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) Texel<TT, C>::acc(r[k], ok ? w[k] : 0.0f, h);
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-core fragments for the decoder
+// ---------------------------------------------------------------------------
+//
+// Queries run along the N dimension of every 16x16 output tile, neurons along
+// M. An output tile gives lane l the rows 16m + 4g + j (j = 0..3) of column
+// q = l % 16, with g = l / 16. A K-chunk of 32 inputs is held as 8 slots per
+// lane; slot i of lane l (group g) carries input neuron
+//     nu(kb, g, i) = 32 kb + 16 (i >> 2) + 4 g + (i & 3),
+// so that output tiles 2kb and 2kb+1 of one layer are, unchanged, the
+// K-chunk kb of the next layer. Operands A (weights) and B (activations) use
+// the same nu, so every product pairs matching neurons. FP16/BF16 issue one
+// 16x16x32 MFMA per chunk; FP32 issues eight 16x16x4 MFMAs, one per slot.
+
+__host__ __device__ inline int nu(int kb, int g, int i) { return 32 * kb + 16 * (i >> 2) + 4 * g + (i & 3); }
+
+template <class MT>
+struct FragT;
+template <>
+struct FragT<f16> {
+  typedef f16x8 type;
+};
+template <>
+struct FragT<bf16> {
+  typedef bf16x8 type;
+};
+template <>
+struct FragT<float> {
+  typedef f32x8 type;
+};
+
+__device__ inline f32x4 mma(const f16x8& a, const f16x8& b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+__device__ inline f32x4 mma(const bf16x8& a, const bf16x8& b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ inline f32x4 mma(const f32x8& a, const f32x8& b, f32x4 c) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[i], c, 0, 0, 0);
+  return c;
+}
+
+// Position of input neuron k inside a fragment: chunk kb, lane group g, slot i.
+__device__ inline void nu_inv(int k, int& kb, int& g, int& i) {
+  kb = k >> 5;
+  const int r = k & 31;
+  g = (r & 15) >> 2;
+  i = ((r >> 4) << 2) | (r & 3);
+}
+
+// Activation tile in LDS for one 16-query N-tile set, fragment-major:
+// element (q, k) of a tile with KB chunks lives at
+//   ((q / 16) * KB + kb) * 64 * 8 + (16 g + q % 16) * 8 + i.
+// Reading chunk kb of N-tile t is then one contiguous 8-element read per lane.
+template <class MT>
+__device__ inline int htile_index(int q, int k, int KB) {
+  int kb, g, i;
+  nu_inv(k, kb, g, i);
+  return (((q >> 4) * KB + kb) * kWave + (g << 4) + (q & 15)) * 8 + i;
+}
+
+// Four consecutive inputs k0..k0+3 (k0 % 4 == 0) of query q: they share
+// (kb, g) and occupy slots 4h..4h+3, so one vector store writes them.
+template <class MT>
+__device__ inline void htile_put4(MT* tile, int KB, int q, int k0, const float v[4]) {
+  const int idx = htile_index<MT>(q, k0, KB);
+  typedef MT v4 __attribute__((ext_vector_type(4)));
+  v4 x;
+  x[0] = from_f32<MT>(v[0]);
+  x[1] = from_f32<MT>(v[1]);
+  x[2] = from_f32<MT>(v[2]);
+  x[3] = from_f32<MT>(v[3]);
+  *reinterpret_cast<v4*>(tile + idx) = x;
+}
+
+template <class MT>
+__device__ inline typename FragT<MT>::type htile_get(const MT* tile, int KB, int t, int kb, int lane) {
+  return *reinterpret_cast<const typename FragT<MT>::type*>(tile + ((t * KB + kb) * kWave + lane) * 8);
+}
+
+// Weight fragment (A operand) of a row-major [n_out][n_in] matrix with
+// leading dimension ld (a multiple of 4, zero padded beyond n_in), for output
+// tile m and chunk kb. Slots 0..3 and 4..7 are 4 consecutive columns each,
+// so the fragment is two vector loads; columns past the row read as zero.
+template <class MT>
+__device__ inline typename FragT<MT>::type wfrag_global(const MT* W, int n_out, int n_in, int ld, int m, int kb,
+                                                        int lane) {
+  typedef MT v4 __attribute__((ext_vector_type(4)));
+  typename FragT<MT>::type a;
+  const int row = 16 * m + (lane & 15), g = lane >> 4;
+  const bool rok = row < n_out;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int col = 32 * kb + 16 * h + 4 * g;
+    v4 v;
+    if (rok && col < n_in) {
+      v = *reinterpret_cast<const v4*>(W + (int64_t)row * ld + col);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] = from_f32<MT>(0.0f);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a[4 * h + j] = v[j];
+  }
+  return a;
+}
+
+// B-operand chunk kb built from two output tiles (2kb, 2kb+1) of the
+// previous layer: bias already added; ReLU applied when relu is set.
+template <class MT>
+__device__ inline typename FragT<MT>::type chain_frag(const f32x4& lo, const f32x4& hi, bool relu) {
+  typename FragT<MT>::type b;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float a0 = relu ? fmaxf(lo[j], 0.0f) : lo[j];
+    const float a1 = relu ? fmaxf(hi[j], 0.0f) : hi[j];
+    b[j] = from_f32<MT>(a0);
+    b[4 + j] = from_f32<MT>(a1);
+  }
+  return b;
+}
+
+// Returns p unchanged but opaque to the optimiser. Weight fragments are
+// loop-invariant in the persistent tile loops; laundering their base pointer
+// per iteration keeps the compiler from hoisting every fragment load out of
+// the loop and pinning hundreds of registers. The loads then hit L2.
+template <class P>
+__device__ inline P* launder_ptr(P* p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+// Orders this wave's LDS writes before its following LDS reads.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// XCD-aware work split: workgroups are dispatched round-robin over the 8
+// XCDs, so workgroup b runs on XCD b % 8. Each XCD takes one contiguous range
+// of tiles (neighbouring queries share nodes and texels, and each XCD has
+// its own L2); inside it the workers stride through the range.
+struct TileRange {
+  int64_t first, end, stride;
+};
+__device__ inline TileRange xcd_tiles(int64_t n_tiles, int workers_per_wg, int worker) {
+  const int G = gridDim.x;
+  TileRange r;
+  if (G % 8 != 0 || G < 8) {
+    r.first = (int64_t)blockIdx.x * workers_per_wg + worker;
+    r.end = n_tiles;
+    r.stride = (int64_t)G * workers_per_wg;
+    return r;
+  }
+  const int xcd = blockIdx.x & 7, per = G >> 3;
+  const int64_t lo = n_tiles * xcd / 8, hi = n_tiles * (xcd + 1) / 8;
+  r.first = lo + (int64_t)(blockIdx.x >> 3) * workers_per_wg + worker;
+  r.end = hi;
+  r.stride = (int64_t)per * workers_per_wg;
+  return r;
+}
+
+}  // namespace oo

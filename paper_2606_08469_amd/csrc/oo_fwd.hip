@@ -1,0 +1,587 @@
+// Forward kernels: standalone encoding, standalone decoder, the fused
+// encode + decode query, the residual assembly with its FP64 loss
+// reduction, and the FP32 -> FP16/BF16 parameter cast.
+#include <hip/hip_runtime.h>
+
+#include "oo_device.h"
+#include "oo_internal.h"
+
+namespace oo {
+
+// ---------------------------------------------------------------------------
+// Standalone encoding: one thread per query, h written row-major to memory.
+// ---------------------------------------------------------------------------
+template <class TT, class HT, int C>
+__global__ __launch_bounds__(256) void encode_kernel(const TreeArgs T, const float* __restrict__ x,
+                                                     const float* __restrict__ dir, int64_t B,
+                                                     HT* __restrict__ h_out, int32_t* __restrict__ idx_out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = q < B;
+  float xq[3] = {0.f, 0.f, 0.f}, dq[3] = {0.f, 0.f, 1.f};
+  if (valid) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      xq[a] = x[3 * q + a];
+      dq[a] = dir[3 * q + a];
+    }
+  }
+  int idx[kMaxLevels];
+  descend(T, valid, xq, idx);
+  if (!valid) return;
+  float s, t;
+  octa(dq, s, t);
+  const int L = T.L;
+  HT* hrow = h_out + q * (int64_t)(L * C);
+#pragma unroll
+  for (int l = 0; l < kMaxLevels; ++l) {
+    if (l >= L) break;
+    float h[C];
+    gather_level<TT, C>(T, l, idx[l], s, t, h);
+    typedef HT vC __attribute__((ext_vector_type(C)));
+    vC v;
+#pragma unroll
+    for (int c = 0; c < C; ++c) v[c] = from_f32<HT>(h[c]);
+    *reinterpret_cast<vC*>(hrow + l * C) = v;
+    if (idx_out) idx_out[q * L + l] = idx[l];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Decoder forward on one wave's 64-query activation tile.
+// ---------------------------------------------------------------------------
+
+// Weight fragments: packed in LDS in fragment order (zero padded), or read
+// straight from the row-major matrices. Packed layout: layer 0 first
+// ((H/16) x KB0 fragments), then each hidden layer ((H/16) x (H/32)), then
+// the output layer (H/32); one fragment is 64 lanes x 8 elements.
+template <class MT, bool WLDS>
+struct WFrag {
+  const MT* lds;
+  int KB0;
+  __device__ inline typename FragT<MT>::type get(const MlpArgs& M, int layer, int m, int kb, int lane) const {
+    if constexpr (WLDS) {
+      const int MH = M.H / 16, KH = M.H / 32;
+      int base, KB;
+      if (layer == 0) {
+        base = 0;
+        KB = KB0;
+      } else {
+        base = MH * KB0 + (layer - 1) * MH * KH;
+        KB = KH;
+      }
+      return *reinterpret_cast<const typename FragT<MT>::type*>(lds + ((base + m * KB + kb) * kWave + lane) * 8);
+    } else {
+      const int n_in = layer == 0 ? M.K0 : M.H;
+      const int n_out = layer == M.n_layers - 1 ? 3 : M.H;
+      return wfrag_global<MT>(launder_ptr(reinterpret_cast<const MT*>(M.W[layer])), n_out, n_in, n_in, m, kb, lane);
+    }
+  }
+};
+
+__device__ inline f32x4 bias_tile(const float* b, int n_out, int m, int lane) {
+  f32x4 v;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int row = 16 * m + 4 * (lane >> 4) + j;
+    v[j] = row < n_out ? b[row] : 0.0f;
+  }
+  return v;
+}
+
+// Runs the MLP on N-tiles t0 .. t0+NT-1 of the activation tile and returns
+// the output tile per N-tile (rows 0..2 = RGB in lanes 0..15).
+template <class MT, int H, int NT, class WSrc>
+__device__ inline void mlp_forward_tiles(const MlpArgs& M, const WSrc& W, const MT* htile, int KB0, int t0,
+                                         int lane, f32x4 out[NT]) {
+  // M is a kernel argument: indexing its arrays reads the argument segment.
+  typedef typename FragT<MT>::type frag;
+  constexpr int MH = H / 16, KH = H / 32;
+  f32x4 acc[MH][NT];
+  // layer 0: K0 -> H
+#pragma unroll
+  for (int m = 0; m < MH; ++m) {
+    const f32x4 bt = bias_tile(M.b[0], H, m, lane);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = bt;
+  }
+  for (int kb = 0; kb < KB0; ++kb) {
+    frag bf[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) bf[t] = htile_get<MT>(htile, KB0, t0 + t, kb, lane);
+#pragma unroll
+    for (int m = 0; m < MH; ++m) {
+      const frag a = W.get(M, 0, m, kb, lane);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[m][t] = mma(a, bf[t], acc[m][t]);
+    }
+  }
+  // hidden layers H -> H
+  for (int layer = 1; layer < M.n_layers - 1; ++layer) {
+    frag bf[KH][NT];
+#pragma unroll
+    for (int kb = 0; kb < KH; ++kb)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) bf[kb][t] = chain_frag<MT>(acc[2 * kb][t], acc[2 * kb + 1][t], true);
+#pragma unroll
+    for (int m = 0; m < MH; ++m) {
+      const f32x4 bt = bias_tile(M.b[layer], H, m, lane);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[m][t] = bt;
+    }
+#pragma unroll
+    for (int kb = 0; kb < KH; ++kb)
+#pragma unroll
+      for (int m = 0; m < MH; ++m) {
+        const frag a = W.get(M, layer, m, kb, lane);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = mma(a, bf[kb][t], acc[m][t]);
+      }
+  }
+  // output layer H -> 3
+  const int lo = M.n_layers - 1;
+  const f32x4 bt = bias_tile(M.b[lo], 3, 0, lane);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) out[t] = bt;
+#pragma unroll
+  for (int kb = 0; kb < KH; ++kb) {
+    const frag a = W.get(M, lo, 0, kb, lane);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) out[t] = mma(a, chain_frag<MT>(acc[2 * kb][t], acc[2 * kb + 1][t], true), out[t]);
+  }
+}
+
+// Packs every layer's weights into LDS in fragment order (zero padded).
+template <class MT>
+__device__ inline void pack_weights_lds(const MlpArgs& M, MT* lds) {
+  int offset = 0;
+  for (int layer = 0; layer < M.n_layers; ++layer) {
+    const int n_in = layer == 0 ? M.K0 : M.H;
+    const int n_out = layer == M.n_layers - 1 ? 3 : M.H;
+    const int KB = (n_in + 31) / 32;
+    const int total = ((n_out + 15) / 16) * KB * kWave * 8;
+    const MT* src = reinterpret_cast<const MT*>(M.W[layer]);
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+      const int i = e & 7, lane = (e >> 3) & 63, frag = e >> 9;
+      const int kb = frag % KB, m = frag / KB;
+      const int row = 16 * m + (lane & 15), col = nu(kb, lane >> 4, i);
+      lds[offset + e] = (row < n_out && col < n_in) ? src[(int64_t)row * n_in + col] : from_f32<MT>(0.0f);
+    }
+    offset += total;
+  }
+}
+
+template <class MT>
+__host__ __device__ inline int packed_weight_elems(int n_layers, int K0, int H) {
+  int total = 0;
+  for (int layer = 0; layer < n_layers; ++layer) {
+    const int n_in = layer == 0 ? K0 : H;
+    const int n_out = layer == n_layers - 1 ? 3 : H;
+    total += ((n_out + 15) / 16) * ((n_in + 31) / 32) * kWave * 8;
+  }
+  return total;
+}
+
+template <class MT, int NT>
+__device__ inline void store_rgb(const f32x4 out[NT], int t0, int64_t q_base, int64_t Q, int lane, float* rgb) {
+  if (lane < 16) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int64_t q = q_base + 16 * (t0 + t) + lane;
+      if (q < Q) {
+        rgb[3 * q + 0] = out[t][0];
+        rgb[3 * q + 1] = out[t][1];
+        rgb[3 * q + 2] = out[t][2];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused query: encode 64 queries per wave into LDS, decode them there.
+// ---------------------------------------------------------------------------
+template <class TT, class MT, int C, int H, bool WLDS>
+__global__ __launch_bounds__(512) void query_kernel(const TreeArgs T, const MlpArgs M, const QuerySrc src,
+                                                    int64_t Q, float* __restrict__ rgb) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  constexpr int NT = 2;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63, waves = blockDim.x >> 6;
+  const int KB0 = (M.K0 + 31) / 32;
+  const int wl_elems = WLDS ? packed_weight_elems<MT>(M.n_layers, M.K0, M.H) : 0;
+  MT* wl = reinterpret_cast<MT*>(smem);
+  MT* htile = wl + wl_elems + wave * (4 * KB0 * kWave * 8);
+  if (WLDS) pack_weights_lds<MT>(M, wl);
+  {  // zero the K padding of this lane's row once
+    const float z[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int k = M.K0; k < 32 * KB0; k += 4) htile_put4<MT>(htile, KB0, lane, k, z);
+  }
+  __syncthreads();
+  const WFrag<MT, WLDS> W{wl, KB0};
+  const int64_t n_tiles = (Q + 63) / 64;
+  const TileRange tr = xcd_tiles(n_tiles, waves, wave);
+  for (int64_t tile = tr.first; tile < tr.end; tile += tr.stride) {
+    const int64_t q = tile * 64 + lane;
+    const bool valid = q < Q;
+    float x[3] = {0.f, 0.f, 0.f}, d[3] = {0.f, 0.f, 1.f};
+    if (valid) load_query(src, q, x, d);
+    int idx[kMaxLevels];
+    descend(T, valid, x, idx);
+    float s, t;
+    octa(d, s, t);
+#pragma unroll
+    for (int l = 0; l < kMaxLevels; ++l) {
+      if (l >= T.L) break;
+      float h[C];
+      gather_level<TT, C>(T, l, idx[l], s, t, h);
+#pragma unroll
+      for (int c = 0; c < C; c += 4) htile_put4<MT>(htile, KB0, lane, l * C + c, &h[c]);
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int t0 = 0; t0 < 4; t0 += NT) {
+      f32x4 out[NT];
+      mlp_forward_tiles<MT, H, NT>(M, W, htile, KB0, t0, lane, out);
+      store_rgb<MT, NT>(out, t0, tile * 64, Q, lane, rgb);
+    }
+    wave_lds_sync();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Standalone decoder: h rows from memory into the LDS tile, then decode.
+// ---------------------------------------------------------------------------
+template <class MT, int H, bool WLDS>
+__global__ __launch_bounds__(512) void mlp_kernel(const MlpArgs M, const MT* __restrict__ h, int64_t Q,
+                                                  float* __restrict__ rgb) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  constexpr int NT = 2;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63, waves = blockDim.x >> 6;
+  const int KB0 = (M.K0 + 31) / 32;
+  const int wl_elems = WLDS ? packed_weight_elems<MT>(M.n_layers, M.K0, M.H) : 0;
+  MT* wl = reinterpret_cast<MT*>(smem);
+  MT* htile = wl + wl_elems + wave * (4 * KB0 * kWave * 8);
+  if (WLDS) pack_weights_lds<MT>(M, wl);
+  {
+    const float z[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int k = M.K0; k < 32 * KB0; k += 4) htile_put4<MT>(htile, KB0, lane, k, z);
+  }
+  __syncthreads();
+  const WFrag<MT, WLDS> W{wl, KB0};
+  const int64_t n_tiles = (Q + 63) / 64;
+  const TileRange tr = xcd_tiles(n_tiles, waves, wave);
+  for (int64_t tile = tr.first; tile < tr.end; tile += tr.stride) {
+    const int64_t q = tile * 64 + lane;
+    const MT* row = h + q * (int64_t)M.K0;
+    for (int k = 0; k < M.K0; k += 4) {
+      float v[4] = {0.f, 0.f, 0.f, 0.f};
+      if (q < Q)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[c] = to_f32(row[k + c]);
+      htile_put4<MT>(htile, KB0, lane, k, v);
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int t0 = 0; t0 < 4; t0 += NT) {
+      f32x4 out[NT];
+      mlp_forward_tiles<MT, H, NT>(M, W, htile, KB0, t0, lane, out);
+      store_rgb<MT, NT>(out, t0, tile * 64, Q, lane, rgb);
+    }
+    wave_lds_sync();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Residual assembly (rendering-equation RHS) and loss partials.
+// ---------------------------------------------------------------------------
+
+// GGX + Lambert sample weight f |n.wi| / pdf for unit n, wo, wi. The GGX
+// denominator (n.h)^2 (a^2 - 1) + 1 is evaluated as a^2 (n.h)^2 + |n x h|^2,
+// which avoids the cancellation near the specular peak.
+__device__ inline void bsdf_weight(const float n[3], const float wo[3], const float wi[3], const float alb[3],
+                                   float alpha, float F0, float pdf, float w[3]) {
+  const float ci = n[0] * wi[0] + n[1] * wi[1] + n[2] * wi[2];
+  const float co = n[0] * wo[0] + n[1] * wo[1] + n[2] * wo[2];
+  if (!(ci > 0.0f) || !(co > 0.0f)) {
+    w[0] = w[1] = w[2] = 0.0f;
+    return;
+  }
+  float h[3] = {wi[0] + wo[0], wi[1] + wo[1], wi[2] + wo[2]};
+  const float hl = sqrtf(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) h[a] /= hl;
+  const float nh = n[0] * h[0] + n[1] * h[1] + n[2] * h[2];
+  const float cx = n[1] * h[2] - n[2] * h[1], cy = n[2] * h[0] - n[0] * h[2], cz = n[0] * h[1] - n[1] * h[0];
+  const float a2 = alpha * alpha;
+  const float den = a2 * nh * nh + (cx * cx + cy * cy + cz * cz);
+  const float Dm = a2 / (3.14159265358979f * den * den);
+  const float g1i = 2.0f * ci / (ci + sqrtf(a2 + (1.0f - a2) * ci * ci));
+  const float g1o = 2.0f * co / (co + sqrtf(a2 + (1.0f - a2) * co * co));
+  const float vh = 1.0f - (wi[0] * h[0] + wi[1] * h[1] + wi[2] * h[2]);
+  const float vh2 = vh * vh;
+  const float F = F0 + (1.0f - F0) * (vh2 * vh2 * vh);
+  const float spec = Dm * g1i * g1o * F / (4.0f * ci * co);
+  const float sc = ci / pdf;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) w[c] = (alb[c] * (1.0f / 3.14159265358979f) + spec) * sc;
+}
+
+__device__ inline void load_unit(const float* p, float v[3]) {
+  v[0] = p[0];
+  v[1] = p[1];
+  v[2] = p[2];
+  const float l = sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  if (l > 0.0f) {
+    v[0] /= l;
+    v[1] /= l;
+    v[2] /= l;
+  }
+}
+
+// One thread per LHS point: T = Le + (1/N) sum_k w_k * L(x2_k), r = L - T;
+// per-block FP64 partial of sum r^2 (or (r / rho)^2).
+__global__ __launch_bounds__(256) void combine_kernel(const ResidualArgs A, const float* __restrict__ Lq,
+                                                      float* __restrict__ lhs_out, float* __restrict__ rhs_out,
+                                                      float* __restrict__ resid_out, double* __restrict__ partials) {
+  __shared__ double red[256];
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (b < A.B) {
+    float L[3] = {Lq[3 * b], Lq[3 * b + 1], Lq[3 * b + 2]};
+    float T[3];
+    if (A.target_override) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) T[c] = A.target_override[3 * b + c];
+    } else {
+      float n[3], wo[3], alb[3] = {A.albedo[3 * b], A.albedo[3 * b + 1], A.albedo[3 * b + 2]};
+      load_unit(A.n + 3 * b, n);
+      load_unit(A.wo + 3 * b, wo);
+      const float alpha = A.rough[b];
+      float s[3] = {0.f, 0.f, 0.f};
+      for (int k = 0; k < A.N; ++k) {
+        const int64_t bk = b * A.N + k;
+        float wi[3], w[3];
+        load_unit(A.wi + 3 * bk, wi);
+        bsdf_weight(n, wo, wi, alb, alpha, A.F0, A.pdf ? A.pdf[bk] : 1.0f, w);
+        const float* Lk = Lq + 3 * (A.B + bk);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) s[c] += w[c] * Lk[c];
+      }
+      const float invN = A.N > 0 ? 1.0f / (float)A.N : 0.0f;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) T[c] = A.Le[3 * b + c] + s[c] * invN;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float r = L[c] - T[c];
+      lhs_out[3 * b + c] = L[c];
+      rhs_out[3 * b + c] = T[c];
+      resid_out[3 * b + c] = r;
+      double rr = (double)r;
+      if (A.loss_kind == 1) {
+        const double rho = fmax((double)L[c] + (double)T[c], 0.0) + (double)A.eps;
+        rr /= rho;
+      }
+      acc += rr * rr;
+    }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+// Fixed-order sum of the block partials: loss = sum / (3B).
+__global__ __launch_bounds__(256) void loss_reduce_kernel(const double* __restrict__ partials, int n, int64_t B,
+                                                          double* __restrict__ loss) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += partials[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = B > 0 ? red[0] / (3.0 * (double)B) : 0.0;
+}
+
+template <class DT>
+__global__ __launch_bounds__(256) void cast_kernel(const float* __restrict__ src, DT* __restrict__ dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = from_f32<DT>(src[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+static int device_cus() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (cus <= 0) cus = 256;
+  }
+  return cus;
+}
+
+static int max_lds() {
+  static int lds = 0;
+  if (!lds) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (lds <= 0) lds = 65536;
+  }
+  return lds;
+}
+
+template <class TT, class HT, int C>
+static hipError_t launch_encode_t(const TreeArgs& T, const float* x, const float* d, int64_t B, void* h,
+                                  int32_t* idx, hipStream_t st) {
+  const int64_t blocks = (B + 255) / 256;
+  hipLaunchKernelGGL((encode_kernel<TT, HT, C>), dim3((unsigned)blocks), dim3(256), 0, st, T, x, d, B,
+                     reinterpret_cast<HT*>(h), idx);
+  return hipGetLastError();
+}
+
+template <class TT, int C>
+static hipError_t launch_encode_h(const TreeArgs& T, const float* x, const float* d, int64_t B, void* h,
+                                  oo_dtype hd, int32_t* idx, hipStream_t st) {
+  switch (hd) {
+    case OO_F32: return launch_encode_t<TT, float, C>(T, x, d, B, h, idx, st);
+    case OO_F16: return launch_encode_t<TT, f16, C>(T, x, d, B, h, idx, st);
+    default: return launch_encode_t<TT, bf16, C>(T, x, d, B, h, idx, st);
+  }
+}
+
+hipError_t launch_encode(const TreeArgs& T, oo_dtype td, const float* x, const float* d, int64_t B, void* h,
+                         oo_dtype hd, int32_t* idx, hipStream_t st) {
+  if (B == 0) return hipSuccess;
+  if (td == OO_F32)
+    return T.C == 4 ? launch_encode_h<float, 4>(T, x, d, B, h, hd, idx, st)
+                    : launch_encode_h<float, 8>(T, x, d, B, h, hd, idx, st);
+  if (td == OO_F16)
+    return T.C == 4 ? launch_encode_h<f16, 4>(T, x, d, B, h, hd, idx, st)
+                    : launch_encode_h<f16, 8>(T, x, d, B, h, hd, idx, st);
+  return T.C == 4 ? launch_encode_h<bf16, 4>(T, x, d, B, h, hd, idx, st)
+                  : launch_encode_h<bf16, 8>(T, x, d, B, h, hd, idx, st);
+}
+
+// Workgroup shape for the tile kernels: up to 8 waves, each with a 64-query
+// activation tile, plus the packed weights when they fit next to them.
+template <class MT>
+static void tile_launch_shape(const MlpArgs& M, int64_t Q, bool& wlds, int& waves, size_t& lds, int& grid) {
+  const int KB0 = (M.K0 + 31) / 32;
+  const size_t tile_bytes = (size_t)4 * KB0 * kWave * 8 * sizeof(MT);
+  const size_t wbytes = (size_t)packed_weight_elems<MT>(M.n_layers, M.K0, M.H) * sizeof(MT);
+  const size_t cap = (size_t)max_lds();
+  waves = 8;
+  wlds = true;
+  while (waves > 4 && wbytes + waves * tile_bytes > cap) --waves;
+  if (wlds && wbytes + waves * tile_bytes > cap) wlds = false;
+  if (!wlds) {
+    waves = 8;
+    while (waves > 1 && waves * tile_bytes > cap) --waves;
+  }
+  lds = (wlds ? wbytes : 0) + waves * tile_bytes;
+  const int64_t n_tiles = (Q + 63) / 64;
+  // LDS per CU on gfx950 is 160 KiB: one or two workgroups fit per CU.
+  const int per_cu = lds * 2 <= (size_t)160 * 1024 ? 2 : 1;
+  int64_t g = (int64_t)device_cus() * per_cu;
+  const int64_t need = (n_tiles + waves - 1) / waves;
+  if (g > need) g = need;
+  if (g >= 8) g -= g % 8;
+  grid = (int)(g > 0 ? g : 1);
+}
+
+template <class TT, class MT, int C, int H>
+static hipError_t launch_query_t(const TreeArgs& T, const MlpArgs& M, const QuerySrc& src, int64_t Q, float* rgb,
+                                 hipStream_t st) {
+  bool wlds;
+  int waves, grid;
+  size_t lds;
+  tile_launch_shape<MT>(M, Q, wlds, waves, lds, grid);
+  if (wlds) {
+    auto k = query_kernel<TT, MT, C, H, true>;
+    hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, st, T, M, src, Q, rgb);
+  } else {
+    auto k = query_kernel<TT, MT, C, H, false>;
+    hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, st, T, M, src, Q, rgb);
+  }
+  return hipGetLastError();
+}
+
+template <class TT, class MT, int C>
+static hipError_t launch_query_c(const TreeArgs& T, const MlpArgs& M, const QuerySrc& src, int64_t Q, float* rgb,
+                                 hipStream_t st) {
+  return M.H == 64 ? launch_query_t<TT, MT, C, 64>(T, M, src, Q, rgb, st)
+                   : launch_query_t<TT, MT, C, 128>(T, M, src, Q, rgb, st);
+}
+
+hipError_t launch_query(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, const QuerySrc& src,
+                        int64_t Q, float* rgb, hipStream_t st) {
+  if (Q == 0) return hipSuccess;
+  if (td == OO_F32)
+    return T.C == 4 ? launch_query_c<float, float, 4>(T, M, src, Q, rgb, st)
+                    : launch_query_c<float, float, 8>(T, M, src, Q, rgb, st);
+  if (td == OO_F16) return launch_query_c<f16, f16, 8>(T, M, src, Q, rgb, st);
+  return launch_query_c<bf16, bf16, 8>(T, M, src, Q, rgb, st);
+  (void)md;
+}
+
+template <class MT, int H>
+static hipError_t launch_mlp_t(const MlpArgs& M, const void* h, int64_t Q, float* rgb, hipStream_t st) {
+  bool wlds;
+  int waves, grid;
+  size_t lds;
+  tile_launch_shape<MT>(M, Q, wlds, waves, lds, grid);
+  if (wlds) {
+    auto k = mlp_kernel<MT, H, true>;
+    hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, st, M, reinterpret_cast<const MT*>(h), Q, rgb);
+  } else {
+    auto k = mlp_kernel<MT, H, false>;
+    hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, st, M, reinterpret_cast<const MT*>(h), Q, rgb);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp(const MlpArgs& M, oo_dtype md, const void* h, int64_t Q, float* rgb, hipStream_t st) {
+  if (Q == 0) return hipSuccess;
+  if (md == OO_F32) return M.H == 64 ? launch_mlp_t<float, 64>(M, h, Q, rgb, st) : launch_mlp_t<float, 128>(M, h, Q, rgb, st);
+  if (md == OO_F16) return M.H == 64 ? launch_mlp_t<f16, 64>(M, h, Q, rgb, st) : launch_mlp_t<f16, 128>(M, h, Q, rgb, st);
+  return M.H == 64 ? launch_mlp_t<bf16, 64>(M, h, Q, rgb, st) : launch_mlp_t<bf16, 128>(M, h, Q, rgb, st);
+}
+
+int combine_blocks(int64_t B) { return (int)((B + 255) / 256); }
+
+hipError_t launch_combine(const ResidualArgs& A, const float* Lq, float* lhs, float* rhs, float* resid,
+                          double* partials, double* loss, hipStream_t st) {
+  const int nb = combine_blocks(A.B);
+  if (nb > 0)
+    hipLaunchKernelGGL(combine_kernel, dim3(nb), dim3(256), 0, st, A, Lq, lhs, rhs, resid, partials);
+  hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(256), 0, st, partials, nb, A.B, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast(const float* src, void* dst, oo_dtype dt, int64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (dt == OO_F32)
+    hipLaunchKernelGGL(cast_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st, src, (float*)dst, n);
+  else if (dt == OO_F16)
+    hipLaunchKernelGGL(cast_kernel<f16>, dim3((unsigned)blocks), dim3(256), 0, st, src, (f16*)dst, n);
+  else
+    hipLaunchKernelGGL(cast_kernel<bf16>, dim3((unsigned)blocks), dim3(256), 0, st, src, (bf16*)dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace oo

@@ -1,0 +1,64 @@
+// Launchers shared between the C-ABI layer and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "octaoctree.h"
+#include "oo_device.h"
+
+namespace oo {
+
+// Residual inputs as the kernels read them.
+struct ResidualArgs {
+  int64_t B;
+  int32_t N;
+  const float *n, *wo, *albedo, *Le, *rough, *wi, *pdf, *target_override;
+  float F0;
+  int32_t loss_kind;
+  float eps;
+};
+
+struct GradArgs {
+  float* dfeat[kMaxLevels];
+};
+
+// Flat parameter layout of the dW/db partials: layer i's W block at
+// w_off[i] (n_out x n_in), its b block at b_off[i].
+struct ParamLayout {
+  int32_t n_layers;
+  int32_t n_in[kMaxLayers], n_out[kMaxLayers];
+  int64_t w_off[kMaxLayers], b_off[kMaxLayers];
+  int64_t P;
+};
+
+struct ReduceDst {
+  int32_t n_seg;
+  int64_t start[2 * kMaxLayers + 1];
+  float* dst[2 * kMaxLayers];
+};
+
+hipError_t launch_encode(const TreeArgs& T, oo_dtype td, const float* x, const float* d, int64_t B, void* h,
+                         oo_dtype hd, int32_t* idx, hipStream_t st);
+hipError_t launch_mlp(const MlpArgs& M, oo_dtype md, const void* h, int64_t Q, float* rgb, hipStream_t st);
+hipError_t launch_query(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, const QuerySrc& src,
+                        int64_t Q, float* rgb, hipStream_t st);
+int combine_blocks(int64_t B);
+hipError_t launch_combine(const ResidualArgs& A, const float* Lq, float* lhs, float* rhs, float* resid,
+                          double* partials, double* loss, hipStream_t st);
+hipError_t launch_cast(const float* src, void* dst, oo_dtype dt, int64_t n, hipStream_t st);
+
+// Backward.
+int bwd_grid(const MlpArgs& M, int64_t Q);
+size_t bwd_lds_bytes(const MlpArgs& M, oo_dtype md, int L);
+hipError_t launch_seeds(const ResidualArgs& A, const float* resid, const float* rhs, const double* grad_loss,
+                        int full, float* seeds, hipStream_t st);
+hipError_t launch_transpose_weights(const MlpArgs& M, oo_dtype md, void* const* Wt, hipStream_t st);
+hipError_t launch_bwd(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, void* const* Wt,
+                      const QuerySrc& src, int64_t Q, const float* seeds, float post_scale, const GradArgs& G,
+                      const ParamLayout& PL, float* partials, int grid, hipStream_t st);
+hipError_t launch_dw_reduce(const float* partials, int grid, const ParamLayout& PL, const ReduceDst& D, float scale,
+                            hipStream_t st);
+
+}  // namespace oo

@@ -1,0 +1,92 @@
+"""Shared setup for the GPU parity tests: seeded workloads built once per
+session, each with the library's tree (checked bit-identical to the
+oracle's) and the FP32 masters both sides read."""
+import dataclasses
+import functools
+import math
+
+import numpy as np
+import torch
+
+import oracle
+from paper_2606_08469_amd import binding, synth
+
+
+def rel_l2(got, want):
+    got = np.asarray(got, np.float64).ravel()
+    want = np.asarray(want, np.float64).ravel()
+    den = np.linalg.norm(want)
+    return float(np.linalg.norm(got - want) / (den if den > 0 else 1.0))
+
+
+def cosine(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300))
+
+
+def report(name, **kv):
+    print(f"[parity] {name}: " + ", ".join(f"{k}={v:.3e}" if isinstance(v, float) else f"{k}={v}" for k, v in kv.items()),
+          flush=True)
+
+
+@functools.lru_cache(maxsize=None)
+def tree_for(tree_cfg: int):
+    """(samples, nodes, level_offset) of a config's tree, library-built."""
+    cfg = synth.CONFIGS[tree_cfg]
+    s = synth.tree_samples(cfg)
+    nodes, lo = binding.build_octree(s, cfg.D, cfg.tau)
+    return s, nodes, lo
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_tree_for(tree_cfg: int):
+    cfg = synth.CONFIGS[tree_cfg]
+    return oracle.build_octree(synth.tree_samples(cfg), cfg.D, cfg.tau)
+
+
+@functools.lru_cache(maxsize=None)
+def params_for(ci: int):
+    cfg = synth.CONFIGS[ci]
+    _, nodes, lo = tree_for(cfg.tree_cfg)
+    feat = synth.init_tables(cfg, np.diff(lo))
+    W, b = synth.init_mlp(cfg)
+    return feat, W, b
+
+
+def oracle_models(ci: int):
+    cfg = synth.CONFIGS[ci]
+    _, nodes, lo = tree_for(cfg.tree_cfg)
+    feat, W, b = params_for(ci)
+    return oracle.Tree(nodes, lo, list(cfg.res), cfg.C, feat), oracle.MLP(W, b)
+
+
+def gpu_models(ci: int, dtype=torch.float32):
+    cfg = synth.CONFIGS[ci]
+    _, nodes, lo = tree_for(cfg.tree_cfg)
+    feat, W, b = params_for(ci)
+    return binding.OctaOctree(nodes, lo, list(cfg.res), cfg.C, feat, W, b, dtype=dtype)
+
+
+@functools.lru_cache(maxsize=None)
+def render_queries(ci: int):
+    return synth.render_queries(synth.CONFIGS[ci])
+
+
+@functools.lru_cache(maxsize=None)
+def train_batch(ci: int, B: int | None = None):
+    cfg = synth.CONFIGS[ci]
+    if B is not None:
+        cfg = dataclasses.replace(cfg, B=B)
+    return synth.train_batch(cfg)
+
+
+def subset_batch(batch: dict, idx) -> dict:
+    out = {}
+    for k, v in batch.items():
+        out[k] = v[idx] if isinstance(v, np.ndarray) else v
+    return out
+
+
+def to_np(t):
+    return t.detach().float().cpu().numpy() if t.dtype != torch.float64 else t.detach().cpu().numpy()

@@ -1,0 +1,136 @@
+"""Host-side checks of liboctaoctree (no GPU needed): every symbol declared in
+include/octaoctree.h is exported, the host octree builder is bit-identical to
+the oracle's independent builder, and argument validation rejects bad input
+before any device work."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_08469_amd import binding, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2606_08469_amd import build as pbuild
+        pbuild.build()
+    return binding.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    hdr = open(os.path.join(ROOT, "include", "octaoctree.h")).read()
+    names = set(re.findall(r"^\s*(?:int|const char\*)\s+(oo_\w+)\s*\(", hdr, re.M))
+    assert len(names) == 9, names
+    for n in sorted(names):
+        assert hasattr(L, n), n
+
+
+@pytest.mark.parametrize("D,tau,n,seed", [(0, 4, 10, 0), (1, 2, 50, 1), (4, 32, 20000, 2), (6, 3, 3000, 3),
+                                          (10, 8, 5000, 4), (15, 1, 300, 5)])
+def test_builder_matches_oracle(L, D, tau, n, seed):
+    g = np.random.default_rng(seed)
+    x = (g.uniform(0, 1, (n, 3)) ** 2).astype(np.float32)
+    x[: n // 10] = g.choice([0.0, 0.5, 1.0, -0.25, 1.5], (n // 10, 3))
+    nodes, lo = binding.build_octree(x, D, tau)
+    onodes, olo = oracle.build_octree(x, D, tau)
+    np.testing.assert_array_equal(lo, olo)
+    np.testing.assert_array_equal(nodes, onodes)
+
+
+def test_builder_matches_oracle_config1(L):
+    cfg = synth.CONFIGS[1]
+    s = synth.tree_samples(cfg)
+    nodes, lo = binding.build_octree(s, cfg.D, cfg.tau)
+    onodes, olo = oracle.build_octree(s, cfg.D, cfg.tau)
+    np.testing.assert_array_equal(nodes, onodes)
+    np.testing.assert_array_equal(lo, olo)
+
+
+def test_builder_size_query_and_capacity(L):
+    x = np.random.default_rng(0).uniform(0, 1, (500, 3)).astype(np.float32)
+    lo = np.zeros(5, np.int64)
+    nn = np.zeros(1, np.int64)
+    assert L.oo_build_octree(x.ctypes.data, 500, 3, 4, None, 0, lo.ctypes.data, nn.ctypes.data) == 0
+    need = int(nn[0])
+    small = np.zeros(need - 1, np.uint32)
+    rc = L.oo_build_octree(x.ctypes.data, 500, 3, 4, small.ctypes.data, need - 1, lo.ctypes.data, nn.ctypes.data)
+    assert rc == -2 and int(nn[0]) == need and b"capacity" in L.oo_last_error()
+    assert L.oo_build_octree(x.ctypes.data, 500, -1, 4, None, 0, lo.ctypes.data, nn.ctypes.data) == -1
+    assert L.oo_build_octree(x.ctypes.data, 500, 16, 4, None, 0, lo.ctypes.data, nn.ctypes.data) == -1
+
+
+def _tree(n_levels=3, C_=8, res=(4, 4, 2), dtype=binding.F16):
+    t = binding._Tree()
+    t.n_levels, t.C = n_levels, C_
+    for l, r in enumerate(res):
+        t.res[l] = r
+    for l in range(n_levels + 1):
+        t.level_offset[l] = min(l, 1) + max(0, l - 1) * 2
+    t.nodes = 0x1000
+    t.feat_dtype = dtype
+    for l in range(n_levels):
+        t.feat[l] = 0x10000 * (l + 1)
+    return t
+
+
+def _mlp(K0=24, H=64, n_layers=3, dtype=binding.F16):
+    m = binding._MLP()
+    m.n_layers = n_layers
+    m.dims[0] = K0
+    for i in range(1, n_layers):
+        m.dims[i] = H
+    m.dims[n_layers] = 3
+    m.dtype = dtype
+    for i in range(n_layers):
+        m.W[i] = 0x2000 * (i + 1)
+        m.b[i] = 0x3000 * (i + 1)
+    return m
+
+
+def test_validation_errors(L):
+    t, m = _tree(), _mlp()
+    stream = None
+    x = C.c_void_p(0x4000)
+    # B = 0 is a no-op
+    assert L.oo_query_fwd(C.byref(t), C.byref(m), x, x, 0, x, stream) == 0
+    bad = _tree()
+    bad.C = 5
+    assert L.oo_query_fwd(C.byref(bad), C.byref(m), x, x, 16, x, stream) == -1
+    bad = _tree()
+    bad.res[1] = 3
+    assert L.oo_query_fwd(C.byref(bad), C.byref(m), x, x, 16, x, stream) == -1
+    bad = _tree()
+    bad.feat[1] = 0x10008  # not 16-byte aligned
+    assert L.oo_query_fwd(C.byref(bad), C.byref(m), x, x, 16, x, stream) == -1
+    bad = _tree()
+    bad.n_levels = 0
+    assert L.oo_encode_query(C.byref(bad), x, x, 4, x, 0, None, stream) == -1
+    assert L.oo_query_fwd(C.byref(t), C.byref(_mlp(K0=20)), x, x, 16, x, stream) == -1     # dims[0] != L*C
+    assert L.oo_query_fwd(C.byref(t), C.byref(_mlp(H=96)), x, x, 16, x, stream) == -4      # width unsupported
+    assert L.oo_query_fwd(C.byref(t), C.byref(_mlp(H=128, n_layers=4)), x, x, 16, x, stream) == -4
+    assert L.oo_query_fwd(C.byref(t), C.byref(_mlp(dtype=binding.BF16)), x, x, 16, x, stream) == -4  # dtype pair
+    assert L.oo_query_fwd(C.byref(t), C.byref(m), x, x, -1, x, stream) == -1
+    assert L.oo_cast_params(x, x, 7, 4, stream) == -1
+    assert L.oo_cast_params(x, x, 1, -2, stream) == -1
+    assert b"" != L.oo_last_error()
+
+
+def test_residual_batch_validation(L):
+    t, m = _tree(), _mlp()
+    b = binding._Batch()
+    b.B, b.N = 8, 2
+    b.x = b.dir = b.Le = 0x5000
+    n = C.c_size_t(0)
+    assert L.oo_residual_workspace_bytes(C.byref(t), C.byref(m), C.byref(b), C.byref(n)) == -1  # x2 etc missing
+    b.n = b.wo = b.albedo = b.rough = b.x2 = b.dir2 = b.wi = 0x5000
+    b.loss_kind = 3
+    assert L.oo_residual_workspace_bytes(C.byref(t), C.byref(m), C.byref(b), C.byref(n)) == -1
+    b.loss_kind = 0
+    b.N = -1
+    assert L.oo_residual_workspace_bytes(C.byref(t), C.byref(m), C.byref(b), C.byref(n)) == -1
