@@ -1,0 +1,287 @@
+"""Throughput of the OctaOctree neural-radiosity hot path on one MI355X.
+
+One step = one neural-radiosity training step over one batch of synthetic
+input, every stage of the hot path included: FP32 -> FP16 refresh of the
+working tables and weights, zeroing of the FP32 gradients, the residual
+forward (octree descent, octahedral bilinear fetch per level, decoder MLP for
+the B LHS and B*N secondary queries, GGX-weighted Monte-Carlo target, FP64
+loss) and the residual backward (recomputed LHS encoding, decoder backward on
+matrix cores, FP32 atomic scatter into the feature tables, dW/db reduction).
+
+Workload (the largest configuration, all stages): 2^20 LHS points x (1 + 8)
+queries on a depth-10 octree (~0.98M nodes), 11 levels x 8 FP16 channels,
+decoder 88-128-128-3 on FP16 matrix cores with FP32 accumulation. The same
+batch also runs on the FP32 plain path, and the render forwards at 1280x720
+(FP32 unfused and FP16 fused) and 1024x1024 (BF16 fused) are timed alongside.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the FP32 step and render forwards")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 1 GiB device-to-device copy first (counter calibration under rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the hot path has no multi-GPU component in this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2606_08469_amd import binding, synth
+
+    if not os.path.exists(binding.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    if args.calib_copy:
+        # A plain copy of known size: its FETCH_SIZE / WRITE_SIZE under the
+        # profiler give the scale between counter readings and bytes moved.
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
+
+    # ---------------- workload --------------------------------------------
+    cfg = synth.CONFIGS[5]
+    t0 = time.time()
+    samples = synth.tree_samples(cfg)
+    nodes, lo = binding.build_octree(samples, cfg.D, cfg.tau)
+    counts = np.diff(lo)
+    feat = synth.init_tables(cfg, counts)
+    W, b = synth.init_mlp(cfg)
+    batch_np = synth.train_batch(cfg)
+    log(f"workload built in {time.time() - t0:.1f}s: nodes={len(nodes)} levels={counts.tolist()}")
+    B, N = cfg.B, cfg.N
+    Q = B * (1 + N)
+
+    mixed = binding.OctaOctree(nodes, lo, list(cfg.res), cfg.C, feat, W, b, dtype=torch.float16)
+    batch = binding.device_batch(batch_np)
+    grads = {
+        "dfeat": [torch.zeros(f.shape, dtype=torch.float32, device=dev) for f in mixed.feat],
+        "dW": [torch.zeros(w.shape, dtype=torch.float32, device=dev) for w in mixed.W],
+        "db": [torch.zeros(v.shape, dtype=torch.float32, device=dev) for v in mixed.b],
+    }
+    ws = mixed.workspace(batch)
+    outs = tuple(torch.empty((B, 3), dtype=torch.float32, device=dev) for _ in range(3)) + (
+        torch.empty((), dtype=torch.float64, device=dev),)
+    gl = torch.ones((), dtype=torch.float64, device=dev)
+
+    def step(model, ev=None):
+        model.refresh()
+        for g in grads["dfeat"] + grads["dW"] + grads["db"]:
+            g.zero_()
+        if ev:
+            ev[0].record()
+        lhs, rhs, res, loss = binding.residual_fwd(model.tree, model.mlp, batch, ws, feat=model.work_feat,
+                                                   W=model.work_W, outs=outs)
+        if ev:
+            ev[1].record()
+        binding.residual_bwd(model.tree, model.mlp, batch, res, rhs, gl, grads["dfeat"], grads["dW"], grads["db"],
+                             ws, feat=model.work_feat, W=model.work_W)
+        if ev:
+            ev[2].record()
+        return loss
+
+    def timed(model, steps, warmup):
+        for _ in range(warmup):
+            step(model)
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for i in range(steps):
+            step(model, evs[i])
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t) / steps
+        fwd = [e[0].elapsed_time(e[1]) for e in evs]
+        bwd = [e[1].elapsed_time(e[2]) for e in evs]
+        return wall * 1e3, float(np.mean(fwd)), float(np.mean(bwd))
+
+    log("timing mixed step")
+    ms, fwd_ms, bwd_ms = timed(mixed, args.steps, args.warmup)
+    loss_mixed = float(outs[3].item())
+    log(f"mixed: {ms:.3f} ms/step (fwd {fwd_ms:.3f} ms, bwd {bwd_ms:.3f} ms)")
+
+    # ---------------- algorithmic bytes / FLOPs ----------------------------
+    # Levels present per query: the descent stops at the first missing child.
+    xq = torch.cat([batch["x"], batch["x2"].reshape(-1, 3)])
+    dq = torch.cat([batch["dir"], batch["dir2"].reshape(-1, 3)])
+    _, idx = binding.encode_query(mixed.tree, xq, dq, torch.float16, feat=mixed.work_feat)
+    present = (idx >= 0).sum(1).to(torch.float64)
+    lv_all = float(present.sum().item())
+    lv_lhs = float(present[:B].sum().item())
+    del xq, dq, idx, present
+    C, s16 = cfg.C, 2
+    H0, H = cfg.mlp[0], cfg.mlp[1]
+    mlp_flop = 2 * (H0 * H + (len(cfg.mlp) - 3) * H * H + H * 3)
+    # forward: per query, present levels x (4 taps x C x 2 B + 4 B node word),
+    # 24 B of x and dir in, 12 B of radiance out; per point the combine reads
+    # 76 B of point inputs and 40 B per secondary sample (counted in fwd).
+    fwd_bytes = lv_all * (4 * C * s16 + 4) + Q * (24 + 12)
+    fwd_bytes_combine = B * (76 + 36) + B * N * (40 + 12)
+    # backward: recomputed LHS gather, FP32 atomics (4 B each) per tap and
+    # channel, 12 B seed per point, 24 B x and dir.
+    bwd_bytes = lv_lhs * (4 * C * s16 + 4 + 4 * C * 4) + B * (24 + 12)
+    bwd_flop = B * 3 * mlp_flop
+    fwd_flop = Q * mlp_flop
+
+    # ---------------- FP32 plain step and render forwards -------------------
+    extra = {}
+    if not args.no_extra:
+        fp32 = binding.OctaOctree(nodes, lo, list(cfg.res), cfg.C, feat, W, b, dtype=torch.float32)
+        log("timing FP32 plain step")
+        ms32, f32, b32 = timed(fp32, max(3, args.steps // 4), 2)
+        loss32 = float(outs[3].item())
+        extra["fp32_plain_step"] = {"ms_per_step": round(ms32, 4), "fwd_ms": round(f32, 4), "bwd_ms": round(b32, 4),
+                                    "value": round(Q / (ms32 * 1e-3) / 1e6, 2), "unit": "Mqueries/s"}
+        extra["speedup_mixed_vs_fp32"] = round(ms32 / ms, 3)
+        extra["loss_mixed_vs_fp32_rel"] = abs(loss_mixed - loss32) / abs(loss32)
+        del fp32
+        torch.cuda.empty_cache()
+        extra["render"] = render_bench(torch, binding, synth, args)
+
+    # ---------------- CPU baseline (oracle) --------------------------------
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(batch_np, nodes, lo, cfg, feat, W, b)
+
+    value = Q / (ms * 1e-3) / 1e6
+    achieved = fwd_bytes / (fwd_ms * 1e-3) / 1e9
+    line = {
+        "metric": "Mqueries/s encode+MLP fwd and fwd+bwd, mixed vs FP32 at <=1e-2 err; % HBM/MFMA peak",
+        "value": round(value, 2),
+        "unit": "Mqueries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16",
+        "data": "synthetic",
+        "config": {
+            "workload": "neural-radiosity training step: 2^20 LHS points x (1+8) queries, fwd+bwd, "
+                        "depth-10 octree (%d nodes), 11 levels x 8 FP16 channels, MLP 88-128-128-3 "
+                        "FP16 MFMA, FP32 atomics" % len(nodes),
+            "queries_per_step": Q, "lhs_points_per_step": B,
+            "lhs_points_per_s_M": round(B / (ms * 1e-3) / 1e6, 3),
+            "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4),
+        },
+        "roofline": {
+            "kernel": "residual forward (fused encode+decode query kernel over B(1+N) queries, plus the "
+                      "residual assembly)",
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+            "frac": round(achieved / 8000.0, 4), "traffic": None,
+            "algorithmic_bytes_per_launch": int(fwd_bytes + fwd_bytes_combine),
+            "mfma_frac_fwd": round(fwd_flop / (fwd_ms * 1e-3) / 2.5e15, 4),
+            "bwd": {"algorithmic_bytes": int(bwd_bytes), "achieved_GBps": round(bwd_bytes / (bwd_ms * 1e-3) / 1e9, 1),
+                    "mfma_frac": round(bwd_flop / (bwd_ms * 1e-3) / 2.5e15, 4)},
+        },
+        "cpu_baseline": cpu,
+    }
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
+def render_bench(torch, binding, synth, args):
+    """Render-query forwards (one query per pixel) on the FP32 plain path
+    (encode to memory + decoder kernel) and the 16-bit fused path."""
+    out = {}
+    reps = max(5, args.steps)
+    for ci, dtypes in ((2, (torch.float32, torch.float16)), (4, (torch.float32, torch.bfloat16))):
+        cfg = synth.CONFIGS[ci]
+        s = synth.tree_samples(cfg)
+        nodes, lo = binding.build_octree(s, cfg.D, cfg.tau)
+        feat = synth.init_tables(cfg, np.diff(lo))
+        W, b = synth.init_mlp(cfg)
+        x, d = synth.render_queries(cfg)
+        xt = torch.from_numpy(x).cuda()
+        dt = torch.from_numpy(d).cuda()
+        res = {}
+        ref = None
+        for dtype in dtypes:
+            m = binding.OctaOctree(nodes, lo, list(cfg.res), cfg.C, feat, W, b, dtype=dtype)
+            if dtype == torch.float32:
+                def run():
+                    h, _ = binding.encode_query(m.tree, xt, dt, torch.float32, with_idx=False)
+                    return binding.mlp_fwd(m.mlp, h)
+                name = "fp32_plain_unfused"
+            else:
+                run = lambda: m(xt, dt)
+                name = f"{str(dtype).split('.')[-1]}_fused"
+            for _ in range(3):
+                out_ = run()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                out_ = run()
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) / reps
+            if ref is None:
+                ref = out_.clone()
+            err = float(((out_ - ref).norm() / ref.norm()).item())
+            res[name] = {"ms": round(t, 4), "Mqueries_s": round(len(x) / (t * 1e-3) / 1e6, 1),
+                         "rel_l2_vs_fp32": err}
+            log(f"render cfg{ci} {name}: {t:.4f} ms, {len(x) / (t * 1e-3) / 1e6:.0f} Mq/s, err {err:.2e}")
+            del m
+        out[f"cfg{ci}_{cfg.width}x{cfg.height}"] = res
+        torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(batch_np, nodes, lo, cfg, feat, W, b):
+    """The FP64 oracle as it stands, on a bounded sample of the same batch:
+    the first S LHS points with their N secondary queries, forward (queries
+    spread over all host threads) plus backward (single thread)."""
+    import oracle
+    if not os.path.exists(oracle.LIB_PATH):
+        from oracle import build as obuild
+        obuild.build()
+    S = 4096
+    sb = {k: (v[:S] if isinstance(v, np.ndarray) else v) for k, v in batch_np.items()}
+    ot, om = oracle.Tree(nodes, lo, list(cfg.res), cfg.C, feat), oracle.MLP(W, b)
+    nt = os.cpu_count() or 1
+    t = time.perf_counter()
+    oracle.residual_fwd(ot, om, sb, nthreads=nt)
+    oracle.residual_bwd(ot, om, sb, nthreads=nt)
+    dt = time.perf_counter() - t
+    q = S * (1 + cfg.N)
+    log(f"oracle: {dt:.2f}s for {S} points")
+    return {"value": round(q / dt / 1e6, 6), "unit": "Mqueries/s", "cores": nt, "kind": "oracle",
+            "sample": f"first {S} of 2^20 LHS points with their {cfg.N} secondary queries each "
+                      f"({q} queries), residual fwd (query evaluation on {nt} threads) + bwd (1 thread, "
+                      f"which recomputes the forward), FP64; {dt:.2f} s"}
+
+
+if __name__ == "__main__":
+    main()

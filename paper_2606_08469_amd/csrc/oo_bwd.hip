@@ -208,6 +208,10 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
   const int64_t n_tiles = (Q + kQW - 1) / kQW;
   for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const int64_t qbase = tile * kQW;
+    // Lane-derived LDS addresses are loop-invariant; recompute them per tile
+    // rather than holding a hundred of them in registers across the loop.
+    const int tid = launder_lane(threadIdx.x), lane = tid & 63, g = lane >> 4, r16 = lane & 15;
+    const int col = 16 * nt + r16;
     // ---- 1. encode: kLanesPerQuery lanes per query, one level each -----
     {
       const int ql = tid / kLanesPerQuery, part = tid % kLanesPerQuery;
@@ -290,18 +294,15 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
       }
       store_tq<MT, 1>(dT, so, 0, 1, 3, nt, lane, false);
     }
-    for (int i = NL - 1; i >= 0; --i) {
+    // One layer of the backward: dW_i over the workgroup's 64 queries into
+    // this wave's accumulators accs, db_i, then delta_{i-1} (or dh for i = 0).
+    // Each call site gets its own accumulator array, and the lane index is
+    // re-laundered so addresses are not kept live from one layer to the next.
+    auto step = [&](auto& accs, int i) {
+      const int ln = launder_lane(lane), gs = ln >> 4, cs = 16 * nt + (ln & 15);
       const int n_out = i == NL - 1 ? 3 : H, n_in = i == 0 ? K0 : H;
       __syncthreads();  // delta_i and the activations are complete
-      if (i == NL - 1)
-        dw_layer<MT, UO>(accO, dT, act(i), n_out, n_in, wave, lane);
-      else if (i == 0)
-        dw_layer<MT, U0>(acc0, dT, act0, n_out, n_in, wave, lane);
-      else {
-#pragma unroll
-        for (int hh = 0; hh < NHH; ++hh)
-          if (hh == i - 1) dw_layer<MT, UH>(accH[hh], dT, act(i), n_out, n_in, wave, lane);
-      }
+      dw_layer<MT>(accs, dT, act(i), n_out, n_in, wave, ln);
       if (tid < n_out) {
         float sum = 0.0f;
 #pragma unroll
@@ -322,9 +323,9 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
 #pragma unroll
         for (int mi = 0; mi < MH2; ++mi) dacc[mi] = z4;
         for (int kb = 0; kb < KBo; ++kb) {
-          const frag b = tq_bfrag<MT>(dT, kb, g, col, n_out);
+          const frag b = tq_bfrag<MT>(dT, kb, gs, cs, n_out);
 #pragma unroll
-          for (int mi = 0; mi < MH2; ++mi) dacc[mi] = mma(wfrag_global<MT>(Wt, H, n_out, ldt, mh * MH2 + mi, kb, lane), b, dacc[mi]);
+          for (int mi = 0; mi < MH2; ++mi) dacc[mi] = mma(wfrag_global<MT>(Wt, H, n_out, ldt, mh * MH2 + mi, kb, ln), b, dacc[mi]);
         }
         // ReLU'(z) = 1 where the layer-i input activation is positive
         const MT* a = act(i);
@@ -332,11 +333,11 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
         for (int mi = 0; mi < MH2; ++mi)
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const int n = 16 * (mh * MH2 + mi) + 4 * g + j;
-            if (!(to_f32(a[tq_index(n, col)]) > 0.0f)) dacc[mi][j] = 0.0f;
+            const int n = 16 * (mh * MH2 + mi) + 4 * gs + j;
+            if (!(to_f32(a[tq_index(n, cs)]) > 0.0f)) dacc[mi][j] = 0.0f;
           }
         __syncthreads();  // every wave has read delta_i
-        store_tq<MT, MH2>(dT, dacc, mh * MH2, MH, H, nt, lane, false);
+        store_tq<MT, MH2>(dT, dacc, mh * MH2, MH, H, nt, ln, false);
       } else {
         constexpr int MK2 = 8 / kMSplit;  // up to 8 row tiles of dh (K0 <= 128)
         const int MK = (K0 + 15) / 16;
@@ -344,10 +345,10 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
 #pragma unroll
         for (int mi = 0; mi < MK2; ++mi) dacc[mi] = z4;
         for (int kb = 0; kb < KBo; ++kb) {
-          const frag b = tq_bfrag<MT>(dT, kb, g, col, n_out);
+          const frag b = tq_bfrag<MT>(dT, kb, gs, cs, n_out);
 #pragma unroll
           for (int mi = 0; mi < MK2; ++mi)
-            if (mh * MK2 + mi < MK) dacc[mi] = mma(wfrag_global<MT>(Wt, K0, n_out, ldt, mh * MK2 + mi, kb, lane), b, dacc[mi]);
+            if (mh * MK2 + mi < MK) dacc[mi] = mma(wfrag_global<MT>(Wt, K0, n_out, ldt, mh * MK2 + mi, kb, ln), b, dacc[mi]);
         }
         __syncthreads();  // dh may alias the h tile; all reads of it are done
 #pragma unroll
@@ -355,11 +356,16 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
           if (mh * MK2 + mi < MK)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-              const int k = 16 * (mh * MK2 + mi) + 4 * g + j;
-              if (k < K0) dh[col * R0 + k] = dacc[mi][j];
+              const int k = 16 * (mh * MK2 + mi) + 4 * gs + j;
+              if (k < K0) dh[cs * R0 + k] = dacc[mi][j];
             }
       }
-    }
+    };
+    step(accO, NL - 1);
+#pragma unroll
+    for (int hh = NHH - 1; hh >= 0; --hh)
+      if (hh + 1 < NL - 1) step(accH[hh], hh + 1);
+    step(acc0, 0);
     __syncthreads();
 
     // ---- 4. scatter into the feature gradient tables ---------------------

@@ -371,6 +371,13 @@ __device__ inline P* launder_ptr(P* p) {
   return p;
 }
 
+// Same for a lane-varying integer: values derived from it are recomputed
+// where they are used instead of being hoisted and held in registers.
+__device__ inline int launder_lane(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 // Orders this wave's LDS writes before its following LDS reads.
 __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

@@ -311,8 +311,19 @@ def test_fd_config3_fp32():
         adj.append(float(p.grad.view(-1)[flat].item()))
     adj, fd = np.array(adj), np.array(fd)
     err = rel_l2(adj, fd)
-    per = np.abs(adj - fd) / np.maximum(np.abs(fd), 1e-3 * np.abs(fd).max())
-    report("fd cfg3", rel_l2=err, worst_entry=float(per.max()), n=len(adj))
+    kinds = np.array([k for k, _, _ in picks])
+    for kind in ("feat", "W"):
+        sel = kinds == kind
+        e = rel_l2(adj[sel], fd[sel])
+        report(f"fd cfg3 {kind}", rel_l2=e, n=int(sel.sum()))
+    # per entry: error relative to the entry, floored at the group's RMS so
+    # that near-zero gradients are judged on the FD noise scale
+    rms = {k: float(np.sqrt(np.mean(fd[kinds == k] ** 2))) for k in ("feat", "W")}
+    per = np.array([abs(a - f) / max(abs(f), rms[k]) for a, f, k in zip(adj, fd, kinds)])
+    worst = np.argsort(per)[::-1][:8]
+    for i in worst:
+        print(f"[fd] {picks[i]} adj={adj[i]:.6e} fd={fd[i]:.6e} rel={per[i]:.2e}", flush=True)
+    report("fd cfg3", rel_l2=err, worst_entry=float(per.max()), p95=float(np.quantile(per, 0.95)), n=len(adj))
     assert err <= 5e-3
     assert np.quantile(per, 0.95) <= 1e-2
 
