@@ -65,9 +65,10 @@ int check_tree(const oo_tree* t, TreeArgs& A) {
   }
   if (t->level_offset[t->n_levels] > (int64_t(1) << 24))
     return fail(OO_EUNSUPPORTED, "more than 2^24 nodes");
-  // Levels without nodes are never read with a non-zero weight; point them at
-  // level 0 so that the kernels' predicated loads stay in bounds.
-  for (int l = 0; l < t->n_levels; ++l)
+  // Levels without nodes, and the unused slots past n_levels, are never read
+  // with a non-zero weight; point them at level 0 so that the kernels'
+  // predicated loads (texel 0) stay in bounds.
+  for (int l = 0; l < OO_MAX_LEVELS; ++l)
     if (!A.feat[l]) A.feat[l] = A.feat[0];
   return OO_OK;
 }

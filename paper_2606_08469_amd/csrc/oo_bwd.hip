@@ -234,16 +234,24 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
       }
       wave_lds_sync();  // the lanes of a query are in one wave
       const float s = qst[2 * ql], t = qst[2 * ql + 1];
+      // this lane's levels part, part + 4, ...: all their gathers in flight
+      constexpr int G = kMaxLevels / kLanesPerQuery;
+      int lidx[G];
 #pragma unroll
-      for (int l0 = 0; l0 < kMaxLevels; l0 += kLanesPerQuery) {
-        const int l = l0 + part;
+      for (int gi = 0; gi < G; ++gi) {
+        const int l = part + kLanesPerQuery * gi;
+        lidx[gi] = l < L ? qidx[ql * L + l] : -1;
+      }
+      float h[G][C];
+      gather_levels<TT, C, G, kLanesPerQuery>(T, part, lidx, s, t, h);
+#pragma unroll
+      for (int gi = 0; gi < G; ++gi) {
+        const int l = part + kLanesPerQuery * gi;
         if (l < L) {
-          float h[C];
-          gather_level<TT, C>(T, l, qidx[ql * L + l], s, t, h);
 #pragma unroll
-          for (int c = 0; c < C; c += 4) htile_put4<MT>(htile, KB0, ql, l * C + c, &h[c]);
+          for (int c = 0; c < C; c += 4) htile_put4<MT>(htile, KB0, ql, l * C + c, &h[gi][c]);
 #pragma unroll
-          for (int c = 0; c < C; ++c) act0[tq_index(l * C + c, ql)] = from_f32<MT>(h[c]);
+          for (int c = 0; c < C; ++c) act0[tq_index(l * C + c, ql)] = from_f32<MT>(h[gi][c]);
         }
       }
     }

@@ -215,8 +215,7 @@ struct Texel<bf16, C> : Texel16<bf16, C> {};
 
 // Per-level feature h_l of one query: the 4 taps of the level-l map of node
 // idx (zeros when idx < 0). Loads are issued branch-free (a missing level
-// reads texel 0 of the level table with weight 0) so that all levels' loads
-// can be in flight together.
+// reads texel 0 of the level table with weight 0).
 template <class TT, int C>
 __device__ inline void gather_level(const TreeArgs& T, int l, int idx, float s, float t, float* h) {
   const int R = T.res[l];
@@ -236,6 +235,40 @@ __device__ inline void gather_level(const TreeArgs& T, int l, int idx, float s, 
   for (int c = 0; c < C; ++c) h[c] = 0.0f;
 #pragma unroll
   for (int k = 0; k < 4; ++k) Texel<TT, C>::acc(r[k], ok ? w[k] : 0.0f, h);
+}
+
+// Levels l0, l0 + STRIDE, ... (G of them) of one query in one straight-line
+// block: all 4G texel loads are issued before any is consumed, so a lane
+// keeps 4G gathers in flight. Levels at or past T.L (and missing nodes) read
+// texel 0 of a valid table with weight 0. idx[gi] is the node index of the
+// gi-th of those levels.
+template <class TT, int C, int G, int STRIDE = 1>
+__device__ inline void gather_levels(const TreeArgs& T, int l0, const int* idx, float s, float t, float (*h)[C]) {
+  typename Texel<TT, C>::raw r[G][4];
+  float w[G][4];
+#pragma unroll
+  for (int gi = 0; gi < G; ++gi) {
+    const int l = l0 + STRIDE * gi;
+    const int R = T.res[l];
+    int tx[4];
+    taps(s, t, R, tx, w[gi]);
+    const bool ok = l < T.L && idx[gi] >= 0;
+    const int64_t node = ok ? (int64_t)idx[gi] - T.off[l] : 0;
+    const TT* base = reinterpret_cast<const TT*>(T.feat[l]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t e = ok ? ((node * R * R) + tx[k]) * C : 0;
+      Texel<TT, C>::load(base + e, r[gi][k]);
+      if (!ok) w[gi][k] = 0.0f;
+    }
+  }
+#pragma unroll
+  for (int gi = 0; gi < G; ++gi) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) h[gi][c] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Texel<TT, C>::acc(r[gi][k], w[gi][k], h[gi]);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -33,16 +33,22 @@ __global__ __launch_bounds__(256) void encode_kernel(const TreeArgs T, const flo
   const int L = T.L;
   HT* hrow = h_out + q * (int64_t)(L * C);
 #pragma unroll
-  for (int l = 0; l < kMaxLevels; ++l) {
-    if (l >= L) break;
-    float h[C];
-    gather_level<TT, C>(T, l, idx[l], s, t, h);
-    typedef HT vC __attribute__((ext_vector_type(C)));
-    vC v;
+  for (int l0 = 0; l0 < kMaxLevels; l0 += 4) {
+    if (l0 >= L) break;
+    float h[4][C];
+    gather_levels<TT, C, 4>(T, l0, &idx[l0], s, t, h);
 #pragma unroll
-    for (int c = 0; c < C; ++c) v[c] = from_f32<HT>(h[c]);
-    *reinterpret_cast<vC*>(hrow + l * C) = v;
-    if (idx_out) idx_out[q * L + l] = idx[l];
+    for (int gi = 0; gi < 4; ++gi) {
+      const int l = l0 + gi;
+      if (l < L) {
+        typedef HT vC __attribute__((ext_vector_type(C)));
+        vC v;
+#pragma unroll
+        for (int c = 0; c < C; ++c) v[c] = from_f32<HT>(h[gi][c]);
+        *reinterpret_cast<vC*>(hrow + l * C) = v;
+        if (idx_out) idx_out[q * L + l] = idx[l];
+      }
+    }
   }
 }
 
@@ -227,13 +233,17 @@ __global__ __launch_bounds__(512) void query_kernel(const TreeArgs T, const MlpA
     descend(T, valid, x, idx);
     float s, t;
     octa(d, s, t);
+    // gathers in groups of 4 levels: 16 texel loads in flight per lane
 #pragma unroll
-    for (int l = 0; l < kMaxLevels; ++l) {
-      if (l >= T.L) break;
-      float h[C];
-      gather_level<TT, C>(T, l, idx[l], s, t, h);
+    for (int l0 = 0; l0 < kMaxLevels; l0 += 4) {
+      if (l0 >= T.L) break;
+      float h[4][C];
+      gather_levels<TT, C, 4>(T, l0, &idx[l0], s, t, h);
 #pragma unroll
-      for (int c = 0; c < C; c += 4) htile_put4<MT>(htile, KB0, lane, l * C + c, &h[c]);
+      for (int gi = 0; gi < 4; ++gi)
+        if (l0 + gi < T.L)
+#pragma unroll
+          for (int c = 0; c < C; c += 4) htile_put4<MT>(htile, KB0, lane, (l0 + gi) * C + c, &h[gi][c]);
     }
     wave_lds_sync();
 #pragma unroll
