@@ -21,7 +21,9 @@ import numpy as np
 MAX_LEVELS = 16
 MAX_LAYERS = 7
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liboo_oracle.so")
+# ORACLE_LIB lets the mutation test point the wrapper at a deliberately
+# broken build of the same source.
+LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboo_oracle.so")
 
 
 class _Tree(C.Structure):

@@ -181,18 +181,20 @@ struct Texel;
 template <int C>
 struct Texel<float, C> {
   static_assert(C == 4 || C == 8, "C");
-  typedef float4 raw[C / 4];
+  struct raw {
+    float4 v[C / 4];
+  };
   __device__ static inline void load(const float* p, raw& r) {
 #pragma unroll
-    for (int v = 0; v < C / 4; ++v) r[v] = reinterpret_cast<const float4*>(p)[v];
+    for (int v = 0; v < C / 4; ++v) r.v[v] = reinterpret_cast<const float4*>(p)[v];
   }
   __device__ static inline void acc(const raw& r, float w, float* a) {
 #pragma unroll
     for (int v = 0; v < C / 4; ++v) {
-      a[4 * v + 0] += w * r[v].x;
-      a[4 * v + 1] += w * r[v].y;
-      a[4 * v + 2] += w * r[v].z;
-      a[4 * v + 3] += w * r[v].w;
+      a[4 * v + 0] += w * r.v[v].x;
+      a[4 * v + 1] += w * r.v[v].y;
+      a[4 * v + 2] += w * r.v[v].z;
+      a[4 * v + 3] += w * r.v[v].w;
     }
   }
 };
@@ -269,6 +271,81 @@ __device__ inline void gather_levels(const TreeArgs& T, int l0, const int* idx, 
 #pragma unroll
     for (int k = 0; k < 4; ++k) Texel<TT, C>::acc(r[gi][k], w[gi][k], h[gi]);
   }
+}
+
+// Descent and gathers of one query, software-pipelined over the levels. At
+// level l the lane first loads the node word that selects the level-(l+1)
+// node, then issues the 4 texel loads of level l, and only then consumes the
+// texels of level l-1; so while the dependent node-word chain advances, two
+// levels of gathers are in flight behind it. put(l, h) receives each level's
+// C features (zeros where the tree has no node). Returns nothing; the wave
+// stops walking once none of its lanes has a node left.
+template <class TT, int C, class Put>
+__device__ inline void encode_pipelined(const TreeArgs& T, bool valid, const float x[3], float s, float t,
+                                        Put&& put) {
+  typedef typename Texel<TT, C>::raw Raw;
+  const int D = T.D, L = T.L;
+  const int qx = quant_axis(x[0], D), qy = quant_axis(x[1], D), qz = quant_axis(x[2], D);
+  int cur = valid ? 0 : -1;
+  Raw rp[4];
+  float wp[4] = {0.f, 0.f, 0.f, 0.f};
+  int l = 0;
+  for (; l < L; ++l) {
+    if (!__any(cur >= 0)) break;
+    const bool has = cur >= 0;
+    // 1. node word of the current node (selects the next level's node)
+    uint32_t word = 0;
+    if (l < D) word = T.nodes[has ? cur : 0];
+    // 2. texels of level l
+    Raw rn[4];
+    float wn[4];
+    {
+      const int R = T.res[l];
+      int tx[4];
+      taps(s, t, R, tx, wn);
+      const int64_t node = has ? (int64_t)cur - T.off[l] : 0;
+      const TT* base = reinterpret_cast<const TT*>(T.feat[l]);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        Texel<TT, C>::load(base + (has ? (node * R * R + tx[k]) * C : 0), rn[k]);
+        if (!has) wn[k] = 0.0f;
+      }
+    }
+    // 3. features of level l - 1
+    if (l > 0) {
+      float h[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) h[c] = 0.0f;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) Texel<TT, C>::acc(rp[k], wp[k], h);
+      put(l - 1, h);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      rp[k] = rn[k];
+      wp[k] = wn[k];
+    }
+    // 4. next level's node
+    if (l < D) {
+      const int sh = D - l - 1;
+      const int o = ((qx >> sh) & 1) | (((qy >> sh) & 1) << 1) | (((qz >> sh) & 1) << 2);
+      const uint32_t m = word & 0xffu;
+      cur = (has && ((m >> o) & 1u)) ? (int)(word >> 8) + __popc(m & ((1u << o) - 1u)) : -1;
+    }
+  }
+  // drain: the last level fetched, then zeros for levels never reached
+  if (l > 0) {
+    float h[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) h[c] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Texel<TT, C>::acc(rp[k], wp[k], h);
+    put(l - 1, h);
+  }
+  float z[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) z[c] = 0.0f;
+  for (; l < L; ++l) put(l, z);
 }
 
 // ---------------------------------------------------------------------------

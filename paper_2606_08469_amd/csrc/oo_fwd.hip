@@ -229,22 +229,12 @@ __global__ __launch_bounds__(512) void query_kernel(const TreeArgs T, const MlpA
     const bool valid = q < Q;
     float x[3] = {0.f, 0.f, 0.f}, d[3] = {0.f, 0.f, 1.f};
     if (valid) load_query(src, q, x, d);
-    int idx[kMaxLevels];
-    descend(T, valid, x, idx);
     float s, t;
     octa(d, s, t);
-    // gathers in groups of 4 levels: 16 texel loads in flight per lane
+    encode_pipelined<TT, C>(T, valid, x, s, t, [&](int l, const float* h) {
 #pragma unroll
-    for (int l0 = 0; l0 < kMaxLevels; l0 += 4) {
-      if (l0 >= T.L) break;
-      float h[4][C];
-      gather_levels<TT, C, 4>(T, l0, &idx[l0], s, t, h);
-#pragma unroll
-      for (int gi = 0; gi < 4; ++gi)
-        if (l0 + gi < T.L)
-#pragma unroll
-          for (int c = 0; c < C; c += 4) htile_put4<MT>(htile, KB0, lane, (l0 + gi) * C + c, &h[gi][c]);
-    }
+      for (int c = 0; c < C; c += 4) htile_put4<MT>(htile, KB0, lane, l * C + c, &h[c]);
+    });
     wave_lds_sync();
 #pragma unroll
     for (int t0 = 0; t0 < 4; t0 += NT) {

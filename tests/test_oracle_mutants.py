@@ -1,0 +1,55 @@
+"""The pins must catch plausible mistakes: each mutant below is the oracle's
+C source with one planted error, compiled on the CPU; the oracle pin suite
+must fail against every one of them."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "octaoctree_oracle.c")
+
+MUTANTS = {
+    "fold_sequential": ("double fy = (1.0 - fabs(ux)) * sign_pos(uy);",
+                        "double fy = (1.0 - fabs(fx)) * sign_pos(uy);"),
+    "seam_no_mirror": ("      i = -1 - i;\n      j = R - 1 - j;", "      i = -1 - i;"),
+    "tap_weight_swapped": ("w[k] = (a ? fu : 1.0 - fu) * (bb ? fv : 1.0 - fv);",
+                           "w[k] = (a ? 1.0 - fu : fu) * (bb ? fv : 1.0 - fv);"),
+    "octant_axes_swapped": ("return bx | (by << 1) | (bz << 2);", "return bz | (by << 1) | (bx << 2);"),
+    "descent_popcount_off_by_one": ("cur = first + popcount8(mask & ((1u << o) - 1u));",
+                                    "cur = first + popcount8(mask & ((2u << o) - 1u));"),
+    "refine_at_threshold": ("if (cnt <= tau) continue; /* leaf */", "if (cnt < tau) continue; /* leaf */"),
+    "bias_dropped": ("double z = (double)m->b[i][o];", "double z = 0.0;"),
+    "ggx_denominator_unsquared": ("double Dm = a2 / (PI * den * den);", "double Dm = a2 / (PI * den);"),
+    "fresnel_wrong_power": ("pow(1.0 - dot3(wi, hv), 5.0)", "pow(1.0 - dot3(wi, hv), 4.0)"),
+    "rhs_mean_missing": ("T[3 * b + c] += acc / (double)N;", "T[3 * b + c] += acc;"),
+    "residual_sign": ("r[i] = lhs[i] - T[i];", "r[i] = T[i] - lhs[i];"),
+    "loss_mean_over_B": ("*loss_out = B > 0 ? acc / (3.0 * (double)B) : 0.0;",
+                         "*loss_out = B > 0 ? acc / (double)B : 0.0;"),
+    "backprop_transposed_weight": ("s += (double)m->W[i][(int64_t)o * fin + k] * delta[o];",
+                                   "s += (double)m->W[i][(int64_t)k * fout + o] * delta[o];"),
+    "relu_mask_missing": ("if (i > 0 && !(pre[i - 1][k] > 0.0)) s = 0.0;", ""),
+    "scatter_wrong_tap_weight": ("dfeat[l][base + c] += qt.w[l][k] * delta[l * C + c];",
+                                 "dfeat[l][base + c] += 0.25 * delta[l * C + c];"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation site for {name} not found exactly once"
+    msrc = tmp_path / "octaoctree_oracle.c"
+    msrc.write_text(src.replace(old, new))
+    (tmp_path / "octaoctree_oracle.h").write_text(open(SRC.replace(".c", ".h")).read())
+    lib = tmp_path / "liboo_mutant.so"
+    subprocess.run(["gcc", "-O1", "-std=gnu11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-o", str(lib),
+                    str(msrc), "-lm"], check=True, capture_output=True)
+    env = dict(os.environ, ORACLE_LIB=str(lib))
+    pins = [os.path.join(ROOT, "tests", f) for f in sorted(os.listdir(os.path.join(ROOT, "tests")))
+            if f.startswith("test_oracle_") and f != "test_oracle_mutants.py"]
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        "--hypothesis-seed=0"] + pins, env=env, capture_output=True, text=True, timeout=600,
+                       cwd=ROOT)
+    assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"

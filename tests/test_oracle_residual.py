@@ -43,6 +43,12 @@ def test_alpha_one_closed_form_any_angle():
         co = float(wo[2]) / np.linalg.norm(wo.astype(np.float64))
         w = one_sample(n, wo, wi, [0, 0, 0], 1.0, F0=1.0)
         np.testing.assert_allclose(w, ci / (math.pi * (ci + 1) * (co + 1)), rtol=1e-11)
+        # with F0 = 0 Schlick's term is (1 - wi.h)^5 at any angle
+        u = lambda v: v.astype(np.float64) / np.linalg.norm(v.astype(np.float64))
+        hv = u(u(wi) + u(wo))
+        fres = (1.0 - float(np.dot(u(wi), hv))) ** 5
+        w0 = one_sample(n, wo, wi, [0, 0, 0], 1.0, F0=0.0)
+        np.testing.assert_allclose(w0, ci * fres / (math.pi * (ci + 1) * (co + 1)), rtol=1e-9, atol=1e-15)
 
 
 def test_reciprocity_horizon_albedo_and_pdf():
