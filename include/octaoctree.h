@@ -213,7 +213,12 @@ int oo_radiosity_residual_fwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
                               void* workspace, hipStream_t stream);
 
 /*
- * Residual backward. The encoding is recomputed, not stored.
+ * Residual backward. The texel gathers and the decoder forward are
+ * recomputed, not stored; the node index per level comes from the forward.
+ *  - workspace: the one the forward of this batch used, unchanged since.
+ *    The forward leaves there the node indices of every query the backward
+ *    processes. Indices found outside their level (a workspace the forward
+ *    did not fill) are treated as missing nodes; they are never dereferenced.
  *  - resid, rhs: the forward's outputs for the same batch and parameters.
  *  - grad_loss: device FP64 scalar, dLoss_total/dloss.
  *  - dfeat[l]: FP32 [n_l][res][res][C]. Receives += the feature gradient by

@@ -136,7 +136,8 @@ int check_batch(const oo_residual_batch* b, ResidualArgs& A) {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Workspace {
-  size_t Lq, lossp, seeds, wt[OO_MAX_LAYERS], dwp, total;
+  size_t Lq, lossp, seeds, nidx, wt[OO_MAX_LAYERS], dwp, total;
+  int64_t Qb;
   int grid;
   ParamLayout PL;
 };
@@ -155,7 +156,7 @@ void param_layout(const MlpArgs& M, ParamLayout& PL) {
   PL.P = off;
 }
 
-Workspace workspace_layout(const MlpArgs& M, oo_dtype md, const oo_residual_batch* b) {
+Workspace workspace_layout(const MlpArgs& M, oo_dtype md, const oo_residual_batch* b, int L) {
   Workspace w;
   const int64_t B = b->B;
   const int N = b->target_override ? 0 : b->N;
@@ -163,14 +164,17 @@ Workspace workspace_layout(const MlpArgs& M, oo_dtype md, const oo_residual_batc
   const bool full = b->grad_through_rhs && !b->target_override && N > 0;
   const int64_t Qb = full ? Qf : B;
   param_layout(M, w.PL);
-  w.grid = bwd_grid(M, Qb);
+  w.grid = bwd_grid(M, md, L, Qb);
   size_t o = 0;
   w.Lq = o;
   o = align256(o + (size_t)Qf * 3 * sizeof(float));
   w.lossp = o;
-  o = align256(o + (size_t)(combine_blocks(B) + 1) * sizeof(double));
+  o = align256(o + (size_t)(combine_blocks(B, N) + 1) * sizeof(double));
   w.seeds = o;
   o = align256(o + (size_t)Qb * 3 * sizeof(float));
+  w.Qb = Qb;
+  w.nidx = o;  // node index per level of every backward query, written by the forward
+  o = align256(o + (size_t)Qb * L * sizeof(int32_t));
   const size_t esz = md == OO_F32 ? 4 : 2;
   for (int i = 0; i < M.n_layers; ++i) {
     w.wt[i] = o;
@@ -306,7 +310,8 @@ int oo_query_fwd(const oo_tree* tree, const oo_mlp* mlp, const float* x, const f
   if (B == 0) return OO_OK;
   if (!x || !dir || !rgb_out) return fail(OO_EINVAL, "x, dir and rgb_out are required");
   QuerySrc src{x, dir, B, x, dir};
-  return hip_status(launch_query(T, tree->feat_dtype, M, mlp->dtype, src, B, rgb_out, stream), "query_fwd launch");
+  return hip_status(launch_query(T, tree->feat_dtype, M, mlp->dtype, src, B, rgb_out, nullptr, 0, stream),
+                    "query_fwd launch");
 }
 
 int oo_residual_workspace_bytes(const oo_tree* tree, const oo_mlp* mlp, const oo_residual_batch* batch, size_t* bytes) {
@@ -320,7 +325,7 @@ int oo_residual_workspace_bytes(const oo_tree* tree, const oo_mlp* mlp, const oo
   if ((rc = check_pair(tree, mlp))) return rc;
   if ((rc = check_batch(batch, A))) return rc;
   if (!bytes) return fail(OO_EINVAL, "bytes is NULL");
-  *bytes = workspace_layout(M, mlp->dtype, batch).total;
+  *bytes = workspace_layout(M, mlp->dtype, batch, tree->n_levels).total;
   return OO_OK;
 }
 
@@ -337,13 +342,14 @@ int oo_radiosity_residual_fwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   if ((rc = check_batch(batch, A))) return rc;
   if (!loss_out || !workspace) return fail(OO_EINVAL, "loss_out and workspace are required");
   if (A.B > 0 && (!lhs_out || !rhs_out || !resid_out)) return fail(OO_EINVAL, "lhs_out, rhs_out, resid_out are required");
-  const Workspace w = workspace_layout(M, mlp->dtype, batch);
+  const Workspace w = workspace_layout(M, mlp->dtype, batch, tree->n_levels);
   char* ws = static_cast<char*>(workspace);
   float* Lq = reinterpret_cast<float*>(ws + w.Lq);
   double* lossp = reinterpret_cast<double*>(ws + w.lossp);
+  int32_t* nidx = reinterpret_cast<int32_t*>(ws + w.nidx);
   const int64_t Q = A.B * (1 + A.N);
   QuerySrc src{batch->x, batch->dir, A.B, A.N > 0 ? batch->x2 : batch->x, A.N > 0 ? batch->dir2 : batch->dir};
-  hipError_t e = launch_query(T, tree->feat_dtype, M, mlp->dtype, src, Q, Lq, stream);
+  hipError_t e = launch_query(T, tree->feat_dtype, M, mlp->dtype, src, Q, Lq, nidx, w.Qb, stream);
   if (e != hipSuccess) return hip_status(e, "residual query launch");
   return hip_status(launch_combine(A, Lq, lhs_out, rhs_out, resid_out, lossp, loss_out, stream), "combine launch");
 }
@@ -372,9 +378,10 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   }
   for (int i = 0; i < mlp->n_layers; ++i)
     if (!dW[i] || !db[i]) return fail(OO_EINVAL, "dW[%d] or db[%d] is NULL", i, i);
-  const Workspace w = workspace_layout(M, mlp->dtype, batch);
+  const Workspace w = workspace_layout(M, mlp->dtype, batch, tree->n_levels);
   char* ws = static_cast<char*>(workspace);
   float* seeds = reinterpret_cast<float*>(ws + w.seeds);
+  const int32_t* nidx = reinterpret_cast<const int32_t*>(ws + w.nidx);
   float* partials = reinterpret_cast<float*>(ws + w.dwp);
   void* Wt[OO_MAX_LAYERS];
   for (int i = 0; i < mlp->n_layers; ++i) Wt[i] = ws + w.wt[i];
@@ -386,7 +393,8 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   e = launch_transpose_weights(M, mlp->dtype, Wt, stream);
   if (e != hipSuccess) return hip_status(e, "transpose launch");
   QuerySrc src{batch->x, batch->dir, A.B, full ? batch->x2 : batch->x, full ? batch->dir2 : batch->dir};
-  e = launch_bwd(T, tree->feat_dtype, M, mlp->dtype, Wt, src, Qb, seeds, post_scale, G, w.PL, partials, w.grid, stream);
+  e = launch_bwd(T, tree->feat_dtype, M, mlp->dtype, Wt, src, Qb, nidx, seeds, post_scale, G, w.PL, partials, w.grid,
+                 stream);
   if (e != hipSuccess) return hip_status(e, "backward launch");
   ReduceDst D;
   D.n_seg = 2 * mlp->n_layers;

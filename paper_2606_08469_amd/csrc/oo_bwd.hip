@@ -158,7 +158,8 @@ __device__ inline void store_tq(MT* buf, const f32x4 (&acc)[MT2], int m0, int n_
 // [row][query] buffers.
 template <class TT, class MT, int C, int H>
 __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, const MlpArgs M, const MlpArgs Mt,
-                                                  const QuerySrc src, int64_t Q, const float* __restrict__ seeds,
+                                                  const QuerySrc src, int64_t Q, const int32_t* __restrict__ nidx,
+                                                  const float* __restrict__ seeds,
                                                   float post_scale, const GradArgs G, const ParamLayout PL,
                                                   float* __restrict__ partials) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -212,27 +213,27 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
     // rather than holding a hundred of them in registers across the loop.
     const int tid = launder_lane(threadIdx.x), lane = tid & 63, g = lane >> 4, r16 = lane & 15;
     const int col = 16 * nt + r16;
-    // ---- 1. encode: kLanesPerQuery lanes per query, one level each -----
+    // ---- 1. encode: node indices come from the forward (no second walk of
+    //      the tree); kLanesPerQuery lanes per query gather its levels -----
     {
+      const int nv = (int)(Q - qbase < kQW ? Q - qbase : kQW);  // valid queries in this tile
+      for (int e = tid; e < kQW * L; e += blockDim.x) {
+        int v = e < nv * L ? nidx[qbase * L + e] : -1;
+        const int l = e % L;
+        if (v < T.off[l] || v >= T.off[l + 1]) v = -1;  // never index outside level l
+        qidx[e] = v;
+      }
       const int ql = tid / kLanesPerQuery, part = tid % kLanesPerQuery;
       const int64_t q = qbase + ql;
-      const bool valid = q < Q;
-      float x[3] = {0.f, 0.f, 0.f}, d[3] = {0.f, 0.f, 1.f};
-      if (valid) load_query(src, q, x, d);
-      {
-        int idx[kMaxLevels];
-        descend(T, valid, x, idx);
+      if (part == 0) {
+        float x[3] = {0.f, 0.f, 0.f}, d[3] = {0.f, 0.f, 1.f};
+        if (q < Q) load_query(src, q, x, d);
         float s, t;
         octa(d, s, t);
-        if (part == 0) {
-          qst[2 * ql] = s;
-          qst[2 * ql + 1] = t;
-#pragma unroll
-          for (int l = 0; l < kMaxLevels; ++l)
-            if (l < L) qidx[ql * L + l] = idx[l];
-        }
+        qst[2 * ql] = s;
+        qst[2 * ql + 1] = t;
       }
-      wave_lds_sync();  // the lanes of a query are in one wave
+      __syncthreads();
       const float s = qst[2 * ql], t = qst[2 * ql + 1];
       // this lane's levels part, part + 4, ...: all their gathers in flight
       constexpr int G = kMaxLevels / kLanesPerQuery;
@@ -474,6 +475,7 @@ __global__ __launch_bounds__(256) void dw_reduce_kernel(const float* __restrict_
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
   double s = 0.0;
+#pragma unroll 8
   for (int g = 0; g < grid; ++g) s += (double)partials[(int64_t)g * P + p];
   int seg = 0;
   while (seg + 1 < D.n_seg && p >= D.start[seg + 1]) ++seg;
@@ -548,12 +550,17 @@ size_t bwd_lds_bytes(const MlpArgs& M, oo_dtype md, int L) {
   return bwd_layout(M.K0, M.H, M.n_layers, L, md == OO_F32 ? 4 : 2).total;
 }
 
-int bwd_grid(const MlpArgs& M, int64_t Q) {
+// Persistent grid: as many workgroups as fit on the chip at once (LDS
+// bound, 160 KiB per CU on gfx950), so that there is one dW partial per
+// resident workgroup.
+int bwd_grid(const MlpArgs& M, oo_dtype md, int L, int64_t Q) {
   const int64_t n_tiles = (Q + kQW - 1) / kQW;
-  int64_t g = (int64_t)cu_count() * 2;
+  const size_t lds = bwd_lds_bytes(M, md, L);
+  int per_cu = (int)((size_t)160 * 1024 / (lds ? lds : 1));
+  per_cu = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
+  int64_t g = (int64_t)cu_count() * per_cu;
   if (g > n_tiles) g = n_tiles;
   return (int)(g > 0 ? g : 1);
-  (void)M;
 }
 
 hipError_t launch_seeds(const ResidualArgs& A, const float* resid, const float* rhs, const double* grad_loss,
@@ -576,33 +583,37 @@ hipError_t launch_transpose_weights(const MlpArgs& M, oo_dtype md, void* const* 
 
 template <class TT, class MT, int C, int H>
 static hipError_t launch_bwd_t(const TreeArgs& T, const MlpArgs& M, const MlpArgs& Mt, const QuerySrc& src,
-                               int64_t Q, const float* seeds, float post_scale, const GradArgs& G,
+                               int64_t Q, const int32_t* nidx, const float* seeds, float post_scale, const GradArgs& G,
                                const ParamLayout& PL, float* partials, int grid, hipStream_t st) {
   const size_t lds = bwd_layout(M.K0, H, M.n_layers, T.L, (int)sizeof(MT)).total;
   auto k = bwd_kernel<TT, MT, C, H>;
   hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * kBwdWaves), lds, st, T, M, Mt, src, Q, seeds, post_scale, G, PL, partials);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * kBwdWaves), lds, st, T, M, Mt, src, Q, nidx, seeds, post_scale, G, PL,
+                     partials);
   return hipGetLastError();
 }
 
 template <class TT, class MT, int C>
 static hipError_t launch_bwd_c(const TreeArgs& T, const MlpArgs& M, const MlpArgs& Mt, const QuerySrc& src,
-                               int64_t Q, const float* seeds, float post_scale, const GradArgs& G,
+                               int64_t Q, const int32_t* nidx, const float* seeds, float post_scale, const GradArgs& G,
                                const ParamLayout& PL, float* partials, int grid, hipStream_t st) {
-  return M.H == 64 ? launch_bwd_t<TT, MT, C, 64>(T, M, Mt, src, Q, seeds, post_scale, G, PL, partials, grid, st)
-                   : launch_bwd_t<TT, MT, C, 128>(T, M, Mt, src, Q, seeds, post_scale, G, PL, partials, grid, st);
+  return M.H == 64
+             ? launch_bwd_t<TT, MT, C, 64>(T, M, Mt, src, Q, nidx, seeds, post_scale, G, PL, partials, grid, st)
+             : launch_bwd_t<TT, MT, C, 128>(T, M, Mt, src, Q, nidx, seeds, post_scale, G, PL, partials, grid, st);
 }
 
 hipError_t launch_bwd(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, void* const* Wt,
-                      const QuerySrc& src, int64_t Q, const float* seeds, float post_scale, const GradArgs& G,
-                      const ParamLayout& PL, float* partials, int grid, hipStream_t st) {
+                      const QuerySrc& src, int64_t Q, const int32_t* nidx, const float* seeds, float post_scale,
+                      const GradArgs& G, const ParamLayout& PL, float* partials, int grid, hipStream_t st) {
   MlpArgs Mt = M;
   for (int i = 0; i < M.n_layers; ++i) Mt.W[i] = Wt[i];
   if (td == OO_F32)
-    return T.C == 4 ? launch_bwd_c<float, float, 4>(T, M, Mt, src, Q, seeds, post_scale, G, PL, partials, grid, st)
-                    : launch_bwd_c<float, float, 8>(T, M, Mt, src, Q, seeds, post_scale, G, PL, partials, grid, st);
-  if (td == OO_F16) return launch_bwd_c<f16, f16, 8>(T, M, Mt, src, Q, seeds, post_scale, G, PL, partials, grid, st);
-  return launch_bwd_c<bf16, bf16, 8>(T, M, Mt, src, Q, seeds, post_scale, G, PL, partials, grid, st);
+    return T.C == 4
+               ? launch_bwd_c<float, float, 4>(T, M, Mt, src, Q, nidx, seeds, post_scale, G, PL, partials, grid, st)
+               : launch_bwd_c<float, float, 8>(T, M, Mt, src, Q, nidx, seeds, post_scale, G, PL, partials, grid, st);
+  if (td == OO_F16)
+    return launch_bwd_c<f16, f16, 8>(T, M, Mt, src, Q, nidx, seeds, post_scale, G, PL, partials, grid, st);
+  return launch_bwd_c<bf16, bf16, 8>(T, M, Mt, src, Q, nidx, seeds, post_scale, G, PL, partials, grid, st);
   (void)md;
 }
 

@@ -277,9 +277,9 @@ __device__ inline void gather_levels(const TreeArgs& T, int l0, const int* idx, 
 // level l the lane first loads the node word that selects the level-(l+1)
 // node, then issues the 4 texel loads of level l, and only then consumes the
 // texels of level l-1; so while the dependent node-word chain advances, two
-// levels of gathers are in flight behind it. put(l, h) receives each level's
-// C features (zeros where the tree has no node). Returns nothing; the wave
-// stops walking once none of its lanes has a node left.
+// levels of gathers are in flight behind it. put(l, h, node) receives each
+// level's C features and node index (zeros and -1 where the tree has no
+// node). The wave stops walking once none of its lanes has a node left.
 template <class TT, int C, class Put>
 __device__ inline void encode_pipelined(const TreeArgs& T, bool valid, const float x[3], float s, float t,
                                         Put&& put) {
@@ -289,6 +289,7 @@ __device__ inline void encode_pipelined(const TreeArgs& T, bool valid, const flo
   int cur = valid ? 0 : -1;
   Raw rp[4];
   float wp[4] = {0.f, 0.f, 0.f, 0.f};
+  int np = -1;  // node of the level whose texels are in flight
   int l = 0;
   for (; l < L; ++l) {
     if (!__any(cur >= 0)) break;
@@ -318,13 +319,14 @@ __device__ inline void encode_pipelined(const TreeArgs& T, bool valid, const flo
       for (int c = 0; c < C; ++c) h[c] = 0.0f;
 #pragma unroll
       for (int k = 0; k < 4; ++k) Texel<TT, C>::acc(rp[k], wp[k], h);
-      put(l - 1, h);
+      put(l - 1, h, np);
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       rp[k] = rn[k];
       wp[k] = wn[k];
     }
+    np = cur;
     // 4. next level's node
     if (l < D) {
       const int sh = D - l - 1;
@@ -340,12 +342,12 @@ __device__ inline void encode_pipelined(const TreeArgs& T, bool valid, const flo
     for (int c = 0; c < C; ++c) h[c] = 0.0f;
 #pragma unroll
     for (int k = 0; k < 4; ++k) Texel<TT, C>::acc(rp[k], wp[k], h);
-    put(l - 1, h);
+    put(l - 1, h, np);
   }
   float z[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) z[c] = 0.0f;
-  for (; l < L; ++l) put(l, z);
+  for (; l < L; ++l) put(l, z, -1);
 }
 
 // ---------------------------------------------------------------------------

@@ -205,9 +205,12 @@ __device__ inline void store_rgb(const f32x4 out[NT], int t0, int64_t q_base, in
 // ---------------------------------------------------------------------------
 // Fused query: encode 64 queries per wave into LDS, decode them there.
 // ---------------------------------------------------------------------------
+// Queries q < n_idx also store their node index per level in idx_out
+// ([n_idx][L]), which the residual backward reads instead of descending again.
 template <class TT, class MT, int C, int H, bool WLDS>
 __global__ __launch_bounds__(512) void query_kernel(const TreeArgs T, const MlpArgs M, const QuerySrc src,
-                                                    int64_t Q, float* __restrict__ rgb) {
+                                                    int64_t Q, float* __restrict__ rgb, int32_t* __restrict__ idx_out,
+                                                    int64_t n_idx) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   constexpr int NT = 2;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63, waves = blockDim.x >> 6;
@@ -231,9 +234,11 @@ __global__ __launch_bounds__(512) void query_kernel(const TreeArgs T, const MlpA
     if (valid) load_query(src, q, x, d);
     float s, t;
     octa(d, s, t);
-    encode_pipelined<TT, C>(T, valid, x, s, t, [&](int l, const float* h) {
+    const bool keep = q < n_idx;
+    encode_pipelined<TT, C>(T, valid, x, s, t, [&](int l, const float* h, int node) {
 #pragma unroll
       for (int c = 0; c < C; c += 4) htile_put4<MT>(htile, KB0, lane, l * C + c, &h[c]);
+      if (keep) idx_out[q * T.L + l] = node;
     });
     wave_lds_sync();
 #pragma unroll
@@ -336,35 +341,47 @@ __device__ inline void load_unit(const float* p, float v[3]) {
   }
 }
 
-// One thread per LHS point: T = Le + (1/N) sum_k w_k * L(x2_k), r = L - T;
-// per-block FP64 partial of sum r^2 (or (r / rho)^2).
-__global__ __launch_bounds__(256) void combine_kernel(const ResidualArgs A, const float* __restrict__ Lq,
+// One group of G lanes per LHS point (G = N rounded up to a power of two,
+// at most 64): lane k of the group weighs secondary sample k (and k + G, ...)
+// so the per-sample inputs are read coalesced; the group sums its products
+// with lane shuffles in a fixed order. The group leader forms
+// T = Le + (1/N) sum_k w_k * L(x2_k) and r = L - T and writes the outputs;
+// each block leaves one FP64 partial of sum r^2 (or (r / rho)^2).
+__global__ __launch_bounds__(256) void combine_kernel(const ResidualArgs A, int G, const float* __restrict__ Lq,
                                                       float* __restrict__ lhs_out, float* __restrict__ rhs_out,
                                                       float* __restrict__ resid_out, double* __restrict__ partials) {
   __shared__ double red[256];
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  const int64_t b = gid / G;
+  const int k0 = (int)(gid % G);
+  const bool valid = b < A.B;
+  float s[3] = {0.f, 0.f, 0.f};
+  if (valid && !A.target_override && A.N > 0) {
+    float n[3], wo[3], alb[3] = {A.albedo[3 * b], A.albedo[3 * b + 1], A.albedo[3 * b + 2]};
+    load_unit(A.n + 3 * b, n);
+    load_unit(A.wo + 3 * b, wo);
+    const float alpha = A.rough[b];
+    for (int k = k0; k < A.N; k += G) {
+      const int64_t bk = b * A.N + k;
+      float wi[3], w[3];
+      load_unit(A.wi + 3 * bk, wi);
+      bsdf_weight(n, wo, wi, alb, alpha, A.F0, A.pdf ? A.pdf[bk] : 1.0f, w);
+      const float* Lk = Lq + 3 * (A.B + bk);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) s[c] += w[c] * Lk[c];
+    }
+  }
+  for (int off = G >> 1; off > 0; off >>= 1)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s[c] += __shfl_xor(s[c], off, G);
   double acc = 0.0;
-  if (b < A.B) {
+  if (valid && k0 == 0) {
     float L[3] = {Lq[3 * b], Lq[3 * b + 1], Lq[3 * b + 2]};
     float T[3];
     if (A.target_override) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) T[c] = A.target_override[3 * b + c];
     } else {
-      float n[3], wo[3], alb[3] = {A.albedo[3 * b], A.albedo[3 * b + 1], A.albedo[3 * b + 2]};
-      load_unit(A.n + 3 * b, n);
-      load_unit(A.wo + 3 * b, wo);
-      const float alpha = A.rough[b];
-      float s[3] = {0.f, 0.f, 0.f};
-      for (int k = 0; k < A.N; ++k) {
-        const int64_t bk = b * A.N + k;
-        float wi[3], w[3];
-        load_unit(A.wi + 3 * bk, wi);
-        bsdf_weight(n, wo, wi, alb, alpha, A.F0, A.pdf ? A.pdf[bk] : 1.0f, w);
-        const float* Lk = Lq + 3 * (A.B + bk);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) s[c] += w[c] * Lk[c];
-      }
       const float invN = A.N > 0 ? 1.0f / (float)A.N : 0.0f;
 #pragma unroll
       for (int c = 0; c < 3; ++c) T[c] = A.Le[3 * b + c] + s[c] * invN;
@@ -385,8 +402,8 @@ __global__ __launch_bounds__(256) void combine_kernel(const ResidualArgs A, cons
   }
   red[threadIdx.x] = acc;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
     __syncthreads();
   }
   if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
@@ -407,10 +424,27 @@ __global__ __launch_bounds__(256) void loss_reduce_kernel(const double* __restri
   if (threadIdx.x == 0) *loss = B > 0 ? red[0] / (3.0 * (double)B) : 0.0;
 }
 
+// Four elements per thread and iteration (16-byte loads) when both pointers
+// allow it; the tail and unaligned arrays go element by element.
 template <class DT>
 __global__ __launch_bounds__(256) void cast_kernel(const float* __restrict__ src, DT* __restrict__ dst, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    dst[i] = from_f32<DT>(src[i]);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t nv = 0;
+  if ((reinterpret_cast<uintptr_t>(src) % 16) == 0 && (reinterpret_cast<uintptr_t>(dst) % (4 * sizeof(DT))) == 0) {
+    nv = n / 4;
+    typedef DT v4 __attribute__((ext_vector_type(4)));
+    for (int64_t i = i0; i < nv; i += stride) {
+      const float4 v = reinterpret_cast<const float4*>(src)[i];
+      v4 o;
+      o[0] = from_f32<DT>(v.x);
+      o[1] = from_f32<DT>(v.y);
+      o[2] = from_f32<DT>(v.z);
+      o[3] = from_f32<DT>(v.w);
+      reinterpret_cast<v4*>(dst)[i] = o;
+    }
+  }
+  for (int64_t i = 4 * nv + i0; i < n; i += stride) dst[i] = from_f32<DT>(src[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -500,7 +534,7 @@ static void tile_launch_shape(const MlpArgs& M, int64_t Q, bool& wlds, int& wave
 
 template <class TT, class MT, int C, int H>
 static hipError_t launch_query_t(const TreeArgs& T, const MlpArgs& M, const QuerySrc& src, int64_t Q, float* rgb,
-                                 hipStream_t st) {
+                                 int32_t* idx_out, int64_t n_idx, hipStream_t st) {
   bool wlds;
   int waves, grid;
   size_t lds;
@@ -508,30 +542,30 @@ static hipError_t launch_query_t(const TreeArgs& T, const MlpArgs& M, const Quer
   if (wlds) {
     auto k = query_kernel<TT, MT, C, H, true>;
     hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, st, T, M, src, Q, rgb);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, st, T, M, src, Q, rgb, idx_out, n_idx);
   } else {
     auto k = query_kernel<TT, MT, C, H, false>;
     hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, st, T, M, src, Q, rgb);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, st, T, M, src, Q, rgb, idx_out, n_idx);
   }
   return hipGetLastError();
 }
 
 template <class TT, class MT, int C>
 static hipError_t launch_query_c(const TreeArgs& T, const MlpArgs& M, const QuerySrc& src, int64_t Q, float* rgb,
-                                 hipStream_t st) {
-  return M.H == 64 ? launch_query_t<TT, MT, C, 64>(T, M, src, Q, rgb, st)
-                   : launch_query_t<TT, MT, C, 128>(T, M, src, Q, rgb, st);
+                                 int32_t* idx_out, int64_t n_idx, hipStream_t st) {
+  return M.H == 64 ? launch_query_t<TT, MT, C, 64>(T, M, src, Q, rgb, idx_out, n_idx, st)
+                   : launch_query_t<TT, MT, C, 128>(T, M, src, Q, rgb, idx_out, n_idx, st);
 }
 
 hipError_t launch_query(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, const QuerySrc& src,
-                        int64_t Q, float* rgb, hipStream_t st) {
+                        int64_t Q, float* rgb, int32_t* idx_out, int64_t n_idx, hipStream_t st) {
   if (Q == 0) return hipSuccess;
   if (td == OO_F32)
-    return T.C == 4 ? launch_query_c<float, float, 4>(T, M, src, Q, rgb, st)
-                    : launch_query_c<float, float, 8>(T, M, src, Q, rgb, st);
-  if (td == OO_F16) return launch_query_c<f16, f16, 8>(T, M, src, Q, rgb, st);
-  return launch_query_c<bf16, bf16, 8>(T, M, src, Q, rgb, st);
+    return T.C == 4 ? launch_query_c<float, float, 4>(T, M, src, Q, rgb, idx_out, n_idx, st)
+                    : launch_query_c<float, float, 8>(T, M, src, Q, rgb, idx_out, n_idx, st);
+  if (td == OO_F16) return launch_query_c<f16, f16, 8>(T, M, src, Q, rgb, idx_out, n_idx, st);
+  return launch_query_c<bf16, bf16, 8>(T, M, src, Q, rgb, idx_out, n_idx, st);
   (void)md;
 }
 
@@ -560,21 +594,29 @@ hipError_t launch_mlp(const MlpArgs& M, oo_dtype md, const void* h, int64_t Q, f
   return M.H == 64 ? launch_mlp_t<bf16, 64>(M, h, Q, rgb, st) : launch_mlp_t<bf16, 128>(M, h, Q, rgb, st);
 }
 
-int combine_blocks(int64_t B) { return (int)((B + 255) / 256); }
+static int combine_group(int N) {
+  int G = 1;
+  while (G < N && G < 64) G <<= 1;
+  return G;
+}
+
+int combine_blocks(int64_t B, int N) { return (int)((B * combine_group(N) + 255) / 256); }
 
 hipError_t launch_combine(const ResidualArgs& A, const float* Lq, float* lhs, float* rhs, float* resid,
                           double* partials, double* loss, hipStream_t st) {
-  const int nb = combine_blocks(A.B);
+  const int G = combine_group(A.target_override ? 0 : A.N);
+  const int nb = combine_blocks(A.B, A.target_override ? 0 : A.N);
   if (nb > 0)
-    hipLaunchKernelGGL(combine_kernel, dim3(nb), dim3(256), 0, st, A, Lq, lhs, rhs, resid, partials);
+    hipLaunchKernelGGL(combine_kernel, dim3(nb), dim3(256), 0, st, A, G, Lq, lhs, rhs, resid, partials);
   hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(256), 0, st, partials, nb, A.B, loss);
   return hipGetLastError();
 }
 
 hipError_t launch_cast(const float* src, void* dst, oo_dtype dt, int64_t n, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
+  int64_t blocks = (n / 4 + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
   if (dt == OO_F32)
     hipLaunchKernelGGL(cast_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st, src, (float*)dst, n);
   else if (dt == OO_F16)

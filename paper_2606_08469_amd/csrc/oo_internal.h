@@ -43,21 +43,21 @@ hipError_t launch_encode(const TreeArgs& T, oo_dtype td, const float* x, const f
                          oo_dtype hd, int32_t* idx, hipStream_t st);
 hipError_t launch_mlp(const MlpArgs& M, oo_dtype md, const void* h, int64_t Q, float* rgb, hipStream_t st);
 hipError_t launch_query(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, const QuerySrc& src,
-                        int64_t Q, float* rgb, hipStream_t st);
-int combine_blocks(int64_t B);
+                        int64_t Q, float* rgb, int32_t* idx_out, int64_t n_idx, hipStream_t st);
+int combine_blocks(int64_t B, int N);
 hipError_t launch_combine(const ResidualArgs& A, const float* Lq, float* lhs, float* rhs, float* resid,
                           double* partials, double* loss, hipStream_t st);
 hipError_t launch_cast(const float* src, void* dst, oo_dtype dt, int64_t n, hipStream_t st);
 
 // Backward.
-int bwd_grid(const MlpArgs& M, int64_t Q);
+int bwd_grid(const MlpArgs& M, oo_dtype md, int L, int64_t Q);
 size_t bwd_lds_bytes(const MlpArgs& M, oo_dtype md, int L);
 hipError_t launch_seeds(const ResidualArgs& A, const float* resid, const float* rhs, const double* grad_loss,
                         int full, float* seeds, hipStream_t st);
 hipError_t launch_transpose_weights(const MlpArgs& M, oo_dtype md, void* const* Wt, hipStream_t st);
 hipError_t launch_bwd(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, void* const* Wt,
-                      const QuerySrc& src, int64_t Q, const float* seeds, float post_scale, const GradArgs& G,
-                      const ParamLayout& PL, float* partials, int grid, hipStream_t st);
+                      const QuerySrc& src, int64_t Q, const int32_t* nidx, const float* seeds, float post_scale,
+                      const GradArgs& G, const ParamLayout& PL, float* partials, int grid, hipStream_t st);
 hipError_t launch_dw_reduce(const float* partials, int grid, const ParamLayout& PL, const ReduceDst& D, float scale,
                             hipStream_t st);
 

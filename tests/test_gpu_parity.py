@@ -247,6 +247,24 @@ def test_residual_mixed(ci, B):
     compare_grads(f"mixed bwd cfg{ci}", got, otree, omlp, batch, cos=MIX_COS)
 
 
+def test_bwd_with_unfilled_workspace_stays_in_bounds():
+    """The backward reads node indices the forward left in the workspace;
+    indices outside their level (here: random words, as if the forward never
+    ran) are treated as missing nodes and never dereferenced."""
+    batch = train_batch(3, 512)
+    model = gpu_models(3)
+    b = binding.device_batch(batch)
+    ws = model.workspace(b)
+    lhs, rhs, res, loss = binding.residual_fwd(model.tree, model.mlp, b, ws)
+    ws.copy_(torch.randint(0, 256, ws.shape, dtype=torch.uint8, device="cuda"))
+    dfeat = [torch.zeros(f.shape, device="cuda") for f in model.feat]
+    dW = [torch.zeros(w.shape, device="cuda") for w in model.W]
+    db = [torch.zeros(v.shape, device="cuda") for v in model.b]
+    binding.residual_bwd(model.tree, model.mlp, b, res, rhs, torch.ones((), dtype=torch.float64), dfeat, dW, db, ws)
+    torch.cuda.synchronize()
+    assert all(torch.isfinite(g).all() for g in dfeat + dW + db)
+
+
 def test_residual_zero_points():
     model = gpu_models(1)
     batch = subset_batch(train_batch(1), np.arange(0))
