@@ -136,7 +136,7 @@ int check_batch(const oo_residual_batch* b, ResidualArgs& A) {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Workspace {
-  size_t Lq, lossp, seeds, nidx, wt[OO_MAX_LAYERS], dwp, total;
+  size_t Lq, lossp, seeds, nidx, dh, wt[OO_MAX_LAYERS], dwp, total;
   int64_t Qb;
   int grid;
   ParamLayout PL;
@@ -173,8 +173,10 @@ Workspace workspace_layout(const MlpArgs& M, oo_dtype md, const oo_residual_batc
   w.seeds = o;
   o = align256(o + (size_t)Qb * 3 * sizeof(float));
   w.Qb = Qb;
-  w.nidx = o;  // node index per level of every backward query, written by the forward
+  w.nidx = o;  // node index per level of every backward query, written by the forward, [L][Qb]
   o = align256(o + (size_t)Qb * L * sizeof(int32_t));
+  w.dh = o;  // dLoss/dh of every backward query, [Qb][K0] FP32
+  o = align256(o + (size_t)Qb * M.K0 * sizeof(float));
   const size_t esz = md == OO_F32 ? 4 : 2;
   for (int i = 0; i < M.n_layers; ++i) {
     w.wt[i] = o;
@@ -393,9 +395,11 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   e = launch_transpose_weights(M, mlp->dtype, Wt, stream);
   if (e != hipSuccess) return hip_status(e, "transpose launch");
   QuerySrc src{batch->x, batch->dir, A.B, full ? batch->x2 : batch->x, full ? batch->dir2 : batch->dir};
-  e = launch_bwd(T, tree->feat_dtype, M, mlp->dtype, Wt, src, Qb, nidx, seeds, post_scale, G, w.PL, partials, w.grid,
-                 stream);
+  float* dh = reinterpret_cast<float*>(ws + w.dh);
+  e = launch_bwd(T, tree->feat_dtype, M, mlp->dtype, Wt, src, Qb, nidx, seeds, w.PL, partials, dh, w.grid, stream);
   if (e != hipSuccess) return hip_status(e, "backward launch");
+  e = launch_scatter(T, src, Qb, nidx, dh, post_scale, G, stream);
+  if (e != hipSuccess) return hip_status(e, "scatter launch");
   ReduceDst D;
   D.n_seg = 2 * mlp->n_layers;
   for (int i = 0; i < mlp->n_layers; ++i) {

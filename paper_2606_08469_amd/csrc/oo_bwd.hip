@@ -8,11 +8,14 @@
 //  2. forward recompute of the hidden layers on matrix cores, activations
 //     kept in LDS as [neuron][query];
 //  3. backward: delta chained through W^T on matrix cores; dW of every layer
-//     contracted over the workgroup's 64 queries, each wave owning an eighth
-//     of the dW tiles in registers for the whole kernel; dh for every query;
-//  4. scatter: lanes grouped by channel add w_tap * dh into the FP32 feature
-//     gradient tables with hardware float atomics.
+//     contracted over the workgroup's 64 queries, each wave owning a share of
+//     the dW tiles in registers for the whole kernel; dh of every query
+//     written to memory.
 // dW/db leave as one partial per workgroup, reduced in a fixed order later.
+// A separate, high-occupancy kernel then scatters w_tap * dh into the FP32
+// feature gradient tables with hardware float atomics: inside the fused
+// kernel (one workgroup per CU) the atomic stream had too little latency
+// hiding.
 #include <hip/hip_runtime.h>
 
 #include "oo_device.h"
@@ -24,7 +27,7 @@ constexpr int kQW = 64;  // queries per workgroup tile
 
 struct BwdLayout {
   int KB0, R0;
-  size_t htile, act0, act1, delta, dh, qidx, qst, total;
+  size_t htile, act0, act1, delta, qidx, qst, total;
 };
 
 __host__ __device__ inline BwdLayout bwd_layout(int K0, int H, int n_layers, int L, int msz) {
@@ -33,21 +36,13 @@ __host__ __device__ inline BwdLayout bwd_layout(int K0, int H, int n_layers, int
   b.R0 = (K0 + 15) / 16 * 16;
   size_t o = 0;
   b.htile = o;
-  const size_t hbytes = (size_t)4 * b.KB0 * kWave * 8 * msz;
-  o += hbytes;
+  o += (size_t)4 * b.KB0 * kWave * 8 * msz;
   b.act0 = o;
   o += (size_t)b.R0 * kQW * msz;
   b.act1 = o;  // hidden-layer activations a_1 .. a_{n_layers-1}, H rows each
   o += (size_t)(n_layers - 1) * H * kQW * msz;
   b.delta = o;
   o += (size_t)H * kQW * msz;
-  const size_t dbytes = (size_t)kQW * b.R0 * 4;
-  if (dbytes <= hbytes) {
-    b.dh = b.htile;  // h is dead once the forward recompute is done
-  } else {
-    b.dh = o;
-    o += dbytes;
-  }
   b.qidx = o;
   o += (size_t)kQW * L * 4;
   b.qst = o;
@@ -160,8 +155,8 @@ template <class TT, class MT, int C, int H>
 __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, const MlpArgs M, const MlpArgs Mt,
                                                   const QuerySrc src, int64_t Q, const int32_t* __restrict__ nidx,
                                                   const float* __restrict__ seeds,
-                                                  float post_scale, const GradArgs G, const ParamLayout PL,
-                                                  float* __restrict__ partials) {
+                                                  const ParamLayout PL, float* __restrict__ partials,
+                                                  float* __restrict__ dh_out) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   typedef typename FragT<MT>::type frag;
   constexpr int MH = H / 16, MH2 = MH / kMSplit;
@@ -180,7 +175,6 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
   // input activation buffer of layer i: a_0 = h, a_i = ReLU(z_{i-1})
   auto act = [&](int i) { return i == 0 ? act0 : act1 + (size_t)(i - 1) * H * kQW; };
   MT* dT = reinterpret_cast<MT*>(smem + lay.delta);
-  float* dh = reinterpret_cast<float*>(smem + lay.dh);
   int* qidx = reinterpret_cast<int*>(smem + lay.qidx);
   float* qst = reinterpret_cast<float*>(smem + lay.qst);
 
@@ -218,10 +212,10 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
     {
       const int nv = (int)(Q - qbase < kQW ? Q - qbase : kQW);  // valid queries in this tile
       for (int e = tid; e < kQW * L; e += blockDim.x) {
-        int v = e < nv * L ? nidx[qbase * L + e] : -1;
-        const int l = e % L;
+        const int l = e / kQW, qq = e % kQW;  // nidx is level-major [L][Q]
+        int v = qq < nv ? nidx[(int64_t)l * Q + qbase + qq] : -1;
         if (v < T.off[l] || v >= T.off[l + 1]) v = -1;  // never index outside level l
-        qidx[e] = v;
+        qidx[qq * L + l] = v;
       }
       const int ql = tid / kLanesPerQuery, part = tid % kLanesPerQuery;
       const int64_t q = qbase + ql;
@@ -359,15 +353,16 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
           for (int mi = 0; mi < MK2; ++mi)
             if (mh * MK2 + mi < MK) dacc[mi] = mma(wfrag_global<MT>(Wt, K0, n_out, ldt, mh * MK2 + mi, kb, ln), b, dacc[mi]);
         }
-        __syncthreads();  // dh may alias the h tile; all reads of it are done
+        // dh of query column cs, rows 16m + 4g .. +3: one 16-byte store each
+        const int64_t q = qbase + cs;
+        if (q < Q) {
 #pragma unroll
-        for (int mi = 0; mi < MK2; ++mi)
-          if (mh * MK2 + mi < MK)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const int k = 16 * (mh * MK2 + mi) + 4 * gs + j;
-              if (k < K0) dh[cs * R0 + k] = dacc[mi][j];
-            }
+          for (int mi = 0; mi < MK2; ++mi) {
+            const int k = 16 * (mh * MK2 + mi) + 4 * gs;
+            if (mh * MK2 + mi < MK && k < K0)
+              *reinterpret_cast<float4*>(dh_out + q * K0 + k) = make_float4(dacc[mi][0], dacc[mi][1], dacc[mi][2], dacc[mi][3]);
+          }
+        }
       }
     };
     step(accO, NL - 1);
@@ -375,26 +370,7 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
     for (int hh = NHH - 1; hh >= 0; --hh)
       if (hh + 1 < NL - 1) step(accH[hh], hh + 1);
     step(acc0, 0);
-    __syncthreads();
-
-    // ---- 4. scatter into the feature gradient tables ---------------------
-    {
-      const int c = tid % C;
-      for (int p = tid / C; p < kQW * L; p += blockDim.x / C) {
-        const int ql = p / L, l = p % L;
-        const int id = qidx[ql * L + l];
-        if (id < 0) continue;
-        const int R = T.res[l];
-        int tx[4];
-        float w[4];
-        taps(qst[2 * ql], qst[2 * ql + 1], R, tx, w);
-        const float gv = dh[ql * R0 + l * C + c] * post_scale;
-        float* base = G.dfeat[l] + ((int64_t)(id - T.off[l]) * R * R) * C + c;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) unsafeAtomicAdd(base + (int64_t)tx[k] * C, w[k] * gv);
-      }
-    }
-    __syncthreads();
+    __syncthreads();  // LDS buffers are reused by the next tile
   }
 
   // ---- partials ------------------------------------------------------------
@@ -583,38 +559,89 @@ hipError_t launch_transpose_weights(const MlpArgs& M, oo_dtype md, void* const* 
 
 template <class TT, class MT, int C, int H>
 static hipError_t launch_bwd_t(const TreeArgs& T, const MlpArgs& M, const MlpArgs& Mt, const QuerySrc& src,
-                               int64_t Q, const int32_t* nidx, const float* seeds, float post_scale, const GradArgs& G,
-                               const ParamLayout& PL, float* partials, int grid, hipStream_t st) {
+                               int64_t Q, const int32_t* nidx, const float* seeds, const ParamLayout& PL,
+                               float* partials, float* dh, int grid, hipStream_t st) {
   const size_t lds = bwd_layout(M.K0, H, M.n_layers, T.L, (int)sizeof(MT)).total;
   auto k = bwd_kernel<TT, MT, C, H>;
   hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * kBwdWaves), lds, st, T, M, Mt, src, Q, nidx, seeds, post_scale, G, PL,
-                     partials);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * kBwdWaves), lds, st, T, M, Mt, src, Q, nidx, seeds, PL, partials, dh);
   return hipGetLastError();
 }
 
 template <class TT, class MT, int C>
 static hipError_t launch_bwd_c(const TreeArgs& T, const MlpArgs& M, const MlpArgs& Mt, const QuerySrc& src,
-                               int64_t Q, const int32_t* nidx, const float* seeds, float post_scale, const GradArgs& G,
-                               const ParamLayout& PL, float* partials, int grid, hipStream_t st) {
-  return M.H == 64
-             ? launch_bwd_t<TT, MT, C, 64>(T, M, Mt, src, Q, nidx, seeds, post_scale, G, PL, partials, grid, st)
-             : launch_bwd_t<TT, MT, C, 128>(T, M, Mt, src, Q, nidx, seeds, post_scale, G, PL, partials, grid, st);
+                               int64_t Q, const int32_t* nidx, const float* seeds, const ParamLayout& PL,
+                               float* partials, float* dh, int grid, hipStream_t st) {
+  return M.H == 64 ? launch_bwd_t<TT, MT, C, 64>(T, M, Mt, src, Q, nidx, seeds, PL, partials, dh, grid, st)
+                   : launch_bwd_t<TT, MT, C, 128>(T, M, Mt, src, Q, nidx, seeds, PL, partials, dh, grid, st);
 }
 
 hipError_t launch_bwd(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, void* const* Wt,
-                      const QuerySrc& src, int64_t Q, const int32_t* nidx, const float* seeds, float post_scale,
-                      const GradArgs& G, const ParamLayout& PL, float* partials, int grid, hipStream_t st) {
+                      const QuerySrc& src, int64_t Q, const int32_t* nidx, const float* seeds,
+                      const ParamLayout& PL, float* partials, float* dh, int grid, hipStream_t st) {
   MlpArgs Mt = M;
   for (int i = 0; i < M.n_layers; ++i) Mt.W[i] = Wt[i];
   if (td == OO_F32)
-    return T.C == 4
-               ? launch_bwd_c<float, float, 4>(T, M, Mt, src, Q, nidx, seeds, post_scale, G, PL, partials, grid, st)
-               : launch_bwd_c<float, float, 8>(T, M, Mt, src, Q, nidx, seeds, post_scale, G, PL, partials, grid, st);
-  if (td == OO_F16)
-    return launch_bwd_c<f16, f16, 8>(T, M, Mt, src, Q, nidx, seeds, post_scale, G, PL, partials, grid, st);
-  return launch_bwd_c<bf16, bf16, 8>(T, M, Mt, src, Q, nidx, seeds, post_scale, G, PL, partials, grid, st);
+    return T.C == 4 ? launch_bwd_c<float, float, 4>(T, M, Mt, src, Q, nidx, seeds, PL, partials, dh, grid, st)
+                    : launch_bwd_c<float, float, 8>(T, M, Mt, src, Q, nidx, seeds, PL, partials, dh, grid, st);
+  if (td == OO_F16) return launch_bwd_c<f16, f16, 8>(T, M, Mt, src, Q, nidx, seeds, PL, partials, dh, grid, st);
+  return launch_bwd_c<bf16, bf16, 8>(T, M, Mt, src, Q, nidx, seeds, PL, partials, dh, grid, st);
   (void)md;
+}
+
+// Feature-gradient scatter: one lane per (query, tap, channel) at level
+// l = blockIdx.y, queries along x, so one atomic instruction of a wave covers
+// whole bilinear footprints (4C consecutive lanes per query). The memory-side
+// atomic units work on 64-byte chunks, one chunk per instruction and chunk
+// touched, so the two taps of a footprint row (2C contiguous floats) mostly
+// share one chunk and a 2x2 map (the finest levels) takes two chunks per
+// query. Each lane adds w_tap * dh[q][l C + c] * post_scale with a hardware
+// FP32 atomic. Node indices come from the forward ([L][Q]) and are
+// range-checked; taps are recomputed from the direction.
+template <int C>
+__global__ __launch_bounds__(256) void scatter_kernel(const TreeArgs T, const QuerySrc src, int64_t Q,
+                                                      const int32_t* __restrict__ nidx, const float* __restrict__ dh,
+                                                      float post_scale, const GradArgs G) {
+  const int l = blockIdx.y;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t q = gid / (4 * C);
+  const int k = (int)(gid / C) & 3;
+  const int c = (int)(gid % C);
+  if (q >= Q) return;
+  const int id = nidx[(int64_t)l * Q + q];
+  if (id < T.off[l] || id >= T.off[l + 1]) return;
+  float x[3], d[3];
+  load_query(src, q, x, d);
+  float s, t;
+  octa(d, s, t);
+  const int R = T.res[l];
+  int tx[4];
+  float w[4];
+  taps(s, t, R, tx, w);
+  int txk = tx[0];
+  float wk = w[0];
+#pragma unroll
+  for (int j = 1; j < 4; ++j)
+    if (k == j) {
+      txk = tx[j];
+      wk = w[j];
+    }
+  const float gv = dh[q * (int64_t)(T.L * C) + l * C + c] * post_scale;
+  unsafeAtomicAdd(G.dfeat[l] + ((int64_t)(id - T.off[l]) * R * R + txk) * C + c, wk * gv);
+}
+
+hipError_t launch_scatter(const TreeArgs& T, const QuerySrc& src, int64_t Q, const int32_t* nidx, const float* dh,
+                          float post_scale, const GradArgs& G, hipStream_t st) {
+  if (Q == 0) return hipSuccess;
+  const int64_t blocks = (Q * 4 * T.C + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  if (T.C == 4)
+    hipLaunchKernelGGL(scatter_kernel<4>, dim3((unsigned)blocks, T.L), dim3(256), 0, st, T, src, Q, nidx, dh,
+                       post_scale, G);
+  else
+    hipLaunchKernelGGL(scatter_kernel<8>, dim3((unsigned)blocks, T.L), dim3(256), 0, st, T, src, Q, nidx, dh,
+                       post_scale, G);
+  return hipGetLastError();
 }
 
 hipError_t launch_dw_reduce(const float* partials, int grid, const ParamLayout& PL, const ReduceDst& D, float scale,

@@ -206,7 +206,8 @@ __device__ inline void store_rgb(const f32x4 out[NT], int t0, int64_t q_base, in
 // Fused query: encode 64 queries per wave into LDS, decode them there.
 // ---------------------------------------------------------------------------
 // Queries q < n_idx also store their node index per level in idx_out
-// ([n_idx][L]), which the residual backward reads instead of descending again.
+// (level-major [L][n_idx]), which the residual backward reads instead of
+// descending again.
 template <class TT, class MT, int C, int H, bool WLDS>
 __global__ __launch_bounds__(512) void query_kernel(const TreeArgs T, const MlpArgs M, const QuerySrc src,
                                                     int64_t Q, float* __restrict__ rgb, int32_t* __restrict__ idx_out,
@@ -238,7 +239,7 @@ __global__ __launch_bounds__(512) void query_kernel(const TreeArgs T, const MlpA
     encode_pipelined<TT, C>(T, valid, x, s, t, [&](int l, const float* h, int node) {
 #pragma unroll
       for (int c = 0; c < C; c += 4) htile_put4<MT>(htile, KB0, lane, l * C + c, &h[c]);
-      if (keep) idx_out[q * T.L + l] = node;
+      if (keep) idx_out[l * n_idx + q] = node;  // level-major: coalesced across lanes
     });
     wave_lds_sync();
 #pragma unroll

@@ -56,8 +56,10 @@ hipError_t launch_seeds(const ResidualArgs& A, const float* resid, const float* 
                         int full, float* seeds, hipStream_t st);
 hipError_t launch_transpose_weights(const MlpArgs& M, oo_dtype md, void* const* Wt, hipStream_t st);
 hipError_t launch_bwd(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, void* const* Wt,
-                      const QuerySrc& src, int64_t Q, const int32_t* nidx, const float* seeds, float post_scale,
-                      const GradArgs& G, const ParamLayout& PL, float* partials, int grid, hipStream_t st);
+                      const QuerySrc& src, int64_t Q, const int32_t* nidx, const float* seeds,
+                      const ParamLayout& PL, float* partials, float* dh, int grid, hipStream_t st);
+hipError_t launch_scatter(const TreeArgs& T, const QuerySrc& src, int64_t Q, const int32_t* nidx, const float* dh,
+                          float post_scale, const GradArgs& G, hipStream_t st);
 hipError_t launch_dw_reduce(const float* partials, int grid, const ParamLayout& PL, const ReduceDst& D, float scale,
                             hipStream_t st);
 
