@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -136,7 +137,7 @@ int check_batch(const oo_residual_batch* b, ResidualArgs& A) {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Workspace {
-  size_t Lq, lossp, seeds, nidx, dh, wt[OO_MAX_LAYERS], dwp, total;
+  size_t Lq, lossp, seeds, nidx, dh, wt[OO_MAX_LAYERS], dwp, xs, ds, order, scount, stotal, sstart, total;
   int64_t Qb;
   int grid;
   ParamLayout PL;
@@ -184,6 +185,20 @@ Workspace workspace_layout(const MlpArgs& M, oo_dtype md, const oo_residual_batc
   }
   w.dwp = o;
   o = align256(o + (size_t)w.grid * w.PL.P * sizeof(float));
+  // spatially bucketed queries, written by the forward and read by both passes
+  const SortShape ss = sort_shape(Qf, L - 1);
+  w.xs = o;
+  o = align256(o + (size_t)Qf * sizeof(float4));
+  w.ds = o;
+  o = align256(o + (size_t)Qf * sizeof(float4));
+  w.order = o;
+  o = align256(o + (size_t)Qf * sizeof(int32_t));
+  w.scount = o;
+  o = align256(o + (size_t)ss.NB * ss.K * sizeof(int32_t));
+  w.stotal = o;
+  o = align256(o + (size_t)ss.K * sizeof(int32_t));
+  w.sstart = o;
+  o = align256(o + (size_t)ss.K * sizeof(int32_t));
   w.total = o;
   return w;
 }
@@ -312,7 +327,7 @@ int oo_query_fwd(const oo_tree* tree, const oo_mlp* mlp, const float* x, const f
   if (B == 0) return OO_OK;
   if (!x || !dir || !rgb_out) return fail(OO_EINVAL, "x, dir and rgb_out are required");
   QuerySrc src{x, dir, B, x, dir};
-  return hip_status(launch_query(T, tree->feat_dtype, M, mlp->dtype, src, B, rgb_out, nullptr, 0, stream),
+  return hip_status(launch_query(T, tree->feat_dtype, M, mlp->dtype, src, B, rgb_out, nullptr, 0, nullptr, stream),
                     "query_fwd launch");
 }
 
@@ -350,8 +365,22 @@ int oo_radiosity_residual_fwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   double* lossp = reinterpret_cast<double*>(ws + w.lossp);
   int32_t* nidx = reinterpret_cast<int32_t*>(ws + w.nidx);
   const int64_t Q = A.B * (1 + A.N);
+  if (Q > INT32_MAX) return fail(OO_EUNSUPPORTED, "B (1 + N) = %lld exceeds 2^31 - 1 queries", (long long)Q);
   QuerySrc src{batch->x, batch->dir, A.B, A.N > 0 ? batch->x2 : batch->x, A.N > 0 ? batch->dir2 : batch->dir};
-  hipError_t e = launch_query(T, tree->feat_dtype, M, mlp->dtype, src, Q, Lq, nidx, w.Qb, stream);
+  // bucket the queries by octree cell (LHS first), then evaluate them in that
+  // order; radiance lands back in the caller's order
+  float4* xs = reinterpret_cast<float4*>(ws + w.xs);
+  float4* ds = reinterpret_cast<float4*>(ws + w.ds);
+  int32_t* order = reinterpret_cast<int32_t*>(ws + w.order);
+  hipError_t e = launch_spatial_sort(src, Q, A.B, tree->n_levels - 1, reinterpret_cast<int32_t*>(ws + w.scount),
+                                     reinterpret_cast<int32_t*>(ws + w.stotal),
+                                     reinterpret_cast<int32_t*>(ws + w.sstart), xs, ds, order, stream);
+  if (e != hipSuccess) return hip_status(e, "query bucketing launch");
+  QuerySrc sorted{};
+  sorted.nA = Q;
+  sorted.x4 = xs;
+  sorted.d4 = ds;
+  e = launch_query(T, tree->feat_dtype, M, mlp->dtype, sorted, Q, Lq, nidx, w.Qb, order, stream);
   if (e != hipSuccess) return hip_status(e, "residual query launch");
   return hip_status(launch_combine(A, Lq, lhs_out, rhs_out, resid_out, lossp, loss_out, stream), "combine launch");
 }
@@ -394,9 +423,16 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   if (e != hipSuccess) return hip_status(e, "seed launch");
   e = launch_transpose_weights(M, mlp->dtype, Wt, stream);
   if (e != hipSuccess) return hip_status(e, "transpose launch");
-  QuerySrc src{batch->x, batch->dir, A.B, full ? batch->x2 : batch->x, full ? batch->dir2 : batch->dir};
+  // the forward's bucketed queries: the first Qb sorted positions are the
+  // backward's queries (all LHS queries come first)
+  QuerySrc src{};
+  src.nA = Qb;
+  src.x4 = reinterpret_cast<const float4*>(ws + w.xs);
+  src.d4 = reinterpret_cast<const float4*>(ws + w.ds);
+  const int32_t* order = reinterpret_cast<const int32_t*>(ws + w.order);
   float* dh = reinterpret_cast<float*>(ws + w.dh);
-  e = launch_bwd(T, tree->feat_dtype, M, mlp->dtype, Wt, src, Qb, nidx, seeds, w.PL, partials, dh, w.grid, stream);
+  e = launch_bwd(T, tree->feat_dtype, M, mlp->dtype, Wt, src, Qb, nidx, seeds, order, w.PL, partials, dh, w.grid,
+                 stream);
   if (e != hipSuccess) return hip_status(e, "backward launch");
   e = launch_scatter(T, src, Qb, nidx, dh, post_scale, G, stream);
   if (e != hipSuccess) return hip_status(e, "scatter launch");

@@ -1,10 +1,11 @@
 // Backward of the residual step: seeds, the fused recompute + decoder
-// backward + feature scatter kernel, and the fixed-order dW/db reduction.
+// backward kernel, the feature-gradient scatter, and the fixed-order dW/db
+// reduction.
 //
-// One workgroup (8 waves) handles 64 queries at a time:
-//  1. encode: 8 lanes per query, each gathering whole texels of every eighth
-//     level; h written to an LDS fragment tile and, transposed, to the
-//     layer-0 activation buffer;
+// One workgroup (16 waves) handles 64 queries at a time:
+//  1. encode: node indices come from the forward; 16 lanes per query, each
+//     gathering whole texels of one level; h written to an LDS fragment tile
+//     and, transposed, to the layer-0 activation buffer;
 //  2. forward recompute of the hidden layers on matrix cores, activations
 //     kept in LDS as [neuron][query];
 //  3. backward: delta chained through W^T on matrix cores; dW of every layer
@@ -13,9 +14,7 @@
 //     written to memory.
 // dW/db leave as one partial per workgroup, reduced in a fixed order later.
 // A separate, high-occupancy kernel then scatters w_tap * dh into the FP32
-// feature gradient tables with hardware float atomics: inside the fused
-// kernel (one workgroup per CU) the atomic stream had too little latency
-// hiding.
+// feature gradient tables with hardware float atomics.
 #include <hip/hip_runtime.h>
 
 #include "oo_device.h"
@@ -66,9 +65,11 @@ __device__ inline void htile_put1(MT* tile, int KB, int q, int k, float v) {
   tile[htile_index<MT>(q, k, KB)] = from_f32<MT>(v);
 }
 
-// Waves per workgroup. 4 waves give each wave 512 registers (one wave per
-// SIMD), enough for the dW accumulators of a 128-wide MLP without spilling.
-constexpr int kBwdWaves = 4;
+// Waves per workgroup. With 16 waves (four per SIMD) each wave owns a
+// sixteenth of the dW tiles, which keeps a 128-wide MLP's accumulators and
+// working set within 128 registers; the extra waves hide the gather and
+// weight-load latency that dominates this kernel.
+constexpr int kBwdWaves = 16;
 constexpr int kMSplit = kBwdWaves / 4;           // waves sharing one query column block
 constexpr int kLanesPerQuery = 64 * kBwdWaves / kQW;
 
@@ -154,7 +155,7 @@ __device__ inline void store_tq(MT* buf, const f32x4 (&acc)[MT2], int m0, int n_
 template <class TT, class MT, int C, int H>
 __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, const MlpArgs M, const MlpArgs Mt,
                                                   const QuerySrc src, int64_t Q, const int32_t* __restrict__ nidx,
-                                                  const float* __restrict__ seeds,
+                                                  const float* __restrict__ seeds, const int32_t* __restrict__ order,
                                                   const ParamLayout PL, float* __restrict__ partials,
                                                   float* __restrict__ dh_out) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -201,7 +202,8 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
   __syncthreads();
 
   const int64_t n_tiles = (Q + kQW - 1) / kQW;
-  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+  const TileRange tr = xcd_tiles(n_tiles, 1, 0);  // neighbouring tiles share an XCD's L2
+  for (int64_t tile = tr.first; tile < tr.end; tile += tr.stride) {
     const int64_t qbase = tile * kQW;
     // Lane-derived LDS addresses are loop-invariant; recompute them per tile
     // rather than holding a hundred of them in registers across the loop.
@@ -224,8 +226,10 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
         if (q < Q) load_query(src, q, x, d);
         float s, t;
         octa(d, s, t);
-        qst[2 * ql] = s;
-        qst[2 * ql + 1] = t;
+        // directions come from the workspace: keep the taps inside the map
+        // even for a workspace the forward did not fill
+        qst[2 * ql] = fminf(fmaxf(s, 0.0f), 1.0f);
+        qst[2 * ql + 1] = fminf(fmaxf(t, 0.0f), 1.0f);
       }
       __syncthreads();
       const float s = qst[2 * ql], t = qst[2 * ql + 1];
@@ -289,11 +293,17 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
     // ---- 3. backward ------------------------------------------------------
     if (mh == 0) {  // seeds of the output layer into the delta buffer, rows 0..15
       const int64_t q = qbase + col;
+      // seeds are stored in the caller's query order
+      int64_t qs = q < Q ? q : -1;
+      if (order && qs >= 0) {
+        qs = order[q];
+        if (qs >= Q) qs = -1;
+      }
       f32x4 so[1];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int row = 4 * g + j;
-        so[0][j] = (row < 3 && q < Q) ? seeds[3 * q + row] : 0.0f;
+        so[0][j] = (row < 3 && qs >= 0) ? seeds[3 * qs + row] : 0.0f;
       }
       store_tq<MT, 1>(dT, so, 0, 1, 3, nt, lane, false);
     }
@@ -533,7 +543,9 @@ int bwd_grid(const MlpArgs& M, oo_dtype md, int L, int64_t Q) {
   const int64_t n_tiles = (Q + kQW - 1) / kQW;
   const size_t lds = bwd_lds_bytes(M, md, L);
   int per_cu = (int)((size_t)160 * 1024 / (lds ? lds : 1));
-  per_cu = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
+  const int by_waves = 16 / kBwdWaves;  // four waves per SIMD fit the kernel's registers
+  if (per_cu > by_waves) per_cu = by_waves;
+  per_cu = per_cu < 1 ? 1 : per_cu;
   int64_t g = (int64_t)cu_count() * per_cu;
   if (g > n_tiles) g = n_tiles;
   return (int)(g > 0 ? g : 1);
@@ -559,33 +571,34 @@ hipError_t launch_transpose_weights(const MlpArgs& M, oo_dtype md, void* const* 
 
 template <class TT, class MT, int C, int H>
 static hipError_t launch_bwd_t(const TreeArgs& T, const MlpArgs& M, const MlpArgs& Mt, const QuerySrc& src,
-                               int64_t Q, const int32_t* nidx, const float* seeds, const ParamLayout& PL,
-                               float* partials, float* dh, int grid, hipStream_t st) {
+                               int64_t Q, const int32_t* nidx, const float* seeds, const int32_t* order,
+                               const ParamLayout& PL, float* partials, float* dh, int grid, hipStream_t st) {
   const size_t lds = bwd_layout(M.K0, H, M.n_layers, T.L, (int)sizeof(MT)).total;
   auto k = bwd_kernel<TT, MT, C, H>;
   hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * kBwdWaves), lds, st, T, M, Mt, src, Q, nidx, seeds, PL, partials, dh);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * kBwdWaves), lds, st, T, M, Mt, src, Q, nidx, seeds, order, PL, partials,
+                     dh);
   return hipGetLastError();
 }
 
 template <class TT, class MT, int C>
 static hipError_t launch_bwd_c(const TreeArgs& T, const MlpArgs& M, const MlpArgs& Mt, const QuerySrc& src,
-                               int64_t Q, const int32_t* nidx, const float* seeds, const ParamLayout& PL,
-                               float* partials, float* dh, int grid, hipStream_t st) {
-  return M.H == 64 ? launch_bwd_t<TT, MT, C, 64>(T, M, Mt, src, Q, nidx, seeds, PL, partials, dh, grid, st)
-                   : launch_bwd_t<TT, MT, C, 128>(T, M, Mt, src, Q, nidx, seeds, PL, partials, dh, grid, st);
+                               int64_t Q, const int32_t* nidx, const float* seeds, const int32_t* order,
+                               const ParamLayout& PL, float* partials, float* dh, int grid, hipStream_t st) {
+  return M.H == 64 ? launch_bwd_t<TT, MT, C, 64>(T, M, Mt, src, Q, nidx, seeds, order, PL, partials, dh, grid, st)
+                   : launch_bwd_t<TT, MT, C, 128>(T, M, Mt, src, Q, nidx, seeds, order, PL, partials, dh, grid, st);
 }
 
 hipError_t launch_bwd(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, void* const* Wt,
-                      const QuerySrc& src, int64_t Q, const int32_t* nidx, const float* seeds,
+                      const QuerySrc& src, int64_t Q, const int32_t* nidx, const float* seeds, const int32_t* order,
                       const ParamLayout& PL, float* partials, float* dh, int grid, hipStream_t st) {
   MlpArgs Mt = M;
   for (int i = 0; i < M.n_layers; ++i) Mt.W[i] = Wt[i];
   if (td == OO_F32)
-    return T.C == 4 ? launch_bwd_c<float, float, 4>(T, M, Mt, src, Q, nidx, seeds, PL, partials, dh, grid, st)
-                    : launch_bwd_c<float, float, 8>(T, M, Mt, src, Q, nidx, seeds, PL, partials, dh, grid, st);
-  if (td == OO_F16) return launch_bwd_c<f16, f16, 8>(T, M, Mt, src, Q, nidx, seeds, PL, partials, dh, grid, st);
-  return launch_bwd_c<bf16, bf16, 8>(T, M, Mt, src, Q, nidx, seeds, PL, partials, dh, grid, st);
+    return T.C == 4 ? launch_bwd_c<float, float, 4>(T, M, Mt, src, Q, nidx, seeds, order, PL, partials, dh, grid, st)
+                    : launch_bwd_c<float, float, 8>(T, M, Mt, src, Q, nidx, seeds, order, PL, partials, dh, grid, st);
+  if (td == OO_F16) return launch_bwd_c<f16, f16, 8>(T, M, Mt, src, Q, nidx, seeds, order, PL, partials, dh, grid, st);
+  return launch_bwd_c<bf16, bf16, 8>(T, M, Mt, src, Q, nidx, seeds, order, PL, partials, dh, grid, st);
   (void)md;
 }
 
@@ -614,6 +627,8 @@ __global__ __launch_bounds__(256) void scatter_kernel(const TreeArgs T, const Qu
   load_query(src, q, x, d);
   float s, t;
   octa(d, s, t);
+  s = fminf(fmaxf(s, 0.0f), 1.0f);  // directions come from the workspace
+  t = fminf(fmaxf(t, 0.0f), 1.0f);
   const int R = T.res[l];
   int tx[4];
   float w[4];

@@ -42,9 +42,36 @@ struct QuerySrc {
   int64_t nA;
   const float* xB;
   const float* dB;
+  // When set: packed [Q] position / direction arrays (w unused), read
+  // instead of the two-part source above.
+  const float4* x4;
+  const float4* d4;
 };
 
+__device__ inline void load_pos(const QuerySrc& s, int64_t q, float x[3]) {
+  if (s.x4) {
+    const float4 a = s.x4[q];
+    x[0] = a.x;
+    x[1] = a.y;
+    x[2] = a.z;
+    return;
+  }
+  const float* xp = q < s.nA ? s.xA + 3 * q : s.xB + 3 * (q - s.nA);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) x[a] = xp[a];
+}
+
 __device__ inline void load_query(const QuerySrc& s, int64_t q, float x[3], float d[3]) {
+  if (s.x4) {
+    const float4 a = s.x4[q], b = s.d4[q];
+    x[0] = a.x;
+    x[1] = a.y;
+    x[2] = a.z;
+    d[0] = b.x;
+    d[1] = b.y;
+    d[2] = b.z;
+    return;
+  }
   const float* xp = q < s.nA ? s.xA + 3 * q : s.xB + 3 * (q - s.nA);
   const float* dp = q < s.nA ? s.dA + 3 * q : s.dB + 3 * (q - s.nA);
 #pragma unroll

@@ -188,15 +188,17 @@ __host__ __device__ inline int packed_weight_elems(int n_layers, int K0, int H) 
 }
 
 template <class MT, int NT>
-__device__ inline void store_rgb(const f32x4 out[NT], int t0, int64_t q_base, int64_t Q, int lane, float* rgb) {
+__device__ inline void store_rgb(const f32x4 out[NT], int t0, int64_t q_base, int64_t Q, int lane, float* rgb,
+                                 const int32_t* out_row = nullptr) {
   if (lane < 16) {
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int64_t q = q_base + 16 * (t0 + t) + lane;
       if (q < Q) {
-        rgb[3 * q + 0] = out[t][0];
-        rgb[3 * q + 1] = out[t][1];
-        rgb[3 * q + 2] = out[t][2];
+        const int64_t r = out_row ? (int64_t)out_row[q] : q;
+        rgb[3 * r + 0] = out[t][0];
+        rgb[3 * r + 1] = out[t][1];
+        rgb[3 * r + 2] = out[t][2];
       }
     }
   }
@@ -207,11 +209,12 @@ __device__ inline void store_rgb(const f32x4 out[NT], int t0, int64_t q_base, in
 // ---------------------------------------------------------------------------
 // Queries q < n_idx also store their node index per level in idx_out
 // (level-major [L][n_idx]), which the residual backward reads instead of
-// descending again.
+// descending again. With out_row set, query q's radiance goes to row
+// out_row[q] (the caller's order when the queries were bucketed).
 template <class TT, class MT, int C, int H, bool WLDS>
 __global__ __launch_bounds__(512) void query_kernel(const TreeArgs T, const MlpArgs M, const QuerySrc src,
                                                     int64_t Q, float* __restrict__ rgb, int32_t* __restrict__ idx_out,
-                                                    int64_t n_idx) {
+                                                    int64_t n_idx, const int32_t* __restrict__ out_row) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   constexpr int NT = 2;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63, waves = blockDim.x >> 6;
@@ -246,7 +249,7 @@ __global__ __launch_bounds__(512) void query_kernel(const TreeArgs T, const MlpA
     for (int t0 = 0; t0 < 4; t0 += NT) {
       f32x4 out[NT];
       mlp_forward_tiles<MT, H, NT>(M, W, htile, KB0, t0, lane, out);
-      store_rgb<MT, NT>(out, t0, tile * 64, Q, lane, rgb);
+      store_rgb<MT, NT>(out, t0, tile * 64, Q, lane, rgb, out_row);
     }
     wave_lds_sync();
   }
@@ -535,7 +538,7 @@ static void tile_launch_shape(const MlpArgs& M, int64_t Q, bool& wlds, int& wave
 
 template <class TT, class MT, int C, int H>
 static hipError_t launch_query_t(const TreeArgs& T, const MlpArgs& M, const QuerySrc& src, int64_t Q, float* rgb,
-                                 int32_t* idx_out, int64_t n_idx, hipStream_t st) {
+                                 int32_t* idx_out, int64_t n_idx, const int32_t* out_row, hipStream_t st) {
   bool wlds;
   int waves, grid;
   size_t lds;
@@ -543,30 +546,31 @@ static hipError_t launch_query_t(const TreeArgs& T, const MlpArgs& M, const Quer
   if (wlds) {
     auto k = query_kernel<TT, MT, C, H, true>;
     hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, st, T, M, src, Q, rgb, idx_out, n_idx);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, st, T, M, src, Q, rgb, idx_out, n_idx, out_row);
   } else {
     auto k = query_kernel<TT, MT, C, H, false>;
     hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, st, T, M, src, Q, rgb, idx_out, n_idx);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, st, T, M, src, Q, rgb, idx_out, n_idx, out_row);
   }
   return hipGetLastError();
 }
 
 template <class TT, class MT, int C>
 static hipError_t launch_query_c(const TreeArgs& T, const MlpArgs& M, const QuerySrc& src, int64_t Q, float* rgb,
-                                 int32_t* idx_out, int64_t n_idx, hipStream_t st) {
-  return M.H == 64 ? launch_query_t<TT, MT, C, 64>(T, M, src, Q, rgb, idx_out, n_idx, st)
-                   : launch_query_t<TT, MT, C, 128>(T, M, src, Q, rgb, idx_out, n_idx, st);
+                                 int32_t* idx_out, int64_t n_idx, const int32_t* out_row, hipStream_t st) {
+  return M.H == 64 ? launch_query_t<TT, MT, C, 64>(T, M, src, Q, rgb, idx_out, n_idx, out_row, st)
+                   : launch_query_t<TT, MT, C, 128>(T, M, src, Q, rgb, idx_out, n_idx, out_row, st);
 }
 
 hipError_t launch_query(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, const QuerySrc& src,
-                        int64_t Q, float* rgb, int32_t* idx_out, int64_t n_idx, hipStream_t st) {
+                        int64_t Q, float* rgb, int32_t* idx_out, int64_t n_idx, const int32_t* out_row,
+                        hipStream_t st) {
   if (Q == 0) return hipSuccess;
   if (td == OO_F32)
-    return T.C == 4 ? launch_query_c<float, float, 4>(T, M, src, Q, rgb, idx_out, n_idx, st)
-                    : launch_query_c<float, float, 8>(T, M, src, Q, rgb, idx_out, n_idx, st);
-  if (td == OO_F16) return launch_query_c<f16, f16, 8>(T, M, src, Q, rgb, idx_out, n_idx, st);
-  return launch_query_c<bf16, bf16, 8>(T, M, src, Q, rgb, idx_out, n_idx, st);
+    return T.C == 4 ? launch_query_c<float, float, 4>(T, M, src, Q, rgb, idx_out, n_idx, out_row, st)
+                    : launch_query_c<float, float, 8>(T, M, src, Q, rgb, idx_out, n_idx, out_row, st);
+  if (td == OO_F16) return launch_query_c<f16, f16, 8>(T, M, src, Q, rgb, idx_out, n_idx, out_row, st);
+  return launch_query_c<bf16, bf16, 8>(T, M, src, Q, rgb, idx_out, n_idx, out_row, st);
   (void)md;
 }
 
