@@ -137,7 +137,7 @@ int check_batch(const oo_residual_batch* b, ResidualArgs& A) {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Workspace {
-  size_t Lq, lossp, seeds, nidx, dh, wt[OO_MAX_LAYERS], dwp, xs, ds, order, scount, stotal, sstart, total;
+  size_t Lq, lossp, seeds, nidx, uv, dh, wt[OO_MAX_LAYERS], dwp, order, rank, scount, stotal, sstart, total;
   int64_t Qb;
   int grid;
   ParamLayout PL;
@@ -176,6 +176,8 @@ Workspace workspace_layout(const MlpArgs& M, oo_dtype md, const oo_residual_batc
   w.Qb = Qb;
   w.nidx = o;  // node index per level of every backward query, written by the forward, [L][Qb]
   o = align256(o + (size_t)Qb * L * sizeof(int32_t));
+  w.uv = o;  // octahedral coordinates of every backward query, written by the forward, [Qb]
+  o = align256(o + (size_t)Qb * sizeof(float2));
   w.dh = o;  // dLoss/dh of every backward query, [Qb][K0] FP32
   o = align256(o + (size_t)Qb * M.K0 * sizeof(float));
   const size_t esz = md == OO_F32 ? 4 : 2;
@@ -187,11 +189,9 @@ Workspace workspace_layout(const MlpArgs& M, oo_dtype md, const oo_residual_batc
   o = align256(o + (size_t)w.grid * w.PL.P * sizeof(float));
   // spatially bucketed queries, written by the forward and read by both passes
   const SortShape ss = sort_shape(Qf, L - 1);
-  w.xs = o;
-  o = align256(o + (size_t)Qf * sizeof(float4));
-  w.ds = o;
-  o = align256(o + (size_t)Qf * sizeof(float4));
   w.order = o;
+  o = align256(o + (size_t)Qf * sizeof(int32_t));
+  w.rank = o;
   o = align256(o + (size_t)Qf * sizeof(int32_t));
   w.scount = o;
   o = align256(o + (size_t)ss.NB * ss.K * sizeof(int32_t));
@@ -327,7 +327,7 @@ int oo_query_fwd(const oo_tree* tree, const oo_mlp* mlp, const float* x, const f
   if (B == 0) return OO_OK;
   if (!x || !dir || !rgb_out) return fail(OO_EINVAL, "x, dir and rgb_out are required");
   QuerySrc src{x, dir, B, x, dir};
-  return hip_status(launch_query(T, tree->feat_dtype, M, mlp->dtype, src, B, rgb_out, nullptr, 0, nullptr, stream),
+  return hip_status(launch_query(T, tree->feat_dtype, M, mlp->dtype, src, B, rgb_out, nullptr, nullptr, 0, stream),
                     "query_fwd launch");
 }
 
@@ -367,22 +367,21 @@ int oo_radiosity_residual_fwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   const int64_t Q = A.B * (1 + A.N);
   if (Q > INT32_MAX) return fail(OO_EUNSUPPORTED, "B (1 + N) = %lld exceeds 2^31 - 1 queries", (long long)Q);
   QuerySrc src{batch->x, batch->dir, A.B, A.N > 0 ? batch->x2 : batch->x, A.N > 0 ? batch->dir2 : batch->dir};
-  // bucket the queries by octree cell (LHS first), then evaluate them in that
-  // order; radiance lands back in the caller's order
-  float4* xs = reinterpret_cast<float4*>(ws + w.xs);
-  float4* ds = reinterpret_cast<float4*>(ws + w.ds);
+  // bucket the queries by octree cell (LHS first) and evaluate them in that
+  // order: Lq and the stored node indices are in sorted order
   int32_t* order = reinterpret_cast<int32_t*>(ws + w.order);
+  int32_t* rank = reinterpret_cast<int32_t*>(ws + w.rank);
   hipError_t e = launch_spatial_sort(src, Q, A.B, tree->n_levels - 1, reinterpret_cast<int32_t*>(ws + w.scount),
                                      reinterpret_cast<int32_t*>(ws + w.stotal),
-                                     reinterpret_cast<int32_t*>(ws + w.sstart), xs, ds, order, stream);
+                                     reinterpret_cast<int32_t*>(ws + w.sstart), order, rank, stream);
   if (e != hipSuccess) return hip_status(e, "query bucketing launch");
-  QuerySrc sorted{};
-  sorted.nA = Q;
-  sorted.x4 = xs;
-  sorted.d4 = ds;
-  e = launch_query(T, tree->feat_dtype, M, mlp->dtype, sorted, Q, Lq, nidx, w.Qb, order, stream);
+  QuerySrc sorted = src;
+  sorted.idx = order;
+  sorted.n = Q;
+  e = launch_query(T, tree->feat_dtype, M, mlp->dtype, sorted, Q, Lq, nidx, reinterpret_cast<float2*>(ws + w.uv), w.Qb,
+                   stream);
   if (e != hipSuccess) return hip_status(e, "residual query launch");
-  return hip_status(launch_combine(A, Lq, lhs_out, rhs_out, resid_out, lossp, loss_out, stream), "combine launch");
+  return hip_status(launch_combine(A, Lq, rank, lhs_out, rhs_out, resid_out, lossp, loss_out, stream), "combine launch");
 }
 
 int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_residual_batch* batch,
@@ -423,18 +422,15 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   if (e != hipSuccess) return hip_status(e, "seed launch");
   e = launch_transpose_weights(M, mlp->dtype, Wt, stream);
   if (e != hipSuccess) return hip_status(e, "transpose launch");
-  // the forward's bucketed queries: the first Qb sorted positions are the
-  // backward's queries (all LHS queries come first)
-  QuerySrc src{};
-  src.nA = Qb;
-  src.x4 = reinterpret_cast<const float4*>(ws + w.xs);
-  src.d4 = reinterpret_cast<const float4*>(ws + w.ds);
+  // the forward's bucketed order: its first Qb sorted positions are the
+  // backward's queries (all LHS queries come first); node indices and
+  // octahedral coordinates were stored at those positions
   const int32_t* order = reinterpret_cast<const int32_t*>(ws + w.order);
+  const float2* uv = reinterpret_cast<const float2*>(ws + w.uv);
   float* dh = reinterpret_cast<float*>(ws + w.dh);
-  e = launch_bwd(T, tree->feat_dtype, M, mlp->dtype, Wt, src, Qb, nidx, seeds, order, w.PL, partials, dh, w.grid,
-                 stream);
+  e = launch_bwd(T, tree->feat_dtype, M, mlp->dtype, Wt, Qb, nidx, uv, seeds, order, w.PL, partials, dh, w.grid, stream);
   if (e != hipSuccess) return hip_status(e, "backward launch");
-  e = launch_scatter(T, src, Qb, nidx, dh, post_scale, G, stream);
+  e = launch_scatter(T, Qb, nidx, uv, dh, post_scale, G, stream);
   if (e != hipSuccess) return hip_status(e, "scatter launch");
   ReduceDst D;
   D.n_seg = 2 * mlp->n_layers;

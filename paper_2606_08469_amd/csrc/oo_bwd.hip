@@ -154,7 +154,8 @@ __device__ inline void store_tq(MT* buf, const f32x4 (&acc)[MT2], int m0, int n_
 // [row][query] buffers.
 template <class TT, class MT, int C, int H>
 __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, const MlpArgs M, const MlpArgs Mt,
-                                                  const QuerySrc src, int64_t Q, const int32_t* __restrict__ nidx,
+                                                  int64_t Q, const int32_t* __restrict__ nidx,
+                                                  const float2* __restrict__ uv,
                                                   const float* __restrict__ seeds, const int32_t* __restrict__ order,
                                                   const ParamLayout PL, float* __restrict__ partials,
                                                   float* __restrict__ dh_out) {
@@ -222,14 +223,11 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
       const int ql = tid / kLanesPerQuery, part = tid % kLanesPerQuery;
       const int64_t q = qbase + ql;
       if (part == 0) {
-        float x[3] = {0.f, 0.f, 0.f}, d[3] = {0.f, 0.f, 1.f};
-        if (q < Q) load_query(src, q, x, d);
-        float s, t;
-        octa(d, s, t);
-        // directions come from the workspace: keep the taps inside the map
-        // even for a workspace the forward did not fill
-        qst[2 * ql] = fminf(fmaxf(s, 0.0f), 1.0f);
-        qst[2 * ql + 1] = fminf(fmaxf(t, 0.0f), 1.0f);
+        // octahedral coordinates stored by the forward; clamped so the taps
+        // stay inside the map even for a workspace the forward did not fill
+        const float2 p = q < Q ? uv[q] : make_float2(0.5f, 0.5f);
+        qst[2 * ql] = fminf(fmaxf(p.x, 0.0f), 1.0f);
+        qst[2 * ql + 1] = fminf(fmaxf(p.y, 0.0f), 1.0f);
       }
       __syncthreads();
       const float s = qst[2 * ql], t = qst[2 * ql + 1];
@@ -570,35 +568,35 @@ hipError_t launch_transpose_weights(const MlpArgs& M, oo_dtype md, void* const* 
 }
 
 template <class TT, class MT, int C, int H>
-static hipError_t launch_bwd_t(const TreeArgs& T, const MlpArgs& M, const MlpArgs& Mt, const QuerySrc& src,
-                               int64_t Q, const int32_t* nidx, const float* seeds, const int32_t* order,
+static hipError_t launch_bwd_t(const TreeArgs& T, const MlpArgs& M, const MlpArgs& Mt, int64_t Q,
+                               const int32_t* nidx, const float2* uv, const float* seeds, const int32_t* order,
                                const ParamLayout& PL, float* partials, float* dh, int grid, hipStream_t st) {
   const size_t lds = bwd_layout(M.K0, H, M.n_layers, T.L, (int)sizeof(MT)).total;
   auto k = bwd_kernel<TT, MT, C, H>;
   hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * kBwdWaves), lds, st, T, M, Mt, src, Q, nidx, seeds, order, PL, partials,
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * kBwdWaves), lds, st, T, M, Mt, Q, nidx, uv, seeds, order, PL, partials,
                      dh);
   return hipGetLastError();
 }
 
 template <class TT, class MT, int C>
-static hipError_t launch_bwd_c(const TreeArgs& T, const MlpArgs& M, const MlpArgs& Mt, const QuerySrc& src,
-                               int64_t Q, const int32_t* nidx, const float* seeds, const int32_t* order,
+static hipError_t launch_bwd_c(const TreeArgs& T, const MlpArgs& M, const MlpArgs& Mt, int64_t Q,
+                               const int32_t* nidx, const float2* uv, const float* seeds, const int32_t* order,
                                const ParamLayout& PL, float* partials, float* dh, int grid, hipStream_t st) {
-  return M.H == 64 ? launch_bwd_t<TT, MT, C, 64>(T, M, Mt, src, Q, nidx, seeds, order, PL, partials, dh, grid, st)
-                   : launch_bwd_t<TT, MT, C, 128>(T, M, Mt, src, Q, nidx, seeds, order, PL, partials, dh, grid, st);
+  return M.H == 64 ? launch_bwd_t<TT, MT, C, 64>(T, M, Mt, Q, nidx, uv, seeds, order, PL, partials, dh, grid, st)
+                   : launch_bwd_t<TT, MT, C, 128>(T, M, Mt, Q, nidx, uv, seeds, order, PL, partials, dh, grid, st);
 }
 
 hipError_t launch_bwd(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, void* const* Wt,
-                      const QuerySrc& src, int64_t Q, const int32_t* nidx, const float* seeds, const int32_t* order,
+                      int64_t Q, const int32_t* nidx, const float2* uv, const float* seeds, const int32_t* order,
                       const ParamLayout& PL, float* partials, float* dh, int grid, hipStream_t st) {
   MlpArgs Mt = M;
   for (int i = 0; i < M.n_layers; ++i) Mt.W[i] = Wt[i];
   if (td == OO_F32)
-    return T.C == 4 ? launch_bwd_c<float, float, 4>(T, M, Mt, src, Q, nidx, seeds, order, PL, partials, dh, grid, st)
-                    : launch_bwd_c<float, float, 8>(T, M, Mt, src, Q, nidx, seeds, order, PL, partials, dh, grid, st);
-  if (td == OO_F16) return launch_bwd_c<f16, f16, 8>(T, M, Mt, src, Q, nidx, seeds, order, PL, partials, dh, grid, st);
-  return launch_bwd_c<bf16, bf16, 8>(T, M, Mt, src, Q, nidx, seeds, order, PL, partials, dh, grid, st);
+    return T.C == 4 ? launch_bwd_c<float, float, 4>(T, M, Mt, Q, nidx, uv, seeds, order, PL, partials, dh, grid, st)
+                    : launch_bwd_c<float, float, 8>(T, M, Mt, Q, nidx, uv, seeds, order, PL, partials, dh, grid, st);
+  if (td == OO_F16) return launch_bwd_c<f16, f16, 8>(T, M, Mt, Q, nidx, uv, seeds, order, PL, partials, dh, grid, st);
+  return launch_bwd_c<bf16, bf16, 8>(T, M, Mt, Q, nidx, uv, seeds, order, PL, partials, dh, grid, st);
   (void)md;
 }
 
@@ -609,11 +607,12 @@ hipError_t launch_bwd(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype
 // touched, so the two taps of a footprint row (2C contiguous floats) mostly
 // share one chunk and a 2x2 map (the finest levels) takes two chunks per
 // query. Each lane adds w_tap * dh[q][l C + c] * post_scale with a hardware
-// FP32 atomic. Node indices come from the forward ([L][Q]) and are
-// range-checked; taps are recomputed from the direction.
+// FP32 atomic. Node indices and octahedral coordinates come from the
+// forward ([L][Q] and [Q]); indices are range-checked and coordinates
+// clamped, and the taps are recomputed from the coordinates.
 template <int C>
-__global__ __launch_bounds__(256) void scatter_kernel(const TreeArgs T, const QuerySrc src, int64_t Q,
-                                                      const int32_t* __restrict__ nidx, const float* __restrict__ dh,
+__global__ __launch_bounds__(256) void scatter_kernel(const TreeArgs T, int64_t Q, const int32_t* __restrict__ nidx,
+                                                      const float2* __restrict__ uv, const float* __restrict__ dh,
                                                       float post_scale, const GradArgs G) {
   const int l = blockIdx.y;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -623,12 +622,8 @@ __global__ __launch_bounds__(256) void scatter_kernel(const TreeArgs T, const Qu
   if (q >= Q) return;
   const int id = nidx[(int64_t)l * Q + q];
   if (id < T.off[l] || id >= T.off[l + 1]) return;
-  float x[3], d[3];
-  load_query(src, q, x, d);
-  float s, t;
-  octa(d, s, t);
-  s = fminf(fmaxf(s, 0.0f), 1.0f);  // directions come from the workspace
-  t = fminf(fmaxf(t, 0.0f), 1.0f);
+  const float2 p = uv[q];
+  const float s = fminf(fmaxf(p.x, 0.0f), 1.0f), t = fminf(fmaxf(p.y, 0.0f), 1.0f);
   const int R = T.res[l];
   int tx[4];
   float w[4];
@@ -645,16 +640,16 @@ __global__ __launch_bounds__(256) void scatter_kernel(const TreeArgs T, const Qu
   unsafeAtomicAdd(G.dfeat[l] + ((int64_t)(id - T.off[l]) * R * R + txk) * C + c, wk * gv);
 }
 
-hipError_t launch_scatter(const TreeArgs& T, const QuerySrc& src, int64_t Q, const int32_t* nidx, const float* dh,
+hipError_t launch_scatter(const TreeArgs& T, int64_t Q, const int32_t* nidx, const float2* uv, const float* dh,
                           float post_scale, const GradArgs& G, hipStream_t st) {
   if (Q == 0) return hipSuccess;
   const int64_t blocks = (Q * 4 * T.C + 255) / 256;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   if (T.C == 4)
-    hipLaunchKernelGGL(scatter_kernel<4>, dim3((unsigned)blocks, T.L), dim3(256), 0, st, T, src, Q, nidx, dh,
+    hipLaunchKernelGGL(scatter_kernel<4>, dim3((unsigned)blocks, T.L), dim3(256), 0, st, T, Q, nidx, uv, dh,
                        post_scale, G);
   else
-    hipLaunchKernelGGL(scatter_kernel<8>, dim3((unsigned)blocks, T.L), dim3(256), 0, st, T, src, Q, nidx, dh,
+    hipLaunchKernelGGL(scatter_kernel<8>, dim3((unsigned)blocks, T.L), dim3(256), 0, st, T, Q, nidx, uv, dh,
                        post_scale, G);
   return hipGetLastError();
 }

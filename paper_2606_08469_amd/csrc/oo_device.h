@@ -42,18 +42,22 @@ struct QuerySrc {
   int64_t nA;
   const float* xB;
   const float* dB;
-  // When set: packed [Q] position / direction arrays (w unused), read
-  // instead of the two-part source above.
-  const float4* x4;
-  const float4* d4;
+  // When set, query i is the source query idx[i] (a permutation into the
+  // n queries above); an index outside [0, n) reads as x = 0, dir = +z.
+  const int32_t* idx;
+  int64_t n;
 };
 
-__device__ inline void load_pos(const QuerySrc& s, int64_t q, float x[3]) {
-  if (s.x4) {
-    const float4 a = s.x4[q];
-    x[0] = a.x;
-    x[1] = a.y;
-    x[2] = a.z;
+__device__ inline int64_t source_query(const QuerySrc& s, int64_t i) {
+  if (!s.idx) return i;
+  const int64_t q = s.idx[i];
+  return q >= 0 && q < s.n ? q : -1;
+}
+
+__device__ inline void load_pos(const QuerySrc& s, int64_t i, float x[3]) {
+  const int64_t q = source_query(s, i);
+  if (q < 0) {
+    x[0] = x[1] = x[2] = 0.0f;
     return;
   }
   const float* xp = q < s.nA ? s.xA + 3 * q : s.xB + 3 * (q - s.nA);
@@ -61,15 +65,12 @@ __device__ inline void load_pos(const QuerySrc& s, int64_t q, float x[3]) {
   for (int a = 0; a < 3; ++a) x[a] = xp[a];
 }
 
-__device__ inline void load_query(const QuerySrc& s, int64_t q, float x[3], float d[3]) {
-  if (s.x4) {
-    const float4 a = s.x4[q], b = s.d4[q];
-    x[0] = a.x;
-    x[1] = a.y;
-    x[2] = a.z;
-    d[0] = b.x;
-    d[1] = b.y;
-    d[2] = b.z;
+__device__ inline void load_query(const QuerySrc& s, int64_t i, float x[3], float d[3]) {
+  const int64_t q = source_query(s, i);
+  if (q < 0) {
+    x[0] = x[1] = x[2] = 0.0f;
+    d[0] = d[1] = 0.0f;
+    d[2] = 1.0f;
     return;
   }
   const float* xp = q < s.nA ? s.xA + 3 * q : s.xB + 3 * (q - s.nA);

@@ -188,17 +188,15 @@ __host__ __device__ inline int packed_weight_elems(int n_layers, int K0, int H) 
 }
 
 template <class MT, int NT>
-__device__ inline void store_rgb(const f32x4 out[NT], int t0, int64_t q_base, int64_t Q, int lane, float* rgb,
-                                 const int32_t* out_row = nullptr) {
+__device__ inline void store_rgb(const f32x4 out[NT], int t0, int64_t q_base, int64_t Q, int lane, float* rgb) {
   if (lane < 16) {
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int64_t q = q_base + 16 * (t0 + t) + lane;
       if (q < Q) {
-        const int64_t r = out_row ? (int64_t)out_row[q] : q;
-        rgb[3 * r + 0] = out[t][0];
-        rgb[3 * r + 1] = out[t][1];
-        rgb[3 * r + 2] = out[t][2];
+        rgb[3 * q + 0] = out[t][0];
+        rgb[3 * q + 1] = out[t][1];
+        rgb[3 * q + 2] = out[t][2];
       }
     }
   }
@@ -208,13 +206,12 @@ __device__ inline void store_rgb(const f32x4 out[NT], int t0, int64_t q_base, in
 // Fused query: encode 64 queries per wave into LDS, decode them there.
 // ---------------------------------------------------------------------------
 // Queries q < n_idx also store their node index per level in idx_out
-// (level-major [L][n_idx]), which the residual backward reads instead of
-// descending again. With out_row set, query q's radiance goes to row
-// out_row[q] (the caller's order when the queries were bucketed).
+// (level-major [L][n_idx]) and their octahedral coordinates in uv_out, which
+// the residual backward reads instead of descending and mapping again.
 template <class TT, class MT, int C, int H, bool WLDS>
 __global__ __launch_bounds__(512) void query_kernel(const TreeArgs T, const MlpArgs M, const QuerySrc src,
                                                     int64_t Q, float* __restrict__ rgb, int32_t* __restrict__ idx_out,
-                                                    int64_t n_idx, const int32_t* __restrict__ out_row) {
+                                                    float2* __restrict__ uv_out, int64_t n_idx) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   constexpr int NT = 2;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63, waves = blockDim.x >> 6;
@@ -239,6 +236,7 @@ __global__ __launch_bounds__(512) void query_kernel(const TreeArgs T, const MlpA
     float s, t;
     octa(d, s, t);
     const bool keep = q < n_idx;
+    if (keep) uv_out[q] = make_float2(s, t);
     encode_pipelined<TT, C>(T, valid, x, s, t, [&](int l, const float* h, int node) {
 #pragma unroll
       for (int c = 0; c < C; c += 4) htile_put4<MT>(htile, KB0, lane, l * C + c, &h[c]);
@@ -249,7 +247,7 @@ __global__ __launch_bounds__(512) void query_kernel(const TreeArgs T, const MlpA
     for (int t0 = 0; t0 < 4; t0 += NT) {
       f32x4 out[NT];
       mlp_forward_tiles<MT, H, NT>(M, W, htile, KB0, t0, lane, out);
-      store_rgb<MT, NT>(out, t0, tile * 64, Q, lane, rgb, out_row);
+      store_rgb<MT, NT>(out, t0, tile * 64, Q, lane, rgb);
     }
     wave_lds_sync();
   }
@@ -352,7 +350,7 @@ __device__ inline void load_unit(const float* p, float v[3]) {
 // T = Le + (1/N) sum_k w_k * L(x2_k) and r = L - T and writes the outputs;
 // each block leaves one FP64 partial of sum r^2 (or (r / rho)^2).
 __global__ __launch_bounds__(256) void combine_kernel(const ResidualArgs A, int G, const float* __restrict__ Lq,
-                                                      float* __restrict__ lhs_out, float* __restrict__ rhs_out,
+                                                      const int32_t* __restrict__ rank, float* __restrict__ lhs_out, float* __restrict__ rhs_out,
                                                       float* __restrict__ resid_out, double* __restrict__ partials) {
   __shared__ double red[256];
   const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
@@ -370,7 +368,8 @@ __global__ __launch_bounds__(256) void combine_kernel(const ResidualArgs A, int 
       float wi[3], w[3];
       load_unit(A.wi + 3 * bk, wi);
       bsdf_weight(n, wo, wi, alb, alpha, A.F0, A.pdf ? A.pdf[bk] : 1.0f, w);
-      const float* Lk = Lq + 3 * (A.B + bk);
+      const int64_t qk = A.B + bk;
+      const float* Lk = Lq + 3 * (rank ? (int64_t)rank[qk] : qk);
 #pragma unroll
       for (int c = 0; c < 3; ++c) s[c] += w[c] * Lk[c];
     }
@@ -380,7 +379,8 @@ __global__ __launch_bounds__(256) void combine_kernel(const ResidualArgs A, int 
     for (int c = 0; c < 3; ++c) s[c] += __shfl_xor(s[c], off, G);
   double acc = 0.0;
   if (valid && k0 == 0) {
-    float L[3] = {Lq[3 * b], Lq[3 * b + 1], Lq[3 * b + 2]};
+    const float* Lb = Lq + 3 * (rank ? (int64_t)rank[b] : b);
+    float L[3] = {Lb[0], Lb[1], Lb[2]};
     float T[3];
     if (A.target_override) {
 #pragma unroll
@@ -538,7 +538,7 @@ static void tile_launch_shape(const MlpArgs& M, int64_t Q, bool& wlds, int& wave
 
 template <class TT, class MT, int C, int H>
 static hipError_t launch_query_t(const TreeArgs& T, const MlpArgs& M, const QuerySrc& src, int64_t Q, float* rgb,
-                                 int32_t* idx_out, int64_t n_idx, const int32_t* out_row, hipStream_t st) {
+                                 int32_t* idx_out, float2* uv_out, int64_t n_idx, hipStream_t st) {
   bool wlds;
   int waves, grid;
   size_t lds;
@@ -546,31 +546,30 @@ static hipError_t launch_query_t(const TreeArgs& T, const MlpArgs& M, const Quer
   if (wlds) {
     auto k = query_kernel<TT, MT, C, H, true>;
     hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, st, T, M, src, Q, rgb, idx_out, n_idx, out_row);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, st, T, M, src, Q, rgb, idx_out, uv_out, n_idx);
   } else {
     auto k = query_kernel<TT, MT, C, H, false>;
     hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, st, T, M, src, Q, rgb, idx_out, n_idx, out_row);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, st, T, M, src, Q, rgb, idx_out, uv_out, n_idx);
   }
   return hipGetLastError();
 }
 
 template <class TT, class MT, int C>
 static hipError_t launch_query_c(const TreeArgs& T, const MlpArgs& M, const QuerySrc& src, int64_t Q, float* rgb,
-                                 int32_t* idx_out, int64_t n_idx, const int32_t* out_row, hipStream_t st) {
-  return M.H == 64 ? launch_query_t<TT, MT, C, 64>(T, M, src, Q, rgb, idx_out, n_idx, out_row, st)
-                   : launch_query_t<TT, MT, C, 128>(T, M, src, Q, rgb, idx_out, n_idx, out_row, st);
+                                 int32_t* idx_out, float2* uv_out, int64_t n_idx, hipStream_t st) {
+  return M.H == 64 ? launch_query_t<TT, MT, C, 64>(T, M, src, Q, rgb, idx_out, uv_out, n_idx, st)
+                   : launch_query_t<TT, MT, C, 128>(T, M, src, Q, rgb, idx_out, uv_out, n_idx, st);
 }
 
 hipError_t launch_query(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, const QuerySrc& src,
-                        int64_t Q, float* rgb, int32_t* idx_out, int64_t n_idx, const int32_t* out_row,
-                        hipStream_t st) {
+                        int64_t Q, float* rgb, int32_t* idx_out, float2* uv_out, int64_t n_idx, hipStream_t st) {
   if (Q == 0) return hipSuccess;
   if (td == OO_F32)
-    return T.C == 4 ? launch_query_c<float, float, 4>(T, M, src, Q, rgb, idx_out, n_idx, out_row, st)
-                    : launch_query_c<float, float, 8>(T, M, src, Q, rgb, idx_out, n_idx, out_row, st);
-  if (td == OO_F16) return launch_query_c<f16, f16, 8>(T, M, src, Q, rgb, idx_out, n_idx, out_row, st);
-  return launch_query_c<bf16, bf16, 8>(T, M, src, Q, rgb, idx_out, n_idx, out_row, st);
+    return T.C == 4 ? launch_query_c<float, float, 4>(T, M, src, Q, rgb, idx_out, uv_out, n_idx, st)
+                    : launch_query_c<float, float, 8>(T, M, src, Q, rgb, idx_out, uv_out, n_idx, st);
+  if (td == OO_F16) return launch_query_c<f16, f16, 8>(T, M, src, Q, rgb, idx_out, uv_out, n_idx, st);
+  return launch_query_c<bf16, bf16, 8>(T, M, src, Q, rgb, idx_out, uv_out, n_idx, st);
   (void)md;
 }
 
@@ -607,12 +606,12 @@ static int combine_group(int N) {
 
 int combine_blocks(int64_t B, int N) { return (int)((B * combine_group(N) + 255) / 256); }
 
-hipError_t launch_combine(const ResidualArgs& A, const float* Lq, float* lhs, float* rhs, float* resid,
-                          double* partials, double* loss, hipStream_t st) {
+hipError_t launch_combine(const ResidualArgs& A, const float* Lq, const int32_t* rank, float* lhs, float* rhs,
+                          float* resid, double* partials, double* loss, hipStream_t st) {
   const int G = combine_group(A.target_override ? 0 : A.N);
   const int nb = combine_blocks(A.B, A.target_override ? 0 : A.N);
   if (nb > 0)
-    hipLaunchKernelGGL(combine_kernel, dim3(nb), dim3(256), 0, st, A, G, Lq, lhs, rhs, resid, partials);
+    hipLaunchKernelGGL(combine_kernel, dim3(nb), dim3(256), 0, st, A, G, Lq, rank, lhs, rhs, resid, partials);
   hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(256), 0, st, partials, nb, A.B, loss);
   return hipGetLastError();
 }

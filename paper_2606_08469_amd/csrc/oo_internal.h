@@ -42,25 +42,26 @@ struct ReduceDst {
 hipError_t launch_encode(const TreeArgs& T, oo_dtype td, const float* x, const float* d, int64_t B, void* h,
                          oo_dtype hd, int32_t* idx, hipStream_t st);
 hipError_t launch_mlp(const MlpArgs& M, oo_dtype md, const void* h, int64_t Q, float* rgb, hipStream_t st);
-// rgb row of query q is out_row[q] when out_row is set, else q.
+// Queries q < n_idx also store their node index per level (idx_out,
+// [L][n_idx]) and octahedral coordinates (uv_out, [n_idx]).
 hipError_t launch_query(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, const QuerySrc& src,
-                        int64_t Q, float* rgb, int32_t* idx_out, int64_t n_idx, const int32_t* out_row,
-                        hipStream_t st);
+                        int64_t Q, float* rgb, int32_t* idx_out, float2* uv_out, int64_t n_idx, hipStream_t st);
 
 // Spatial bucketing of the residual queries: NB chunks, K buckets (octree
 // cell level c). Workspace: counts [NB][K], total [K], start [K] int32;
-// outputs xs, ds [Q] (packed position / direction) and order [Q] (original
-// query index of each sorted position).
+// outputs order [Q] (source query of each sorted position) and rank [Q]
+// (sorted position of each source query).
 struct SortShape {
   int c, K, NB;
   int64_t chunk;
 };
 SortShape sort_shape(int64_t Q, int D);
 hipError_t launch_spatial_sort(const QuerySrc& src, int64_t Q, int64_t n_lhs, int D, int32_t* counts, int32_t* total,
-                               int32_t* start, float4* xs, float4* ds, int32_t* order, hipStream_t st);
+                               int32_t* start, int32_t* order, int32_t* rank, hipStream_t st);
 int combine_blocks(int64_t B, int N);
-hipError_t launch_combine(const ResidualArgs& A, const float* Lq, float* lhs, float* rhs, float* resid,
-                          double* partials, double* loss, hipStream_t st);
+// Lq row of query q is rank[q] when rank is set, else q.
+hipError_t launch_combine(const ResidualArgs& A, const float* Lq, const int32_t* rank, float* lhs, float* rhs,
+                          float* resid, double* partials, double* loss, hipStream_t st);
 hipError_t launch_cast(const float* src, void* dst, oo_dtype dt, int64_t n, hipStream_t st);
 
 // Backward.
@@ -70,9 +71,9 @@ hipError_t launch_seeds(const ResidualArgs& A, const float* resid, const float* 
                         int full, float* seeds, hipStream_t st);
 hipError_t launch_transpose_weights(const MlpArgs& M, oo_dtype md, void* const* Wt, hipStream_t st);
 hipError_t launch_bwd(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, void* const* Wt,
-                      const QuerySrc& src, int64_t Q, const int32_t* nidx, const float* seeds, const int32_t* order,
+                      int64_t Q, const int32_t* nidx, const float2* uv, const float* seeds, const int32_t* order,
                       const ParamLayout& PL, float* partials, float* dh, int grid, hipStream_t st);
-hipError_t launch_scatter(const TreeArgs& T, const QuerySrc& src, int64_t Q, const int32_t* nidx, const float* dh,
+hipError_t launch_scatter(const TreeArgs& T, int64_t Q, const int32_t* nidx, const float2* uv, const float* dh,
                           float post_scale, const GradArgs& G, hipStream_t st);
 hipError_t launch_dw_reduce(const float* partials, int grid, const ParamLayout& PL, const ReduceDst& D, float scale,
                             hipStream_t st);

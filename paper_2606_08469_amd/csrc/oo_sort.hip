@@ -15,8 +15,11 @@
 //   1. per-chunk histograms in LDS          -> counts[NB][K]
 //   2. per-bucket exclusive prefix over the chunks, bucket totals, and the
 //      exclusive scan of the totals          -> counts (in place), start[K]
-//   3. each chunk hands out slots from LDS cursors and writes the packed
-//      position, direction and original index of its queries.
+//   3. each chunk hands out slots from LDS cursors: order[pos] = q (the
+//      query at sorted position pos) and rank[q] = pos.
+// Only 4-byte indices move: the kernels that evaluate the sorted queries
+// read positions and directions through order, and the residual assembly
+// reads the sorted radiance through rank.
 #include <hip/hip_runtime.h>
 
 #include "oo_device.h"
@@ -102,19 +105,18 @@ __global__ __launch_bounds__(kSortThreads) void sort_scatter_kernel(const QueryS
                                                                     int D, int c, int K, int64_t chunk,
                                                                     const int32_t* __restrict__ prefix,
                                                                     const int32_t* __restrict__ start,
-                                                                    float4* __restrict__ xs, float4* __restrict__ ds,
-                                                                    int32_t* __restrict__ order) {
+                                                                    int32_t* __restrict__ order,
+                                                                    int32_t* __restrict__ rank) {
   extern __shared__ int cur[];
   for (int b = threadIdx.x; b < K; b += blockDim.x) cur[b] = start[b] + prefix[(int64_t)blockIdx.x * K + b];
   __syncthreads();
   const int64_t lo = (int64_t)blockIdx.x * chunk, hi = lo + chunk < Q ? lo + chunk : Q;
   for (int64_t q = lo + threadIdx.x; q < hi; q += blockDim.x) {
-    float x[3], d[3];
-    load_query(src, q, x, d);
+    float x[3];
+    load_pos(src, q, x);
     const int pos = atomicAdd(&cur[sort_bucket(x, D, c, q, n_lhs)], 1);
-    xs[pos] = make_float4(x[0], x[1], x[2], 0.0f);
-    ds[pos] = make_float4(d[0], d[1], d[2], 0.0f);
     order[pos] = (int32_t)q;
+    rank[q] = pos;
   }
 }
 
@@ -129,7 +131,7 @@ SortShape sort_shape(int64_t Q, int D) {
 }
 
 hipError_t launch_spatial_sort(const QuerySrc& src, int64_t Q, int64_t n_lhs, int D, int32_t* counts, int32_t* total,
-                               int32_t* start, float4* xs, float4* ds, int32_t* order, hipStream_t st) {
+                               int32_t* start, int32_t* order, int32_t* rank, hipStream_t st) {
   if (Q == 0) return hipSuccess;
   const SortShape s = sort_shape(Q, D);
   const size_t lds = (size_t)s.K * sizeof(int);
@@ -138,7 +140,7 @@ hipError_t launch_spatial_sort(const QuerySrc& src, int64_t Q, int64_t n_lhs, in
   hipLaunchKernelGGL(sort_colscan_kernel, dim3((s.K + 255) / 256), dim3(256), 0, st, counts, s.NB, s.K, total);
   hipLaunchKernelGGL(sort_start_kernel, dim3(1), dim3(1024), 0, st, total, s.K, start);
   hipLaunchKernelGGL(sort_scatter_kernel, dim3(s.NB), dim3(kSortThreads), lds, st, src, Q, n_lhs, D, s.c, s.K, s.chunk,
-                     counts, start, xs, ds, order);
+                     counts, start, order, rank);
   return hipGetLastError();
 }
 
