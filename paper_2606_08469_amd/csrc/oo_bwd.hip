@@ -606,10 +606,13 @@ hipError_t launch_bwd(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype
 // atomic units work on 64-byte chunks, one chunk per instruction and chunk
 // touched, so the two taps of a footprint row (2C contiguous floats) mostly
 // share one chunk and a 2x2 map (the finest levels) takes two chunks per
-// query. Each lane adds w_tap * dh[q][l C + c] * post_scale with a hardware
-// FP32 atomic. Node indices and octahedral coordinates come from the
-// forward ([L][Q] and [Q]); indices are range-checked and coordinates
-// clamped, and the taps are recomputed from the coordinates.
+// query. This request rate, not bandwidth, bounds the step; privatising
+// coarse-level maps in LDS does not pay here, because LDS float atomics
+// retire about one lane per clock per CU. Each lane adds
+// w_tap * dh[q][l C + c] * post_scale with a hardware FP32 atomic. Node
+// indices and octahedral coordinates come from the forward ([L][Q] and [Q]);
+// indices are range-checked and coordinates clamped, and the taps are
+// recomputed from the coordinates.
 template <int C>
 __global__ __launch_bounds__(256) void scatter_kernel(const TreeArgs T, int64_t Q, const int32_t* __restrict__ nidx,
                                                       const float2* __restrict__ uv, const float* __restrict__ dh,

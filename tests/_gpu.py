@@ -90,3 +90,38 @@ def subset_batch(batch: dict, idx) -> dict:
 
 def to_np(t):
     return t.detach().float().cpu().numpy() if t.dtype != torch.float64 else t.detach().cpu().numpy()
+
+
+# Relative distance of a hidden pre-activation from zero below which FP32
+# evaluation (operands rounded to 2^-24, sums of up to 128 products) can put
+# it on the other side of the ReLU kink than the FP64 oracle does.
+KINK_BAND = 1e-5
+
+
+def kink_margin_ok(ci: int, x, d):
+    """True per query when every hidden pre-activation z of the decoder, in
+    FP64, satisfies |z| >= KINK_BAND * (sum of |w a| + |b|): the FP32 path
+    then takes the oracle's ReLU derivative branch for that query."""
+    otree, omlp = oracle_models(ci)
+    _, W, b = params_for(ci)
+    a = oracle.encode(otree, x, d)[0].astype(np.float64)
+    ok = np.ones(len(a), bool)
+    for i in range(len(W) - 1):
+        Wi, bi = np.asarray(W[i], np.float64), np.asarray(b[i], np.float64)
+        z = a @ Wi.T + bi
+        scale = np.abs(a) @ np.abs(Wi).T + np.abs(bi) + 1e-300
+        ok &= (np.abs(z) / scale).min(axis=1) >= KINK_BAND
+        a = np.maximum(z, 0.0)
+    return ok
+
+
+def kink_safe_batch(ci: int, batch: dict, full: bool):
+    """The batch without the points whose differentiated queries (the LHS
+    query; with the gradient through the target also its secondary queries)
+    sit within FP32 rounding of a ReLU kink. Returns (batch, dropped)."""
+    ok = kink_margin_ok(ci, batch["x"], batch["dir"])
+    N = int(batch.get("N", 0))
+    if full and N > 0:
+        ok2 = kink_margin_ok(ci, batch["x2"].reshape(-1, 3), batch["dir2"].reshape(-1, 3))
+        ok &= ok2.reshape(-1, N).all(axis=1)
+    return subset_batch(batch, np.nonzero(ok)[0]), int((~ok).sum())

@@ -13,8 +13,8 @@ import torch
 
 import oracle
 from paper_2606_08469_amd import binding, synth
-from _gpu import (cosine, gpu_models, oracle_models, oracle_tree_for, params_for, rel_l2, render_queries, report,
-                  subset_batch, to_np, train_batch, tree_for)
+from _gpu import (cosine, gpu_models, kink_safe_batch, oracle_models, oracle_tree_for, params_for, rel_l2,
+                  render_queries, report, subset_batch, to_np, train_batch, tree_for)
 
 pytestmark = pytest.mark.gpu
 
@@ -206,8 +206,11 @@ def compare_grads(name, got, otree, omlp, batch_np, tol=None, cos=None):
     return worst
 
 
+# B = 20000 and the full mode at B = 9000 bucket enough queries that many
+# tiles share nodes, and (full mode) tiles straddle the LHS / secondary
+# boundary of the sorted order.
 @pytest.mark.parametrize("ci,B,mode", [(1, None, "l2"), (3, 2048, "l2"), (3, 1000, "l2"), (3, 512, "full"),
-                                       (3, 512, "relative"), (1, 77, "l2")])
+                                       (3, 512, "relative"), (1, 77, "l2"), (3, 20000, "l2"), (3, 9000, "full")])
 def test_residual_fp32(ci, B, mode):
     batch = dict(train_batch(ci) if B is None or ci == 1 else train_batch(ci, B))
     if ci == 1 and B is not None:
@@ -216,9 +219,12 @@ def test_residual_fp32(ci, B, mode):
         batch["grad_through_rhs"] = 1
     if mode == "relative":
         batch["loss_kind"] = 1
+    # points at a ReLU kink may legitimately take the other derivative branch
+    # in FP32; they are left out of this element-wise comparison
+    batch, dropped = kink_safe_batch(ci, batch, mode == "full")
     model = gpu_models(ci)
     otree, omlp = oracle_models(ci)
-    print(f"[case] residual fp32 cfg{ci} B={len(batch['x'])} {mode}", flush=True)
+    print(f"[case] residual fp32 cfg{ci} B={len(batch['x'])} {mode} (kink-dropped {dropped})", flush=True)
     got = run_residual(model, batch)
     lhs, rhs, res, loss = oracle.residual_fwd(otree, omlp, batch)
     for k, w in (("lhs", lhs), ("rhs", rhs), ("resid", res)):
