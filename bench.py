@@ -88,7 +88,7 @@ def main():
         "dW": [torch.zeros(w.shape, dtype=torch.float32, device=dev) for w in mixed.W],
         "db": [torch.zeros(v.shape, dtype=torch.float32, device=dev) for v in mixed.b],
     }
-    ws = mixed.workspace(batch)
+    ws_mixed = mixed.workspace(batch)
     outs = tuple(torch.empty((B, 3), dtype=torch.float32, device=dev) for _ in range(3)) + (
         torch.empty((), dtype=torch.float64, device=dev),)
     gl = torch.ones((), dtype=torch.float64, device=dev)
@@ -99,6 +99,7 @@ def main():
             g.zero_()
         if ev:
             ev[0].record()
+        ws = model.workspace(batch)  # sized for this model's dtypes
         lhs, rhs, res, loss = binding.residual_fwd(model.tree, model.mlp, batch, ws, feat=model.work_feat,
                                                    W=model.work_W, outs=outs)
         if ev:
@@ -109,25 +110,34 @@ def main():
             ev[2].record()
         return loss
 
-    def timed(model, steps, warmup):
+    def timed(model, steps, warmup, kernels=False):
+        """Wall time per step over the timed steps, their mean forward and
+        backward event times, and (kernels=True) the library's own per-launch
+        event timings of every kernel group in the timed region."""
         for _ in range(warmup):
             step(model)
         torch.cuda.synchronize()
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        if kernels:
+            binding.profile_begin(64 * steps)
         torch.cuda.synchronize()
         t = time.perf_counter()
         for i in range(steps):
             step(model, evs[i])
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t) / steps
+        per = None
+        if kernels:
+            per = {k: (v[0] / v[1], v[1]) for k, v in binding.profile_end().items()}
         fwd = [e[0].elapsed_time(e[1]) for e in evs]
         bwd = [e[1].elapsed_time(e[2]) for e in evs]
-        return wall * 1e3, float(np.mean(fwd)), float(np.mean(bwd))
+        return wall * 1e3, float(np.mean(fwd)), float(np.mean(bwd)), per
 
     log("timing mixed step")
-    ms, fwd_ms, bwd_ms = timed(mixed, args.steps, args.warmup)
+    ms, fwd_ms, bwd_ms, per_kernel = timed(mixed, args.steps, args.warmup, kernels=True)
     loss_mixed = float(outs[3].item())
     log(f"mixed: {ms:.3f} ms/step (fwd {fwd_ms:.3f} ms, bwd {bwd_ms:.3f} ms)")
+    log("per launch (ms): " + ", ".join(f"{k} {v[0]:.4f}" for k, v in per_kernel.items()))
 
     # ---------------- algorithmic bytes / FLOPs ----------------------------
     # Levels present per query: the descent stops at the first missing child.
@@ -138,26 +148,22 @@ def main():
     lv_all = float(present.sum().item())
     lv_lhs = float(present[:B].sum().item())
     del xq, dq, idx, present
-    C, s16 = cfg.C, 2
-    H0, H = cfg.mlp[0], cfg.mlp[1]
-    mlp_flop = 2 * (H0 * H + (len(cfg.mlp) - 3) * H * H + H * 3)
-    # forward: per query, present levels x (4 taps x C x 2 B + 4 B node word),
-    # 24 B of x and dir in, 12 B of radiance out; per point the combine reads
-    # 76 B of point inputs and 40 B per secondary sample (counted in fwd).
-    fwd_bytes = lv_all * (4 * C * s16 + 4) + Q * (24 + 12)
-    fwd_bytes_combine = B * (76 + 36) + B * N * (40 + 12)
-    # backward: recomputed LHS gather, FP32 atomics (4 B each) per tap and
-    # channel, 12 B seed per point, 24 B x and dir.
-    bwd_bytes = lv_lhs * (4 * C * s16 + 4 + 4 * C * 4) + B * (24 + 12)
-    bwd_flop = B * 3 * mlp_flop
-    fwd_flop = Q * mlp_flop
+    kern = kernel_rooflines(cfg, B, Q, lv_all, lv_lhs, per_kernel)
+    dom = max(kern, key=lambda k: kern[k]["ms_per_launch"])
+    traffic, traffic_src = hbm_traffic(dom)
+    roof = dict(kern[dom])
+    roof.update(traffic=traffic, traffic_source=traffic_src)
+    roof = {"kernel": dom, **roof, "kernels": kern}
+    for k, v in kern.items():
+        log(f"{k}: {v['ms_per_launch']:.4f} ms/launch, {v['achieved']:.1f} {v['unit']} ({100 * v['frac']:.1f}% of "
+            f"{v['bound']} peak); MFMA {100 * v['mfma_frac']:.2f}%")
 
     # ---------------- FP32 plain step and render forwards -------------------
     extra = {}
     if not args.no_extra:
         fp32 = binding.OctaOctree(nodes, lo, list(cfg.res), cfg.C, feat, W, b, dtype=torch.float32)
         log("timing FP32 plain step")
-        ms32, f32, b32 = timed(fp32, max(3, args.steps // 4), 2)
+        ms32, f32, b32, _ = timed(fp32, max(3, args.steps // 4), 2)
         loss32 = float(outs[3].item())
         extra["fp32_plain_step"] = {"ms_per_step": round(ms32, 4), "fwd_ms": round(f32, 4), "bwd_ms": round(b32, 4),
                                     "value": round(Q / (ms32 * 1e-3) / 1e6, 2), "unit": "Mqueries/s"}
@@ -173,7 +179,6 @@ def main():
         cpu = cpu_baseline(batch_np, nodes, lo, cfg, feat, W, b)
 
     value = Q / (ms * 1e-3) / 1e6
-    achieved = fwd_bytes / (fwd_ms * 1e-3) / 1e9
     line = {
         "metric": "Mqueries/s encode+MLP fwd and fwd+bwd, mixed vs FP32 at <=1e-2 err; % HBM/MFMA peak",
         "value": round(value, 2),
@@ -194,17 +199,9 @@ def main():
             "queries_per_step": Q, "lhs_points_per_step": B,
             "lhs_points_per_s_M": round(B / (ms * 1e-3) / 1e6, 3),
             "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4),
+            "ms_per_launch": {k: round(v[0], 4) for k, v in per_kernel.items()},
         },
-        "roofline": {
-            "kernel": "residual forward (fused encode+decode query kernel over B(1+N) queries, plus the "
-                      "residual assembly)",
-            "bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
-            "frac": round(achieved / 8000.0, 4), "traffic": None,
-            "algorithmic_bytes_per_launch": int(fwd_bytes + fwd_bytes_combine),
-            "mfma_frac_fwd": round(fwd_flop / (fwd_ms * 1e-3) / 2.5e15, 4),
-            "bwd": {"algorithmic_bytes": int(bwd_bytes), "achieved_GBps": round(bwd_bytes / (bwd_ms * 1e-3) / 1e9, 1),
-                    "mfma_frac": round(bwd_flop / (bwd_ms * 1e-3) / 2.5e15, 4)},
-        },
+        "roofline": roof,
         "cpu_baseline": cpu,
     }
     line.update(extra)
@@ -259,6 +256,74 @@ def render_bench(torch, binding, synth, args):
     return out
 
 
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
+MFMA_F16_PEAK_TFS = 2500.0  # MI355X dense FP16 matrix cores
+
+
+def kernel_rooflines(cfg, B, Q, lv_all, lv_lhs, per_kernel):
+    """Algorithmic bytes and FLOPs per launch of the three dominant kernels of
+    the step, against their launch times measured in the timed region.
+
+    Per query and present level (lv = sum over queries of present levels):
+    4 taps x C channels x 2 B (FP16 texels) + 4 B node word in the forward;
+    the same gather again in the backward recompute; in the scatter, 4 taps x
+    C FP32 atomic adds (4 B each) + the C FP32 dh values and the node index it
+    reads. Per query, the forward also reads x and dir (24 B) through the
+    bucketed order (4 B) and writes its radiance (12 B); per LHS query it
+    writes the node index per level and the octahedral coordinates (8 B).
+    The backward reads those coordinates, the order entry and the 12 B seed,
+    and writes dh (K0 x 4 B); the scatter reads the coordinates."""
+    C, L, K0 = cfg.C, len(cfg.res), cfg.mlp[0]
+    H = cfg.mlp[1]
+    mlp_flop = 2 * (K0 * H + (len(cfg.mlp) - 3) * H * H + H * 3)
+    out = {}
+    spec = {
+        "query": (lv_all * (4 * C * 2 + 4) + Q * (24 + 4 + 12) + B * (L * 4 + 8), Q * mlp_flop),
+        "backward": (lv_lhs * (4 * C * 2 + 4) + B * (8 + 4 + 12 + K0 * 4), B * 3 * mlp_flop),
+        "scatter": (lv_lhs * (4 * C * 4 + C * 4 + 4) + B * 8, 0),
+    }
+    for k, (nbytes, flop) in spec.items():
+        if k not in per_kernel:
+            continue
+        t = per_kernel[k][0] * 1e-3
+        gbs = nbytes / t / 1e9
+        out[k] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(gbs / HBM_PEAK_GBS, 4), "ms_per_launch": round(per_kernel[k][0], 4),
+                  "algorithmic_bytes": int(nbytes), "mlp_flop": int(flop),
+                  "mfma_frac": round(flop / t / 1e12 / MFMA_F16_PEAK_TFS, 4)}
+    return out
+
+
+def source_digest():
+    """SHA-256 over the library sources: a stored counter reading is only
+    used while the kernels it measured are unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2606_08469_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    h.update(open(os.path.join(ROOT, "include", "octaoctree.h"), "rb").read())
+    return h.hexdigest()
+
+
+def hbm_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (scaled by the copy calibration), or
+    None when the summary is missing or the sources changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic_train_step_cfg5.txt")
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    rec = json.load(open(path))
+    if rec.get("source_sha256") != source_digest():
+        return None, "kernels changed since the counters were taken"
+    k = rec.get("kernels", {}).get(kernel)
+    if not k:
+        return None, "kernel not in the counter summary"
+    return int(k["hbm_bytes_per_launch"]), os.path.relpath(path, ROOT)
+
+
 def cpu_baseline(batch_np, nodes, lo, cfg, feat, W, b):
     """The FP64 oracle as it stands, on a bounded sample of the same batch:
     the first S LHS points with their N secondary queries, forward (queries
@@ -270,7 +335,7 @@ def cpu_baseline(batch_np, nodes, lo, cfg, feat, W, b):
     S = 4096
     sb = {k: (v[:S] if isinstance(v, np.ndarray) else v) for k, v in batch_np.items()}
     ot, om = oracle.Tree(nodes, lo, list(cfg.res), cfg.C, feat), oracle.MLP(W, b)
-    nt = os.cpu_count() or 1
+    nt = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(16, os.cpu_count() or 1)
     t = time.perf_counter()
     oracle.residual_fwd(ot, om, sb, nthreads=nt)
     oracle.residual_bwd(ot, om, sb, nthreads=nt)

@@ -194,12 +194,19 @@ typedef struct {
 } oo_residual_batch;
 
 /* Workspace size in bytes that the residual forward and backward need for
- * this problem. The same workspace serves both calls. */
+ * this problem (it depends on the batch and on the MLP's dtype). The same
+ * workspace serves both calls; both take its size and return OO_EINVAL,
+ * before launching anything, when it is smaller than this. */
 int oo_residual_workspace_bytes(const oo_tree* tree, const oo_mlp* mlp,
                                 const oo_residual_batch* batch, size_t* bytes);
 
 /*
  * Residual forward.
+ *  - The B (1 + N) queries are first bucketed by the octree cell that holds
+ *    them (a counting sort on the Morton code of a coarse cell, LHS queries
+ *    first) and evaluated in that order, so neighbouring query tiles read
+ *    the same nodes' maps; outputs are in the caller's order. Requires
+ *    B (1 + N) < 2^31 (else OO_EUNSUPPORTED).
  *  - Outputs, each [B][3] FP32: lhs_out = L(x, dir);
  *    rhs_out = T = Le + (1/N) sum_k w_k * L(x2_k, dir2_k), or the override;
  *    resid_out = lhs - T.
@@ -210,21 +217,27 @@ int oo_residual_workspace_bytes(const oo_tree* tree, const oo_mlp* mlp,
  */
 int oo_radiosity_residual_fwd(const oo_tree* tree, const oo_mlp* mlp, const oo_residual_batch* batch,
                               float* lhs_out, float* rhs_out, float* resid_out, double* loss_out,
-                              void* workspace, hipStream_t stream);
+                              void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /*
  * Residual backward. The texel gathers and the decoder forward are
  * recomputed, not stored; the node index per level comes from the forward.
  *  - workspace: the one the forward of this batch used, unchanged since.
- *    The forward leaves there the node indices of every query the backward
- *    processes. Indices found outside their level (a workspace the forward
- *    did not fill) are treated as missing nodes; they are never dereferenced.
+ *    The forward leaves there the bucketed query order and, for every query
+ *    the backward processes, its node indices and octahedral coordinates.
+ *    Indices found outside their level or outside the batch, and
+ *    coordinates outside [0, 1] (a workspace the forward did not fill), are
+ *    treated as missing nodes, as no seed, and clamped; nothing outside the
+ *    tables or the batch is dereferenced.
  *  - resid, rhs: the forward's outputs for the same batch and parameters.
  *  - grad_loss: device FP64 scalar, dLoss_total/dloss.
  *  - dfeat[l]: FP32 [n_l][res][res][C]. Receives += the feature gradient by
  *    atomic scatter; the summation order is not fixed.
  *  - dW[i], db[i]: FP32, shaped like the layer. Receive += the reduced
- *    gradient; the reduction order is fixed.
+ *    gradient. The reduction over workgroups runs in a fixed order, but
+ *    which queries share a workgroup follows the bucketed order, which is
+ *    not fixed inside a bucket: results agree to rounding, not bitwise,
+ *    from call to call.
  *  - Gradients are for the tables and weights the forward read. In
  *    mixed-precision runs those are the FP16/BF16 working copies, and the
  *    gradient is applied to the FP32 masters.
@@ -232,11 +245,44 @@ int oo_radiosity_residual_fwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
 int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_residual_batch* batch,
                               const float* resid, const float* rhs, const double* grad_loss,
                               float* const* dfeat, float* const* dW, float* const* db, void* workspace,
-                              hipStream_t stream);
+                              size_t workspace_bytes, hipStream_t stream);
 
 /* FP32 -> FP16/BF16 (round to nearest even) or FP32 copy, n elements. Used
  * to refresh working copies from FP32 masters. */
 int oo_cast_params(const float* src_fp32, void* dst, oo_dtype dst_dtype, int64_t n, hipStream_t stream);
+
+/*
+ * Opt-in launch timing (a measurement aid, not part of the method). Between
+ * oo_profile_begin and oo_profile_end every entry point records a pair of
+ * HIP events on its stream around each group of kernels it launches, for up
+ * to `capacity` groups (later groups are not timed). oo_profile_end waits
+ * for the recorded events, writes per kind the summed milliseconds
+ * (total_ms) and the number of timed groups (launches), each an array of
+ * OO_PROF_KINDS entries or NULL, and releases the events. Kinds: sort =
+ * query bucketing (4 kernels), query = fused encode + decode, combine =
+ * residual assembly + loss reduction (2 kernels), backward = recompute +
+ * decoder backward, scatter = feature-gradient atomics; the others are one
+ * kernel each. Timing a call adds two event records per group; the events
+ * are host-side objects, no device memory is allocated.
+ */
+#define OO_PROF_KINDS 11
+enum {
+  OO_PROF_SORT = 0,
+  OO_PROF_QUERY = 1,
+  OO_PROF_COMBINE = 2,
+  OO_PROF_SEEDS = 3,
+  OO_PROF_TRANSPOSE = 4,
+  OO_PROF_BACKWARD = 5,
+  OO_PROF_SCATTER = 6,
+  OO_PROF_DW_REDUCE = 7,
+  OO_PROF_CAST = 8,
+  OO_PROF_ENCODE = 9,
+  OO_PROF_MLP = 10
+};
+int oo_profile_begin(int32_t capacity);
+int oo_profile_end(double* total_ms, int64_t* launches);
+/* Name of a kind ("" when out of range). */
+const char* oo_profile_kind_name(int32_t kind);
 
 /* Message for the last failed call on this thread ("" if none). */
 const char* oo_last_error(void);

@@ -67,13 +67,18 @@ def lib():
         L.oo_mlp_fwd.argtypes = [vp, vp, i32, i64, vp, vp]
         L.oo_query_fwd.argtypes = [vp, vp, vp, vp, i64, vp, vp]
         L.oo_residual_workspace_bytes.argtypes = [vp, vp, vp, C.POINTER(C.c_size_t)]
-        L.oo_radiosity_residual_fwd.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
-        L.oo_radiosity_residual_bwd.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        sz = C.c_size_t
+        L.oo_radiosity_residual_fwd.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.oo_radiosity_residual_bwd.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.oo_cast_params.argtypes = [vp, vp, i32, i64, vp]
+        L.oo_profile_begin.argtypes = [i32]
+        L.oo_profile_end.argtypes = [vp, vp]
+        L.oo_profile_kind_name.argtypes = [i32]
+        L.oo_profile_kind_name.restype = C.c_char_p
         L.oo_last_error.restype = C.c_char_p
         for f in ("oo_build_octree", "oo_encode_query", "oo_mlp_fwd", "oo_query_fwd",
                   "oo_residual_workspace_bytes", "oo_radiosity_residual_fwd", "oo_radiosity_residual_bwd",
-                  "oo_cast_params"):
+                  "oo_cast_params", "oo_profile_begin", "oo_profile_end"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -90,6 +95,10 @@ def _stream():
 
 def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _nbytes(t):
+    return 0 if t is None else t.numel() * t.element_size()
 
 
 def _dev(t, dtype=torch.float32):
@@ -243,7 +252,8 @@ def residual_fwd(tree: Tree, mlp: MLP, batch: dict, workspace, feat=None, W=None
     lhs, rhs, res, loss = outs
     ts, ms, bs = tree.struct(feat), mlp.struct(W), batch_struct(batch)
     _check(lib().oo_radiosity_residual_fwd(C.byref(ts), C.byref(ms), C.byref(bs), _ptr(lhs), _ptr(rhs), _ptr(res),
-                                           _ptr(loss), _ptr(workspace), _stream()), "oo_radiosity_residual_fwd")
+                                           _ptr(loss), _ptr(workspace), _nbytes(workspace), _stream()),
+           "oo_radiosity_residual_fwd")
     return lhs, rhs, res, loss
 
 
@@ -254,8 +264,26 @@ def residual_bwd(tree: Tree, mlp: MLP, batch: dict, resid, rhs, grad_loss, dfeat
     arr = lambda ts_: (C.c_void_p * max(1, len(ts_)))(*[t.data_ptr() if t.numel() else None for t in ts_])
     g = grad_loss.to(device="cuda", dtype=torch.float64).contiguous().reshape(())
     _check(lib().oo_radiosity_residual_bwd(C.byref(ts), C.byref(ms), C.byref(bs), _ptr(resid), _ptr(rhs), _ptr(g),
-                                           arr(dfeat), arr(dW), arr(db), _ptr(workspace), _stream()),
+                                           arr(dfeat), arr(dW), arr(db), _ptr(workspace), _nbytes(workspace),
+                                           _stream()),
            "oo_radiosity_residual_bwd")
+
+
+PROF_KINDS = 11
+
+
+def profile_begin(capacity: int = 4096):
+    """Starts the library's launch timing (events around each kernel group)."""
+    _check(lib().oo_profile_begin(int(capacity)), "oo_profile_begin")
+
+
+def profile_end() -> dict:
+    """Stops launch timing: {kind: (summed ms, timed launches)} for the kinds
+    that ran."""
+    ms = (C.c_double * PROF_KINDS)()
+    n = (C.c_int64 * PROF_KINDS)()
+    _check(lib().oo_profile_end(ms, n), "oo_profile_end")
+    return {lib().oo_profile_kind_name(k).decode(): (ms[k], int(n[k])) for k in range(PROF_KINDS) if n[k]}
 
 
 def cast_params(src, dst):

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "octaoctree.h"
@@ -31,6 +32,38 @@ int hip_status(hipError_t e, const char* what) {
   if (e == hipSuccess) return OO_OK;
   return fail(OO_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
+
+// --- opt-in launch timing ----------------------------------------------------
+// While enabled, every kernel launch group records a pair of events on the
+// caller's stream around itself; oo_profile_end sums their elapsed times per
+// kind.
+const char* const kProfNames[OO_PROF_KINDS] = {"bucket_sort", "query",    "combine",   "seeds",
+                                               "transpose",   "backward", "scatter",   "dw_reduce",
+                                               "cast",        "encode",   "mlp_decode"};
+
+struct Profiler {
+  std::mutex m;
+  bool on = false;
+  std::vector<hipEvent_t> ev;  // 2 per slot
+  std::vector<int> kind;
+  int used = 0;
+};
+Profiler g_prof;
+
+struct ProfScope {
+  int slot = -1;
+  hipStream_t st;
+  ProfScope(int kind, hipStream_t s) : st(s) {
+    std::lock_guard<std::mutex> lk(g_prof.m);
+    if (!g_prof.on || g_prof.used >= (int)g_prof.kind.size()) return;
+    slot = g_prof.used++;
+    g_prof.kind[slot] = kind;
+    (void)hipEventRecord(g_prof.ev[2 * slot], st);
+  }
+  ~ProfScope() {
+    if (slot >= 0) (void)hipEventRecord(g_prof.ev[2 * slot + 1], st);
+  }
+};
 
 bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
 
@@ -232,6 +265,57 @@ extern "C" {
 
 const char* oo_last_error(void) { return g_err; }
 
+int oo_profile_begin(int32_t capacity) {
+  g_err[0] = 0;
+  if (capacity < 1 || capacity > (1 << 20)) return fail(OO_EINVAL, "capacity must be in [1, 2^20]");
+  std::lock_guard<std::mutex> lk(g_prof.m);
+  if (g_prof.on) return fail(OO_EINVAL, "profiling already enabled");
+  g_prof.ev.assign(2 * (size_t)capacity, nullptr);
+  for (auto& e : g_prof.ev) {
+    const hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) {
+      for (auto& x : g_prof.ev)
+        if (x) (void)hipEventDestroy(x);
+      g_prof.ev.clear();
+      return hip_status(r, "hipEventCreate");
+    }
+  }
+  g_prof.kind.assign(capacity, -1);
+  g_prof.used = 0;
+  g_prof.on = true;
+  return OO_OK;
+}
+
+int oo_profile_end(double* total_ms, int64_t* launches) {
+  g_err[0] = 0;
+  std::lock_guard<std::mutex> lk(g_prof.m);
+  if (!g_prof.on) return fail(OO_EINVAL, "profiling is not enabled");
+  int rc = OO_OK;
+  for (int k = 0; k < OO_PROF_KINDS; ++k) {
+    if (total_ms) total_ms[k] = 0.0;
+    if (launches) launches[k] = 0;
+  }
+  for (int i = 0; i < g_prof.used && rc == OO_OK; ++i) {
+    hipError_t r = hipEventSynchronize(g_prof.ev[2 * i + 1]);
+    float ms = 0.0f;
+    if (r == hipSuccess) r = hipEventElapsedTime(&ms, g_prof.ev[2 * i], g_prof.ev[2 * i + 1]);
+    if (r != hipSuccess) {
+      rc = hip_status(r, "profile event");
+      break;
+    }
+    if (total_ms) total_ms[g_prof.kind[i]] += ms;
+    if (launches) launches[g_prof.kind[i]] += 1;
+  }
+  for (auto& e : g_prof.ev) (void)hipEventDestroy(e);
+  g_prof.ev.clear();
+  g_prof.kind.clear();
+  g_prof.used = 0;
+  g_prof.on = false;
+  return rc;
+}
+
+const char* oo_profile_kind_name(int32_t kind) { return kind >= 0 && kind < OO_PROF_KINDS ? kProfNames[kind] : ""; }
+
 int oo_build_octree(const float* samples, int64_t n, int32_t max_depth, int32_t split_threshold, uint32_t* nodes_out,
                     int64_t capacity, int64_t* level_offset_out, int64_t* n_nodes_out) {
   g_err[0] = 0;
@@ -296,6 +380,7 @@ int oo_encode_query(const oo_tree* tree, const float* x, const float* dir, int64
   if (h_dtype != OO_F32 && h_dtype != OO_F16 && h_dtype != OO_BF16) return fail(OO_EINVAL, "unknown h_dtype");
   if (B == 0) return OO_OK;
   if (!x || !dir || !h_out) return fail(OO_EINVAL, "x, dir and h_out are required");
+  ProfScope ps(OO_PROF_ENCODE, stream);
   return hip_status(launch_encode(T, tree->feat_dtype, x, dir, B, h_out, h_dtype, node_idx_out, stream),
                     "encode_query launch");
 }
@@ -311,6 +396,7 @@ int oo_mlp_fwd(const oo_mlp* mlp, const void* h, oo_dtype h_dtype, int64_t B, fl
   if (B < 0) return fail(OO_EINVAL, "B must be >= 0");
   if (B == 0) return OO_OK;
   if (!h || !rgb_out) return fail(OO_EINVAL, "h and rgb_out are required");
+  ProfScope ps(OO_PROF_MLP, stream);
   return hip_status(launch_mlp(M, mlp->dtype, h, B, rgb_out, stream), "mlp_fwd launch");
 }
 
@@ -327,6 +413,7 @@ int oo_query_fwd(const oo_tree* tree, const oo_mlp* mlp, const float* x, const f
   if (B == 0) return OO_OK;
   if (!x || !dir || !rgb_out) return fail(OO_EINVAL, "x, dir and rgb_out are required");
   QuerySrc src{x, dir, B, x, dir};
+  ProfScope ps(OO_PROF_QUERY, stream);
   return hip_status(launch_query(T, tree->feat_dtype, M, mlp->dtype, src, B, rgb_out, nullptr, nullptr, 0, stream),
                     "query_fwd launch");
 }
@@ -347,7 +434,8 @@ int oo_residual_workspace_bytes(const oo_tree* tree, const oo_mlp* mlp, const oo
 }
 
 int oo_radiosity_residual_fwd(const oo_tree* tree, const oo_mlp* mlp, const oo_residual_batch* batch, float* lhs_out,
-                              float* rhs_out, float* resid_out, double* loss_out, void* workspace, hipStream_t stream) {
+                              float* rhs_out, float* resid_out, double* loss_out, void* workspace,
+                              size_t workspace_bytes, hipStream_t stream) {
   g_err[0] = 0;
   TreeArgs T;
   MlpArgs M;
@@ -360,6 +448,9 @@ int oo_radiosity_residual_fwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   if (!loss_out || !workspace) return fail(OO_EINVAL, "loss_out and workspace are required");
   if (A.B > 0 && (!lhs_out || !rhs_out || !resid_out)) return fail(OO_EINVAL, "lhs_out, rhs_out, resid_out are required");
   const Workspace w = workspace_layout(M, mlp->dtype, batch, tree->n_levels);
+  if (workspace_bytes < w.total)
+    return fail(OO_EINVAL, "workspace of %zu bytes is smaller than the %zu this problem needs", workspace_bytes,
+                w.total);
   char* ws = static_cast<char*>(workspace);
   float* Lq = reinterpret_cast<float*>(ws + w.Lq);
   double* lossp = reinterpret_cast<double*>(ws + w.lossp);
@@ -371,22 +462,31 @@ int oo_radiosity_residual_fwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   // order: Lq and the stored node indices are in sorted order
   int32_t* order = reinterpret_cast<int32_t*>(ws + w.order);
   int32_t* rank = reinterpret_cast<int32_t*>(ws + w.rank);
-  hipError_t e = launch_spatial_sort(src, Q, A.B, tree->n_levels - 1, reinterpret_cast<int32_t*>(ws + w.scount),
-                                     reinterpret_cast<int32_t*>(ws + w.stotal),
-                                     reinterpret_cast<int32_t*>(ws + w.sstart), order, rank, stream);
+  hipError_t e;
+  {
+    ProfScope ps(OO_PROF_SORT, stream);
+    e = launch_spatial_sort(src, Q, A.B, tree->n_levels - 1, reinterpret_cast<int32_t*>(ws + w.scount),
+                            reinterpret_cast<int32_t*>(ws + w.stotal), reinterpret_cast<int32_t*>(ws + w.sstart),
+                            order, rank, stream);
+  }
   if (e != hipSuccess) return hip_status(e, "query bucketing launch");
   QuerySrc sorted = src;
   sorted.idx = order;
   sorted.n = Q;
-  e = launch_query(T, tree->feat_dtype, M, mlp->dtype, sorted, Q, Lq, nidx, reinterpret_cast<float2*>(ws + w.uv), w.Qb,
-                   stream);
+  {
+    ProfScope ps(OO_PROF_QUERY, stream);
+    e = launch_query(T, tree->feat_dtype, M, mlp->dtype, sorted, Q, Lq, nidx, reinterpret_cast<float2*>(ws + w.uv),
+                     w.Qb, stream);
+  }
   if (e != hipSuccess) return hip_status(e, "residual query launch");
+  ProfScope ps(OO_PROF_COMBINE, stream);
   return hip_status(launch_combine(A, Lq, rank, lhs_out, rhs_out, resid_out, lossp, loss_out, stream), "combine launch");
 }
 
 int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_residual_batch* batch,
                               const float* resid, const float* rhs, const double* grad_loss, float* const* dfeat,
-                              float* const* dW, float* const* db, void* workspace, hipStream_t stream) {
+                              float* const* dW, float* const* db, void* workspace, size_t workspace_bytes,
+                              hipStream_t stream) {
   g_err[0] = 0;
   TreeArgs T;
   MlpArgs M;
@@ -409,6 +509,9 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   for (int i = 0; i < mlp->n_layers; ++i)
     if (!dW[i] || !db[i]) return fail(OO_EINVAL, "dW[%d] or db[%d] is NULL", i, i);
   const Workspace w = workspace_layout(M, mlp->dtype, batch, tree->n_levels);
+  if (workspace_bytes < w.total)
+    return fail(OO_EINVAL, "workspace of %zu bytes is smaller than the %zu this problem needs", workspace_bytes,
+                w.total);
   char* ws = static_cast<char*>(workspace);
   float* seeds = reinterpret_cast<float*>(ws + w.seeds);
   const int32_t* nidx = reinterpret_cast<const int32_t*>(ws + w.nidx);
@@ -418,9 +521,16 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   const bool full = batch->grad_through_rhs && !batch->target_override && batch->N > 0;
   const int64_t Qb = full ? A.B * (1 + A.N) : A.B;
   const float post_scale = (float)(1.0 / (3.0 * (double)A.B));
-  hipError_t e = launch_seeds(A, resid, rhs, grad_loss, full ? 1 : 0, seeds, stream);
+  hipError_t e;
+  {
+    ProfScope ps(OO_PROF_SEEDS, stream);
+    e = launch_seeds(A, resid, rhs, grad_loss, full ? 1 : 0, seeds, stream);
+  }
   if (e != hipSuccess) return hip_status(e, "seed launch");
-  e = launch_transpose_weights(M, mlp->dtype, Wt, stream);
+  {
+    ProfScope ps(OO_PROF_TRANSPOSE, stream);
+    e = launch_transpose_weights(M, mlp->dtype, Wt, stream);
+  }
   if (e != hipSuccess) return hip_status(e, "transpose launch");
   // the forward's bucketed order: its first Qb sorted positions are the
   // backward's queries (all LHS queries come first); node indices and
@@ -428,9 +538,16 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   const int32_t* order = reinterpret_cast<const int32_t*>(ws + w.order);
   const float2* uv = reinterpret_cast<const float2*>(ws + w.uv);
   float* dh = reinterpret_cast<float*>(ws + w.dh);
-  e = launch_bwd(T, tree->feat_dtype, M, mlp->dtype, Wt, Qb, nidx, uv, seeds, order, w.PL, partials, dh, w.grid, stream);
+  {
+    ProfScope ps(OO_PROF_BACKWARD, stream);
+    e = launch_bwd(T, tree->feat_dtype, M, mlp->dtype, Wt, Qb, nidx, uv, seeds, order, w.PL, partials, dh, w.grid,
+                   stream);
+  }
   if (e != hipSuccess) return hip_status(e, "backward launch");
-  e = launch_scatter(T, Qb, nidx, uv, dh, post_scale, G, stream);
+  {
+    ProfScope ps(OO_PROF_SCATTER, stream);
+    e = launch_scatter(T, Qb, nidx, uv, dh, post_scale, G, stream);
+  }
   if (e != hipSuccess) return hip_status(e, "scatter launch");
   ReduceDst D;
   D.n_seg = 2 * mlp->n_layers;
@@ -441,6 +558,7 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
     D.dst[2 * i + 1] = db[i];
   }
   D.start[D.n_seg] = w.PL.P;
+  ProfScope ps(OO_PROF_DW_REDUCE, stream);
   return hip_status(launch_dw_reduce(partials, w.grid, w.PL, D, post_scale, stream), "dW reduce launch");
 }
 
@@ -450,6 +568,7 @@ int oo_cast_params(const float* src, void* dst, oo_dtype dst_dtype, int64_t n, h
   if (dst_dtype != OO_F32 && dst_dtype != OO_F16 && dst_dtype != OO_BF16) return fail(OO_EINVAL, "unknown dtype");
   if (n == 0) return OO_OK;
   if (!src || !dst) return fail(OO_EINVAL, "src and dst are required");
+  ProfScope ps(OO_PROF_CAST, stream);
   return hip_status(launch_cast(src, dst, dst_dtype, n, stream), "cast launch");
 }
 

@@ -26,7 +26,7 @@ def L():
 def test_exports_every_declared_symbol(L):
     hdr = open(os.path.join(ROOT, "include", "octaoctree.h")).read()
     names = set(re.findall(r"^\s*(?:int|const char\*)\s+(oo_\w+)\s*\(", hdr, re.M))
-    assert len(names) == 9, names
+    assert len(names) == 12, names
     for n in sorted(names):
         assert hasattr(L, n), n
 
@@ -121,6 +121,22 @@ def test_validation_errors(L):
     assert b"" != L.oo_last_error()
 
 
+def test_profile_host_paths(L):
+    """Launch timing: argument checks and kind names (host only; enabling it
+    creates HIP events, which needs a device)."""
+    L.oo_profile_kind_name.restype = C.c_char_p
+    assert L.oo_profile_end(None, None) == -1          # not enabled
+    assert b"not enabled" in L.oo_last_error()
+    assert L.oo_profile_begin(0) == -1
+    assert L.oo_profile_begin(1 << 21) == -1
+    names = [L.oo_profile_kind_name(k) for k in range(binding.PROF_KINDS)]
+    assert names[1] == b"query" and names[5] == b"backward" and names[6] == b"scatter"
+    assert len(set(names)) == binding.PROF_KINDS and all(names)
+    assert L.oo_profile_kind_name(binding.PROF_KINDS) == b"" and L.oo_profile_kind_name(-1) == b""
+    hdr = open(os.path.join(ROOT, "include", "octaoctree.h")).read()
+    assert f"#define OO_PROF_KINDS {binding.PROF_KINDS}" in hdr
+
+
 def test_residual_batch_validation(L):
     t, m = _tree(), _mlp()
     b = binding._Batch()
@@ -134,3 +150,24 @@ def test_residual_batch_validation(L):
     b.loss_kind = 0
     b.N = -1
     assert L.oo_residual_workspace_bytes(C.byref(t), C.byref(m), C.byref(b), C.byref(n)) == -1
+
+
+def test_residual_rejects_small_workspace(L):
+    """A workspace smaller than oo_residual_workspace_bytes reports is
+    refused before anything is launched (the pointers here are never
+    dereferenced)."""
+    t, m = _tree(), _mlp()
+    b = binding._Batch()
+    b.B, b.N = 8, 2
+    b.x = b.dir = b.Le = b.n = b.wo = b.albedo = b.rough = b.x2 = b.dir2 = b.wi = 0x5000
+    n = C.c_size_t(0)
+    assert L.oo_residual_workspace_bytes(C.byref(t), C.byref(m), C.byref(b), C.byref(n)) == 0
+    need = n.value
+    assert need > 0
+    p = C.c_void_p(0x5000)
+    rc = L.oo_radiosity_residual_fwd(C.byref(t), C.byref(m), C.byref(b), p, p, p, p, p, need - 1, None)
+    assert rc == -1 and b"workspace" in L.oo_last_error()
+    ptrs = (C.c_void_p * 8)(*([0x5000] * 8))
+    rc = L.oo_radiosity_residual_bwd(C.byref(t), C.byref(m), C.byref(b), p, p, p, ptrs, ptrs, ptrs, p, need - 1,
+                                     None)
+    assert rc == -1 and b"workspace" in L.oo_last_error()
