@@ -332,7 +332,7 @@ def cpu_baseline(batch_np, nodes, lo, cfg, feat, W, b):
     if not os.path.exists(oracle.LIB_PATH):
         from oracle import build as obuild
         obuild.build()
-    S = 4096
+    S = 1 << 18  # about 10-30 s of host work
     sb = {k: (v[:S] if isinstance(v, np.ndarray) else v) for k, v in batch_np.items()}
     ot, om = oracle.Tree(nodes, lo, list(cfg.res), cfg.C, feat), oracle.MLP(W, b)
     nt = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(16, os.cpu_count() or 1)
