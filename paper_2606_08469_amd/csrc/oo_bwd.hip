@@ -59,6 +59,32 @@ __device__ inline typename FragT<MT>::type tq_frag(const MT* buf, int row, int c
   return *reinterpret_cast<const typename FragT<MT>::type*>(buf + row * kQW + ((chunk ^ (row & 7)) << 3));
 }
 
+// Packs an n_rows x n_cols row-major matrix (leading dimension ld) into
+// matrix-core A-fragment order: fragment (m, kb) holds, for lane l and slot
+// i, A[16 m + l % 16][nu(kb, l / 16, i)], zero outside the matrix. One
+// 16-byte LDS read then gives a lane its fragment.
+template <class MT>
+__device__ inline void pack_frags_lds(const MT* src, int n_rows, int n_cols, int ld, MT* dst) {
+  const int KB = (n_cols + 31) / 32, total = ((n_rows + 15) / 16) * KB * kWave * 8;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int i = e & 7, lane = (e >> 3) & 63, frag = e >> 9;
+    const int kb = frag % KB, m = frag / KB;
+    const int row = 16 * m + (lane & 15), col = nu(kb, lane >> 4, i);
+    dst[e] = (row < n_rows && col < n_cols) ? src[(int64_t)row * ld + col] : from_f32<MT>(0.0f);
+  }
+}
+
+template <class MT>
+__device__ inline typename FragT<MT>::type lds_frag(const MT* packed, int KB, int m, int kb, int lane) {
+  return *reinterpret_cast<const typename FragT<MT>::type*>(packed + ((m * KB + kb) * kWave + lane) * 8);
+}
+
+// Bytes of the packed hidden-to-hidden weights (W_i and W_i^T of every
+// layer 0 < i < n_layers - 1) kept in LDS next to the activation buffers.
+__host__ __device__ inline size_t hidden_weight_bytes(int H, int n_layers, int msz) {
+  return (size_t)(n_layers > 2 ? n_layers - 2 : 0) * 2 * H * H * msz;
+}
+
 // Single-element write into the fragment tile (q, k).
 template <class MT>
 __device__ inline void htile_put1(MT* tile, int KB, int q, int k, float v) {
@@ -151,8 +177,11 @@ __device__ inline void store_tq(MT* buf, const f32x4 (&acc)[MT2], int m0, int n_
 // Workgroup of kBwdWaves waves on 64 queries. In the layer chains wave w
 // works on query columns 16 (w % 4) .. +15 and on the share w / 4 of the
 // output rows; the layers exchange activations and deltas through the
-// [row][query] buffers.
-template <class TT, class MT, int C, int H>
+// [row][query] buffers. With WL the hidden-to-hidden weights W_i and W_i^T
+// are packed into LDS once per workgroup (their per-tile fragment loads
+// from L2 dominated the layer chains); the input and output layers' weights
+// are read from L2.
+template <class TT, class MT, int C, int H, bool WL>
 __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, const MlpArgs M, const MlpArgs Mt,
                                                   int64_t Q, const int32_t* __restrict__ nidx,
                                                   const float2* __restrict__ uv,
@@ -179,6 +208,13 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
   MT* dT = reinterpret_cast<MT*>(smem + lay.delta);
   int* qidx = reinterpret_cast<int*>(smem + lay.qidx);
   float* qst = reinterpret_cast<float*>(smem + lay.qst);
+  // packed hidden weights: layer i at hw + 2 (i - 1) H^2 (W_i), + H^2 (W_i^T)
+  MT* const hw = reinterpret_cast<MT*>(smem + lay.total);
+  if (WL)
+    for (int i = 1; i < NL - 1; ++i) {
+      pack_frags_lds<MT>(reinterpret_cast<const MT*>(M.W[i]), H, H, H, hw + (size_t)2 * (i - 1) * H * H);
+      pack_frags_lds<MT>(reinterpret_cast<const MT*>(Mt.W[i]), H, H, H, hw + (size_t)(2 * (i - 1) + 1) * H * H);
+    }
 
   f32x4 acc0[U0], accH[NHH][UH], accO[UO];
   const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
@@ -278,11 +314,16 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
         for (int mi = 0; mi < MH2; ++mi)
 #pragma unroll
           for (int j = 0; j < 4; ++j) acc[mi][j] = bl[16 * (mh * MH2 + mi) + 4 * g + j];
+        const MT* Wp = hw + (size_t)2 * (layer - 1) * H * H;
 #pragma unroll
         for (int kb = 0; kb < H / 32; ++kb) {
           const frag b = tq_bfrag<MT>(a, kb, g, col, H);
 #pragma unroll
-          for (int mi = 0; mi < MH2; ++mi) acc[mi] = mma(wfrag_global<MT>(Wl, H, H, H, mh * MH2 + mi, kb, lane), b, acc[mi]);
+          for (int mi = 0; mi < MH2; ++mi) {
+            const int m = mh * MH2 + mi;
+            acc[mi] = mma(WL ? lds_frag<MT>(Wp, H / 32, m, kb, lane) : wfrag_global<MT>(Wl, H, H, H, m, kb, lane), b,
+                          acc[mi]);
+          }
         }
         store_tq<MT, MH2>(act(layer + 1), acc, mh * MH2, MH, H, nt, lane, true);
       }
@@ -333,10 +374,16 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
         f32x4 dacc[MH2];
 #pragma unroll
         for (int mi = 0; mi < MH2; ++mi) dacc[mi] = z4;
+        const bool hid = WL && i < NL - 1;  // W_i^T packed in LDS
+        const MT* Wp = hw + (size_t)(2 * (i - 1) + 1) * H * H;
         for (int kb = 0; kb < KBo; ++kb) {
           const frag b = tq_bfrag<MT>(dT, kb, gs, cs, n_out);
 #pragma unroll
-          for (int mi = 0; mi < MH2; ++mi) dacc[mi] = mma(wfrag_global<MT>(Wt, H, n_out, ldt, mh * MH2 + mi, kb, ln), b, dacc[mi]);
+          for (int mi = 0; mi < MH2; ++mi) {
+            const int m = mh * MH2 + mi;
+            dacc[mi] = mma(hid ? lds_frag<MT>(Wp, H / 32, m, kb, ln) : wfrag_global<MT>(Wt, H, n_out, ldt, m, kb, ln), b,
+                           dacc[mi]);
+          }
         }
         // ReLU'(z) = 1 where the layer-i input activation is positive
         const MT* a = act(i);
@@ -530,8 +577,20 @@ static int cu_count() {
   return cus;
 }
 
+constexpr size_t kLdsBytes = 160 * 1024;
+
+// LDS of the backward workgroup: the buffers, plus the packed hidden weights
+// when both fit.
+static size_t bwd_lds_total(int K0, int H, int n_layers, int L, int msz, bool& wl) {
+  const size_t base = bwd_layout(K0, H, n_layers, L, msz).total;
+  const size_t hwb = hidden_weight_bytes(H, n_layers, msz);
+  wl = hwb > 0 && base + hwb <= kLdsBytes;
+  return wl ? base + hwb : base;
+}
+
 size_t bwd_lds_bytes(const MlpArgs& M, oo_dtype md, int L) {
-  return bwd_layout(M.K0, M.H, M.n_layers, L, md == OO_F32 ? 4 : 2).total;
+  bool wl;
+  return bwd_lds_total(M.K0, M.H, M.n_layers, L, md == OO_F32 ? 4 : 2, wl);
 }
 
 // Persistent grid: as many workgroups as fit on the chip at once (LDS
@@ -540,7 +599,7 @@ size_t bwd_lds_bytes(const MlpArgs& M, oo_dtype md, int L) {
 int bwd_grid(const MlpArgs& M, oo_dtype md, int L, int64_t Q) {
   const int64_t n_tiles = (Q + kQW - 1) / kQW;
   const size_t lds = bwd_lds_bytes(M, md, L);
-  int per_cu = (int)((size_t)160 * 1024 / (lds ? lds : 1));
+  int per_cu = (int)(kLdsBytes / (lds ? lds : 1));
   const int by_waves = 16 / kBwdWaves;  // four waves per SIMD fit the kernel's registers
   if (per_cu > by_waves) per_cu = by_waves;
   per_cu = per_cu < 1 ? 1 : per_cu;
@@ -571,8 +630,9 @@ template <class TT, class MT, int C, int H>
 static hipError_t launch_bwd_t(const TreeArgs& T, const MlpArgs& M, const MlpArgs& Mt, int64_t Q,
                                const int32_t* nidx, const float2* uv, const float* seeds, const int32_t* order,
                                const ParamLayout& PL, float* partials, float* dh, int grid, hipStream_t st) {
-  const size_t lds = bwd_layout(M.K0, H, M.n_layers, T.L, (int)sizeof(MT)).total;
-  auto k = bwd_kernel<TT, MT, C, H>;
+  bool wl;
+  const size_t lds = bwd_lds_total(M.K0, H, M.n_layers, T.L, (int)sizeof(MT), wl);
+  auto k = wl ? bwd_kernel<TT, MT, C, H, true> : bwd_kernel<TT, MT, C, H, false>;
   hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k, dim3(grid), dim3(64 * kBwdWaves), lds, st, T, M, Mt, Q, nidx, uv, seeds, order, PL, partials,
                      dh);
