@@ -26,7 +26,7 @@ constexpr int kQW = 64;  // queries per workgroup tile
 
 struct BwdLayout {
   int KB0, R0;
-  size_t htile, act0, act1, delta, qidx, qst, total;
+  size_t act0, act1, delta, qidx, qst, total;
 };
 
 __host__ __device__ inline BwdLayout bwd_layout(int K0, int H, int n_layers, int L, int msz) {
@@ -34,8 +34,6 @@ __host__ __device__ inline BwdLayout bwd_layout(int K0, int H, int n_layers, int
   b.KB0 = (K0 + 31) / 32;
   b.R0 = (K0 + 15) / 16 * 16;
   size_t o = 0;
-  b.htile = o;
-  o += (size_t)4 * b.KB0 * kWave * 8 * msz;
   b.act0 = o;
   o += (size_t)b.R0 * kQW * msz;
   b.act1 = o;  // hidden-layer activations a_1 .. a_{n_layers-1}, H rows each
@@ -79,17 +77,16 @@ __device__ inline typename FragT<MT>::type lds_frag(const MT* packed, int KB, in
   return *reinterpret_cast<const typename FragT<MT>::type*>(packed + ((m * KB + kb) * kWave + lane) * 8);
 }
 
-// Bytes of the packed hidden-to-hidden weights (W_i and W_i^T of every
-// layer 0 < i < n_layers - 1) kept in LDS next to the activation buffers.
-__host__ __device__ inline size_t hidden_weight_bytes(int H, int n_layers, int msz) {
-  return (size_t)(n_layers > 2 ? n_layers - 2 : 0) * 2 * H * H * msz;
+// Weights kept packed in LDS next to the activation buffers: W_i and W_i^T
+// of every hidden-to-hidden layer 0 < i < n_layers - 1 (H x H each), then
+// W_0^T (K0 x H), which forms dh.
+__host__ __device__ inline size_t hidden_weight_elems(int H, int n_layers) {
+  return (size_t)(n_layers > 2 ? n_layers - 2 : 0) * 2 * H * H;
+}
+__host__ __device__ inline size_t lds_weight_bytes(int K0, int H, int n_layers, int msz) {
+  return (hidden_weight_elems(H, n_layers) + (size_t)((K0 + 15) / 16) * (H / 32) * kWave * 8) * msz;
 }
 
-// Single-element write into the fragment tile (q, k).
-template <class MT>
-__device__ inline void htile_put1(MT* tile, int KB, int q, int k, float v) {
-  tile[htile_index<MT>(q, k, KB)] = from_f32<MT>(v);
-}
 
 // Waves per workgroup. With 16 waves (four per SIMD) each wave owns a
 // sixteenth of the dW tiles, which keeps a 128-wide MLP's accumulators and
@@ -178,9 +175,9 @@ __device__ inline void store_tq(MT* buf, const f32x4 (&acc)[MT2], int m0, int n_
 // works on query columns 16 (w % 4) .. +15 and on the share w / 4 of the
 // output rows; the layers exchange activations and deltas through the
 // [row][query] buffers. With WL the hidden-to-hidden weights W_i and W_i^T
-// are packed into LDS once per workgroup (their per-tile fragment loads
-// from L2 dominated the layer chains); the input and output layers' weights
-// are read from L2.
+// and W_0^T are packed into LDS once per workgroup (their per-tile fragment
+// loads from L2 dominated the layer chains); W_0 and the output layer's
+// weights are read from L2.
 template <class TT, class MT, int C, int H, bool WL>
 __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, const MlpArgs M, const MlpArgs Mt,
                                                   int64_t Q, const int32_t* __restrict__ nidx,
@@ -200,7 +197,6 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
   const int K0 = M.K0, NL = M.n_layers, L = T.L;
   const BwdLayout lay = bwd_layout(K0, H, NL, L, (int)sizeof(MT));
   const int KB0 = lay.KB0, R0 = lay.R0;
-  MT* htile = reinterpret_cast<MT*>(smem + lay.htile);
   MT* const act0 = reinterpret_cast<MT*>(smem + lay.act0);
   MT* const act1 = reinterpret_cast<MT*>(smem + lay.act1);
   // input activation buffer of layer i: a_0 = h, a_i = ReLU(z_{i-1})
@@ -208,13 +204,17 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
   MT* dT = reinterpret_cast<MT*>(smem + lay.delta);
   int* qidx = reinterpret_cast<int*>(smem + lay.qidx);
   float* qst = reinterpret_cast<float*>(smem + lay.qst);
-  // packed hidden weights: layer i at hw + 2 (i - 1) H^2 (W_i), + H^2 (W_i^T)
+  // packed weights: layer i at hw + 2 (i - 1) H^2 (W_i), + H^2 (W_i^T);
+  // W_0^T after the hidden layers
   MT* const hw = reinterpret_cast<MT*>(smem + lay.total);
-  if (WL)
+  MT* const wt0 = hw + hidden_weight_elems(H, NL);
+  if (WL) {
     for (int i = 1; i < NL - 1; ++i) {
       pack_frags_lds<MT>(reinterpret_cast<const MT*>(M.W[i]), H, H, H, hw + (size_t)2 * (i - 1) * H * H);
       pack_frags_lds<MT>(reinterpret_cast<const MT*>(Mt.W[i]), H, H, H, hw + (size_t)(2 * (i - 1) + 1) * H * H);
     }
+    pack_frags_lds<MT>(reinterpret_cast<const MT*>(Mt.W[0]), K0, H, H, wt0);  // W_0^T is [K0][H]
+  }
 
   f32x4 acc0[U0], accH[NHH][UH], accO[UO];
   const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
@@ -230,11 +230,7 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
 #pragma unroll
   for (int i = 0; i < kMaxLayers; ++i) dbacc[i] = 0.0f;
 
-  // Zero paddings once: h tile inputs [K0, 32 KB0) and layer-0 rows [K0, R0).
-  for (int e = tid; e < kQW * (32 * KB0 - K0); e += blockDim.x) {
-    const int q = e % kQW, k = K0 + e / kQW;
-    htile_put1<MT>(htile, KB0, q, k, 0.0f);
-  }
+  // Zero the layer-0 padding rows [K0, R0) once.
   for (int e = tid; e < (R0 - K0) * kQW; e += blockDim.x) act0[tq_index(K0 + e / kQW, e % kQW)] = from_f32<MT>(0.0f);
   __syncthreads();
 
@@ -282,8 +278,6 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
         const int l = part + kLanesPerQuery * gi;
         if (l < L) {
 #pragma unroll
-          for (int c = 0; c < C; c += 4) htile_put4<MT>(htile, KB0, ql, l * C + c, &h[gi][c]);
-#pragma unroll
           for (int c = 0; c < C; ++c) act0[tq_index(l * C + c, ql)] = from_f32<MT>(h[gi][c]);
         }
       }
@@ -300,7 +294,7 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[mi][j] = b0[16 * (mh * MH2 + mi) + 4 * g + j];
       for (int kb = 0; kb < KB0; ++kb) {
-        const frag b = htile_get<MT>(htile, KB0, nt, kb, lane);
+        const frag b = tq_bfrag<MT>(act0, kb, g, col, K0);
 #pragma unroll
         for (int mi = 0; mi < MH2; ++mi) acc[mi] = mma(wfrag_global<MT>(W0, H, K0, K0, mh * MH2 + mi, kb, lane), b, acc[mi]);
       }
@@ -406,7 +400,11 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
           const frag b = tq_bfrag<MT>(dT, kb, gs, cs, n_out);
 #pragma unroll
           for (int mi = 0; mi < MK2; ++mi)
-            if (mh * MK2 + mi < MK) dacc[mi] = mma(wfrag_global<MT>(Wt, K0, n_out, ldt, mh * MK2 + mi, kb, ln), b, dacc[mi]);
+            if (mh * MK2 + mi < MK) {
+              const int m = mh * MK2 + mi;
+              dacc[mi] = mma(WL ? lds_frag<MT>(wt0, H / 32, m, kb, ln) : wfrag_global<MT>(Wt, K0, n_out, ldt, m, kb, ln),
+                             b, dacc[mi]);
+            }
         }
         // dh of query column cs, rows 16m + 4g .. +3: one 16-byte store each
         const int64_t q = qbase + cs;
@@ -583,8 +581,8 @@ constexpr size_t kLdsBytes = 160 * 1024;
 // when both fit.
 static size_t bwd_lds_total(int K0, int H, int n_layers, int L, int msz, bool& wl) {
   const size_t base = bwd_layout(K0, H, n_layers, L, msz).total;
-  const size_t hwb = hidden_weight_bytes(H, n_layers, msz);
-  wl = hwb > 0 && base + hwb <= kLdsBytes;
+  const size_t hwb = lds_weight_bytes(K0, H, n_layers, msz);
+  wl = base + hwb <= kLdsBytes;
   return wl ? base + hwb : base;
 }
 
