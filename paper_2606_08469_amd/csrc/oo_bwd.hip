@@ -658,8 +658,8 @@ hipError_t launch_bwd(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype
   (void)md;
 }
 
-// Feature-gradient scatter: one lane per (query, tap, channel) at level
-// l = blockIdx.y, queries along x, so one atomic instruction of a wave covers
+// Feature-gradient scatter: one lane per (query, tap, channel), level by
+// level, queries along the grid, so one atomic instruction of a wave covers
 // whole bilinear footprints (4C consecutive lanes per query). The memory-side
 // atomic units work on 64-byte chunks, one chunk per instruction and chunk
 // touched, so the two taps of a footprint row (2C contiguous floats) mostly
@@ -675,43 +675,37 @@ template <int C>
 __global__ __launch_bounds__(256) void scatter_kernel(const TreeArgs T, int64_t Q, const int32_t* __restrict__ nidx,
                                                       const float2* __restrict__ uv, const float* __restrict__ dh,
                                                       float post_scale, const GradArgs G) {
-  const int l = blockIdx.y;
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t q = gid / (4 * C);
-  const int k = (int)(gid / C) & 3;
-  const int c = (int)(gid % C);
-  if (q >= Q) return;
-  const int id = nidx[(int64_t)l * Q + q];
-  if (id < T.off[l] || id >= T.off[l + 1]) return;
-  const float2 p = uv[q];
-  const float s = fminf(fmaxf(p.x, 0.0f), 1.0f), t = fminf(fmaxf(p.y, 0.0f), 1.0f);
-  const int R = T.res[l];
-  int tx[4];
-  float w[4];
-  taps(s, t, R, tx, w);
-  int txk = tx[0];
-  float wk = w[0];
-#pragma unroll
-  for (int j = 1; j < 4; ++j)
-    if (k == j) {
-      txk = tx[j];
-      wk = w[j];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x, n = Q * 4 * C;
+  for (int l = 0; l < T.L; ++l) {
+    const int R = T.res[l];
+    for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < n; gid += stride) {
+      const int64_t q = gid / (4 * C);
+      const int k = (int)(gid / C) & 3;
+      const int c = (int)(gid % C);
+      const int id = nidx[(int64_t)l * Q + q];
+      if (id < T.off[l] || id >= T.off[l + 1]) continue;
+      const float2 p = uv[q];
+      const float s = fminf(fmaxf(p.x, 0.0f), 1.0f), t = fminf(fmaxf(p.y, 0.0f), 1.0f);
+      int txk;
+      float wk;
+      tap(s, t, R, k, txk, wk);
+      const float gv = dh[q * (int64_t)(T.L * C) + l * C + c] * post_scale;
+      unsafeAtomicAdd(G.dfeat[l] + ((int64_t)(id - T.off[l]) * R * R + txk) * C + c, wk * gv);
     }
-  const float gv = dh[q * (int64_t)(T.L * C) + l * C + c] * post_scale;
-  unsafeAtomicAdd(G.dfeat[l] + ((int64_t)(id - T.off[l]) * R * R + txk) * C + c, wk * gv);
+  }
 }
 
 hipError_t launch_scatter(const TreeArgs& T, int64_t Q, const int32_t* nidx, const float2* uv, const float* dh,
                           float post_scale, const GradArgs& G, hipStream_t st) {
   if (Q == 0) return hipSuccess;
-  const int64_t blocks = (Q * 4 * T.C + 255) / 256;
-  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  // a persistent grid walks every level: block scheduling stays out of the
+  // way of the atomic stream
+  int64_t blocks = (Q * 4 * T.C + 255) / 256;
+  if (blocks > 256 * 16) blocks = 256 * 16;
   if (T.C == 4)
-    hipLaunchKernelGGL(scatter_kernel<4>, dim3((unsigned)blocks, T.L), dim3(256), 0, st, T, Q, nidx, uv, dh,
-                       post_scale, G);
+    hipLaunchKernelGGL(scatter_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, st, T, Q, nidx, uv, dh, post_scale, G);
   else
-    hipLaunchKernelGGL(scatter_kernel<8>, dim3((unsigned)blocks, T.L), dim3(256), 0, st, T, Q, nidx, uv, dh,
-                       post_scale, G);
+    hipLaunchKernelGGL(scatter_kernel<8>, dim3((unsigned)blocks), dim3(256), 0, st, T, Q, nidx, uv, dh, post_scale, G);
   return hipGetLastError();
 }
 

@@ -143,36 +143,39 @@ __device__ inline void octa(const float d[3], float& s, float& t) {
   t = 0.5f * (uy + 1.0f);
 }
 
-// Four texel-centred bilinear taps at resolution R. A tap beyond the map is
-// moved across the octahedral seam: columns first (edges s = 0 and s = 1 meet
-// themselves with t mirrored), then rows (edges t = 0 and t = 1 meet
-// themselves with s mirrored). texel[k] = j * R + i.
-__device__ inline void taps(float s, float t, int R, int texel[4], float w[4]) {
+// Texel-centred bilinear tap k (k & 1: column +1, k >> 1: row +1) at
+// resolution R. A tap beyond the map is moved across the octahedral seam:
+// columns first (edges s = 0 and s = 1 meet themselves with t mirrored), then
+// rows (edges t = 0 and t = 1 meet themselves with s mirrored).
+// texel = j * R + i.
+__device__ inline void tap(float s, float t, int R, int k, int& texel, float& w) {
   const float pu = s * (float)R - 0.5f, pv = t * (float)R - 0.5f;
   const float fi = floorf(pu), fj = floorf(pv);
   const float fu = pu - fi, fv = pv - fj;
-  const int i0 = (int)fi, j0 = (int)fj;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int a = k & 1, b = k >> 1;
-    int i = i0 + a, j = j0 + b;
-    w[k] = (a ? fu : 1.0f - fu) * (b ? fv : 1.0f - fv);
-    if (i < 0) {
-      i = -1 - i;
-      j = R - 1 - j;
-    } else if (i >= R) {
-      i = 2 * R - 1 - i;
-      j = R - 1 - j;
-    }
-    if (j < 0) {
-      i = R - 1 - i;
-      j = -1 - j;
-    } else if (j >= R) {
-      i = R - 1 - i;
-      j = 2 * R - 1 - j;
-    }
-    texel[k] = j * R + i;
+  const int a = k & 1, b = k >> 1;
+  int i = (int)fi + a, j = (int)fj + b;
+  w = (a ? fu : 1.0f - fu) * (b ? fv : 1.0f - fv);
+  if (i < 0) {
+    i = -1 - i;
+    j = R - 1 - j;
+  } else if (i >= R) {
+    i = 2 * R - 1 - i;
+    j = R - 1 - j;
   }
+  if (j < 0) {
+    i = R - 1 - i;
+    j = -1 - j;
+  } else if (j >= R) {
+    i = R - 1 - i;
+    j = 2 * R - 1 - j;
+  }
+  texel = j * R + i;
+}
+
+// All four taps.
+__device__ inline void taps(float s, float t, int R, int texel[4], float w[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) tap(s, t, R, k, texel[k], w[k]);
 }
 
 // ---------------------------------------------------------------------------
