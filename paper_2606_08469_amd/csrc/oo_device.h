@@ -147,7 +147,10 @@ __device__ inline void octa(const float d[3], float& s, float& t) {
 // resolution R. A tap beyond the map is moved across the octahedral seam:
 // columns first (edges s = 0 and s = 1 meet themselves with t mirrored), then
 // rows (edges t = 0 and t = 1 meet themselves with s mirrored).
-// texel = j * R + i.
+// texel = j * R + i. For s, t in [0, 1] the unwrapped i and j lie in
+// [-1, R], where a step past an edge lands on the edge texel itself: the wrap
+// is a clamp plus a mirror of the other coordinate, written without branches.
+// Out-of-range (s, t) still give in-range texels.
 __device__ inline void tap(float s, float t, int R, int k, int& texel, float& w) {
   const float pu = s * (float)R - 0.5f, pv = t * (float)R - 0.5f;
   const float fi = floorf(pu), fj = floorf(pv);
@@ -155,20 +158,12 @@ __device__ inline void tap(float s, float t, int R, int k, int& texel, float& w)
   const int a = k & 1, b = k >> 1;
   int i = (int)fi + a, j = (int)fj + b;
   w = (a ? fu : 1.0f - fu) * (b ? fv : 1.0f - fv);
-  if (i < 0) {
-    i = -1 - i;
-    j = R - 1 - j;
-  } else if (i >= R) {
-    i = 2 * R - 1 - i;
-    j = R - 1 - j;
-  }
-  if (j < 0) {
-    i = R - 1 - i;
-    j = -1 - j;
-  } else if (j >= R) {
-    i = R - 1 - i;
-    j = 2 * R - 1 - j;
-  }
+  const bool wrap_col = (unsigned)i >= (unsigned)R;
+  j = wrap_col ? R - 1 - j : j;
+  i = min(max(i, 0), R - 1);
+  const bool wrap_row = (unsigned)j >= (unsigned)R;
+  i = wrap_row ? R - 1 - i : i;
+  j = min(max(j, 0), R - 1);
   texel = j * R + i;
 }
 
