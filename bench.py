@@ -83,11 +83,14 @@ def main():
 
     mixed = binding.OctaOctree(nodes, lo, list(cfg.res), cfg.C, feat, W, b, dtype=torch.float16)
     batch = binding.device_batch(batch_np)
-    grads = {
-        "dfeat": [torch.zeros(f.shape, dtype=torch.float32, device=dev) for f in mixed.feat],
-        "dW": [torch.zeros(w.shape, dtype=torch.float32, device=dev) for w in mixed.W],
-        "db": [torch.zeros(v.shape, dtype=torch.float32, device=dev) for v in mixed.b],
-    }
+    # FP32 gradient accumulators in one flat buffer (aligned views), zeroed
+    # with a single fill per step
+    gshapes = [tuple(t.shape) for t in list(mixed.feat) + list(mixed.W) + list(mixed.b)]
+    goffs, gtotal = binding._flat_layout(gshapes)
+    gflat = torch.zeros(gtotal, dtype=torch.float32, device=dev)
+    gviews = [gflat[o:o + int(np.prod(sh))].view(sh) for sh, o in zip(gshapes, goffs)]
+    nf, nw = len(mixed.feat), len(mixed.W)
+    grads = {"dfeat": gviews[:nf], "dW": gviews[nf:nf + nw], "db": gviews[nf + nw:]}
     ws_mixed = mixed.workspace(batch)
     outs = tuple(torch.empty((B, 3), dtype=torch.float32, device=dev) for _ in range(3)) + (
         torch.empty((), dtype=torch.float64, device=dev),)
@@ -95,8 +98,7 @@ def main():
 
     def step(model, ev=None):
         model.refresh()
-        for g in grads["dfeat"] + grads["dW"] + grads["db"]:
-            g.zero_()
+        gflat.zero_()
         if ev:
             ev[0].record()
         ws = model.workspace(batch)  # sized for this model's dtypes

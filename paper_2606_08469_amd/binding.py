@@ -297,19 +297,45 @@ def cast_params(src, dst):
 # Module and autograd
 # ---------------------------------------------------------------------------
 
+def _flat_layout(shapes, align=8):
+    """Element offsets of tensors packed one after another in a flat buffer,
+    each starting on a multiple of `align` elements (16 B for 16-bit
+    elements, the tables' alignment requirement). Returns (offsets, total)."""
+    offs, o = [], 0
+    for sh in shapes:
+        offs.append(o)
+        n = int(np.prod(sh)) if len(sh) else 1
+        o += (n + align - 1) // align * align
+    return offs, max(o, align)
+
+
 class OctaOctree(torch.nn.Module):
     """FP32 master feature tables and MLP weights as Parameters, with 16-bit
-    working copies (refreshed by ``refresh()``) when ``dtype`` is FP16/BF16."""
+    working copies (refreshed by ``refresh()``) when ``dtype`` is FP16/BF16.
+
+    Masters and working copies each live in one flat buffer with the same
+    aligned layout, so a refresh is a single cast launch over the buffer."""
 
     def __init__(self, nodes, level_offset, res, C_, feat, W, b, dtype=torch.float32):
         super().__init__()
         self.dtype = dtype
-        self.feat = torch.nn.ParameterList([torch.nn.Parameter(_dev(f)) for f in feat])
-        self.W = torch.nn.ParameterList([torch.nn.Parameter(_dev(w)) for w in W])
+        shapes = [tuple(np.shape(f)) for f in feat] + [tuple(np.shape(w)) for w in W]
+        self._offs, total = _flat_layout(shapes)
+        self._master = torch.zeros(total, dtype=torch.float32, device="cuda")
+        views = []
+        for src, sh, o in zip(list(feat) + list(W), shapes, self._offs):
+            n = int(np.prod(sh)) if len(sh) else 1
+            v = self._master[o:o + n].view(sh)
+            v.copy_(_dev(src))
+            views.append(torch.nn.Parameter(v))
+        nf = len(feat)
+        self.feat = torch.nn.ParameterList(views[:nf])
+        self.W = torch.nn.ParameterList(views[nf:])
         self.b = torch.nn.ParameterList([torch.nn.Parameter(_dev(v)) for v in b])
         self.tree = Tree(nodes, level_offset, res, C_, list(self.feat))
         self.mlp = MLP(list(self.W), list(self.b))
         self._ws = None
+        self._work = None
         self.work_feat, self.work_W = None, None
         self.refresh()
 
@@ -318,13 +344,14 @@ class OctaOctree(torch.nn.Module):
         with torch.no_grad():
             if self.dtype == torch.float32:
                 self.work_feat, self.work_W = list(self.feat), list(self.W)
-            else:
-                if self.work_feat is None:
-                    self.work_feat = [torch.empty_like(f, dtype=self.dtype) for f in self.feat]
-                    self.work_W = [torch.empty_like(w, dtype=self.dtype) for w in self.W]
-                for src, dst in zip(list(self.feat) + list(self.W), self.work_feat + self.work_W):
-                    if src.numel():
-                        cast_params(src.detach(), dst)
+                return
+            if self._work is None:
+                self._work = torch.empty(self._master.numel(), dtype=self.dtype, device="cuda")
+                views = [self._work[o:o + p.numel()].view(p.shape)
+                         for p, o in zip(list(self.feat) + list(self.W), self._offs)]
+                nf = len(self.feat)
+                self.work_feat, self.work_W = views[:nf], views[nf:]
+            cast_params(self._master, self._work)
 
     def forward(self, x, d):
         """Radiance at (x, d) [B][3] (inference; no autograd)."""
