@@ -129,8 +129,8 @@ def main():
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t) / steps
         per = None
-        if kernels:
-            per = {k: (v[0] / v[1], v[1]) for k, v in binding.profile_end().items()}
+        if kernels:  # kind -> (ms per launch, launches per step)
+            per = {k: (v[0] / v[1], v[1] / steps) for k, v in binding.profile_end().items()}
         fwd = [e[0].elapsed_time(e[1]) for e in evs]
         bwd = [e[1].elapsed_time(e[2]) for e in evs]
         return wall * 1e3, float(np.mean(fwd)), float(np.mean(bwd)), per
@@ -151,7 +151,7 @@ def main():
     lv_lhs = float(present[:B].sum().item())
     del xq, dq, idx, present
     kern = kernel_rooflines(cfg, B, Q, lv_all, lv_lhs, per_kernel)
-    dom = max(kern, key=lambda k: kern[k]["ms_per_launch"])
+    dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
     traffic, traffic_src = hbm_traffic(dom)
     roof = dict(kern[dom])
     roof.update(traffic=traffic, traffic_source=traffic_src)
@@ -202,6 +202,7 @@ def main():
             "lhs_points_per_s_M": round(B / (ms * 1e-3) / 1e6, 3),
             "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4),
             "ms_per_launch": {k: round(v[0], 4) for k, v in per_kernel.items()},
+            "launches_per_step": {k: round(v[1], 2) for k, v in per_kernel.items()},
         },
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -264,7 +265,9 @@ MFMA_F16_PEAK_TFS = 2500.0  # MI355X dense FP16 matrix cores
 
 def kernel_rooflines(cfg, B, Q, lv_all, lv_lhs, per_kernel):
     """Algorithmic bytes and FLOPs per launch of the three dominant kernels of
-    the step, against their launch times measured in the timed region.
+    the step, against their launch times measured in the timed region (the
+    backward and the scatter run in several launches per step, each over its
+    share of the queries).
 
     Per query and present level (lv = sum over queries of present levels):
     4 taps x C channels x 2 B (FP16 texels) + 4 B node word in the forward;
@@ -287,10 +290,14 @@ def kernel_rooflines(cfg, B, Q, lv_all, lv_lhs, per_kernel):
     for k, (nbytes, flop) in spec.items():
         if k not in per_kernel:
             continue
+        # the backward runs in chunks: per-launch work is the step's share
+        per_step = per_kernel[k][1]
+        nbytes, flop = nbytes / per_step, flop / per_step
         t = per_kernel[k][0] * 1e-3
         gbs = nbytes / t / 1e9
         out[k] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                   "frac": round(gbs / HBM_PEAK_GBS, 4), "ms_per_launch": round(per_kernel[k][0], 4),
+                  "launches_per_step": round(per_step, 2), "ms_per_step": round(per_kernel[k][0] * per_step, 4),
                   "algorithmic_bytes": int(nbytes), "mlp_flop": int(flop),
                   "mfma_frac": round(flop / t / 1e12 / MFMA_F16_PEAK_TFS, 4)}
     return out

@@ -20,6 +20,19 @@ namespace {
 
 thread_local char g_err[512] = "";
 
+// The backward runs in up to kMaxChunks chunks of at least kChunkQueries
+// sorted positions; the feature scatter of chunk c runs on a second stream
+// while the backward kernel works on chunk c + 1 (the scatter is bound by
+// the memory-side atomic units, the backward by latency, so they overlap).
+constexpr int kMaxChunks = 4;
+constexpr int64_t kChunkQueries = 32768;
+
+int bwd_chunks(int64_t Qb) {
+  int64_t n = Qb / kChunkQueries;
+  return (int)(n < 1 ? 1 : (n > kMaxChunks ? kMaxChunks : n));
+}
+
+
 int fail(int code, const char* fmt, ...) {
   va_list ap;
   va_start(ap, fmt);
@@ -64,6 +77,31 @@ struct ProfScope {
     if (slot >= 0) (void)hipEventRecord(g_prof.ev[2 * slot + 1], st);
   }
 };
+
+// Second stream per device for the overlapped feature scatter, with the
+// events that order it against the caller's stream. Created on first use at
+// the default priority; the enqueue sequence that uses it is serialised.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t ev[kMaxChunks + 1] = {};
+};
+std::mutex g_side_m;
+SideStream g_side[64];
+
+hipError_t side_stream(SideStream*& out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  SideStream& S = g_side[dev];
+  if (!S.s) {
+    if ((e = hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking)) != hipSuccess) return e;
+    for (auto& ev : S.ev)
+      if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
+  }
+  out = &S;
+  return hipSuccess;
+}
 
 bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
 
@@ -218,7 +256,7 @@ Workspace workspace_layout(const MlpArgs& M, oo_dtype md, const oo_residual_batc
     w.wt[i] = o;
     o = align256(o + (size_t)w.PL.n_in[i] * ((w.PL.n_out[i] + 3) & ~3) * esz);
   }
-  w.dwp = o;
+  w.dwp = o;  // dW/db partials, [grid][P], accumulated over the backward's chunks
   o = align256(o + (size_t)w.grid * w.PL.P * sizeof(float));
   // spatially bucketed queries, written by the forward and read by both passes
   const SortShape ss = sort_shape(Qf, L - 1);
@@ -538,17 +576,38 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   const int32_t* order = reinterpret_cast<const int32_t*>(ws + w.order);
   const float2* uv = reinterpret_cast<const float2*>(ws + w.uv);
   float* dh = reinterpret_cast<float*>(ws + w.dh);
+  const int nc = bwd_chunks(Qb);
+  const int64_t chunk = ((Qb + nc - 1) / nc + 63) / 64 * 64;  // whole 64-query tiles
   {
-    ProfScope ps(OO_PROF_BACKWARD, stream);
-    e = launch_bwd(T, tree->feat_dtype, M, mlp->dtype, Wt, Qb, nidx, uv, seeds, order, w.PL, partials, dh, w.grid,
-                   stream);
+    std::lock_guard<std::mutex> lk(g_side_m);
+    SideStream* side = nullptr;
+    if (nc > 1 && (e = side_stream(side)) != hipSuccess) return hip_status(e, "side stream");
+    for (int c = 0; c < nc; ++c) {
+      const int64_t q0 = c * chunk, qn = std::min(Qb - q0, chunk);
+      if (qn <= 0) break;
+      BwdArgs B{qn, nidx + q0, Qb, uv + q0, seeds, order + q0, Qb, partials, dh + q0 * M.K0, c > 0};
+      {
+        ProfScope ps(OO_PROF_BACKWARD, stream);
+        e = launch_bwd(T, tree->feat_dtype, M, mlp->dtype, Wt, B, w.PL, w.grid, stream);
+      }
+      if (e != hipSuccess) return hip_status(e, "backward launch");
+      hipStream_t ss = stream;
+      if (side) {  // the scatter of this chunk waits for its dh only
+        if ((e = hipEventRecord(side->ev[c], stream)) != hipSuccess) return hip_status(e, "event record");
+        if ((e = hipStreamWaitEvent(side->s, side->ev[c], 0)) != hipSuccess) return hip_status(e, "stream wait");
+        ss = side->s;
+      }
+      {
+        ProfScope ps(OO_PROF_SCATTER, ss);
+        e = launch_scatter(T, qn, nidx + q0, Qb, uv + q0, dh + q0 * M.K0, post_scale, G, ss);
+      }
+      if (e != hipSuccess) return hip_status(e, "scatter launch");
+    }
+    if (side) {  // the caller's stream continues after the last scatter
+      if ((e = hipEventRecord(side->ev[kMaxChunks], side->s)) != hipSuccess) return hip_status(e, "event record");
+      if ((e = hipStreamWaitEvent(stream, side->ev[kMaxChunks], 0)) != hipSuccess) return hip_status(e, "stream wait");
+    }
   }
-  if (e != hipSuccess) return hip_status(e, "backward launch");
-  {
-    ProfScope ps(OO_PROF_SCATTER, stream);
-    e = launch_scatter(T, Qb, nidx, uv, dh, post_scale, G, stream);
-  }
-  if (e != hipSuccess) return hip_status(e, "scatter launch");
   ReduceDst D;
   D.n_seg = 2 * mlp->n_layers;
   for (int i = 0; i < mlp->n_layers; ++i) {

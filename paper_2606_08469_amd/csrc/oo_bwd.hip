@@ -120,7 +120,7 @@ __device__ inline void dw_layer(f32x4 (&acc)[U], const MT* dT, const MT* act, in
 
 template <int U>
 __device__ inline void dw_store(const f32x4 (&acc)[U], float* part, int64_t off, int n_out, int n_in, int wave,
-                                int lane) {
+                                int lane, bool add) {
   const int MM = (n_out + 15) / 16, NK = (n_in + 15) / 16;
   const int r16 = lane & 15, g = lane >> 4;
 #pragma unroll
@@ -131,7 +131,10 @@ __device__ inline void dw_store(const f32x4 (&acc)[U], float* part, int64_t off,
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int n = 16 * mm + 4 * g + j, k = 16 * nk + r16;
-        if (n < n_out && k < n_in) part[off + (int64_t)n * n_in + k] = acc[u][j];
+        if (n < n_out && k < n_in) {
+          float& dst = part[off + (int64_t)n * n_in + k];
+          dst = add ? dst + acc[u][j] : acc[u][j];
+        }
       }
     }
   }
@@ -180,13 +183,16 @@ __device__ inline void store_tq(MT* buf, const f32x4 (&acc)[MT2], int m0, int n_
 // weights are read from L2.
 template <class TT, class MT, int C, int H, bool WL>
 __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, const MlpArgs M, const MlpArgs Mt,
-                                                  int64_t Q, const int32_t* __restrict__ nidx,
-                                                  const float2* __restrict__ uv,
-                                                  const float* __restrict__ seeds, const int32_t* __restrict__ order,
-                                                  const ParamLayout PL, float* __restrict__ partials,
-                                                  float* __restrict__ dh_out) {
+                                                             const BwdArgs A, const ParamLayout PL) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   typedef typename FragT<MT>::type frag;
+  const int64_t Q = A.Q, ldn = A.ldn, n_seed = A.n_seed;
+  const int32_t* __restrict__ nidx = A.nidx;
+  const float2* __restrict__ uv = A.uv;
+  const float* __restrict__ seeds = A.seeds;
+  const int32_t* __restrict__ order = A.order;
+  float* __restrict__ partials = A.partials;
+  float* __restrict__ dh_out = A.dh;
   constexpr int MH = H / 16, MH2 = MH / kMSplit;
   constexpr int U0 = (MH * 8 + kBwdWaves - 1) / kBwdWaves, UH = (MH * MH + kBwdWaves - 1) / kBwdWaves;
   constexpr int UO = (MH + kBwdWaves - 1) / kBwdWaves;
@@ -248,7 +254,7 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
       const int nv = (int)(Q - qbase < kQW ? Q - qbase : kQW);  // valid queries in this tile
       for (int e = tid; e < kQW * L; e += blockDim.x) {
         const int l = e / kQW, qq = e % kQW;  // nidx is level-major [L][Q]
-        int v = qq < nv ? nidx[(int64_t)l * Q + qbase + qq] : -1;
+        int v = qq < nv ? nidx[(int64_t)l * ldn + qbase + qq] : -1;
         if (v < T.off[l] || v >= T.off[l + 1]) v = -1;  // never index outside level l
         qidx[qq * L + l] = v;
       }
@@ -330,7 +336,7 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
       int64_t qs = q < Q ? q : -1;
       if (order && qs >= 0) {
         qs = order[q];
-        if (qs >= Q) qs = -1;
+        if (qs >= n_seed) qs = -1;
       }
       f32x4 so[1];
 #pragma unroll
@@ -431,17 +437,20 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
   for (int i = 0; i < NL; ++i) {
     const int n_out = PL.n_out[i], n_in = PL.n_in[i];
     if (i == NL - 1)
-      dw_store<UO>(accO, part, PL.w_off[i], n_out, n_in, wave, lane);
+      dw_store<UO>(accO, part, PL.w_off[i], n_out, n_in, wave, lane, A.accumulate);
     else if (i == 0)
-      dw_store<U0>(acc0, part, PL.w_off[i], n_out, n_in, wave, lane);
+      dw_store<U0>(acc0, part, PL.w_off[i], n_out, n_in, wave, lane, A.accumulate);
     else {
 #pragma unroll
       for (int hh = 0; hh < NHH; ++hh)
-        if (hh == i - 1) dw_store<UH>(accH[hh], part, PL.w_off[i], n_out, n_in, wave, lane);
+        if (hh == i - 1) dw_store<UH>(accH[hh], part, PL.w_off[i], n_out, n_in, wave, lane, A.accumulate);
     }
 #pragma unroll
     for (int ii = 0; ii < kMaxLayers; ++ii)
-      if (ii == i && tid < n_out) part[PL.b_off[i] + tid] = dbacc[ii];
+      if (ii == i && tid < n_out) {
+        float& dst = part[PL.b_off[i] + tid];
+        dst = A.accumulate ? dst + dbacc[ii] : dbacc[ii];
+      }
   }
 }
 
@@ -625,36 +634,33 @@ hipError_t launch_transpose_weights(const MlpArgs& M, oo_dtype md, void* const* 
 }
 
 template <class TT, class MT, int C, int H>
-static hipError_t launch_bwd_t(const TreeArgs& T, const MlpArgs& M, const MlpArgs& Mt, int64_t Q,
-                               const int32_t* nidx, const float2* uv, const float* seeds, const int32_t* order,
-                               const ParamLayout& PL, float* partials, float* dh, int grid, hipStream_t st) {
+static hipError_t launch_bwd_t(const TreeArgs& T, const MlpArgs& M, const MlpArgs& Mt, const BwdArgs& A,
+                               const ParamLayout& PL, int grid, hipStream_t st) {
   bool wl;
   const size_t lds = bwd_lds_total(M.K0, H, M.n_layers, T.L, (int)sizeof(MT), wl);
   auto k = wl ? bwd_kernel<TT, MT, C, H, true> : bwd_kernel<TT, MT, C, H, false>;
   hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * kBwdWaves), lds, st, T, M, Mt, Q, nidx, uv, seeds, order, PL, partials,
-                     dh);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * kBwdWaves), lds, st, T, M, Mt, A, PL);
   return hipGetLastError();
 }
 
 template <class TT, class MT, int C>
-static hipError_t launch_bwd_c(const TreeArgs& T, const MlpArgs& M, const MlpArgs& Mt, int64_t Q,
-                               const int32_t* nidx, const float2* uv, const float* seeds, const int32_t* order,
-                               const ParamLayout& PL, float* partials, float* dh, int grid, hipStream_t st) {
-  return M.H == 64 ? launch_bwd_t<TT, MT, C, 64>(T, M, Mt, Q, nidx, uv, seeds, order, PL, partials, dh, grid, st)
-                   : launch_bwd_t<TT, MT, C, 128>(T, M, Mt, Q, nidx, uv, seeds, order, PL, partials, dh, grid, st);
+static hipError_t launch_bwd_c(const TreeArgs& T, const MlpArgs& M, const MlpArgs& Mt, const BwdArgs& A,
+                               const ParamLayout& PL, int grid, hipStream_t st) {
+  return M.H == 64 ? launch_bwd_t<TT, MT, C, 64>(T, M, Mt, A, PL, grid, st)
+                   : launch_bwd_t<TT, MT, C, 128>(T, M, Mt, A, PL, grid, st);
 }
 
 hipError_t launch_bwd(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, void* const* Wt,
-                      int64_t Q, const int32_t* nidx, const float2* uv, const float* seeds, const int32_t* order,
-                      const ParamLayout& PL, float* partials, float* dh, int grid, hipStream_t st) {
+                      const BwdArgs& A, const ParamLayout& PL, int grid, hipStream_t st) {
+  if (A.Q == 0) return hipSuccess;
   MlpArgs Mt = M;
   for (int i = 0; i < M.n_layers; ++i) Mt.W[i] = Wt[i];
   if (td == OO_F32)
-    return T.C == 4 ? launch_bwd_c<float, float, 4>(T, M, Mt, Q, nidx, uv, seeds, order, PL, partials, dh, grid, st)
-                    : launch_bwd_c<float, float, 8>(T, M, Mt, Q, nidx, uv, seeds, order, PL, partials, dh, grid, st);
-  if (td == OO_F16) return launch_bwd_c<f16, f16, 8>(T, M, Mt, Q, nidx, uv, seeds, order, PL, partials, dh, grid, st);
-  return launch_bwd_c<bf16, bf16, 8>(T, M, Mt, Q, nidx, uv, seeds, order, PL, partials, dh, grid, st);
+    return T.C == 4 ? launch_bwd_c<float, float, 4>(T, M, Mt, A, PL, grid, st)
+                    : launch_bwd_c<float, float, 8>(T, M, Mt, A, PL, grid, st);
+  if (td == OO_F16) return launch_bwd_c<f16, f16, 8>(T, M, Mt, A, PL, grid, st);
+  return launch_bwd_c<bf16, bf16, 8>(T, M, Mt, A, PL, grid, st);
   (void)md;
 }
 
@@ -673,6 +679,7 @@ hipError_t launch_bwd(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype
 // recomputed from the coordinates.
 template <int C>
 __global__ __launch_bounds__(256) void scatter_kernel(const TreeArgs T, int64_t Q, const int32_t* __restrict__ nidx,
+                                                      int64_t ldn,
                                                       const float2* __restrict__ uv, const float* __restrict__ dh,
                                                       float post_scale, const GradArgs G) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x, n = Q * 4 * C;
@@ -682,7 +689,7 @@ __global__ __launch_bounds__(256) void scatter_kernel(const TreeArgs T, int64_t 
       const int64_t q = gid / (4 * C);
       const int k = (int)(gid / C) & 3;
       const int c = (int)(gid % C);
-      const int id = nidx[(int64_t)l * Q + q];
+      const int id = nidx[(int64_t)l * ldn + q];
       if (id < T.off[l] || id >= T.off[l + 1]) continue;
       const float2 p = uv[q];
       const float s = fminf(fmaxf(p.x, 0.0f), 1.0f), t = fminf(fmaxf(p.y, 0.0f), 1.0f);
@@ -695,7 +702,8 @@ __global__ __launch_bounds__(256) void scatter_kernel(const TreeArgs T, int64_t 
   }
 }
 
-hipError_t launch_scatter(const TreeArgs& T, int64_t Q, const int32_t* nidx, const float2* uv, const float* dh,
+hipError_t launch_scatter(const TreeArgs& T, int64_t Q, const int32_t* nidx, int64_t ldn, const float2* uv,
+                          const float* dh,
                           float post_scale, const GradArgs& G, hipStream_t st) {
   if (Q == 0) return hipSuccess;
   // a persistent grid walks every level: block scheduling stays out of the
@@ -703,9 +711,11 @@ hipError_t launch_scatter(const TreeArgs& T, int64_t Q, const int32_t* nidx, con
   int64_t blocks = (Q * 4 * T.C + 255) / 256;
   if (blocks > 256 * 16) blocks = 256 * 16;
   if (T.C == 4)
-    hipLaunchKernelGGL(scatter_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, st, T, Q, nidx, uv, dh, post_scale, G);
+    hipLaunchKernelGGL(scatter_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, st, T, Q, nidx, ldn, uv, dh, post_scale,
+                       G);
   else
-    hipLaunchKernelGGL(scatter_kernel<8>, dim3((unsigned)blocks), dim3(256), 0, st, T, Q, nidx, uv, dh, post_scale, G);
+    hipLaunchKernelGGL(scatter_kernel<8>, dim3((unsigned)blocks), dim3(256), 0, st, T, Q, nidx, ldn, uv, dh, post_scale,
+                       G);
   return hipGetLastError();
 }
 

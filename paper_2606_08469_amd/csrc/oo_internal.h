@@ -70,11 +70,27 @@ size_t bwd_lds_bytes(const MlpArgs& M, oo_dtype md, int L);
 hipError_t launch_seeds(const ResidualArgs& A, const float* resid, const float* rhs, const double* grad_loss,
                         int full, float* seeds, hipStream_t st);
 hipError_t launch_transpose_weights(const MlpArgs& M, oo_dtype md, void* const* Wt, hipStream_t st);
+// One backward launch over Q consecutive sorted positions: node indices
+// nidx[l * ldn + q], coordinates uv[q], order[q] (source query, whose seed
+// row is read if it is below n_seed), dh[q][K0] out, one dW/db partial per
+// workgroup into partials [grid][P] (added to what is there when
+// accumulate is set).
+struct BwdArgs {
+  int64_t Q;
+  const int32_t* nidx;
+  int64_t ldn;
+  const float2* uv;
+  const float* seeds;
+  const int32_t* order;
+  int64_t n_seed;
+  float* partials;
+  float* dh;
+  int accumulate;
+};
 hipError_t launch_bwd(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, void* const* Wt,
-                      int64_t Q, const int32_t* nidx, const float2* uv, const float* seeds, const int32_t* order,
-                      const ParamLayout& PL, float* partials, float* dh, int grid, hipStream_t st);
-hipError_t launch_scatter(const TreeArgs& T, int64_t Q, const int32_t* nidx, const float2* uv, const float* dh,
-                          float post_scale, const GradArgs& G, hipStream_t st);
+                      const BwdArgs& A, const ParamLayout& PL, int grid, hipStream_t st);
+hipError_t launch_scatter(const TreeArgs& T, int64_t Q, const int32_t* nidx, int64_t ldn, const float2* uv,
+                          const float* dh, float post_scale, const GradArgs& G, hipStream_t st);
 hipError_t launch_dw_reduce(const float* partials, int grid, const ParamLayout& PL, const ReduceDst& D, float scale,
                             hipStream_t st);
 

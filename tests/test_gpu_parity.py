@@ -208,9 +208,12 @@ def compare_grads(name, got, otree, omlp, batch_np, tol=None, cos=None):
 
 # B = 20000 and the full mode at B = 9000 bucket enough queries that many
 # tiles share nodes, and (full mode) tiles straddle the LHS / secondary
-# boundary of the sorted order.
+# boundary of the sorted order. B = 70000 and the full mode at B = 15000
+# (75000 backward queries) run the backward in two chunks, each chunk's
+# scatter overlapped with the next chunk on a second stream.
 @pytest.mark.parametrize("ci,B,mode", [(1, None, "l2"), (3, 2048, "l2"), (3, 1000, "l2"), (3, 512, "full"),
-                                       (3, 512, "relative"), (1, 77, "l2"), (3, 20000, "l2"), (3, 9000, "full")])
+                                       (3, 512, "relative"), (1, 77, "l2"), (3, 20000, "l2"), (3, 9000, "full"),
+                                       (3, 70000, "l2"), (3, 15000, "full")])
 def test_residual_fp32(ci, B, mode):
     batch = dict(train_batch(ci) if B is None or ci == 1 else train_batch(ci, B))
     if ci == 1 and B is not None:
