@@ -241,6 +241,12 @@ int oo_radiosity_residual_fwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
  *  - Gradients are for the tables and weights the forward read. In
  *    mixed-precision runs those are the FP16/BF16 working copies, and the
  *    gradient is applied to the FP32 masters.
+ *  - Streams: with at least 65,536 backward queries the work runs in up to
+ *    four chunks, and the feature scatter of each chunk runs on a second
+ *    stream that the library creates once per device (default priority),
+ *    ordered by events: it starts after that chunk's decoder backward on
+ *    `stream`, and `stream` waits for the last scatter before the dW/db
+ *    reduction. To the caller the call behaves as work enqueued on `stream`.
  */
 int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_residual_batch* batch,
                               const float* resid, const float* rhs, const double* grad_loss,

@@ -3,18 +3,20 @@
 // reduction.
 //
 // One workgroup (16 waves) handles 64 queries at a time:
-//  1. encode: node indices come from the forward; 16 lanes per query, each
-//     gathering whole texels of one level; h written to an LDS fragment tile
-//     and, transposed, to the layer-0 activation buffer;
+//  1. encode: node indices and octahedral coordinates come from the forward;
+//     16 lanes per query, each gathering whole texels of one level; h written
+//     to the layer-0 activation buffer as [feature][query];
 //  2. forward recompute of the hidden layers on matrix cores, activations
 //     kept in LDS as [neuron][query];
 //  3. backward: delta chained through W^T on matrix cores; dW of every layer
 //     contracted over the workgroup's 64 queries, each wave owning a share of
 //     the dW tiles in registers for the whole kernel; dh of every query
 //     written to memory.
-// dW/db leave as one partial per workgroup, reduced in a fixed order later.
-// A separate, high-occupancy kernel then scatters w_tap * dh into the FP32
-// feature gradient tables with hardware float atomics.
+// dW/db leave as one partial per workgroup (accumulated over the launches
+// of one backward), reduced in a fixed order later. A separate,
+// high-occupancy kernel scatters w_tap * dh into the FP32 feature gradient
+// tables with hardware float atomics; the caller runs it on a second stream
+// so that it overlaps the next launch of the fused kernel.
 #include <hip/hip_runtime.h>
 
 #include "oo_device.h"
@@ -269,7 +271,8 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
       }
       __syncthreads();
       const float s = qst[2 * ql], t = qst[2 * ql + 1];
-      // this lane's levels part, part + 4, ...: all their gathers in flight
+      // this lane's levels part, part + kLanesPerQuery, ...: all their
+      // gathers in flight
       constexpr int G = kMaxLevels / kLanesPerQuery;
       int lidx[G];
 #pragma unroll
