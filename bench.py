@@ -149,8 +149,19 @@ def main():
     present = (idx >= 0).sum(1).to(torch.float64)
     lv_all = float(present.sum().item())
     lv_lhs = float(present[:B].sum().item())
+    # scatter requests to the atomic units: per LHS query and present level,
+    # two footprint rows of 2 texels, each one 64-byte chunk when it starts on
+    # an even texel and two otherwise (1.5 on average); a 2x2 map is 2 chunks
+    per_level = (idx[:B] >= 0).sum(0).to(torch.float64).cpu().numpy()
+    atomic_req = float(sum(n * (2.0 if r == 2 else 3.0) for n, r in zip(per_level, cfg.res)))
     del xq, dq, idx, present
     kern = kernel_rooflines(cfg, B, Q, lv_all, lv_lhs, per_kernel)
+    if "scatter" in kern:
+        k = kern["scatter"]
+        req = atomic_req / k["launches_per_step"]
+        rate = req / (k["ms_per_launch"] * 1e-3) / 1e9
+        k.update(atomic_requests=int(req), atomic_Greq_s=round(rate, 2), atomic_ceiling_Greq_s=ATOMIC_GREQ_S,
+                 frac_of_atomic_ceiling=round(rate / ATOMIC_GREQ_S, 4))
     dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
     traffic, traffic_src = hbm_traffic(dom)
     roof = dict(kern[dom])
@@ -260,6 +271,9 @@ def render_bench(torch, binding, synth, args):
 
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
+# Sustained rate of global FP32 atomic-add requests (one per 64-byte chunk an
+# instruction touches) measured on MI355X with a plain atomic kernel.
+ATOMIC_GREQ_S = 21.0
 MFMA_F16_PEAK_TFS = 2500.0  # MI355X dense FP16 matrix cores
 
 
