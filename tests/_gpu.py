@@ -102,8 +102,12 @@ def kink_margin_ok(ci: int, x, d):
     """True per query when every hidden pre-activation z of the decoder, in
     FP64, satisfies |z| >= KINK_BAND * (sum of |w a| + |b|): the FP32 path
     then takes the oracle's ReLU derivative branch for that query."""
-    otree, omlp = oracle_models(ci)
+    otree, _ = oracle_models(ci)
     _, W, b = params_for(ci)
+    return kink_margin_ok_tree(otree, W, b, x, d)
+
+
+def kink_margin_ok_tree(otree, W, b, x, d):
     a = oracle.encode(otree, x, d)[0].astype(np.float64)
     ok = np.ones(len(a), bool)
     for i in range(len(W) - 1):

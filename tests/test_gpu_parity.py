@@ -13,8 +13,8 @@ import torch
 
 import oracle
 from paper_2606_08469_amd import binding, synth
-from _gpu import (cosine, gpu_models, kink_safe_batch, oracle_models, oracle_tree_for, params_for, rel_l2,
-                  render_queries, report, subset_batch, to_np, train_batch, tree_for)
+from _gpu import (cosine, gpu_models, kink_margin_ok_tree, kink_safe_batch, oracle_models, oracle_tree_for,
+                  params_for, rel_l2, render_queries, report, subset_batch, to_np, train_batch, tree_for)
 
 pytestmark = pytest.mark.gpu
 
@@ -157,6 +157,72 @@ def test_tree_with_empty_levels():
     got = to_np(model(dev(x), dev(d)))
     want = oracle.query_fwd(oracle.Tree(nodes, lo, res, 8, feat), oracle.MLP(W, b), x, d)
     assert rel_l2(got, want) <= FP32_TOL
+
+
+def _unit(v):
+    return v / np.linalg.norm(v, axis=-1, keepdims=True)
+
+
+def deep_tree_case(seed=11):
+    """The largest shapes the boundary takes: 16 levels (D = 15, reached by
+    sample pairs 1e-6 apart), C = 8, a 128-wide decoder input, maps from 8^2
+    at the top to 2^2 at the bottom."""
+    g = np.random.default_rng(seed)
+    base = g.uniform(0.05, 0.95, (300, 3))
+    s = np.concatenate([base, base + 1e-6, g.uniform(0, 1, (2000, 3))]).astype(np.float32)
+    nodes, lo = binding.build_octree(s, 15, 1)
+    res = [8, 8, 8, 4, 4, 4, 4, 2, 2, 2, 2, 2, 2, 2, 2, 2]
+    feat = [g.normal(0, 0.1, (int(n), R, R, 8)).astype(np.float32) for n, R in zip(np.diff(lo), res)]
+    W = [g.uniform(-0.2, 0.2, (64, 128)).astype(np.float32), g.uniform(-0.3, 0.3, (64, 64)).astype(np.float32),
+         g.uniform(-0.3, 0.3, (3, 64)).astype(np.float32)]
+    b = [g.uniform(-0.1, 0.1, 64).astype(np.float32), g.uniform(-0.1, 0.1, 64).astype(np.float32),
+         np.zeros(3, np.float32)]
+    return s, nodes, lo, res, feat, W, b
+
+
+def deep_batch(s, B, N, seed=12):
+    """Residual batch around the deep tree's samples (half of the points on
+    the clustered pairs, so their queries reach level 15)."""
+    g = np.random.default_rng(seed)
+    x = np.where(g.uniform(size=(B, 1)) < 0.5, s[g.integers(0, 300, B)], g.uniform(0, 1, (B, 3)))
+    n = _unit(g.normal(size=(B, 3)))
+    wo = _unit(n + 0.8 * _unit(g.normal(size=(B, 3))))
+    wi = _unit(n[:, None, :] + 0.8 * _unit(g.normal(size=(B, N, 3))))
+    cos = np.maximum((wi * n[:, None, :]).sum(-1), 1e-3)
+    f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    return dict(B=B, N=N, x=f32(x), dir=f32(wo), n=f32(n), wo=f32(wo),
+                albedo=f32(g.uniform(0.1, 0.9, (B, 3))), Le=f32(g.uniform(0, 1, (B, 3))),
+                rough=f32(g.uniform(0.05, 1.0, B)), x2=f32(s[g.integers(0, len(s), (B, N))]),
+                dir2=f32(-wi), wi=f32(wi), pdf=f32(cos / np.pi), F0=0.04, loss_kind=0, eps=0.01,
+                grad_through_rhs=0, target_override=None)
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, FP32_TOL), (torch.float16, MIX_TOL)])
+def test_deep_tree_max_shapes(dtype, tol):
+    """16 levels and a 128-wide input through the query and the residual step
+    (FP32: gradients element-wise; FP16: by cosine)."""
+    s, nodes, lo, res, feat, W, b = deep_tree_case()
+    assert len(lo) == 17 and lo[16] > lo[15], "the tree must reach level 15"
+    otree, omlp = oracle.Tree(nodes, lo, res, 8, feat), oracle.MLP(W, b)
+    model = binding.OctaOctree(nodes, lo, res, 8, feat, W, b, dtype=dtype)
+    batch = deep_batch(s, 3000, 2)
+    if dtype == torch.float32:
+        ok = kink_margin_ok_tree(otree, W, b, batch["x"], batch["dir"])
+        batch = subset_batch(batch, np.nonzero(ok)[0])
+    print(f"[case] deep tree {dtype} B={len(batch['x'])} nodes={len(nodes)}", flush=True)
+    rgb = to_np(model(dev(batch["x"]), dev(batch["dir"])))
+    e = rel_l2(rgb, oracle.query_fwd(otree, omlp, batch["x"], batch["dir"]))
+    report(f"deep tree query {dtype}", rel_l2=e)
+    assert e <= tol
+    got = run_residual(model, batch)
+    lhs, rhs, res_, loss = oracle.residual_fwd(otree, omlp, batch)
+    e = rel_l2(got["resid"], res_)
+    report(f"deep tree resid {dtype}", rel_l2=e)
+    assert e <= tol
+    if dtype == torch.float32:
+        compare_grads("deep tree fp32", got, otree, omlp, batch, tol=FP32_TOL)
+    else:
+        compare_grads("deep tree fp16", got, otree, omlp, batch, cos=MIX_COS)
 
 
 # --------------------------------------------------------------------------
