@@ -428,27 +428,33 @@ __global__ __launch_bounds__(256) void loss_reduce_kernel(const double* __restri
   if (threadIdx.x == 0) *loss = B > 0 ? red[0] / (3.0 * (double)B) : 0.0;
 }
 
-// Four elements per thread and iteration (16-byte loads) when both pointers
-// allow it; the tail and unaligned arrays go element by element.
+// Eight elements per thread and iteration (two 16-byte loads, one store of
+// 8 x sizeof(DT) bytes) when both pointers allow it, both loads issued before
+// either is converted; the tail and unaligned arrays go element by element.
 template <class DT>
 __global__ __launch_bounds__(256) void cast_kernel(const float* __restrict__ src, DT* __restrict__ dst, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t nv = 0;
-  if ((reinterpret_cast<uintptr_t>(src) % 16) == 0 && (reinterpret_cast<uintptr_t>(dst) % (4 * sizeof(DT))) == 0) {
-    nv = n / 4;
-    typedef DT v4 __attribute__((ext_vector_type(4)));
+  if ((reinterpret_cast<uintptr_t>(src) % 16) == 0 && (reinterpret_cast<uintptr_t>(dst) % (8 * sizeof(DT))) == 0) {
+    nv = n / 8;
+    typedef DT v8 __attribute__((ext_vector_type(8)));
     for (int64_t i = i0; i < nv; i += stride) {
-      const float4 v = reinterpret_cast<const float4*>(src)[i];
-      v4 o;
-      o[0] = from_f32<DT>(v.x);
-      o[1] = from_f32<DT>(v.y);
-      o[2] = from_f32<DT>(v.z);
-      o[3] = from_f32<DT>(v.w);
-      reinterpret_cast<v4*>(dst)[i] = o;
+      const float4 a = reinterpret_cast<const float4*>(src)[2 * i];
+      const float4 b = reinterpret_cast<const float4*>(src)[2 * i + 1];
+      v8 o;
+      o[0] = from_f32<DT>(a.x);
+      o[1] = from_f32<DT>(a.y);
+      o[2] = from_f32<DT>(a.z);
+      o[3] = from_f32<DT>(a.w);
+      o[4] = from_f32<DT>(b.x);
+      o[5] = from_f32<DT>(b.y);
+      o[6] = from_f32<DT>(b.z);
+      o[7] = from_f32<DT>(b.w);
+      reinterpret_cast<v8*>(dst)[i] = o;
     }
   }
-  for (int64_t i = 4 * nv + i0; i < n; i += stride) dst[i] = from_f32<DT>(src[i]);
+  for (int64_t i = 8 * nv + i0; i < n; i += stride) dst[i] = from_f32<DT>(src[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -618,7 +624,7 @@ hipError_t launch_combine(const ResidualArgs& A, const float* Lq, const int32_t*
 
 hipError_t launch_cast(const float* src, void* dst, oo_dtype dt, int64_t n, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  int64_t blocks = (n / 4 + 255) / 256;
+  int64_t blocks = (n / 8 + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   if (blocks < 1) blocks = 1;
   if (dt == OO_F32)
