@@ -28,7 +28,7 @@ constexpr int kQW = 64;  // queries per workgroup tile
 
 struct BwdLayout {
   int KB0, R0;
-  size_t act0, act1, delta, qidx, qst, total;
+  size_t act0, act1, seed, total;
 };
 
 __host__ __device__ inline BwdLayout bwd_layout(int K0, int H, int n_layers, int L, int msz) {
@@ -38,16 +38,13 @@ __host__ __device__ inline BwdLayout bwd_layout(int K0, int H, int n_layers, int
   size_t o = 0;
   b.act0 = o;
   o += (size_t)b.R0 * kQW * msz;
-  b.act1 = o;  // hidden-layer activations a_1 .. a_{n_layers-1}, H rows each
-  o += (size_t)(n_layers - 1) * H * kQW * msz;
-  b.delta = o;
-  o += (size_t)H * kQW * msz;
-  b.qidx = o;
-  o += (size_t)kQW * L * 4;
-  b.qst = o;
-  o += (size_t)kQW * 2 * 4;
+  b.act1 = o;  // hidden-layer activations a_1 .. a_{n_layers-1}, H rows each;
+  o += (size_t)(n_layers - 1) * H * kQW * msz;  // the backward overwrites a_i with delta_i
+  b.seed = o;  // output-layer seeds, 16 rows (3 used)
+  o += (size_t)16 * kQW * msz;
   b.total = o;
   return b;
+  (void)L;
 }
 
 // [row][query] buffer of 64 queries, 16-byte chunks XOR-swizzled by row so
@@ -81,12 +78,14 @@ __device__ inline typename FragT<MT>::type lds_frag(const MT* packed, int KB, in
 
 // Weights kept packed in LDS next to the activation buffers: W_i and W_i^T
 // of every hidden-to-hidden layer 0 < i < n_layers - 1 (H x H each), then
-// W_0^T (K0 x H), which forms dh.
+// W_0^T (K0 x H), which forms dh, then W_0 (H x K0) for the recompute.
 __host__ __device__ inline size_t hidden_weight_elems(int H, int n_layers) {
   return (size_t)(n_layers > 2 ? n_layers - 2 : 0) * 2 * H * H;
 }
 __host__ __device__ inline size_t lds_weight_bytes(int K0, int H, int n_layers, int msz) {
-  return (hidden_weight_elems(H, n_layers) + (size_t)((K0 + 15) / 16) * (H / 32) * kWave * 8) * msz;
+  const size_t wt0 = (size_t)((K0 + 15) / 16) * (H / 32) * kWave * 8;  // W_0^T: K0 rows, H inputs
+  const size_t w0 = (size_t)(H / 16) * ((K0 + 31) / 32) * kWave * 8;   // W_0: H rows, K0 inputs
+  return (hidden_weight_elems(H, n_layers) + wt0 + w0) * msz;
 }
 
 
@@ -209,19 +208,23 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
   MT* const act1 = reinterpret_cast<MT*>(smem + lay.act1);
   // input activation buffer of layer i: a_0 = h, a_i = ReLU(z_{i-1})
   auto act = [&](int i) { return i == 0 ? act0 : act1 + (size_t)(i - 1) * H * kQW; };
-  MT* dT = reinterpret_cast<MT*>(smem + lay.delta);
-  int* qidx = reinterpret_cast<int*>(smem + lay.qidx);
-  float* qst = reinterpret_cast<float*>(smem + lay.qst);
+  MT* const seedb = reinterpret_cast<MT*>(smem + lay.seed);
+  // Buffer of the gradient flowing into layer i's output: the seeds for the
+  // output layer, else the buffer of a_{i+1}, which step i + 1 overwrote with
+  // delta_{i+1} once a_{i+1} was no longer needed.
+  auto din = [&](int i) { return i == NL - 1 ? seedb : act(i + 1); };
   // packed weights: layer i at hw + 2 (i - 1) H^2 (W_i), + H^2 (W_i^T);
-  // W_0^T after the hidden layers
+  // then W_0^T, then W_0
   MT* const hw = reinterpret_cast<MT*>(smem + lay.total);
   MT* const wt0 = hw + hidden_weight_elems(H, NL);
+  MT* const w0p = wt0 + (size_t)((K0 + 15) / 16) * (H / 32) * kWave * 8;
   if (WL) {
     for (int i = 1; i < NL - 1; ++i) {
       pack_frags_lds<MT>(reinterpret_cast<const MT*>(M.W[i]), H, H, H, hw + (size_t)2 * (i - 1) * H * H);
       pack_frags_lds<MT>(reinterpret_cast<const MT*>(Mt.W[i]), H, H, H, hw + (size_t)(2 * (i - 1) + 1) * H * H);
     }
     pack_frags_lds<MT>(reinterpret_cast<const MT*>(Mt.W[0]), K0, H, H, wt0);  // W_0^T is [K0][H]
+    pack_frags_lds<MT>(reinterpret_cast<const MT*>(M.W[0]), H, K0, K0, w0p);  // W_0 is [H][K0]
   }
 
   f32x4 acc0[U0], accH[NHH][UH], accO[UO];
@@ -253,24 +256,12 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
     // ---- 1. encode: node indices come from the forward (no second walk of
     //      the tree); kLanesPerQuery lanes per query gather its levels -----
     {
-      const int nv = (int)(Q - qbase < kQW ? Q - qbase : kQW);  // valid queries in this tile
-      for (int e = tid; e < kQW * L; e += blockDim.x) {
-        const int l = e / kQW, qq = e % kQW;  // nidx is level-major [L][Q]
-        int v = qq < nv ? nidx[(int64_t)l * ldn + qbase + qq] : -1;
-        if (v < T.off[l] || v >= T.off[l + 1]) v = -1;  // never index outside level l
-        qidx[qq * L + l] = v;
-      }
       const int ql = tid / kLanesPerQuery, part = tid % kLanesPerQuery;
       const int64_t q = qbase + ql;
-      if (part == 0) {
-        // octahedral coordinates stored by the forward; clamped so the taps
-        // stay inside the map even for a workspace the forward did not fill
-        const float2 p = q < Q ? uv[q] : make_float2(0.5f, 0.5f);
-        qst[2 * ql] = fminf(fmaxf(p.x, 0.0f), 1.0f);
-        qst[2 * ql + 1] = fminf(fmaxf(p.y, 0.0f), 1.0f);
-      }
-      __syncthreads();
-      const float s = qst[2 * ql], t = qst[2 * ql + 1];
+      // octahedral coordinates stored by the forward; clamped so the taps
+      // stay inside the map even for a workspace the forward did not fill
+      const float2 p = q < Q ? uv[q] : make_float2(0.5f, 0.5f);
+      const float s = fminf(fmaxf(p.x, 0.0f), 1.0f), t = fminf(fmaxf(p.y, 0.0f), 1.0f);
       // this lane's levels part, part + kLanesPerQuery, ...: all their
       // gathers in flight
       constexpr int G = kMaxLevels / kLanesPerQuery;
@@ -278,7 +269,9 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
 #pragma unroll
       for (int gi = 0; gi < G; ++gi) {
         const int l = part + kLanesPerQuery * gi;
-        lidx[gi] = l < L ? qidx[ql * L + l] : -1;
+        int v = (l < L && q < Q) ? nidx[(int64_t)l * ldn + q] : -1;  // nidx is level-major [L][Q]
+        if (l < L && (v < T.off[l] || v >= T.off[l + 1])) v = -1;  // never index outside level l
+        lidx[gi] = v;
       }
       float h[G][C];
       gather_levels<TT, C, G, kLanesPerQuery>(T, part, lidx, s, t, h);
@@ -305,7 +298,11 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
       for (int kb = 0; kb < KB0; ++kb) {
         const frag b = tq_bfrag<MT>(act0, kb, g, col, K0);
 #pragma unroll
-        for (int mi = 0; mi < MH2; ++mi) acc[mi] = mma(wfrag_global<MT>(W0, H, K0, K0, mh * MH2 + mi, kb, lane), b, acc[mi]);
+        for (int mi = 0; mi < MH2; ++mi) {
+          const int m = mh * MH2 + mi;
+          acc[mi] = mma(WL ? lds_frag<MT>(w0p, KB0, m, kb, lane) : wfrag_global<MT>(W0, H, K0, K0, m, kb, lane), b,
+                        acc[mi]);
+        }
       }
       store_tq<MT, MH2>(act(1), acc, mh * MH2, MH, H, nt, lane, true);
       for (int layer = 1; layer < NL - 1; ++layer) {
@@ -333,7 +330,7 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
     }
 
     // ---- 3. backward ------------------------------------------------------
-    if (mh == 0) {  // seeds of the output layer into the delta buffer, rows 0..15
+    if (mh == 0) {  // seeds of the output layer into the seed buffer, rows 0..15
       const int64_t q = qbase + col;
       // seeds are stored in the caller's query order
       int64_t qs = q < Q ? q : -1;
@@ -347,16 +344,19 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
         const int row = 4 * g + j;
         so[0][j] = (row < 3 && qs >= 0) ? seeds[3 * qs + row] : 0.0f;
       }
-      store_tq<MT, 1>(dT, so, 0, 1, 3, nt, lane, false);
+      store_tq<MT, 1>(seedb, so, 0, 1, 3, nt, lane, false);
     }
-    // One layer of the backward: dW_i over the workgroup's 64 queries into
-    // this wave's accumulators accs, db_i, then delta_{i-1} (or dh for i = 0).
+    // One layer of the backward: with delta_{i+1} (the gradient at layer i's
+    // output) in din(i), dW_i over the workgroup's 64 queries into this
+    // wave's accumulators accs, db_i, then delta_i into a_i's buffer (or dh
+    // for i = 0).
     // Each call site gets its own accumulator array, and the lane index is
     // re-laundered so addresses are not kept live from one layer to the next.
     auto step = [&](auto& accs, int i) {
       const int ln = launder_lane(lane), gs = ln >> 4, cs = 16 * nt + (ln & 15);
       const int n_out = i == NL - 1 ? 3 : H, n_in = i == 0 ? K0 : H;
-      __syncthreads();  // delta_i and the activations are complete
+      __syncthreads();  // din(i) and the activations are complete
+      const MT* dT = din(i);
       dw_layer<MT>(accs, dT, act(i), n_out, n_in, wave, ln);
       if (tid < n_out) {
         float sum = 0.0f;
@@ -397,8 +397,8 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
             const int n = 16 * (mh * MH2 + mi) + 4 * gs + j;
             if (!(to_f32(a[tq_index(n, cs)]) > 0.0f)) dacc[mi][j] = 0.0f;
           }
-        __syncthreads();  // every wave has read delta_i
-        store_tq<MT, MH2>(dT, dacc, mh * MH2, MH, H, nt, ln, false);
+        __syncthreads();  // every wave has read din(i) and a_i
+        store_tq<MT, MH2>(act(i), dacc, mh * MH2, MH, H, nt, ln, false);
       } else {
         constexpr int MK2 = 8 / kMSplit;  // up to 8 row tiles of dh (K0 <= 128)
         const int MK = (K0 + 15) / 16;
