@@ -499,6 +499,30 @@ __device__ inline typename FragT<MT>::type chain_frag(const f32x4& lo, const f32
   return b;
 }
 
+// FP16: round first, then the ReLU on packed halves (rounding keeps the
+// sign, so the result is the same and the max runs on pairs).
+template <>
+__device__ inline FragT<f16>::type chain_frag<f16>(const f32x4& lo, const f32x4& hi, bool relu) {
+  FragT<f16>::type b;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    b[j] = from_f32<f16>(lo[j]);
+    b[4 + j] = from_f32<f16>(hi[j]);
+  }
+  if (relu) {
+    typedef f16 h2 __attribute__((ext_vector_type(2)));
+    const h2 z = {(f16)0.0f, (f16)0.0f};
+#pragma unroll
+    for (int j = 0; j < 8; j += 2) {
+      h2 v = {b[j], b[j + 1]};
+      v = __builtin_elementwise_max(v, z);
+      b[j] = v[0];
+      b[j + 1] = v[1];
+    }
+  }
+  return b;
+}
+
 // Returns p unchanged but opaque to the optimiser. Weight fragments are
 // loop-invariant in the persistent tile loops; laundering their base pointer
 // per iteration keeps the compiler from hoisting every fragment load out of
