@@ -178,9 +178,9 @@ __device__ inline void store_tq(MT* buf, const f32x4 (&acc)[MT2], int m0, int n_
 // Workgroup of kBwdWaves waves on 64 queries. In the layer chains wave w
 // works on query columns 16 (w % 4) .. +15 and on the share w / 4 of the
 // output rows; the layers exchange activations and deltas through the
-// [row][query] buffers. With WL the hidden-to-hidden weights W_i and W_i^T
-// and W_0^T are packed into LDS once per workgroup (their per-tile fragment
-// loads from L2 dominated the layer chains); W_0 and the output layer's
+// [row][query] buffers. With WL the hidden-to-hidden weights W_i and W_i^T,
+// W_0^T and W_0 are packed into LDS once per workgroup (their per-tile
+// fragment loads from L2 dominated the layer chains); the output layer's
 // weights are read from L2.
 template <class TT, class MT, int C, int H, bool WL>
 __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, const MlpArgs M, const MlpArgs Mt,
