@@ -98,34 +98,35 @@ def to_np(t):
 KINK_BAND = 1e-5
 
 
-def kink_margin_ok(ci: int, x, d):
+def kink_margin_ok(ci: int, x, d, band=KINK_BAND):
     """True per query when every hidden pre-activation z of the decoder, in
-    FP64, satisfies |z| >= KINK_BAND * (sum of |w a| + |b|): the FP32 path
-    then takes the oracle's ReLU derivative branch for that query."""
+    FP64, satisfies |z| >= band * (sum of |w a| + |b|): a path whose rounding
+    of z stays below that band takes the oracle's ReLU derivative branch."""
     otree, _ = oracle_models(ci)
     _, W, b = params_for(ci)
-    return kink_margin_ok_tree(otree, W, b, x, d)
+    return kink_margin_ok_tree(otree, W, b, x, d, band)
 
 
-def kink_margin_ok_tree(otree, W, b, x, d):
+def kink_margin_ok_tree(otree, W, b, x, d, band=KINK_BAND):
     a = oracle.encode(otree, x, d)[0].astype(np.float64)
     ok = np.ones(len(a), bool)
     for i in range(len(W) - 1):
         Wi, bi = np.asarray(W[i], np.float64), np.asarray(b[i], np.float64)
         z = a @ Wi.T + bi
         scale = np.abs(a) @ np.abs(Wi).T + np.abs(bi) + 1e-300
-        ok &= (np.abs(z) / scale).min(axis=1) >= KINK_BAND
+        ok &= (np.abs(z) / scale).min(axis=1) >= band
         a = np.maximum(z, 0.0)
     return ok
 
 
-def kink_safe_batch(ci: int, batch: dict, full: bool):
+def kink_safe_batch(ci: int, batch: dict, full: bool, band=KINK_BAND):
     """The batch without the points whose differentiated queries (the LHS
     query; with the gradient through the target also its secondary queries)
-    sit within FP32 rounding of a ReLU kink. Returns (batch, dropped)."""
-    ok = kink_margin_ok(ci, batch["x"], batch["dir"])
+    sit within `band` (relative rounding of the path) of a ReLU kink.
+    Returns (batch, dropped)."""
+    ok = kink_margin_ok(ci, batch["x"], batch["dir"], band)
     N = int(batch.get("N", 0))
     if full and N > 0:
-        ok2 = kink_margin_ok(ci, batch["x2"].reshape(-1, 3), batch["dir2"].reshape(-1, 3))
+        ok2 = kink_margin_ok(ci, batch["x2"].reshape(-1, 3), batch["dir2"].reshape(-1, 3), band)
         ok &= ok2.reshape(-1, N).all(axis=1)
     return subset_batch(batch, np.nonzero(ok)[0]), int((~ok).sum())

@@ -306,20 +306,42 @@ def test_residual_fp32(ci, B, mode):
     compare_grads(f"bwd cfg{ci} {mode}", got, otree, omlp, batch, tol=FP32_TOL)
 
 
-@pytest.mark.parametrize("ci,B", [(5, 2048), (3, 2048)])
-def test_residual_mixed(ci, B):
+# BF16 keeps 8 significand bits: the kernels' rounding of a hidden
+# pre-activation z is up to about 2^-8 of sum |w a| + |b|, so a ReLU whose
+# |z| is inside that band may take the other derivative branch than the FP64
+# oracle. Across a batch those flips leave the gradients at cosine 0.98-0.995
+# (FP16, 2^-11, stays above 0.99999); on the points clear of the band the
+# match is back above MIX_COS.
+BF16_KINK_BAND = 2.0 ** -8
+BF16_COS_ALL = 0.95
+
+
+@pytest.mark.parametrize("ci,B,dtype", [(5, 2048, torch.float16), (3, 2048, torch.float16),
+                                        (5, 32768, torch.bfloat16), (3, 70000, torch.bfloat16)])
+def test_residual_mixed(ci, B, dtype):
+    """16-bit tables and decoder against the oracle at the FP32 masters:
+    radiance and loss within MIX_TOL, gradients by cosine (BF16: on the
+    points outside its kink band, plus a coarse bound on the whole batch)."""
     batch = train_batch(ci, B)
-    model = gpu_models(ci, torch.float16)
+    model = gpu_models(ci, dtype)
     otree, omlp = oracle_models(ci)
-    print(f"[case] residual mixed cfg{ci} B={B}", flush=True)
+    print(f"[case] residual mixed cfg{ci} B={B} {dtype}", flush=True)
     got = run_residual(model, batch)
     lhs, rhs, res, loss = oracle.residual_fwd(otree, omlp, batch)
     e = rel_l2(got["lhs"], lhs)
     el = abs(got["loss"] - loss) / abs(loss)
-    report(f"mixed cfg{ci} lhs", rel_l2=e)
-    report(f"mixed cfg{ci} loss", rel=el)
+    report(f"mixed cfg{ci} {dtype} lhs", rel_l2=e)
+    report(f"mixed cfg{ci} {dtype} loss", rel=el)
     assert e <= MIX_TOL and el <= MIX_TOL
-    compare_grads(f"mixed bwd cfg{ci}", got, otree, omlp, batch, cos=MIX_COS)
+    if dtype == torch.float16:
+        compare_grads(f"mixed bwd cfg{ci} {dtype}", got, otree, omlp, batch, cos=MIX_COS)
+        return
+    compare_grads(f"mixed bwd cfg{ci} {dtype} all", got, otree, omlp, batch, cos=BF16_COS_ALL)
+    sub, dropped = kink_safe_batch(ci, batch, False, BF16_KINK_BAND)
+    assert B - dropped >= 256, dropped
+    report(f"mixed cfg{ci} {dtype} kink-safe points", kept=B - dropped)
+    got = run_residual(model, sub)
+    compare_grads(f"mixed bwd cfg{ci} {dtype} kink-safe", got, otree, omlp, sub, cos=MIX_COS)
 
 
 def test_bwd_with_unfilled_workspace_stays_in_bounds():
