@@ -2,9 +2,9 @@
 // backward kernel, the feature-gradient scatter, and the fixed-order dW/db
 // reduction.
 //
-// One workgroup (16 waves) handles 64 queries at a time:
+// One workgroup (8 waves) handles 64 queries at a time:
 //  1. encode: node indices and octahedral coordinates come from the forward;
-//     16 lanes per query, each gathering whole texels of one level; h written
+//     8 lanes per query, each gathering whole texels of up to two levels; h written
 //     to the layer-0 activation buffer as [feature][query];
 //  2. forward recompute of the hidden layers on matrix cores, activations
 //     kept in LDS as [neuron][query];
@@ -89,11 +89,12 @@ __host__ __device__ inline size_t lds_weight_bytes(int K0, int H, int n_layers, 
 }
 
 
-// Waves per workgroup. With 16 waves (four per SIMD) each wave owns a
-// sixteenth of the dW tiles, which keeps a 128-wide MLP's accumulators and
-// working set within 128 registers; the extra waves hide the gather and
-// weight-load latency that dominates this kernel.
-constexpr int kBwdWaves = 16;
+// Waves per workgroup. With 8 waves (two per SIMD, up to 256 registers
+// each) a wave owns an eighth of the dW tiles in registers. The LDS holds one
+// workgroup per CU, so the feature scatter, which runs beside this kernel on a
+// second stream, gets the wave slots the workgroup leaves free: fewer, larger
+// waves here measured faster for the pair than 16 waves of 128 registers.
+constexpr int kBwdWaves = 8;
 constexpr int kMSplit = kBwdWaves / 4;           // waves sharing one query column block
 constexpr int kLanesPerQuery = 64 * kBwdWaves / kQW;
 
@@ -237,9 +238,9 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
     for (int u = 0; u < UH; ++u) accH[h][u] = z4;
 #pragma unroll
   for (int u = 0; u < UO; ++u) accO[u] = z4;
-  float dbacc[kMaxLayers];
+  float dbO = 0.0f, db0 = 0.0f, dbH[NHH];
 #pragma unroll
-  for (int i = 0; i < kMaxLayers; ++i) dbacc[i] = 0.0f;
+  for (int h = 0; h < NHH; ++h) dbH[h] = 0.0f;
 
   // Zero the layer-0 padding rows [K0, R0) once.
   for (int e = tid; e < (R0 - K0) * kQW; e += blockDim.x) act0[tq_index(K0 + e / kQW, e % kQW)] = from_f32<MT>(0.0f);
@@ -352,7 +353,7 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
     // for i = 0).
     // Each call site gets its own accumulator array, and the lane index is
     // re-laundered so addresses are not kept live from one layer to the next.
-    auto step = [&](auto& accs, int i) {
+    auto step = [&](auto& accs, float& dbr, int i) {
       const int ln = launder_lane(lane), gs = ln >> 4, cs = 16 * nt + (ln & 15);
       const int n_out = i == NL - 1 ? 3 : H, n_in = i == 0 ? K0 : H;
       __syncthreads();  // din(i) and the activations are complete
@@ -366,9 +367,7 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
 #pragma unroll
           for (int e = 0; e < 8; ++e) sum += to_f32(v[e]);
         }
-#pragma unroll
-        for (int ii = 0; ii < kMaxLayers; ++ii)
-          if (ii == i) dbacc[ii] += sum;
+        dbr += sum;
       }
       const MT* Wt = launder_ptr(reinterpret_cast<const MT*>(Mt.W[i]));  // [n_in][ldt], ldt = n_out rounded up to 4
       const int ldt = (n_out + 3) & ~3;
@@ -427,11 +426,11 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
         }
       }
     };
-    step(accO, NL - 1);
+    step(accO, dbO, NL - 1);
 #pragma unroll
     for (int hh = NHH - 1; hh >= 0; --hh)
-      if (hh + 1 < NL - 1) step(accH[hh], hh + 1);
-    step(acc0, 0);
+      if (hh + 1 < NL - 1) step(accH[hh], dbH[hh], hh + 1);
+    step(acc0, db0, 0);
     __syncthreads();  // LDS buffers are reused by the next tile
   }
 
@@ -448,12 +447,14 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
       for (int hh = 0; hh < NHH; ++hh)
         if (hh == i - 1) dw_store<UH>(accH[hh], part, PL.w_off[i], n_out, n_in, wave, lane, A.accumulate);
     }
+    float dbv = i == NL - 1 ? dbO : db0;
 #pragma unroll
-    for (int ii = 0; ii < kMaxLayers; ++ii)
-      if (ii == i && tid < n_out) {
-        float& dst = part[PL.b_off[i] + tid];
-        dst = A.accumulate ? dst + dbacc[ii] : dbacc[ii];
-      }
+    for (int hh = 0; hh < NHH; ++hh)
+      if (i > 0 && i < NL - 1 && hh == i - 1) dbv = dbH[hh];
+    if (tid < n_out) {
+      float& dst = part[PL.b_off[i] + tid];
+      dst = A.accumulate ? dst + dbv : dbv;
+    }
   }
 }
 
@@ -610,7 +611,7 @@ int bwd_grid(const MlpArgs& M, oo_dtype md, int L, int64_t Q) {
   const int64_t n_tiles = (Q + kQW - 1) / kQW;
   const size_t lds = bwd_lds_bytes(M, md, L);
   int per_cu = (int)(kLdsBytes / (lds ? lds : 1));
-  const int by_waves = 16 / kBwdWaves;  // four waves per SIMD fit the kernel's registers
+  const int by_waves = 16 / kBwdWaves;  // at most 16 of this kernel's waves per CU
   if (per_cu > by_waves) per_cu = by_waves;
   per_cu = per_cu < 1 ? 1 : per_cu;
   int64_t g = (int64_t)cu_count() * per_cu;
