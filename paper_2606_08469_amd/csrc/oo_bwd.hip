@@ -2,10 +2,12 @@
 // backward kernel, the feature-gradient scatter, and the fixed-order dW/db
 // reduction.
 //
-// One workgroup (8 waves) handles 64 queries at a time:
+// One workgroup (8 waves with 16-bit operands, 16 with FP32) handles 64
+// queries at a time:
 //  1. encode: node indices and octahedral coordinates come from the forward;
-//     8 lanes per query, each gathering whole texels of up to two levels; h written
-//     to the layer-0 activation buffer as [feature][query];
+//     one lane per wave for each query (8 or 16), each gathering whole texels
+//     of its levels; h written to the layer-0 activation buffer as
+//     [feature][query];
 //  2. forward recompute of the hidden layers on matrix cores, activations
 //     kept in LDS as [neuron][query];
 //  3. backward: delta chained through W^T on matrix cores; dW of every layer
@@ -89,23 +91,25 @@ __host__ __device__ inline size_t lds_weight_bytes(int K0, int H, int n_layers, 
 }
 
 
-// Waves per workgroup. With 8 waves (two per SIMD, up to 256 registers
-// each) a wave owns an eighth of the dW tiles in registers. The LDS holds one
-// workgroup per CU, so the feature scatter, which runs beside this kernel on a
-// second stream, gets the wave slots the workgroup leaves free: fewer, larger
-// waves here measured faster for the pair than 16 waves of 128 registers.
-constexpr int kBwdWaves = 8;
-constexpr int kMSplit = kBwdWaves / 4;           // waves sharing one query column block
-constexpr int kLanesPerQuery = 64 * kBwdWaves / kQW;
+// Waves per workgroup. The LDS holds one workgroup per CU, and the feature
+// scatter, which runs beside this kernel on a second stream, gets the wave
+// slots the workgroup leaves free. With 16-bit operands 8 waves (two per SIMD,
+// up to 256 registers each, an eighth of the dW tiles per wave) measured
+// faster for the pair than 16 waves of 128 registers. FP32 reads its weights
+// from L2 (they do not fit in LDS) and needs the latency hiding of 16 waves.
+template <class MT>
+__host__ __device__ constexpr int bwd_waves() {
+  return sizeof(MT) == 4 ? 16 : 8;
+}
 
-// dW tiles of one layer owned by this wave: tile tau = wave + 8u.
-template <class MT, int U>
+// dW tiles of one layer owned by this wave: tile tau = wave + NW u.
+template <class MT, int NW, int U>
 __device__ inline void dw_layer(f32x4 (&acc)[U], const MT* dT, const MT* act, int n_out, int n_in, int wave, int lane) {
   const int MM = (n_out + 15) / 16, NK = (n_in + 15) / 16;
   const int r16 = lane & 15, g = lane >> 4;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int tau = wave + kBwdWaves * u;
+    const int tau = wave + NW * u;
     if (tau < MM * NK) {
       const int mm = tau / NK, nk = tau % NK;
 #pragma unroll
@@ -120,14 +124,14 @@ __device__ inline void dw_layer(f32x4 (&acc)[U], const MT* dT, const MT* act, in
   }
 }
 
-template <int U>
+template <int NW, int U>
 __device__ inline void dw_store(const f32x4 (&acc)[U], float* part, int64_t off, int n_out, int n_in, int wave,
                                 int lane, bool add) {
   const int MM = (n_out + 15) / 16, NK = (n_in + 15) / 16;
   const int r16 = lane & 15, g = lane >> 4;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int tau = wave + kBwdWaves * u;
+    const int tau = wave + NW * u;
     if (tau < MM * NK) {
       const int mm = tau / NK, nk = tau % NK;
 #pragma unroll
@@ -176,7 +180,7 @@ __device__ inline void store_tq(MT* buf, const f32x4 (&acc)[MT2], int m0, int n_
   }
 }
 
-// Workgroup of kBwdWaves waves on 64 queries. In the layer chains wave w
+// Workgroup of bwd_waves<MT>() waves on 64 queries. In the layer chains wave w
 // works on query columns 16 (w % 4) .. +15 and on the share w / 4 of the
 // output rows; the layers exchange activations and deltas through the
 // [row][query] buffers. With WL the hidden-to-hidden weights W_i and W_i^T,
@@ -184,7 +188,7 @@ __device__ inline void store_tq(MT* buf, const f32x4 (&acc)[MT2], int m0, int n_
 // fragment loads from L2 dominated the layer chains); the output layer's
 // weights are read from L2.
 template <class TT, class MT, int C, int H, bool WL>
-__global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, const MlpArgs M, const MlpArgs Mt,
+__global__ __launch_bounds__(64 * bwd_waves<MT>()) void bwd_kernel(const TreeArgs T, const MlpArgs M, const MlpArgs Mt,
                                                              const BwdArgs A, const ParamLayout PL) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   typedef typename FragT<MT>::type frag;
@@ -195,9 +199,12 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
   const int32_t* __restrict__ order = A.order;
   float* __restrict__ partials = A.partials;
   float* __restrict__ dh_out = A.dh;
+  constexpr int NW = bwd_waves<MT>();
+  constexpr int kMSplit = NW / 4;                  // waves sharing one query column block
+  constexpr int kLanesPerQuery = 64 * NW / kQW;
   constexpr int MH = H / 16, MH2 = MH / kMSplit;
-  constexpr int U0 = (MH * 8 + kBwdWaves - 1) / kBwdWaves, UH = (MH * MH + kBwdWaves - 1) / kBwdWaves;
-  constexpr int UO = (MH + kBwdWaves - 1) / kBwdWaves;
+  constexpr int U0 = (MH * 8 + NW - 1) / NW, UH = (MH * MH + NW - 1) / NW;
+  constexpr int UO = (MH + NW - 1) / NW;
   constexpr int NHH = H == 128 ? 1 : 3;  // hidden-to-hidden layers supported
   const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, r16 = lane & 15;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: scalar branches
@@ -358,7 +365,7 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
       const int n_out = i == NL - 1 ? 3 : H, n_in = i == 0 ? K0 : H;
       __syncthreads();  // din(i) and the activations are complete
       const MT* dT = din(i);
-      dw_layer<MT>(accs, dT, act(i), n_out, n_in, wave, ln);
+      dw_layer<MT, NW>(accs, dT, act(i), n_out, n_in, wave, ln);
       if (tid < n_out) {
         float sum = 0.0f;
 #pragma unroll
@@ -439,13 +446,13 @@ __global__ __launch_bounds__(64 * kBwdWaves) void bwd_kernel(const TreeArgs T, c
   for (int i = 0; i < NL; ++i) {
     const int n_out = PL.n_out[i], n_in = PL.n_in[i];
     if (i == NL - 1)
-      dw_store<UO>(accO, part, PL.w_off[i], n_out, n_in, wave, lane, A.accumulate);
+      dw_store<NW, UO>(accO, part, PL.w_off[i], n_out, n_in, wave, lane, A.accumulate);
     else if (i == 0)
-      dw_store<U0>(acc0, part, PL.w_off[i], n_out, n_in, wave, lane, A.accumulate);
+      dw_store<NW, U0>(acc0, part, PL.w_off[i], n_out, n_in, wave, lane, A.accumulate);
     else {
 #pragma unroll
       for (int hh = 0; hh < NHH; ++hh)
-        if (hh == i - 1) dw_store<UH>(accH[hh], part, PL.w_off[i], n_out, n_in, wave, lane, A.accumulate);
+        if (hh == i - 1) dw_store<NW, UH>(accH[hh], part, PL.w_off[i], n_out, n_in, wave, lane, A.accumulate);
     }
     float dbv = i == NL - 1 ? dbO : db0;
 #pragma unroll
@@ -611,7 +618,7 @@ int bwd_grid(const MlpArgs& M, oo_dtype md, int L, int64_t Q) {
   const int64_t n_tiles = (Q + kQW - 1) / kQW;
   const size_t lds = bwd_lds_bytes(M, md, L);
   int per_cu = (int)(kLdsBytes / (lds ? lds : 1));
-  const int by_waves = 16 / kBwdWaves;  // at most 16 of this kernel's waves per CU
+  const int by_waves = 16 / (md == OO_F32 ? bwd_waves<float>() : bwd_waves<f16>());  // at most 16 waves per CU
   if (per_cu > by_waves) per_cu = by_waves;
   per_cu = per_cu < 1 ? 1 : per_cu;
   int64_t g = (int64_t)cu_count() * per_cu;
@@ -644,7 +651,7 @@ static hipError_t launch_bwd_t(const TreeArgs& T, const MlpArgs& M, const MlpArg
   const size_t lds = bwd_lds_total(M.K0, H, M.n_layers, T.L, (int)sizeof(MT), wl);
   auto k = wl ? bwd_kernel<TT, MT, C, H, true> : bwd_kernel<TT, MT, C, H, false>;
   hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * kBwdWaves), lds, st, T, M, Mt, A, PL);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * bwd_waves<MT>()), lds, st, T, M, Mt, A, PL);
   return hipGetLastError();
 }
 
