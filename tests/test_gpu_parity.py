@@ -473,3 +473,30 @@ def test_full_size_config5_sampled():
             e = rel_l2(a, 0.5 * (b1 + b2))
             report(f"cfg5 additivity {key}[{i}]", rel_l2=e)
             assert e <= 1e-4
+
+
+# --------------------------------------------------------------------------
+# FP32 -> 16-bit refresh
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16, torch.float32])
+@pytest.mark.parametrize("n,off", [(1, 0), (7, 0), (8, 0), (1000003, 0), (4099, 1), ((1 << 21) + 13, 0)])
+def test_cast_params_bit_exact(dtype, n, off):
+    """The refresh cast rounds to nearest even exactly as a plain conversion
+    does: on the 8-element vector path, on the ragged tail, and on arrays
+    off 16-byte alignment (off = 1 element shifts both pointers). Values
+    include signed zeros, 16-bit underflow and overflow (65520 is the
+    midpoint that rounds to infinity in FP16) and infinities."""
+    g = torch.Generator().manual_seed(n + off)
+    src_h = torch.randn(n + off, generator=g) * 300.0
+    special = torch.tensor([0.0, -0.0, 1e-8, -3e-6, 65504.0, 65520.0, -7e4, 1e38, float("inf"), -float("inf")])
+    k = min(len(special), n)
+    src_h[off:off + k] = special[:k]
+    src = src_h.cuda()[off:]
+    dst = torch.full((n + off,), 7.0, dtype=dtype, device="cuda")[off:]
+    print(f"[case] cast n={n} off={off} {dtype}", flush=True)
+    binding.cast_params(src, dst)
+    torch.cuda.synchronize()
+    ref = src_h[off:].to(dtype)
+    bits = torch.int16 if dtype != torch.float32 else torch.int32
+    assert torch.equal(dst.cpu().view(bits), ref.view(bits))
