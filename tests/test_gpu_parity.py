@@ -432,7 +432,7 @@ def test_fd_config3_fp32():
         e = rel_l2(adj[sel], fd[sel])
         report(f"fd cfg3 {kind}", rel_l2=e, n=int(sel.sum()))
     # per entry: error relative to the entry, floored at the group's RMS so
-    # that near-zero gradients are judged on the FD noise scale
+    # that near-zero gradients are measured against the FD noise scale
     rms = {k: float(np.sqrt(np.mean(fd[kinds == k] ** 2))) for k in ("feat", "W")}
     per = np.array([abs(a - f) / max(abs(f), rms[k]) for a, f, k in zip(adj, fd, kinds)])
     worst = np.argsort(per)[::-1][:8]
