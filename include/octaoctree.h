@@ -267,8 +267,10 @@ int oo_cast_params(const float* src_fp32, void* dst, oo_dtype dst_dtype, int64_t
  * OO_PROF_KINDS entries or NULL, and releases the events. Kinds: sort =
  * query bucketing (4 kernels), query = fused encode + decode, combine =
  * residual assembly + loss reduction (2 kernels), backward = recompute +
- * decoder backward, scatter = feature-gradient atomics; the others are one
- * kernel each. Timing a call adds two event records per group; the events
+ * decoder backward, scatter = feature-gradient atomics, seeds = backward
+ * seeds + clear of the coarse levels' gradient pair buffers, dw_reduce =
+ * fold of those buffers into the feature gradients + dW/db reduction; the
+ * others are one kernel each. Timing a call adds two event records per group; the events
  * are host-side objects, no device memory is allocated.
  */
 #define OO_PROF_KINDS 11

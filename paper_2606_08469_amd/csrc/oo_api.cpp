@@ -208,7 +208,9 @@ int check_batch(const oo_residual_batch* b, ResidualArgs& A) {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Workspace {
-  size_t Lq, lossp, seeds, nidx, uv, dh, wt[OO_MAX_LAYERS], dwp, order, rank, scount, stotal, sstart, total;
+  size_t Lq, lossp, seeds, nidx, uv, dh, wt[OO_MAX_LAYERS], dwp, order, rank, scount, stotal, sstart, gpad, total;
+  int64_t pad_off[OO_MAX_LEVELS];  // float offset of each level's pair buffer in gpad, or -1
+  int64_t pad_total;               // floats in gpad
   int64_t Qb;
   int grid;
   ParamLayout PL;
@@ -228,8 +230,16 @@ void param_layout(const MlpArgs& M, ParamLayout& PL) {
   PL.P = off;
 }
 
-Workspace workspace_layout(const MlpArgs& M, oo_dtype md, const oo_residual_batch* b, int L) {
+// Levels whose feature gradients go through pair buffers: the leading
+// levels with maps of at least 8x8 texels whose buffers fit in 64 MiB
+// together. There a footprint row always costs one 64-byte atomic request
+// instead of 1.5 on average; their tables are small and nearly every query
+// touches them, so the clear and the fold cost little.
+constexpr size_t kPadBudget = size_t(64) << 20;
+
+Workspace workspace_layout(const MlpArgs& M, oo_dtype md, const oo_residual_batch* b, const oo_tree* tree) {
   Workspace w;
+  const int L = tree->n_levels;
   const int64_t B = b->B;
   const int N = b->target_override ? 0 : b->N;
   const int64_t Qf = B * (1 + N);
@@ -270,6 +280,24 @@ Workspace workspace_layout(const MlpArgs& M, oo_dtype md, const oo_residual_batc
   o = align256(o + (size_t)ss.K * sizeof(int32_t));
   w.sstart = o;
   o = align256(o + (size_t)ss.K * sizeof(int32_t));
+  // coarse-level pair buffers of the feature-gradient scatter
+  w.gpad = o;
+  w.pad_total = 0;
+  bool open = tree->C == 8;
+  for (int l = 0; l < OO_MAX_LEVELS; ++l) {
+    w.pad_off[l] = -1;
+    if (l >= L || !open) continue;
+    const int R = tree->res[l];
+    const int64_t nodes = tree->level_offset[l + 1] - tree->level_offset[l];
+    const int64_t f = pad_floats(R, nodes, tree->C);
+    if (R < 8 || (size_t)(w.pad_total + f) * sizeof(float) > kPadBudget) {
+      open = false;
+      continue;
+    }
+    w.pad_off[l] = w.pad_total;
+    w.pad_total += f;
+  }
+  o = align256(o + (size_t)w.pad_total * sizeof(float));
   w.total = o;
   return w;
 }
@@ -467,7 +495,7 @@ int oo_residual_workspace_bytes(const oo_tree* tree, const oo_mlp* mlp, const oo
   if ((rc = check_pair(tree, mlp))) return rc;
   if ((rc = check_batch(batch, A))) return rc;
   if (!bytes) return fail(OO_EINVAL, "bytes is NULL");
-  *bytes = workspace_layout(M, mlp->dtype, batch, tree->n_levels).total;
+  *bytes = workspace_layout(M, mlp->dtype, batch, tree).total;
   return OO_OK;
 }
 
@@ -485,7 +513,7 @@ int oo_radiosity_residual_fwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   if ((rc = check_batch(batch, A))) return rc;
   if (!loss_out || !workspace) return fail(OO_EINVAL, "loss_out and workspace are required");
   if (A.B > 0 && (!lhs_out || !rhs_out || !resid_out)) return fail(OO_EINVAL, "lhs_out, rhs_out, resid_out are required");
-  const Workspace w = workspace_layout(M, mlp->dtype, batch, tree->n_levels);
+  const Workspace w = workspace_layout(M, mlp->dtype, batch, tree);
   if (workspace_bytes < w.total)
     return fail(OO_EINVAL, "workspace of %zu bytes is smaller than the %zu this problem needs", workspace_bytes,
                 w.total);
@@ -538,7 +566,7 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   if (A.B == 0) return OO_OK;
   if (!resid || !rhs) return fail(OO_EINVAL, "resid and rhs are required");
   GradArgs G;
-  for (int l = 0; l < OO_MAX_LEVELS; ++l) G.dfeat[l] = nullptr;
+  for (int l = 0; l < OO_MAX_LEVELS; ++l) G.dfeat[l] = G.pad[l] = nullptr;
   for (int l = 0; l < tree->n_levels; ++l) {
     const bool has_nodes = tree->level_offset[l + 1] > tree->level_offset[l];
     if (has_nodes && !dfeat[l]) return fail(OO_EINVAL, "dfeat[%d] is NULL", l);
@@ -546,11 +574,14 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   }
   for (int i = 0; i < mlp->n_layers; ++i)
     if (!dW[i] || !db[i]) return fail(OO_EINVAL, "dW[%d] or db[%d] is NULL", i, i);
-  const Workspace w = workspace_layout(M, mlp->dtype, batch, tree->n_levels);
+  const Workspace w = workspace_layout(M, mlp->dtype, batch, tree);
   if (workspace_bytes < w.total)
     return fail(OO_EINVAL, "workspace of %zu bytes is smaller than the %zu this problem needs", workspace_bytes,
                 w.total);
   char* ws = static_cast<char*>(workspace);
+  float* const gpad = reinterpret_cast<float*>(ws + w.gpad);
+  for (int l = 0; l < tree->n_levels; ++l)
+    if (w.pad_off[l] >= 0 && G.dfeat[l]) G.pad[l] = gpad + w.pad_off[l];
   float* seeds = reinterpret_cast<float*>(ws + w.seeds);
   const int32_t* nidx = reinterpret_cast<const int32_t*>(ws + w.nidx);
   float* partials = reinterpret_cast<float*>(ws + w.dwp);
@@ -563,6 +594,7 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   {
     ProfScope ps(OO_PROF_SEEDS, stream);
     e = launch_seeds(A, resid, rhs, grad_loss, full ? 1 : 0, seeds, stream);
+    if (e == hipSuccess) e = launch_fill_zero(gpad, w.pad_total, stream);
   }
   if (e != hipSuccess) return hip_status(e, "seed launch");
   {
@@ -618,6 +650,7 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   }
   D.start[D.n_seg] = w.PL.P;
   ProfScope ps(OO_PROF_DW_REDUCE, stream);
+  if ((e = launch_pad_fold(T, G, stream)) != hipSuccess) return hip_status(e, "gradient fold launch");
   return hip_status(launch_dw_reduce(partials, w.grid, w.PL, D, post_scale, stream), "dW reduce launch");
 }
 

@@ -696,6 +696,7 @@ __global__ __launch_bounds__(256) void scatter_kernel(const TreeArgs T, int64_t 
   const int64_t stride = (int64_t)gridDim.x * blockDim.x, n = Q * 4 * C;
   for (int l = 0; l < T.L; ++l) {
     const int R = T.res[l];
+    float* const pad = G.pad[l];
     for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < n; gid += stride) {
       const int64_t q = gid / (4 * C);
       const int k = (int)(gid / C) & 3;
@@ -704,11 +705,27 @@ __global__ __launch_bounds__(256) void scatter_kernel(const TreeArgs T, int64_t 
       if (id < T.off[l] || id >= T.off[l + 1]) continue;
       const float2 p = uv[q];
       const float s = fminf(fmaxf(p.x, 0.0f), 1.0f), t = fminf(fmaxf(p.y, 0.0f), 1.0f);
-      int txk;
-      float wk;
-      tap(s, t, R, k, txk, wk);
       const float gv = dh[q * (int64_t)(T.L * C) + l * C + c] * post_scale;
-      unsafeAtomicAdd(G.dfeat[l] + ((int64_t)(id - T.off[l]) * R * R + txk) * C + c, wk * gv);
+      const int64_t node = id - T.off[l];
+      if (pad) {
+        // pair buffer: the tap at unwrapped (i0 + a, j0 + b) goes to slot a
+        // of the pair starting at column i0 in unwrapped row j0 + b, so both
+        // taps of a footprint row share one 64-byte chunk; i0, j0 in
+        // [-1, R - 1] for s, t in [0, 1] (the same arithmetic as tap())
+        const float pu = s * (float)R - 0.5f, pv = t * (float)R - 0.5f;
+        const float fi = floorf(pu), fj = floorf(pv);
+        const float fu = pu - fi, fv = pv - fj;
+        const int a = k & 1, b = k >> 1;
+        const int i0 = (int)fi, jr = (int)fj + b;
+        const float wk = (a ? fu : 1.0f - fu) * (b ? fv : 1.0f - fv);
+        const int64_t slot = ((node * (R + 2) + (jr + 1)) * (R + 1) + (i0 + 1)) * 2 + a;
+        unsafeAtomicAdd(pad + slot * C + c, wk * gv);
+      } else {
+        int txk;
+        float wk;
+        tap(s, t, R, k, txk, wk);
+        unsafeAtomicAdd(G.dfeat[l] + (node * R * R + txk) * C + c, wk * gv);
+      }
     }
   }
 }
@@ -727,6 +744,71 @@ hipError_t launch_scatter(const TreeArgs& T, int64_t Q, const int32_t* nidx, int
   else
     hipLaunchKernelGGL(scatter_kernel<8>, dim3((unsigned)blocks), dim3(256), 0, st, T, Q, nidx, ldn, uv, dh, post_scale,
                        G);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void fill_zero_kernel(float* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (4 * i + 3 < n)
+    reinterpret_cast<float4*>(p)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  else
+    for (int64_t e = 4 * i; e < n; ++e) p[e] = 0.0f;
+}
+
+// Moves level l's pair-buffer sums into its feature gradient: the unwrapped
+// texel (ii, jj), ii and jj in [-1, R], collects slot 0 of the pair starting
+// at ii and slot 1 of the pair starting at ii - 1, and lands on the texel
+// the seam wrap of tap() maps it to (several unwrapped texels of the border
+// land on one texel, hence the atomic add).
+template <int C>
+__global__ __launch_bounds__(256) void pad_fold_kernel(const TreeArgs T, const GradArgs G, int l, int64_t nodes) {
+  const int R = T.res[l];
+  const int64_t n = nodes * (R + 2) * (R + 2) * C;
+  const float* __restrict__ pad = G.pad[l];
+  float* __restrict__ dst = G.dfeat[l];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < n; gid += stride) {
+    const int c = (int)(gid % C);
+    int64_t r = gid / C;
+    const int ii = (int)(r % (R + 2)) - 1;
+    r /= R + 2;
+    const int jj = (int)(r % (R + 2)) - 1;
+    const int64_t node = r / (R + 2);
+    const int64_t row = (node * (R + 2) + (jj + 1)) * (R + 1);
+    float v = 0.0f;
+    if (ii <= R - 1) v += pad[((row + (ii + 1)) * 2 + 0) * C + c];
+    if (ii >= 0) v += pad[((row + ii) * 2 + 1) * C + c];
+    if (v == 0.0f) continue;
+    int i = ii, j = jj;
+    if ((unsigned)i >= (unsigned)R) j = R - 1 - j;
+    i = min(max(i, 0), R - 1);
+    if ((unsigned)j >= (unsigned)R) i = R - 1 - i;
+    j = min(max(j, 0), R - 1);
+    unsafeAtomicAdd(dst + ((node * R + j) * R + i) * C + c, v);
+  }
+}
+
+hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = ((n + 3) / 4 + 255) / 256;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_pad_fold(const TreeArgs& T, const GradArgs& G, hipStream_t st) {
+  for (int l = 0; l < T.L; ++l) {
+    if (!G.pad[l]) continue;
+    const int R = T.res[l];
+    const int64_t nodes = (int64_t)T.off[l + 1] - T.off[l];
+    const int64_t n = nodes * (R + 2) * (R + 2) * T.C;
+    if (n == 0) continue;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 256 * 16) blocks = 256 * 16;
+    if (T.C == 4)
+      hipLaunchKernelGGL(pad_fold_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, st, T, G, l, nodes);
+    else
+      hipLaunchKernelGGL(pad_fold_kernel<8>, dim3((unsigned)blocks), dim3(256), 0, st, T, G, l, nodes);
+  }
   return hipGetLastError();
 }
 

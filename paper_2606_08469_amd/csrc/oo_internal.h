@@ -20,9 +20,18 @@ struct ResidualArgs {
   float eps;
 };
 
+// Feature-gradient targets. pad[l], when set, is the level's pair buffer:
+// the scatter adds level l's taps there at their unwrapped positions and
+// pad_fold moves the sums into dfeat[l] (see scatter_kernel).
 struct GradArgs {
   float* dfeat[kMaxLevels];
+  float* pad[kMaxLevels];
 };
+
+// Floats of a level's pair buffer: per node, R + 2 rows (unwrapped rows -1
+// .. R) of R + 1 pairs (pairs starting at columns -1 .. R - 1) of two texels
+// of C channels.
+inline int64_t pad_floats(int R, int64_t nodes, int C) { return nodes * (R + 2) * (R + 1) * 2 * C; }
 
 // Flat parameter layout of the dW/db partials: layer i's W block at
 // w_off[i] (n_out x n_in), its b block at b_off[i].
@@ -93,5 +102,7 @@ hipError_t launch_scatter(const TreeArgs& T, int64_t Q, const int32_t* nidx, int
                           const float* dh, float post_scale, const GradArgs& G, hipStream_t st);
 hipError_t launch_dw_reduce(const float* partials, int grid, const ParamLayout& PL, const ReduceDst& D, float scale,
                             hipStream_t st);
+hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t st);
+hipError_t launch_pad_fold(const TreeArgs& T, const GradArgs& G, hipStream_t st);
 
 }  // namespace oo
