@@ -151,9 +151,12 @@ def main():
     lv_lhs = float(present[:B].sum().item())
     # scatter requests to the atomic units: per LHS query and present level,
     # two footprint rows of 2 texels, each one 64-byte chunk when it starts on
-    # an even texel and two otherwise (1.5 on average); a 2x2 map is 2 chunks
+    # an even texel and two otherwise (1.5 on average); a 2x2 map is 2 chunks,
+    # and so is a level whose gradients go through the library's pair buffers
     per_level = (idx[:B] >= 0).sum(0).to(torch.float64).cpu().numpy()
-    atomic_req = float(sum(n * (2.0 if r == 2 else 3.0) for n, r in zip(per_level, cfg.res)))
+    paired = pair_buffered_levels(cfg, np.diff(lo))
+    atomic_req = float(sum(n * (2.0 if (r == 2 or l in paired) else 3.0)
+                           for l, (n, r) in enumerate(zip(per_level, cfg.res))))
     del xq, dq, idx, present
     kern = kernel_rooflines(cfg, B, Q, lv_all, lv_lhs, per_kernel)
     if "scatter" in kern:
@@ -314,6 +317,23 @@ def kernel_rooflines(cfg, B, Q, lv_all, lv_lhs, per_kernel):
                   "launches_per_step": round(per_step, 2), "ms_per_step": round(per_kernel[k][0] * per_step, 4),
                   "algorithmic_bytes": int(nbytes), "mlp_flop": int(flop),
                   "mfma_frac": round(flop / t / 1e12 / MFMA_F16_PEAK_TFS, 4)}
+    return out
+
+
+def pair_buffered_levels(cfg, nodes_per_level):
+    """Levels whose feature gradients the library accumulates in pair
+    buffers: with C = 8, the leading levels with maps of at least 8x8 texels
+    whose buffers (per node R + 2 rows of R + 1 pairs of two C-float texels)
+    fit in 64 MiB together."""
+    out, total = set(), 0
+    if cfg.C != 8:
+        return out
+    for l, (R, n) in enumerate(zip(cfg.res, nodes_per_level)):
+        f = int(n) * (R + 2) * (R + 1) * 2 * cfg.C * 4
+        if R < 8 or total + f > (64 << 20):
+            break
+        out.add(l)
+        total += f
     return out
 
 
