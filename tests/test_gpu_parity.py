@@ -306,6 +306,39 @@ def test_residual_fp32(ci, B, mode):
     compare_grads(f"bwd cfg{ci} {mode}", got, otree, omlp, batch, tol=FP32_TOL)
 
 
+def test_residual_fp32_seam_directions():
+    """Backward with every LHS lookup direction at the octahedral map's edges
+    and corners, where the bilinear footprints wrap across the seam. The
+    coarse levels' gradients go through the pair buffers, whose fold must
+    land every wrapped tap on the texel the forward's tap names. Element-wise
+    FP32 bar against the oracle."""
+    batch = dict(train_batch(3, 4000))
+    g = np.random.default_rng(11)
+    n = len(batch["x"])
+    e = g.uniform(0.0, 0.03, n)  # distance from the edge, in map units
+    u = g.uniform(0.0, 1.0, n)
+    side = g.integers(0, 6, n)  # four edges, then corners
+    st = np.empty((n, 2))
+    st[:, 0] = np.where(side == 0, e, np.where(side == 1, 1.0 - e, u))
+    st[:, 1] = np.where(side == 2, e, np.where(side == 3, 1.0 - e, u))
+    corner = side >= 4
+    st[corner, 0] = np.where(side[corner] == 4, e[corner], 1.0 - e[corner])
+    st[corner, 1] = np.where(g.uniform(size=int(corner.sum())) < 0.5, 0.7 * e[corner], 1.0 - 0.7 * e[corner])
+    batch["dir"] = oracle.octa_decode(st).astype(np.float32)
+    back = oracle.octa(batch["dir"])
+    assert np.mean(np.minimum(back, 1.0 - back).min(axis=1) < 0.05) > 0.95  # the directions sit at the edges
+    batch, dropped = kink_safe_batch(3, batch, False)
+    model = gpu_models(3)
+    otree, omlp = oracle_models(3)
+    print(f"[case] residual fp32 cfg3 seam directions B={len(batch['x'])} (kink-dropped {dropped})", flush=True)
+    got = run_residual(model, batch)
+    lhs, rhs, res, loss = oracle.residual_fwd(otree, omlp, batch)
+    e_l = rel_l2(got["lhs"], lhs)
+    report("residual cfg3 seam lhs", rel_l2=e_l)
+    assert e_l <= FP32_TOL
+    compare_grads("bwd cfg3 seam", got, otree, omlp, batch, tol=FP32_TOL)
+
+
 # BF16 keeps 8 significand bits: the kernels' rounding of a hidden
 # pre-activation z is up to about 2^-8 of sum |w a| + |b|, so a ReLU whose
 # |z| is inside that band may take the other derivative branch than the FP64
