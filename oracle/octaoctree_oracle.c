@@ -528,19 +528,19 @@ int ora_residual_fwd(const ora_tree* t, const ora_mlp* m, const ora_batch* bt, d
 }
 
 /* Reverse pass of one query for the radiance seed g: the dense-layer
- * gradients (ReLU'(0) = 0), then dh = W_1^T delta_1, then each tap's share
- * w_tap * dh_l added to the texel it read. */
+ * gradients (ReLU'(0) = 0) added to dW/db, then dh = W_1^T delta_1 written
+ * to dh_out, and the query's node indices, taps and weights to qt, from which
+ * scatter_query later adds each tap's share of dh to the texel it read. */
 static void backprop_query(const ora_tree* t, const ora_mlp* m, const float* x3, const float* d3,
-                           const double g[3], double* const* dfeat, double* const* dW,
-                           double* const* db) {
+                           const double g[3], double* const* dW, double* const* db, query_taps* qt,
+                           double* dh_out) {
   double h[ORA_MAX_LEVELS * 16];
   double act[ORA_MAX_LAYERS + 1][ORA_MAX_WIDTH];
   double pre[ORA_MAX_LAYERS][ORA_MAX_WIDTH];
   double out[ORA_MAX_WIDTH];
   double delta[ORA_MAX_WIDTH], prev[ORA_MAX_WIDTH];
-  query_taps qt;
-  query_locate(t, x3, d3, &qt);
-  encode_from_taps(t, &qt, h);
+  query_locate(t, x3, d3, qt);
+  encode_from_taps(t, qt, h);
   mlp_row(m, h, act, pre, out);
 
   int32_t nl = m->n_layers;
@@ -560,21 +560,59 @@ static void backprop_query(const ora_tree* t, const ora_mlp* m, const float* x3,
     for (int32_t k = 0; k < fin; ++k) delta[k] = prev[k];
   }
   /* delta now holds dL/dh. */
+  for (int32_t k = 0; k < m->dims[0]; ++k) dh_out[k] = delta[k];
+}
+
+/* Adjoint of the level features: each tap's share w_tap * dh_l is added to
+ * the texel the tap read, at the node that holds the query at that level. */
+static void scatter_query(const ora_tree* t, const query_taps* qt, const double* dh, double* const* dfeat) {
   int32_t C = t->C;
   for (int32_t l = 0; l < t->n_levels; ++l) {
-    if (qt.idx[l] < 0) continue;
+    if (qt->idx[l] < 0) continue;
     for (int k = 0; k < 4; ++k) {
-      int64_t base = texel_base(t, l, qt.idx[l], qt.ij[l][2 * k], qt.ij[l][2 * k + 1]);
-      for (int32_t c = 0; c < C; ++c) dfeat[l][base + c] += qt.w[l][k] * delta[l * C + c];
+      int64_t base = texel_base(t, l, qt->idx[l], qt->ij[l][2 * k], qt->ij[l][2 * k + 1]);
+      for (int32_t c = 0; c < C; ++c) dfeat[l][base + c] += qt->w[l][k] * dh[l * C + c];
     }
   }
+}
+
+/* Seed of backward query q (q < B: the LHS query of point q; otherwise the
+ * RHS query (b, k) of point b = (q - B) / N, only with the gradient through
+ * the target). */
+static void query_seed(const ora_batch* bt, const double* lhs, const double* T, const double* r,
+                       const double* w, double grad_loss, int64_t q, double g[3], const float** x3,
+                       const float** d3) {
+  int64_t B = bt->B;
+  int64_t b = q < B ? q : (q - B) / bt->N;
+  for (int c = 0; c < 3; ++c) {
+    double gc = 2.0 * r[3 * b + c] * grad_loss / (3.0 * (double)B);
+    if (bt->loss_kind == 1) {
+      double rho = rel_norm(lhs[3 * b + c], T[3 * b + c], bt->eps);
+      gc /= rho * rho;
+    }
+    g[c] = gc;
+  }
+  if (q < B) {
+    *x3 = &bt->x[3 * q];
+    *d3 = &bt->dir[3 * q];
+    return;
+  }
+  int64_t bk = q - B;
+  for (int c = 0; c < 3; ++c) g[c] = -g[c] * w[3 * bk + c] / (double)bt->N;
+  *x3 = &bt->x2[3 * bk];
+  *d3 = &bt->dir2[3 * bk];
 }
 
 /* Gradient of the loss scaled by grad_loss. With the target detached (the
  * paper's choice) only the LHS query receives the seed
  * 2 r grad_loss / (3B) (divided by the squared normaliser for the relative
  * loss). With grad_through_rhs each RHS query (b, k) also receives
- * -seed_b * w_bk / N. */
+ * -seed_b * w_bk / N.
+ * Queries are processed in blocks: the per-query reverse passes of a block
+ * run in parallel (each thread adds into its own dW/db), then the block's
+ * feature-gradient shares are added in query order on one thread, and at the
+ * end the threads' dW/db are summed in thread order. */
+#define ORA_BWD_BLOCK 16384
 int ora_residual_bwd(const ora_tree* t, const ora_mlp* m, const ora_batch* bt, double grad_loss,
                      double* const* dfeat, double* const* dW, double* const* db,
                      int32_t nthreads) {
@@ -583,11 +621,22 @@ int ora_residual_bwd(const ora_tree* t, const ora_mlp* m, const ora_batch* bt, d
   int64_t B = bt->B;
   int32_t N = bt->N;
   if (B == 0) return 0;
+  int nt = 1;
+#ifdef _OPENMP
+  nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#endif
+  (void)nthreads;
+  int64_t P = 0;
+  for (int32_t i = 0; i < m->n_layers; ++i) P += (int64_t)m->dims[i + 1] * (m->dims[i] + 1);
+  int32_t K0 = m->dims[0];
   double* lhs = (double*)malloc((size_t)(3 * B) * sizeof(double));
   double* T = (double*)malloc((size_t)(3 * B) * sizeof(double));
   double* r = (double*)malloc((size_t)(3 * B) * sizeof(double));
   double* w = NULL;
-  if (!lhs || !T || !r) { rc = -5; goto done; }
+  double* priv = (double*)calloc((size_t)nt * (size_t)P, sizeof(double));
+  query_taps* qts = (query_taps*)malloc((size_t)ORA_BWD_BLOCK * sizeof(query_taps));
+  double* dhs = (double*)malloc((size_t)ORA_BWD_BLOCK * (size_t)K0 * sizeof(double));
+  if (!lhs || !T || !r || !priv || !qts || !dhs) { rc = -5; goto done; }
   rc = residual_parts(t, m, bt, lhs, T, r, nthreads);
   if (rc) goto done;
   int full = bt->grad_through_rhs && !bt->target_override && N > 0;
@@ -596,24 +645,48 @@ int ora_residual_bwd(const ora_tree* t, const ora_mlp* m, const ora_batch* bt, d
     if (!w) { rc = -5; goto done; }
     ora_bsdf_weight(bt, w);
   }
-  for (int64_t b = 0; b < B; ++b) {
-    double g[3];
-    for (int c = 0; c < 3; ++c) {
-      double gc = 2.0 * r[3 * b + c] * grad_loss / (3.0 * (double)B);
-      if (bt->loss_kind == 1) {
-        double rho = rel_norm(lhs[3 * b + c], T[3 * b + c], bt->eps);
-        gc /= rho * rho;
+  int64_t Qb = full ? B * (1 + N) : B;
+  for (int64_t q0 = 0; q0 < Qb; q0 += ORA_BWD_BLOCK) {
+    int64_t nq = Qb - q0 < ORA_BWD_BLOCK ? Qb - q0 : ORA_BWD_BLOCK;
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nt)
+#endif
+    {
+      int tid = 0;
+#ifdef _OPENMP
+      tid = omp_get_thread_num();
+#endif
+      double* mine = priv + (int64_t)tid * P;
+      double* pdW[ORA_MAX_LAYERS];
+      double* pdb[ORA_MAX_LAYERS];
+      int64_t o = 0;
+      for (int32_t i = 0; i < m->n_layers; ++i) {
+        pdW[i] = mine + o;
+        o += (int64_t)m->dims[i + 1] * m->dims[i];
+        pdb[i] = mine + o;
+        o += m->dims[i + 1];
       }
-      g[c] = gc;
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+      for (int64_t j = 0; j < nq; ++j) {
+        double g[3];
+        const float *x3, *d3;
+        query_seed(bt, lhs, T, r, w, grad_loss, q0 + j, g, &x3, &d3);
+        backprop_query(t, m, x3, d3, g, pdW, pdb, &qts[j], &dhs[j * K0]);
+      }
     }
-    backprop_query(t, m, &bt->x[3 * b], &bt->dir[3 * b], g, dfeat, dW, db);
-    if (full) {
-      for (int32_t k = 0; k < N; ++k) {
-        int64_t bk = b * N + k;
-        double gk[3];
-        for (int c = 0; c < 3; ++c) gk[c] = -g[c] * w[3 * bk + c] / (double)N;
-        backprop_query(t, m, &bt->x2[3 * bk], &bt->dir2[3 * bk], gk, dfeat, dW, db);
-      }
+    for (int64_t j = 0; j < nq; ++j) scatter_query(t, &qts[j], &dhs[j * K0], dfeat);
+  }
+  for (int th = 0; th < nt; ++th) {
+    const double* mine = priv + (int64_t)th * P;
+    int64_t o = 0;
+    for (int32_t i = 0; i < m->n_layers; ++i) {
+      int64_t nw = (int64_t)m->dims[i + 1] * m->dims[i];
+      for (int64_t e = 0; e < nw; ++e) dW[i][e] += mine[o + e];
+      o += nw;
+      for (int32_t e = 0; e < m->dims[i + 1]; ++e) db[i][e] += mine[o + e];
+      o += m->dims[i + 1];
     }
   }
 done:
@@ -621,5 +694,8 @@ done:
   free(T);
   free(r);
   free(w);
+  free(priv);
+  free(qts);
+  free(dhs);
   return rc;
 }

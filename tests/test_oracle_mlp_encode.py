@@ -4,6 +4,7 @@ import numpy as np
 
 import oracle
 from _tiny import tiny_problem
+from test_oracle_octree import cells, node_cells
 
 
 def test_mlp_matches_dense_layers():
@@ -72,3 +73,36 @@ def test_query_is_encode_then_mlp_and_thread_invariant():
     q4 = oracle.query_fwd(tree, mlp, batch["x"], batch["dir"], nthreads=4)
     np.testing.assert_array_equal(q1, oracle.mlp_fwd(mlp, h))
     np.testing.assert_array_equal(q1, q4)
+
+
+def test_encode_reads_the_map_of_the_cell_holding_x():
+    """Which node's map a level reads (Sec. 3.4: level j reads the map of the
+    cell c_j that holds x). Every node gets a constant map that spells out its
+    own cell coordinates and level, so the bilinear fetch returns exactly
+    those values and h_l names the node that was read. The cell is found here
+    from the geometry alone, floor(x 2^l) clamped to the cube, and the node
+    cells by walking the child masks from the root; a level whose cell holds
+    no node must read zeros."""
+    for seed in (21, 22):
+        tree, mlp, batch = tiny_problem(seed=seed, D=4, res=(4, 4, 2, 2, 2), B=400, n_samples=3000, tau=3)
+        x, d = batch["x"], batch["dir"]
+        coord = node_cells(tree.nodes, tree.level_offset)
+        feat = []
+        for l in range(tree.n_levels):
+            lo, hi = tree.level_offset[l], tree.level_offset[l + 1]
+            R = tree.res[l]
+            val = np.concatenate([coord[lo:hi] + 1, np.full((hi - lo, 1), l + 1)], axis=1).astype(np.float32)
+            feat.append(np.ascontiguousarray(np.broadcast_to(val[:, None, None, :], (hi - lo, R, R, 4))))
+        t1 = oracle.Tree(tree.nodes, tree.level_offset, tree.res, 4, feat)
+        h, _ = oracle.encode(t1, x, d)
+        deep = 0
+        for l in range(tree.n_levels):
+            lo, hi = tree.level_offset[l], tree.level_offset[l + 1]
+            have = {tuple(c) for c in coord[lo:hi]}
+            c = cells(x, l)
+            exists = np.array([tuple(v) in have for v in c])
+            want = np.where(exists[:, None], np.concatenate([c + 1, np.full((len(x), 1), l + 1)], axis=1), 0)
+            np.testing.assert_allclose(h[:, 4 * l:4 * l + 4], want, rtol=0, atol=1e-12, err_msg=f"level {l}")
+            if l >= 2 and hi - lo > 8:
+                deep += int(exists.sum())
+        assert deep > 100  # many queries read deep levels with many nodes

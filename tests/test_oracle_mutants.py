@@ -30,8 +30,13 @@ MUTANTS = {
     "backprop_transposed_weight": ("s += (double)m->W[i][(int64_t)o * fin + k] * delta[o];",
                                    "s += (double)m->W[i][(int64_t)k * fout + o] * delta[o];"),
     "relu_mask_missing": ("if (i > 0 && !(pre[i - 1][k] > 0.0)) s = 0.0;", ""),
-    "scatter_wrong_tap_weight": ("dfeat[l][base + c] += qt.w[l][k] * delta[l * C + c];",
-                                 "dfeat[l][base + c] += 0.25 * delta[l * C + c];"),
+    "scatter_wrong_tap_weight": ("dfeat[l][base + c] += qt->w[l][k] * dh[l * C + c];",
+                                 "dfeat[l][base + c] += 0.25 * dh[l * C + c];"),
+    "node_offset_dropped": ("int64_t local = (int64_t)idx - t->level_offset[l];", "int64_t local = 0;"),
+    "scatter_into_first_node": ("int64_t base = texel_base(t, l, qt->idx[l], qt->ij[l][2 * k], qt->ij[l][2 * k + 1]);\n"
+                                "      for (int32_t c = 0; c < C; ++c) dfeat",
+                                "int64_t base = texel_base(t, l, (int32_t)t->level_offset[l], qt->ij[l][2 * k], "
+                                "qt->ij[l][2 * k + 1]);\n      for (int32_t c = 0; c < C; ++c) dfeat"),
 }
 
 

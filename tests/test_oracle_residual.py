@@ -269,3 +269,25 @@ def test_scatter_conservation_uniform_shift():
             fd = (at(np.float32(e)) - at(np.float32(-e))) / (2 * e)
             s = dfeat[l][..., c].sum()
             assert abs(s - fd) <= 2e-6 * max(1e-3, abs(fd)), (l, c, s, fd)
+
+
+def test_feature_gradient_lands_on_the_nodes_holding_the_points():
+    """The adjoint of the level features (Sec. 3.4, 3.6) changes only the maps
+    the forward read: with the target detached, node n of level l receives a
+    gradient exactly when some LHS point of the batch lies in n's cell. Cells
+    come from the geometry (floor(x 2^l), clamped) and the node cells from
+    walking the child masks, independently of the descent."""
+    from test_oracle_octree import cells, node_cells
+    tree, mlp, batch = tiny_problem(seed=13, D=4, res=(4, 4, 2, 2, 2), N=2, B=60, n_samples=3000, tau=3,
+                                    bias_scale=0.1)
+    dfeat, _, _ = oracle.residual_bwd(tree, mlp, batch)
+    coord = node_cells(tree.nodes, tree.level_offset)
+    checked = 0
+    for l in range(tree.n_levels):
+        lo, hi = tree.level_offset[l], tree.level_offset[l + 1]
+        pos = {tuple(c): i for i, c in enumerate(coord[lo:hi])}
+        visited = {pos[tuple(c)] for c in cells(batch["x"], l) if tuple(c) in pos}
+        touched = set(np.nonzero(np.abs(dfeat[l]).reshape(hi - lo, -1).sum(1) > 0)[0].tolist())
+        assert touched == visited, (l, sorted(touched), sorted(visited))
+        checked += len(visited)
+    assert checked > 60
