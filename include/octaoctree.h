@@ -253,6 +253,40 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
                               float* const* dfeat, float* const* dW, float* const* db, void* workspace,
                               size_t workspace_bytes, hipStream_t stream);
 
+/*
+ * Node index per level that the residual forward found for each query the
+ * backward processes (Sec. 3.4: the node containing the point at every
+ * level), read back from the workspace in the caller's query order.
+ *  - tree, mlp, batch: as passed to the forward; workspace: the one it
+ *    filled, unchanged since (its size is checked as in the forward).
+ *  - node_idx_out: [Qb][n_levels] int32, -1 where the tree has no node.
+ *    Qb = B (the LHS queries) with the target detached, B (1 + N) with
+ *    grad_through_rhs (LHS queries first, then query (b, k) at B + b N + k).
+ *  - The indices are those the fused query kernel computed during the
+ *    forward and that the backward reads; nothing is recomputed.
+ */
+int oo_residual_node_indices(const oo_tree* tree, const oo_mlp* mlp, const oo_residual_batch* batch,
+                             const void* workspace, size_t workspace_bytes, int32_t* node_idx_out,
+                             hipStream_t stream);
+
+/*
+ * FP64 inner products of FP32 arrays, for the gradient norms and
+ * directional derivatives that finite-difference checks of the residual
+ * adjoint (Sec. 3.6) compare against.
+ *  - a[g], b[g]: device FP32 arrays of n[g] elements, g < n_groups <=
+ *    OO_DOT_MAX_GROUPS. b == NULL, or b[g] == NULL, takes b[g] = a[g]
+ *    (squared norm). a, b and n are host arrays of pointers / sizes.
+ *  - out: device FP64 [n_groups], out[g] = sum_i a[g][i] * b[g][i].
+ *  - partials: device FP64 scratch of n_groups * OO_DOT_BLOCKS elements,
+ *    owned by the caller.
+ *  - Each product is formed and summed in FP64, in an order that depends
+ *    only on n[g]: repeated calls give identical bits.
+ */
+#define OO_DOT_MAX_GROUPS 64
+#define OO_DOT_BLOCKS 256
+int oo_dot_f64(const float* const* a, const float* const* b, const int64_t* n, int32_t n_groups, double* out,
+               double* partials, hipStream_t stream);
+
 /* FP32 -> FP16/BF16 (round to nearest even) or FP32 copy, n elements. Used
  * to refresh working copies from FP32 masters. */
 int oo_cast_params(const float* src_fp32, void* dst, oo_dtype dst_dtype, int64_t n, hipStream_t stream);

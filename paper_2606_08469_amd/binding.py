@@ -71,6 +71,8 @@ def lib():
         L.oo_radiosity_residual_fwd.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.oo_radiosity_residual_bwd.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.oo_cast_params.argtypes = [vp, vp, i32, i64, vp]
+        L.oo_residual_node_indices.argtypes = [vp, vp, vp, vp, sz, vp, vp]
+        L.oo_dot_f64.argtypes = [vp, vp, vp, i32, vp, vp, vp]
         L.oo_profile_begin.argtypes = [i32]
         L.oo_profile_end.argtypes = [vp, vp]
         L.oo_profile_kind_name.argtypes = [i32]
@@ -78,7 +80,8 @@ def lib():
         L.oo_last_error.restype = C.c_char_p
         for f in ("oo_build_octree", "oo_encode_query", "oo_mlp_fwd", "oo_query_fwd",
                   "oo_residual_workspace_bytes", "oo_radiosity_residual_fwd", "oo_radiosity_residual_bwd",
-                  "oo_cast_params", "oo_profile_begin", "oo_profile_end"):
+                  "oo_cast_params", "oo_profile_begin", "oo_profile_end", "oo_residual_node_indices",
+                  "oo_dot_f64"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -269,6 +272,43 @@ def residual_bwd(tree: Tree, mlp: MLP, batch: dict, resid, rhs, grad_loss, dfeat
            "oo_radiosity_residual_bwd")
 
 
+def residual_node_indices(tree: Tree, mlp: MLP, batch: dict, workspace, feat=None, W=None):
+    """Node index per level of every backward query, as the forward stored
+    it in the workspace: int32 [Qb][L] in the caller's query order."""
+    ts, ms, bs = tree.struct(feat), mlp.struct(W), batch_struct(batch)
+    B, N = int(bs.B), int(bs.N)
+    full = bs.grad_through_rhs and batch.get("target_override") is None and N > 0
+    Qb = B * (1 + N) if full else B
+    out = torch.full((Qb, tree.n_levels), -2, dtype=torch.int32, device="cuda")
+    _check(lib().oo_residual_node_indices(C.byref(ts), C.byref(ms), C.byref(bs), _ptr(workspace), _nbytes(workspace),
+                                          _ptr(out), _stream()), "oo_residual_node_indices")
+    return out
+
+
+DOT_MAX_GROUPS, DOT_BLOCKS = 64, 256
+
+
+def dot_f64(a, b=None):
+    """FP64 inner products <a[g], b[g]> of lists of FP32 device tensors
+    (b None: squared norms), summed on the GPU in a fixed order. Returns a
+    FP64 device tensor [len(a)]."""
+    a = [t.contiguous() for t in a]
+    b = None if b is None else [t.contiguous() for t in b]
+    G = len(a)
+    if G > DOT_MAX_GROUPS:
+        raise OOError(f"at most {DOT_MAX_GROUPS} groups")
+    for i, t in enumerate(a):
+        if t.dtype != torch.float32 or (b is not None and (b[i].dtype != torch.float32 or b[i].numel() != t.numel())):
+            raise OOError("dot_f64 takes FP32 tensors of matching sizes")
+    out = torch.empty(max(G, 1), dtype=torch.float64, device="cuda")
+    part = torch.empty(max(G, 1) * DOT_BLOCKS, dtype=torch.float64, device="cuda")
+    pa = (C.c_void_p * max(G, 1))(*[t.data_ptr() if t.numel() else None for t in a])
+    pb = None if b is None else (C.c_void_p * max(G, 1))(*[t.data_ptr() if t.numel() else None for t in b])
+    n = (C.c_int64 * max(G, 1))(*[t.numel() for t in a])
+    _check(lib().oo_dot_f64(pa, pb, n, G, _ptr(out), _ptr(part), _stream()), "oo_dot_f64")
+    return out[:G]
+
+
 PROF_KINDS = 11
 
 
@@ -336,11 +376,13 @@ class OctaOctree(torch.nn.Module):
         self.mlp = MLP(list(self.W), list(self.b))
         self._ws = None
         self._work = None
+        self._gen = 0
         self.work_feat, self.work_W = None, None
         self.refresh()
 
     def refresh(self):
         """Re-derive the working copies from the FP32 masters."""
+        self._gen += 1  # a residual forward recorded before this refresh can no longer be differentiated
         with torch.no_grad():
             if self.dtype == torch.float32:
                 self.work_feat, self.work_W = list(self.feat), list(self.W)
@@ -358,10 +400,18 @@ class OctaOctree(torch.nn.Module):
         return query_fwd(self.tree, self.mlp, x, d, feat=self.work_feat, W=self.work_W)
 
     def workspace(self, batch):
+        """A workspace for explicit residual_fwd / residual_bwd calls on this
+        batch: one buffer kept by the model and grown as needed, so a later
+        call may overwrite what an earlier one left there."""
         n = residual_workspace_bytes(self.tree, self.mlp, batch, feat=self.work_feat, W=self.work_W)
         if self._ws is None or self._ws.numel() < n:
             self._ws = torch.empty(max(n, 256), dtype=torch.uint8, device="cuda")
         return self._ws
+
+    def new_workspace(self, batch):
+        """A workspace of its own for one forward/backward pair."""
+        n = residual_workspace_bytes(self.tree, self.mlp, batch, feat=self.work_feat, W=self.work_W)
+        return torch.empty(max(n, 256), dtype=torch.uint8, device="cuda")
 
     def residual(self, batch):
         """Loss of the residual step (0-dim FP64) with autograd to the masters."""
@@ -373,26 +423,33 @@ class RadiosityResidual(torch.autograd.Function):
     and the FP64 loss; backward recomputes the LHS encoding, runs the decoder
     backward on matrix cores and scatters feature gradients with FP32
     atomics. Gradients w.r.t. the 16-bit working copies are returned for the
-    FP32 masters."""
+    FP32 masters.
+
+    Each forward owns its workspace (the bucketed order, node indices and
+    octahedral coordinates its backward reads), so several forwards may be
+    summed before one backward. The backward refuses to run when the
+    parameters it would differentiate changed after the forward: the FP32
+    masters are saved tensors (an in-place update bumps their version), and
+    a refresh of the 16-bit working copies bumps the model's generation."""
 
     @staticmethod
     def forward(ctx, model: OctaOctree, batch: dict, *params):
-        ws = model.workspace(batch)
+        ws = model.new_workspace(batch)
         lhs, rhs, res, loss = residual_fwd(model.tree, model.mlp, batch, ws, feat=model.work_feat,
                                            W=model.work_W)
-        ctx.model, ctx.batch = model, batch
-        ctx.save_for_backward(res, rhs)
-        ctx.lhs = lhs
+        ctx.model, ctx.batch, ctx.ws, ctx.gen = model, batch, ws, model._gen
+        ctx.save_for_backward(res, rhs, *params)
         return loss
 
     @staticmethod
     def backward(ctx, grad_loss):
         model, batch = ctx.model, ctx.batch
-        res, rhs = ctx.saved_tensors
+        res, rhs = ctx.saved_tensors[:2]  # unpacking checks the masters' versions
+        if model._gen != ctx.gen:
+            raise OOError("RadiosityResidual: the working copies were refreshed after this forward")
         dfeat = [torch.zeros(f.shape, dtype=torch.float32, device="cuda") for f in model.feat]
         dW = [torch.zeros(w.shape, dtype=torch.float32, device="cuda") for w in model.W]
         db = [torch.zeros(v.shape, dtype=torch.float32, device="cuda") for v in model.b]
-        ws = model.workspace(batch)
-        residual_bwd(model.tree, model.mlp, batch, res, rhs, grad_loss, dfeat, dW, db, ws,
+        residual_bwd(model.tree, model.mlp, batch, res, rhs, grad_loss, dfeat, dW, db, ctx.ws,
                      feat=model.work_feat, W=model.work_W)
         return (None, None, *dfeat, *dW, *db)

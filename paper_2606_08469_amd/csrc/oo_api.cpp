@@ -654,6 +654,54 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   return hip_status(launch_dw_reduce(partials, w.grid, w.PL, D, post_scale, stream), "dW reduce launch");
 }
 
+int oo_residual_node_indices(const oo_tree* tree, const oo_mlp* mlp, const oo_residual_batch* batch,
+                             const void* workspace, size_t workspace_bytes, int32_t* node_idx_out,
+                             hipStream_t stream) {
+  g_err[0] = 0;
+  TreeArgs T;
+  MlpArgs M;
+  ResidualArgs A;
+  int rc = check_tree(tree, T);
+  if (rc) return rc;
+  if ((rc = check_mlp(mlp, tree->n_levels * tree->C, M))) return rc;
+  if ((rc = check_pair(tree, mlp))) return rc;
+  if ((rc = check_batch(batch, A))) return rc;
+  if (!workspace) return fail(OO_EINVAL, "workspace is required");
+  const Workspace w = workspace_layout(M, mlp->dtype, batch, tree);
+  if (workspace_bytes < w.total)
+    return fail(OO_EINVAL, "workspace of %zu bytes is smaller than the %zu this problem needs", workspace_bytes,
+                w.total);
+  if (w.Qb == 0) return OO_OK;
+  if (!node_idx_out) return fail(OO_EINVAL, "node_idx_out is required");
+  const char* ws = static_cast<const char*>(workspace);
+  return hip_status(launch_saved_nodes(reinterpret_cast<const int32_t*>(ws + w.nidx),
+                                       reinterpret_cast<const int32_t*>(ws + w.order), w.Qb, tree->n_levels,
+                                       node_idx_out, stream),
+                    "node index readback launch");
+}
+
+int oo_dot_f64(const float* const* a, const float* const* b, const int64_t* n, int32_t n_groups, double* out,
+               double* partials, hipStream_t stream) {
+  g_err[0] = 0;
+  if (n_groups < 0 || n_groups > OO_DOT_MAX_GROUPS)
+    return fail(OO_EINVAL, "n_groups must be in [0, %d], got %d", OO_DOT_MAX_GROUPS, n_groups);
+  if (n_groups == 0) return OO_OK;
+  if (!a || !n || !out || !partials) return fail(OO_EINVAL, "a, n, out and partials are required");
+  DotArgs D;
+  for (int g = 0; g < OO_DOT_MAX_GROUPS; ++g) {
+    D.a[g] = D.b[g] = nullptr;
+    D.n[g] = 0;
+  }
+  for (int g = 0; g < n_groups; ++g) {
+    if (n[g] < 0) return fail(OO_EINVAL, "n[%d] must be >= 0", g);
+    if (n[g] > 0 && !a[g]) return fail(OO_EINVAL, "a[%d] is NULL", g);
+    D.a[g] = a[g];
+    D.b[g] = b ? b[g] : nullptr;
+    D.n[g] = n[g];
+  }
+  return hip_status(launch_dot(D, n_groups, partials, out, stream), "dot launch");
+}
+
 int oo_cast_params(const float* src, void* dst, oo_dtype dst_dtype, int64_t n, hipStream_t stream) {
   g_err[0] = 0;
   if (n < 0) return fail(OO_EINVAL, "n must be >= 0");

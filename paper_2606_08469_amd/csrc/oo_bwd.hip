@@ -812,6 +812,49 @@ hipError_t launch_pad_fold(const TreeArgs& T, const GradArgs& G, hipStream_t st)
   return hipGetLastError();
 }
 
+// FP64 inner products of FP32 arrays in a fixed order: block k of group g
+// sums elements k * 256 + t + (256 * kDotBlocks) j (thread t, j = 0, 1, ...)
+// into per-thread FP64 accumulators, reduces them in a fixed tree and writes
+// partial [g][k]; dot_final sums the kDotBlocks partials of a group in a
+// fixed tree. b[g] == NULL squares a[g].
+__global__ __launch_bounds__(256) void dot_partial_kernel(const DotArgs D, double* __restrict__ partials) {
+  __shared__ double red[256];
+  const int g = blockIdx.y;
+  const float* __restrict__ a = D.a[g];
+  const float* __restrict__ b = D.b[g] ? D.b[g] : D.a[g];
+  const int64_t n = D.n[g], stride = (int64_t)256 * kDotBlocks;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) acc += (double)a[i] * (double)b[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[(int64_t)g * kDotBlocks + blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void dot_final_kernel(const double* __restrict__ partials, double* __restrict__ out) {
+  __shared__ double red[256];
+  const int g = blockIdx.x;
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < kDotBlocks; k += 256) acc += partials[(int64_t)g * kDotBlocks + k];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[g] = red[0];
+}
+
+hipError_t launch_dot(const DotArgs& D, int n_groups, double* partials, double* out, hipStream_t st) {
+  if (n_groups <= 0) return hipSuccess;
+  hipLaunchKernelGGL(dot_partial_kernel, dim3(kDotBlocks, n_groups), dim3(256), 0, st, D, partials);
+  hipLaunchKernelGGL(dot_final_kernel, dim3(n_groups), dim3(256), 0, st, partials, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_dw_reduce(const float* partials, int grid, const ParamLayout& PL, const ReduceDst& D, float scale,
                             hipStream_t st) {
   const int64_t blocks = (PL.P + 255) / 256;

@@ -460,6 +460,19 @@ __global__ __launch_bounds__(256) void cast_kernel(const float* __restrict__ src
   for (int64_t i = 8 * nv + i0; i < n; i += stride) dst[i] = from_f32<DT>(src[i]);
 }
 
+// Node indices the residual forward stored for its backward queries
+// ([L][Qb], sorted positions), returned per source query ([Qb][L]). Sorted
+// position p holds source query order[p]; a value outside [0, Qb) is skipped.
+__global__ __launch_bounds__(256) void saved_nodes_kernel(const int32_t* __restrict__ nidx,
+                                                          const int32_t* __restrict__ order, int64_t Qb, int L,
+                                                          int32_t* __restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= Qb) return;
+  const int64_t q = order[p];
+  if (q < 0 || q >= Qb) return;
+  for (int l = 0; l < L; ++l) out[q * L + l] = nidx[(int64_t)l * Qb + p];
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
@@ -622,6 +635,14 @@ hipError_t launch_combine(const ResidualArgs& A, const float* Lq, const int32_t*
   if (nb > 0)
     hipLaunchKernelGGL(combine_kernel, dim3(nb), dim3(256), 0, st, A, G, Lq, rank, lhs, rhs, resid, partials);
   hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(256), 0, st, partials, nb, A.B, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_saved_nodes(const int32_t* nidx, const int32_t* order, int64_t Qb, int L, int32_t* out,
+                              hipStream_t st) {
+  if (Qb == 0) return hipSuccess;
+  hipLaunchKernelGGL(saved_nodes_kernel, dim3((unsigned)((Qb + 255) / 256)), dim3(256), 0, st, nidx, order, Qb, L,
+                     out);
   return hipGetLastError();
 }
 

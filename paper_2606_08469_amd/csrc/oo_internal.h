@@ -72,6 +72,8 @@ int combine_blocks(int64_t B, int N);
 hipError_t launch_combine(const ResidualArgs& A, const float* Lq, const int32_t* rank, float* lhs, float* rhs,
                           float* resid, double* partials, double* loss, hipStream_t st);
 hipError_t launch_cast(const float* src, void* dst, oo_dtype dt, int64_t n, hipStream_t st);
+hipError_t launch_saved_nodes(const int32_t* nidx, const int32_t* order, int64_t Qb, int L, int32_t* out,
+                              hipStream_t st);
 
 // Backward.
 int bwd_grid(const MlpArgs& M, oo_dtype md, int L, int64_t Q);
@@ -103,6 +105,17 @@ hipError_t launch_scatter(const TreeArgs& T, int64_t Q, const int32_t* nidx, int
 hipError_t launch_dw_reduce(const float* partials, int grid, const ParamLayout& PL, const ReduceDst& D, float scale,
                             hipStream_t st);
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t st);
+
+// FP64 inner products of up to kDotGroups pairs of FP32 arrays (b == NULL:
+// a . a). partials: [n_groups][kDotBlocks] doubles.
+constexpr int kDotGroups = OO_DOT_MAX_GROUPS;
+constexpr int kDotBlocks = OO_DOT_BLOCKS;
+struct DotArgs {
+  const float* a[kDotGroups];
+  const float* b[kDotGroups];
+  int64_t n[kDotGroups];
+};
+hipError_t launch_dot(const DotArgs& D, int n_groups, double* partials, double* out, hipStream_t st);
 hipError_t launch_pad_fold(const TreeArgs& T, const GradArgs& G, hipStream_t st);
 
 }  // namespace oo

@@ -1,6 +1,7 @@
 """Shared setup for the GPU parity tests: seeded workloads built once per
-session, each with the library's tree (checked bit-identical to the
-oracle's) and the FP32 masters both sides read."""
+session. The GPU side runs on the library's tree, the oracle on the tree its
+own builder makes from the same samples (the two are checked bit-identical
+separately); both read the same FP32 masters."""
 import dataclasses
 import functools
 import math
@@ -47,16 +48,19 @@ def oracle_tree_for(tree_cfg: int):
 
 @functools.lru_cache(maxsize=None)
 def params_for(ci: int):
+    """FP32 masters, sized by the oracle's tree (the library's tree has the
+    same level sizes, or its parity tests fail)."""
     cfg = synth.CONFIGS[ci]
-    _, nodes, lo = tree_for(cfg.tree_cfg)
+    _, lo = oracle_tree_for(cfg.tree_cfg)
     feat = synth.init_tables(cfg, np.diff(lo))
     W, b = synth.init_mlp(cfg)
     return feat, W, b
 
 
 def oracle_models(ci: int):
+    """The oracle's view of config ci: its own tree and the FP32 masters."""
     cfg = synth.CONFIGS[ci]
-    _, nodes, lo = tree_for(cfg.tree_cfg)
+    nodes, lo = oracle_tree_for(cfg.tree_cfg)
     feat, W, b = params_for(ci)
     return oracle.Tree(nodes, lo, list(cfg.res), cfg.C, feat), oracle.MLP(W, b)
 

@@ -26,7 +26,7 @@ def L():
 def test_exports_every_declared_symbol(L):
     hdr = open(os.path.join(ROOT, "include", "octaoctree.h")).read()
     names = set(re.findall(r"^\s*(?:int|const char\*)\s+(oo_\w+)\s*\(", hdr, re.M))
-    assert len(names) == 12, names
+    assert len(names) == 14, names
     for n in sorted(names):
         assert hasattr(L, n), n
 
@@ -171,3 +171,22 @@ def test_residual_rejects_small_workspace(L):
     rc = L.oo_radiosity_residual_bwd(C.byref(t), C.byref(m), C.byref(b), p, p, p, ptrs, ptrs, ptrs, p, need - 1,
                                      None)
     assert rc == -1 and b"workspace" in L.oo_last_error()
+    rc = L.oo_residual_node_indices(C.byref(t), C.byref(m), C.byref(b), p, need - 1, p, None)
+    assert rc == -1 and b"workspace" in L.oo_last_error()
+
+
+def test_dot_and_node_readback_validation(L):
+    """Argument checks of oo_dot_f64 and oo_residual_node_indices that fail
+    before any device work."""
+    vp = C.c_void_p
+    out = vp(16)
+    assert L.oo_dot_f64(None, None, None, 0, None, None, None) == 0           # no groups: no-op
+    assert L.oo_dot_f64(None, None, None, -1, out, out, None) == -1
+    assert L.oo_dot_f64(None, None, None, binding.DOT_MAX_GROUPS + 1, out, out, None) == -1
+    n = (C.c_int64 * 1)(5)
+    a = (vp * 1)(None)
+    assert L.oo_dot_f64(a, None, n, 1, out, out, None) == -1                 # NULL array with n > 0
+    assert b"a[0]" in L.oo_last_error()
+    n[0] = -3
+    a[0] = 16
+    assert L.oo_dot_f64(a, None, n, 1, out, out, None) == -1                 # negative size

@@ -155,7 +155,8 @@ def test_tree_with_empty_levels():
     x = g.uniform(0, 1, (100, 3)).astype(np.float32)
     d = g.normal(size=(100, 3)).astype(np.float32)
     got = to_np(model(dev(x), dev(d)))
-    want = oracle.query_fwd(oracle.Tree(nodes, lo, res, 8, feat), oracle.MLP(W, b), x, d)
+    onodes, olo = oracle.build_octree(s, 3, 100)
+    want = oracle.query_fwd(oracle.Tree(onodes, olo, res, 8, feat), oracle.MLP(W, b), x, d)
     assert rel_l2(got, want) <= FP32_TOL
 
 
@@ -171,6 +172,9 @@ def deep_tree_case(seed=11):
     base = g.uniform(0.05, 0.95, (300, 3))
     s = np.concatenate([base, base + 1e-6, g.uniform(0, 1, (2000, 3))]).astype(np.float32)
     nodes, lo = binding.build_octree(s, 15, 1)
+    onodes, olo = oracle.build_octree(s, 15, 1)  # the oracle reads its own build of the same tree
+    np.testing.assert_array_equal(lo, olo)
+    np.testing.assert_array_equal(nodes, onodes)
     res = [8, 8, 8, 4, 4, 4, 4, 2, 2, 2, 2, 2, 2, 2, 2, 2]
     feat = [g.normal(0, 0.1, (int(n), R, R, 8)).astype(np.float32) for n, R in zip(np.diff(lo), res)]
     W = [g.uniform(-0.2, 0.2, (64, 128)).astype(np.float32), g.uniform(-0.3, 0.3, (64, 64)).astype(np.float32),
@@ -533,3 +537,139 @@ def test_cast_params_bit_exact(dtype, n, off):
     ref = src_h[off:].to(dtype)
     bits = torch.int16 if dtype != torch.float32 else torch.int32
     assert torch.equal(dst.cpu().view(bits), ref.view(bits))
+
+
+# --------------------------------------------------------------------------
+# the descent inside the fused query kernel, the bench's backward schedule,
+# and autograd ownership of the forward's saved state
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", ["cfg5_full_batch", "cfg5_grad_through_rhs", "deep16"])
+def test_query_kernel_descent_bit_exact(case):
+    """The node indices the fused query kernel finds during the residual
+    forward (and the backward reads) are bit-identical to the oracle's
+    descent: config 5 at full size (2^20 LHS points, FP16, four backward
+    chunks), config 5 with the gradient through the target (every secondary
+    query stored too), and the 16-level tree."""
+    if case == "deep16":
+        s, nodes, lo, res, feat, W, b = deep_tree_case()
+        otree = oracle.Tree(nodes, lo, res, 8, feat)
+        model = binding.OctaOctree(nodes, lo, res, 8, feat, W, b)
+        batch = deep_batch(s, 20000, 2)
+    else:
+        ci = 5
+        batch = dict(train_batch(5) if case == "cfg5_full_batch" else train_batch(5, 65536))
+        if case == "cfg5_grad_through_rhs":
+            batch["grad_through_rhs"] = 1
+        model = gpu_models(ci, torch.float16)
+        otree, _ = oracle_models(ci)
+    b = binding.device_batch(batch)
+    print(f"[case] query-kernel descent {case} B={len(batch['x'])}", flush=True)
+    ws = model.new_workspace(b)
+    binding.residual_fwd(model.tree, model.mlp, b, ws, feat=model.work_feat, W=model.work_W)
+    got = binding.residual_node_indices(model.tree, model.mlp, b, ws, feat=model.work_feat,
+                                        W=model.work_W).cpu().numpy()
+    x = batch["x"]
+    if case == "cfg5_grad_through_rhs":
+        x = np.concatenate([x, batch["x2"].reshape(-1, 3)])
+    want = oracle.descend(otree, x)
+    report(f"query-kernel descent {case}", queries=len(x), mismatches=int((got != want).sum()),
+           deepest=int((want >= 0).sum(1).max()))
+    np.testing.assert_array_equal(got, want)
+
+
+def test_bench_schedule_backward_fp16_against_oracle():
+    """The backward as the benchmark runs it: config 5 on FP16 tables and
+    matrix cores (decoder 88-128-128-3), 131,072 LHS points so that the
+    backward runs in four chunks with each chunk's scatter on the second
+    stream and the dW/db partials accumulated across launches, coarse levels
+    through the pair buffers. Every gradient group against the FP64 oracle by
+    cosine (>= 0.999), radiance and loss within 1e-2."""
+    ci, B = 5, 131072
+    batch = train_batch(ci, B)
+    model = gpu_models(ci, torch.float16)
+    otree, omlp = oracle_models(ci)
+    print(f"[case] bench-schedule backward fp16 cfg5 B={B}", flush=True)
+    got = run_residual(model, batch)
+    lhs, rhs, res, loss = oracle.residual_fwd(otree, omlp, batch)
+    e, el = rel_l2(got["lhs"], lhs), abs(got["loss"] - loss) / abs(loss)
+    report("bench-schedule fp16 lhs", rel_l2=e)
+    report("bench-schedule fp16 loss", rel=el)
+    assert e <= MIX_TOL and el <= MIX_TOL
+    compare_grads("bench-schedule fp16", got, otree, omlp, batch, cos=MIX_COS)
+
+
+def test_bench_schedule_backward_fp32_against_oracle():
+    """The same four-chunk schedule on the FP32 path at config 5 (decoder
+    88-128-128-3 on FP32 matrix cores), element-wise within 1e-5 on the
+    points clear of the FP32 ReLU-kink band."""
+    ci = 5
+    batch = train_batch(ci, 131072)
+    batch, dropped = kink_safe_batch(ci, batch, False)
+    model = gpu_models(ci, torch.float32)
+    otree, omlp = oracle_models(ci)
+    print(f"[case] bench-schedule backward fp32 cfg5 B={len(batch['x'])} (kink-dropped {dropped})", flush=True)
+    assert len(batch["x"]) >= 4 * 32768, "four backward chunks"
+    got = run_residual(model, batch)
+    lhs, rhs, res, loss = oracle.residual_fwd(otree, omlp, batch)
+    for k, w in (("lhs", lhs), ("rhs", rhs), ("resid", res)):
+        e = rel_l2(got[k], w)
+        report(f"bench-schedule fp32 {k}", rel_l2=e)
+        assert e <= FP32_TOL
+    compare_grads("bench-schedule fp32", got, otree, omlp, batch, tol=FP32_TOL)
+
+
+def _grads(model):
+    return [to_np(p.grad) if p.grad is not None else np.zeros(p.shape)
+            for p in list(model.feat) + list(model.W) + list(model.b)]
+
+
+def test_autograd_two_forwards_one_backward():
+    """Two residual forwards on one model (the second on a larger batch, which
+    needs a larger workspace) summed into one loss, then one backward: each
+    forward keeps its own saved state, so the result equals the sum of the two
+    separate backwards and the oracle's gradients of both batches."""
+    full = train_batch(3, 9000)
+    b1 = kink_safe_batch(3, subset_batch(full, np.arange(3000)), False)[0]
+    b2 = kink_safe_batch(3, subset_batch(full, np.arange(3000, 9000)), False)[0]
+    model = gpu_models(3)
+    d1, d2 = binding.device_batch(b1), binding.device_batch(b2)
+    print(f"[case] autograd two forwards B1={len(b1['x'])} B2={len(b2['x'])}", flush=True)
+    for p in model.parameters():
+        p.grad = None
+    (model.residual(d1) + model.residual(d2)).backward()
+    both = _grads(model)
+    sep = []
+    for d in (d1, d2):
+        for p in model.parameters():
+            p.grad = None
+        model.residual(d).backward()
+        sep.append(_grads(model))
+    otree, omlp = oracle_models(3)
+    o1, o2 = oracle.residual_bwd(otree, omlp, b1), oracle.residual_bwd(otree, omlp, b2)
+    want = [a + c for a, c in zip(o1[0] + o1[1] + o1[2], o2[0] + o2[1] + o2[2])]
+    for i, (g, s1, s2, w) in enumerate(zip(both, sep[0], sep[1], want)):
+        if not np.any(w):
+            continue
+        e_sep, e_ora = rel_l2(g, s1 + s2), rel_l2(g, w)
+        report(f"autograd two forwards group {i}", vs_separate=e_sep, vs_oracle=e_ora)
+        assert e_sep <= 1e-5 and e_ora <= FP32_TOL
+
+
+def test_autograd_refuses_changed_parameters():
+    """A backward after the parameters it would differentiate changed: an
+    in-place update of an FP32 master trips the saved-tensor version check,
+    and a refresh of the 16-bit working copies is refused by the model's
+    generation stamp."""
+    batch = binding.device_batch(train_batch(3, 512))
+    m32 = gpu_models(3)
+    loss = m32.residual(batch)
+    with torch.no_grad():
+        m32.W[0].add_(0.0)
+    with pytest.raises(RuntimeError):
+        loss.backward()
+    m16 = gpu_models(3, torch.float16)
+    loss = m16.residual(batch)
+    m16.refresh()
+    with pytest.raises(binding.OOError):
+        loss.backward()
