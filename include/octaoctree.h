@@ -28,7 +28,9 @@
  *    message for the calling thread.
  *  - Array pointers are DEVICE pointers owned by the caller unless marked
  *    "host". The library allocates no device memory. Scratch memory comes
- *    from a caller-provided workspace.
+ *    from a caller-provided workspace, except for oo_dot_f64_noalloc, whose
+ *    partial sums sit in a fixed 128 KiB device array of the library's code
+ *    object.
  *  - Device work is enqueued asynchronously on the given hipStream_t (NULL
  *    is the default stream). Device faults surface at the caller's next
  *    synchronisation. oo_build_octree runs on the host and is synchronous.
@@ -286,6 +288,26 @@ int oo_residual_node_indices(const oo_tree* tree, const oo_mlp* mlp, const oo_re
 #define OO_DOT_BLOCKS 256
 int oo_dot_f64(const float* const* a, const float* const* b, const int64_t* n, int32_t n_groups, double* out,
                double* partials, hipStream_t stream);
+
+/*
+ * oo_dot_f64 for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same inner products, with the partial sums kept in an array the library
+ * owns instead of a caller workspace.
+ *  - a, b, n, n_groups, out: as in oo_dot_f64. The result bits are those of
+ *    oo_dot_f64 on the same input (same kernels, same summation order).
+ *  - The array holds OO_DOT_MAX_GROUPS x OO_DOT_BLOCKS doubles (128 KiB) per
+ *    device, set up on the first call on that device and kept until the
+ *    process ends. n_groups > OO_DOT_MAX_GROUPS is refused with OO_EINVAL;
+ *    group lengths are not limited.
+ *  - The call allocates nothing on the device or through any library.
+ *  - Every call on one device shares that device's array: calls that overlap
+ *    on one device (different streams or host threads without ordering)
+ *    race and give wrong sums. Calls ordered on one stream are safe; each
+ *    call overwrites every partial it reads, so nothing needs clearing.
+ */
+int oo_dot_f64_noalloc(const float* const* a, const float* const* b, const int64_t* n, int32_t n_groups,
+                       double* out, hipStream_t stream);
 
 /* FP32 -> FP16/BF16 (round to nearest even) or FP32 copy, n elements. Used
  * to refresh working copies from FP32 masters. */

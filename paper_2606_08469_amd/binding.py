@@ -73,6 +73,7 @@ def lib():
         L.oo_cast_params.argtypes = [vp, vp, i32, i64, vp]
         L.oo_residual_node_indices.argtypes = [vp, vp, vp, vp, sz, vp, vp]
         L.oo_dot_f64.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+        L.oo_dot_f64_noalloc.argtypes = [vp, vp, vp, i32, vp, vp]
         L.oo_profile_begin.argtypes = [i32]
         L.oo_profile_end.argtypes = [vp, vp]
         L.oo_profile_kind_name.argtypes = [i32]
@@ -81,7 +82,7 @@ def lib():
         for f in ("oo_build_octree", "oo_encode_query", "oo_mlp_fwd", "oo_query_fwd",
                   "oo_residual_workspace_bytes", "oo_radiosity_residual_fwd", "oo_radiosity_residual_bwd",
                   "oo_cast_params", "oo_profile_begin", "oo_profile_end", "oo_residual_node_indices",
-                  "oo_dot_f64"):
+                  "oo_dot_f64", "oo_dot_f64_noalloc"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -306,6 +307,28 @@ def dot_f64(a, b=None):
     pb = None if b is None else (C.c_void_p * max(G, 1))(*[t.data_ptr() if t.numel() else None for t in b])
     n = (C.c_int64 * max(G, 1))(*[t.numel() for t in a])
     _check(lib().oo_dot_f64(pa, pb, n, G, _ptr(out), _ptr(part), _stream()), "oo_dot_f64")
+    return out[:G]
+
+
+def dot_f64_noalloc(a, b=None, out=None):
+    """dot_f64 through the entry point that allocates nothing: its partial
+    sums live in the library's own per-device array. `out` (FP64 device
+    tensor of at least len(a) elements) may be passed in, so that the call
+    itself needs no allocation either."""
+    a = [t.contiguous() for t in a]
+    b = None if b is None else [t.contiguous() for t in b]
+    G = len(a)
+    for i, t in enumerate(a):
+        if t.dtype != torch.float32 or (b is not None and (b[i].dtype != torch.float32 or b[i].numel() != t.numel())):
+            raise OOError("dot_f64_noalloc takes FP32 tensors of matching sizes")
+    if out is None:
+        out = torch.empty(max(G, 1), dtype=torch.float64, device="cuda")
+    if out.dtype != torch.float64 or out.numel() < G or not out.is_contiguous():
+        raise OOError("out must be a contiguous FP64 tensor of at least len(a) elements")
+    pa = (C.c_void_p * max(G, 1))(*[t.data_ptr() if t.numel() else None for t in a])
+    pb = None if b is None else (C.c_void_p * max(G, 1))(*[t.data_ptr() if t.numel() else None for t in b])
+    n = (C.c_int64 * max(G, 1))(*[t.numel() for t in a])
+    _check(lib().oo_dot_f64_noalloc(pa, pb, n, G, _ptr(out), _stream()), "oo_dot_f64_noalloc")
     return out[:G]
 
 

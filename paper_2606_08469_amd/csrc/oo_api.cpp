@@ -680,14 +680,16 @@ int oo_residual_node_indices(const oo_tree* tree, const oo_mlp* mlp, const oo_re
                     "node index readback launch");
 }
 
-int oo_dot_f64(const float* const* a, const float* const* b, const int64_t* n, int32_t n_groups, double* out,
-               double* partials, hipStream_t stream) {
-  g_err[0] = 0;
+}  // extern "C"
+
+namespace {
+
+int dot_args(const float* const* a, const float* const* b, const int64_t* n, int32_t n_groups, double* out,
+             DotArgs& D) {
   if (n_groups < 0 || n_groups > OO_DOT_MAX_GROUPS)
     return fail(OO_EINVAL, "n_groups must be in [0, %d], got %d", OO_DOT_MAX_GROUPS, n_groups);
   if (n_groups == 0) return OO_OK;
-  if (!a || !n || !out || !partials) return fail(OO_EINVAL, "a, n, out and partials are required");
-  DotArgs D;
+  if (!a || !n || !out) return fail(OO_EINVAL, "a, n and out are required");
   for (int g = 0; g < OO_DOT_MAX_GROUPS; ++g) {
     D.a[g] = D.b[g] = nullptr;
     D.n[g] = 0;
@@ -699,6 +701,36 @@ int oo_dot_f64(const float* const* a, const float* const* b, const int64_t* n, i
     D.b[g] = b ? b[g] : nullptr;
     D.n[g] = n[g];
   }
+  return OO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int oo_dot_f64(const float* const* a, const float* const* b, const int64_t* n, int32_t n_groups, double* out,
+               double* partials, hipStream_t stream) {
+  g_err[0] = 0;
+  DotArgs D;
+  int rc = dot_args(a, b, n, n_groups, out, D);
+  if (rc || n_groups == 0) return rc;
+  if (!partials) return fail(OO_EINVAL, "partials is required");
+  return hip_status(launch_dot(D, n_groups, partials, out, stream), "dot launch");
+}
+
+int oo_dot_f64_noalloc(const float* const* a, const float* const* b, const int64_t* n, int32_t n_groups,
+                       double* out, hipStream_t stream) {
+  g_err[0] = 0;
+  if (n_groups > OO_DOT_MAX_GROUPS)
+    return fail(OO_EINVAL, "n_groups = %d exceeds the %d groups the library's static partials array holds", n_groups,
+                OO_DOT_MAX_GROUPS);
+  DotArgs D;
+  int rc = dot_args(a, b, n, n_groups, out, D);
+  if (rc || n_groups == 0) return rc;
+  double* partials = nullptr;
+  hipError_t e = dot_scratch(&partials);
+  if (e != hipSuccess) return hip_status(e, "static partials lookup");
+  // every partial is overwritten by the launch: nothing to clear
   return hip_status(launch_dot(D, n_groups, partials, out, stream), "dot launch");
 }
 

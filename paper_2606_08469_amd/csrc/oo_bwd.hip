@@ -21,6 +21,8 @@
 // so that it overlaps the next launch of the fused kernel.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "oo_device.h"
 #include "oo_internal.h"
 
@@ -846,6 +848,31 @@ __global__ __launch_bounds__(256) void dot_final_kernel(const double* __restrict
     __syncthreads();
   }
   if (threadIdx.x == 0) out[g] = red[0];
+}
+
+// Partial sums of the allocation-free inner-product entry point: one
+// kDotGroups x kDotBlocks array of doubles (128 KiB) per device, held until
+// the process ends. Host code never passes `scratch` itself to a kernel: its
+// name on the host is a stand-in, not a device address. dot_scratch looks up
+// the current device's copy once (hipGetSymbolAddress, with that device
+// current) and hands out that address.
+static __device__ __align__(256) double scratch[kDotGroups * kDotBlocks];
+
+hipError_t dot_scratch(double** partials) {
+  static std::mutex m;
+  static double* ptr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(m);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess) return e;
+    ptr[dev] = static_cast<double*>(p);
+  }
+  *partials = ptr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_dot(const DotArgs& D, int n_groups, double* partials, double* out, hipStream_t st) {

@@ -116,6 +116,10 @@ struct DotArgs {
   int64_t n[kDotGroups];
 };
 hipError_t launch_dot(const DotArgs& D, int n_groups, double* partials, double* out, hipStream_t st);
+// Device address of the current device's library-owned partials array
+// ([kDotGroups][kDotBlocks] doubles), looked up on first use per device.
+constexpr int kMaxDevices = 64;
+hipError_t dot_scratch(double** partials);
 hipError_t launch_pad_fold(const TreeArgs& T, const GradArgs& G, hipStream_t st);
 
 }  // namespace oo
