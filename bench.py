@@ -36,7 +36,7 @@ def log(*a):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 step and render forwards")
@@ -97,6 +97,8 @@ def main():
     gl = torch.ones((), dtype=torch.float64, device=dev)
 
     def step(model, ev=None):
+        if ev:
+            ev[3].record()
         model.refresh()
         gflat.zero_()
         if ev:
@@ -110,6 +112,7 @@ def main():
                              ws, feat=model.work_feat, W=model.work_W)
         if ev:
             ev[2].record()
+            ev[4].record()
         return loss
 
     def timed(model, steps, warmup, kernels=False):
@@ -119,7 +122,7 @@ def main():
         for _ in range(warmup):
             step(model)
         torch.cuda.synchronize()
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
         if kernels:
             binding.profile_begin(64 * steps)
         torch.cuda.synchronize()
@@ -133,12 +136,16 @@ def main():
             per = {k: (v[0] / v[1], v[1] / steps) for k, v in binding.profile_end().items()}
         fwd = [e[0].elapsed_time(e[1]) for e in evs]
         bwd = [e[1].elapsed_time(e[2]) for e in evs]
-        return wall * 1e3, float(np.mean(fwd)), float(np.mean(bwd)), per
+        tot = np.array([e[3].elapsed_time(e[4]) for e in evs])
+        stats = {"median": float(np.median(tot)), "p10": float(np.percentile(tot, 10)),
+                 "p90": float(np.percentile(tot, 90)), "mean": float(tot.mean())}
+        return wall * 1e3, float(np.mean(fwd)), float(np.mean(bwd)), per, stats
 
     log("timing mixed step")
-    ms, fwd_ms, bwd_ms, per_kernel = timed(mixed, args.steps, args.warmup, kernels=True)
+    ms, fwd_ms, bwd_ms, per_kernel, st_mixed = timed(mixed, args.steps, args.warmup, kernels=True)
     loss_mixed = float(outs[3].item())
-    log(f"mixed: {ms:.3f} ms/step (fwd {fwd_ms:.3f} ms, bwd {bwd_ms:.3f} ms)")
+    log(f"mixed: {ms:.3f} ms/step (fwd {fwd_ms:.3f} ms, bwd {bwd_ms:.3f} ms); step events median "
+        f"{st_mixed['median']:.3f} p10 {st_mixed['p10']:.3f} p90 {st_mixed['p90']:.3f} ms")
     log("per launch (ms): " + ", ".join(f"{k} {v[0]:.4f}" for k, v in per_kernel.items()))
 
     # ---------------- algorithmic bytes / FLOPs ----------------------------
@@ -166,10 +173,9 @@ def main():
         k.update(atomic_requests=int(req), atomic_Greq_s=round(rate, 2), atomic_ceiling_Greq_s=ATOMIC_GREQ_S,
                  frac_of_atomic_ceiling=round(rate / ATOMIC_GREQ_S, 4))
     dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
-    traffic, traffic_src = hbm_traffic(dom)
-    roof = dict(kern[dom])
-    roof.update(traffic=traffic, traffic_source=traffic_src)
-    roof = {"kernel": dom, **roof, "kernels": kern}
+    roof = {"kernel": dom, **kern[dom], "kernels": kern,
+            "traffic_source": ("profiles/traffic_train_step_cfg5.txt" if kern[dom]["traffic"] is not None
+                               else "no counter summary for the current kernels")}
     for k, v in kern.items():
         log(f"{k}: {v['ms_per_launch']:.4f} ms/launch, {v['achieved']:.1f} {v['unit']} ({100 * v['frac']:.1f}% of "
             f"{v['bound']} peak); MFMA {100 * v['mfma_frac']:.2f}%")
@@ -179,9 +185,10 @@ def main():
     if not args.no_extra:
         fp32 = binding.OctaOctree(nodes, lo, list(cfg.res), cfg.C, feat, W, b, dtype=torch.float32)
         log("timing FP32 plain step")
-        ms32, f32, b32, _ = timed(fp32, max(3, args.steps // 4), 2)
+        ms32, f32, b32, _, st32 = timed(fp32, max(3, args.steps // 4), 2)
         loss32 = float(outs[3].item())
         extra["fp32_plain_step"] = {"ms_per_step": round(ms32, 4), "fwd_ms": round(f32, 4), "bwd_ms": round(b32, 4),
+                                    "step_event_ms": {k: round(v, 4) for k, v in st32.items()},
                                     "value": round(Q / (ms32 * 1e-3) / 1e6, 2), "unit": "Mqueries/s"}
         extra["speedup_mixed_vs_fp32"] = round(ms32 / ms, 3)
         extra["loss_mixed_vs_fp32_rel"] = abs(loss_mixed - loss32) / abs(loss32)
@@ -215,6 +222,7 @@ def main():
             "queries_per_step": Q, "lhs_points_per_step": B,
             "lhs_points_per_s_M": round(B / (ms * 1e-3) / 1e6, 3),
             "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4),
+            "step_event_ms": {k: round(v, 4) for k, v in st_mixed.items()},
             "ms_per_launch": {k: round(v[0], 4) for k, v in per_kernel.items()},
             "launches_per_step": {k: round(v[1], 2) for k, v in per_kernel.items()},
         },
@@ -225,11 +233,30 @@ def main():
     print(json.dumps(line), flush=True)
 
 
+def _event_times(torch, run, reps):
+    """Per-call event times (ms) of `run` over `reps` calls after 3 warm-ups;
+    returns (median, p10, p90, last output)."""
+    for _ in range(3):
+        out_ = run()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in evs:
+        e0.record()
+        out_ = run()
+        e1.record()
+    torch.cuda.synchronize()
+    t = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+    return float(np.median(t)), float(np.percentile(t, 10)), float(np.percentile(t, 90)), out_
+
+
 def render_bench(torch, binding, synth, args):
     """Render-query forwards (one query per pixel) on the FP32 plain path
-    (encode to memory + decoder kernel) and the 16-bit fused path."""
+    (encode to memory + decoder kernel) and the 16-bit fused path, with the
+    fused path's roofline; and the standalone 16-bit decoder (oo_mlp_fwd on
+    materialised features) at config 4's 88-128-128-3, the one place where
+    the decoder alone can approach the matrix cores' peak."""
     out = {}
-    reps = max(5, args.steps)
+    reps = max(20, args.steps)
     for ci, dtypes in ((2, (torch.float32, torch.float16)), (4, (torch.float32, torch.bfloat16))):
         cfg = synth.CONFIGS[ci]
         s = synth.tree_samples(cfg)
@@ -241,6 +268,7 @@ def render_bench(torch, binding, synth, args):
         dt = torch.from_numpy(d).cuda()
         res = {}
         ref = None
+        lv = None
         for dtype in dtypes:
             m = binding.OctaOctree(nodes, lo, list(cfg.res), cfg.C, feat, W, b, dtype=dtype)
             if dtype == torch.float32:
@@ -248,25 +276,44 @@ def render_bench(torch, binding, synth, args):
                     h, _ = binding.encode_query(m.tree, xt, dt, torch.float32, with_idx=False)
                     return binding.mlp_fwd(m.mlp, h)
                 name = "fp32_plain_unfused"
+                _, idx = binding.encode_query(m.tree, xt, dt, torch.float32)
+                lv = float((idx >= 0).sum().item())
+                del idx
             else:
                 run = lambda: m(xt, dt)
                 name = f"{str(dtype).split('.')[-1]}_fused"
-            for _ in range(3):
-                out_ = run()
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(reps):
-                out_ = run()
-            e1.record()
-            torch.cuda.synchronize()
-            t = e0.elapsed_time(e1) / reps
+            med, p10, p90, out_ = _event_times(torch, run, reps)
             if ref is None:
                 ref = out_.clone()
             err = float(((out_ - ref).norm() / ref.norm()).item())
-            res[name] = {"ms": round(t, 4), "Mqueries_s": round(len(x) / (t * 1e-3) / 1e6, 1),
-                         "rel_l2_vs_fp32": err}
-            log(f"render cfg{ci} {name}: {t:.4f} ms, {len(x) / (t * 1e-3) / 1e6:.0f} Mq/s, err {err:.2e}")
+            rec = {"ms": round(med, 4), "p10_ms": round(p10, 4), "p90_ms": round(p90, 4),
+                   "Mqueries_s": round(len(x) / (med * 1e-3) / 1e6, 1), "rel_l2_vs_fp32": err}
+            if dtype != torch.float32:
+                rec["roofline"] = render_roofline(cfg, len(x), lv, med, 2)
+            res[name] = rec
+            log(f"render cfg{ci} {name}: {med:.4f} ms (p10 {p10:.4f}, p90 {p90:.4f}), "
+                f"{len(x) / (med * 1e-3) / 1e6:.0f} Mq/s, err {err:.2e}")
+            if ci == 4 and dtype == torch.float32:
+                # standalone decoder on materialised 16-bit features
+                for hd in (torch.float16, torch.bfloat16):
+                    m16 = binding.OctaOctree(nodes, lo, list(cfg.res), cfg.C, feat, W, b, dtype=hd)
+                    h16, _ = binding.encode_query(m.tree, xt, dt, hd, with_idx=False)
+                    med_m, p10_m, p90_m, _ = _event_times(torch, lambda: binding.mlp_fwd(m16.mlp, h16, W=m16.work_W),
+                                                          reps)
+                    K0, Hd = cfg.mlp[0], cfg.mlp[1]
+                    flop = len(x) * 2 * (K0 * Hd + (len(cfg.mlp) - 3) * Hd * Hd + Hd * 3)
+                    nb = len(x) * (K0 * 2 + 12)
+                    tsec = med_m * 1e-3
+                    key = f"mlp_fwd_{str(hd).split('.')[-1]}"
+                    res[key] = {"ms": round(med_m, 4), "p10_ms": round(p10_m, 4), "p90_ms": round(p90_m, 4),
+                                "Mqueries_s": round(len(x) / tsec / 1e6, 1),
+                                "roofline": {"bound": "mfma", "achieved": round(flop / tsec / 1e12, 1),
+                                             "peak": MFMA_F16_PEAK_TFS, "unit": "TFLOP/s",
+                                             "frac": round(flop / tsec / 1e12 / MFMA_F16_PEAK_TFS, 4),
+                                             "hbm_GBs": round(nb / tsec / 1e9, 1)}}
+                    log(f"mlp_fwd cfg4 {key}: {med_m:.4f} ms, {flop / tsec / 1e12:.1f} TFLOP/s "
+                        f"({100 * flop / tsec / 1e12 / MFMA_F16_PEAK_TFS:.1f}% of MFMA peak)")
+                    del m16, h16
             del m
         out[f"cfg{ci}_{cfg.width}x{cfg.height}"] = res
         torch.cuda.empty_cache()
@@ -286,38 +333,67 @@ def kernel_rooflines(cfg, B, Q, lv_all, lv_lhs, per_kernel):
     backward and the scatter run in several launches per step, each over its
     share of the queries).
 
-    Per query and present level (lv = sum over queries of present levels):
-    4 taps x C channels x 2 B (FP16 texels) + 4 B node word in the forward;
-    the same gather again in the backward recompute; in the scatter, 4 taps x
-    C FP32 atomic adds (4 B each) + the C FP32 dh values and the node index it
-    reads. Per query, the forward also reads x and dir (24 B) through the
-    bucketed order (4 B) and writes its radiance (12 B); per LHS query it
-    writes the node index per level and the octahedral coordinates (8 B).
-    The backward reads those coordinates, the order entry and the 12 B seed,
-    and writes dh (K0 x 4 B); the scatter reads the coordinates."""
+    Algorithmic bytes are the method's own work (lv = sum over queries of
+    the levels that have a node, FP16 texels):
+     - query, per query: 4 taps x C channels x 2 B per present level + a 4 B
+       node word per present level + 24 B (x, dir) + 12 B radiance out;
+     - backward, per LHS point: the recomputed LHS query (as above) + the
+       12 B residual seed;
+     - scatter, per LHS point and present level: 4 taps x C FP32 atomic adds
+       of 4 B.
+    Traffic that only this implementation's split causes is listed apart as
+    implementation_bytes: the bucketed order (4 B per query) and the node
+    indices and octahedral coordinates the forward keeps for the backward
+    (4 B per level + 8 B per LHS query); in the backward those indices and
+    coordinates, the order entry, and the FP32 dh it hands to the scatter
+    (K0 x 4 B per LHS query); in the scatter the dh, node index and
+    coordinates it reads back."""
     C, L, K0 = cfg.C, len(cfg.res), cfg.mlp[0]
     H = cfg.mlp[1]
     mlp_flop = 2 * (K0 * H + (len(cfg.mlp) - 3) * H * H + H * 3)
+    gather = 4 * C * 2 + 4
     out = {}
     spec = {
-        "query": (lv_all * (4 * C * 2 + 4) + Q * (24 + 4 + 12) + B * (L * 4 + 8), Q * mlp_flop),
-        "backward": (lv_lhs * (4 * C * 2 + 4) + B * (8 + 4 + 12 + K0 * 4), B * 3 * mlp_flop),
-        "scatter": (lv_lhs * (4 * C * 4 + C * 4 + 4) + B * 8, 0),
+        "query": (lv_all * gather + Q * (24 + 12), Q * 4 + B * (L * 4 + 8), Q * mlp_flop),
+        "backward": (lv_lhs * gather + B * (24 + 12 + 12), B * (8 + 4 + K0 * 4), B * 3 * mlp_flop),
+        "scatter": (lv_lhs * 4 * C * 4, lv_lhs * (C * 4 + 4) + B * 8, 0),
     }
-    for k, (nbytes, flop) in spec.items():
+    counters = counter_traffic()
+    for k, (nbytes, impl, flop) in spec.items():
         if k not in per_kernel:
             continue
         # the backward runs in chunks: per-launch work is the step's share
         per_step = per_kernel[k][1]
-        nbytes, flop = nbytes / per_step, flop / per_step
+        nbytes, impl, flop = nbytes / per_step, impl / per_step, flop / per_step
         t = per_kernel[k][0] * 1e-3
         gbs = nbytes / t / 1e9
-        out[k] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                  "frac": round(gbs / HBM_PEAK_GBS, 4), "ms_per_launch": round(per_kernel[k][0], 4),
-                  "launches_per_step": round(per_step, 2), "ms_per_step": round(per_kernel[k][0] * per_step, 4),
-                  "algorithmic_bytes": int(nbytes), "mlp_flop": int(flop),
-                  "mfma_frac": round(flop / t / 1e12 / MFMA_F16_PEAK_TFS, 4)}
+        rec = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(gbs / HBM_PEAK_GBS, 4), "ms_per_launch": round(per_kernel[k][0], 4),
+               "launches_per_step": round(per_step, 2), "ms_per_step": round(per_kernel[k][0] * per_step, 4),
+               "algorithmic_bytes": int(nbytes), "implementation_bytes": int(impl), "mlp_flop": int(flop),
+               "mfma_frac": round(flop / t / 1e12 / MFMA_F16_PEAK_TFS, 4)}
+        if k in counters:
+            hb = counters[k]
+            rec.update(traffic=hb, measured_GBs=round(hb / t / 1e9, 1),
+                       measured_frac=round(hb / t / 1e9 / HBM_PEAK_GBS, 4))
+        else:
+            rec["traffic"] = None
+        out[k] = rec
     return out
+
+
+def render_roofline(cfg, n_queries, lv, ms, elem_bytes):
+    """Algorithmic bytes of the fused render forward (per query: 4 taps x C
+    x element size per present level, a 4 B node word per present level,
+    24 B position and direction, 12 B radiance) and its decoder FLOPs,
+    against the measured time."""
+    C, K0, H = cfg.C, cfg.mlp[0], cfg.mlp[1]
+    mlp_flop = 2 * (K0 * H + (len(cfg.mlp) - 3) * H * H + H * 3)
+    nbytes = lv * (4 * C * elem_bytes + 4) + n_queries * 36
+    t = ms * 1e-3
+    return {"bound": "hbm", "achieved": round(nbytes / t / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_bytes": int(nbytes),
+            "mlp_flop": int(n_queries * mlp_flop), "mfma_frac": round(n_queries * mlp_flop / t / 1e12 / MFMA_F16_PEAK_TFS, 4)}
 
 
 def pair_buffered_levels(cfg, nodes_per_level):
@@ -351,44 +427,62 @@ def source_digest():
     return h.hexdigest()
 
 
-def hbm_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary (scaled by the copy calibration), or
-    None when the summary is missing or the sources changed since."""
+def counter_traffic():
+    """HBM bytes per launch of each kernel in the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (scaled by the copy calibration), or {}
+    when the summary is missing or the kernels changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "traffic_train_step_cfg5.txt")
     if not os.path.exists(path):
-        return None, "no counter summary"
+        return {}
     rec = json.load(open(path))
     if rec.get("source_sha256") != source_digest():
-        return None, "kernels changed since the counters were taken"
-    k = rec.get("kernels", {}).get(kernel)
-    if not k:
-        return None, "kernel not in the counter summary"
-    return int(k["hbm_bytes_per_launch"]), os.path.relpath(path, ROOT)
+        return {}
+    return {k: int(v["hbm_bytes_per_launch"]) for k, v in rec.get("kernels", {}).items()}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(batch_np, nodes, lo, cfg, feat, W, b):
-    """The FP64 oracle as it stands, on a bounded sample of the same batch:
-    the first S LHS points with their N secondary queries, forward (queries
-    spread over all host threads) plus backward (single thread)."""
+    """The FP64 oracle as it stands, on bounded samples of the same batch:
+    the first S LHS points with their N secondary queries, residual forward
+    plus backward (both spread over T threads). T is every core this
+    process may use, within the OMP_NUM_THREADS share when that is set, and
+    then T = 1 on a smaller sample."""
     import oracle
     if not os.path.exists(oracle.LIB_PATH):
         from oracle import build as obuild
         obuild.build()
-    S = 1 << 18  # about 10-30 s of host work
-    sb = {k: (v[:S] if isinstance(v, np.ndarray) else v) for k, v in batch_np.items()}
     ot, om = oracle.Tree(nodes, lo, list(cfg.res), cfg.C, feat), oracle.MLP(W, b)
-    nt = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(16, os.cpu_count() or 1)
-    t = time.perf_counter()
-    oracle.residual_fwd(ot, om, sb, nthreads=nt)
-    oracle.residual_bwd(ot, om, sb, nthreads=nt)
-    dt = time.perf_counter() - t
-    q = S * (1 + cfg.N)
-    log(f"oracle: {dt:.2f}s for {S} points")
-    return {"value": round(q / dt / 1e6, 6), "unit": "Mqueries/s", "cores": nt, "kind": "oracle",
-            "sample": f"first {S} of 2^20 LHS points with their {cfg.N} secondary queries each "
-                      f"({q} queries), residual fwd (query evaluation on {nt} threads) + bwd (1 thread, "
-                      f"which recomputes the forward), FP64; {dt:.2f} s"}
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    share = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    nt = min(usable, share) if share > 0 else usable
+    runs = {}
+    for S, T in ((1 << 18, nt), (1 << 14, 1)):
+        sb = {k: (v[:S] if isinstance(v, np.ndarray) else v) for k, v in batch_np.items()}
+        t = time.perf_counter()
+        oracle.residual_fwd(ot, om, sb, nthreads=T)
+        oracle.residual_bwd(ot, om, sb, nthreads=T)
+        dt = time.perf_counter() - t
+        q = S * (1 + cfg.N)
+        runs[T] = (q / dt / 1e6, dt, S, q)
+        log(f"oracle: {dt:.2f}s for {S} points on {T} thread(s)")
+    v, dt, S, q = runs[nt]
+    v1, dt1, S1, q1 = runs[1]
+    return {"value": round(v, 6), "unit": "Mqueries/s", "cores": nt, "kind": "oracle",
+            "sample": f"first {S} of 2^20 LHS points with their {cfg.N} secondary queries each ({q} queries), "
+                      f"residual fwd + bwd in FP64 on {nt} threads: {dt:.2f} s",
+            "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(), "usable_cores": usable,
+            "omp_share": share or None,
+            "single_thread": {"value": round(v1, 6), "unit": "Mqueries/s", "cores": 1,
+                              "sample": f"first {S1} LHS points ({q1} queries): {dt1:.2f} s"}}
 
 
 if __name__ == "__main__":
