@@ -34,7 +34,13 @@ class _Tree(C.Structure):
         ("level_offset", C.c_int64 * (MAX_LEVELS + 1)),
         ("nodes", C.c_void_p),
         ("feat", C.c_void_p * MAX_LEVELS),
+        ("interp", C.c_int32),
     ]
+
+
+# Level-feature interpolation schemes.
+INTERP_NODE_BILINEAR = 0  # containing node, bilinear on R x R texels
+INTERP_PAPER = 1          # 8-cell trilinear (renormalised), barycentric on (R+1)^2 vertices
 
 
 class _MLP(C.Structure):
@@ -89,6 +95,10 @@ def lib():
         L.ora_residual_fwd.restype = C.c_int
         L.ora_residual_bwd.argtypes = [vp, vp, vp, C.c_double, vp, vp, vp, i32]
         L.ora_residual_bwd.restype = C.c_int
+        L.ora_map_entries.argtypes = [i32, i32]
+        L.ora_map_entries.restype = C.c_int64
+        L.ora_bary.argtypes = [vp, i64, i32, vp, vp, vp]
+        L.ora_neighbours.argtypes = [vp, vp, i64, i32, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -114,6 +124,8 @@ class Tree:
     res: list                         # R_l per level
     C: int
     feat: list = field(default_factory=list)  # float32 [n_l][R_l][R_l][C] per level
+    # INTERP_PAPER: feat[l] is [n_l][R_l + 1][R_l + 1][C] (map vertices)
+    interp: int = INTERP_NODE_BILINEAR
 
     @property
     def n_levels(self):
@@ -132,6 +144,7 @@ class Tree:
         self._feat = [_f32(f) for f in self.feat]
         for l, f in enumerate(self._feat):
             t.feat[l] = f.ctypes.data
+        t.interp = int(self.interp)
         return t
 
 
@@ -229,6 +242,39 @@ def taps(st, R):
     w = np.zeros((st.shape[0], 4), np.float64)
     lib().ora_taps(_p(st), st.shape[0], int(R), _p(ij), _p(w))
     return ij, w
+
+
+def map_entries(R, interp):
+    """Entries of one node's map: R^2 texels, or (R + 1)^2 vertices for the
+    paper's scheme (Sec. 4.1: features stored at map vertices)."""
+    return int(lib().ora_map_entries(int(R), int(interp)))
+
+
+def bary(st, R):
+    """Barycentric vertex lookup (Sec. 3.3): vertices (i, j) [B][3][2] as
+    found on the unfolded grid, weights [B][3], storage slots after the
+    seam identification [B][3]."""
+    st = _f64(st).reshape(-1, 2)
+    B = st.shape[0]
+    ij = np.zeros((B, 3, 2), np.int32)
+    w = np.zeros((B, 3), np.float64)
+    v = np.zeros((B, 3), np.int32)
+    lib().ora_bary(_p(st), B, int(R), _p(ij), _p(w), _p(v))
+    return ij, w, v
+
+
+def neighbours(tree: Tree, x, l):
+    """The 8 cells around x at level l (Sec. 3.4): node indices [B][8] (-1
+    empty), cell coordinates [B][8][3], renormalised trilinear weights
+    [B][8]."""
+    x = _f32(x).reshape(-1, 3)
+    B = x.shape[0]
+    idx = np.zeros((B, 8), np.int32)
+    cells = np.zeros((B, 8, 3), np.int64)
+    w = np.zeros((B, 8), np.float64)
+    ts = tree._struct()
+    lib().ora_neighbours(C.byref(ts), _p(x), B, int(l), _p(idx), _p(cells), _p(w))
+    return idx, cells, w
 
 
 def encode(tree: Tree, x, d):

@@ -6,12 +6,14 @@
  * double precision, with no blocking or fusion. Where the paper is silent the
  * readings are stated at the function (they are the same readings the GPU
  * library is held to):
- *  - spatial lookup uses the containing node at every level (the paper's
- *    "no octree interpolation" variant, Sec. 4.4) instead of the 8-cell
- *    trilinear blend of Sec. 3.4;
- *  - directional lookup is a texel-centred bilinear fetch on an R x R map
- *    with the octahedral seam identification, in place of the barycentric
- *    vertex lookup of Sec. 3.3;
+ *  - two interpolation schemes (ora_tree.interp):
+ *    ORA_INTERP_NODE_BILINEAR reads the containing node at every level (the
+ *    paper's "no octree interpolation" variant, Sec. 4.4) with a
+ *    texel-centred bilinear fetch on an R x R map and the octahedral seam
+ *    identification; ORA_INTERP_PAPER is the paper's own: the 8 neighbouring
+ *    cells blended trilinearly and renormalised over the non-empty ones
+ *    (Sec. 3.4, level-feature equation), each read by the barycentric
+ *    lookup on an (R+1) x (R+1) vertex map (Sec. 3.3);
  *  - the decoder reads the concatenated levels h only (no G-buffer inputs);
  *  - the BSDF is Lambert + GGX (Smith separable, Schlick Fresnel).
  *
@@ -298,17 +300,174 @@ void ora_taps(const double* st, int64_t B, int32_t R, int32_t* ij_out, double* w
 /* Encoding: per-level features, concatenated level by level (Sec. 3.4)      */
 /* ------------------------------------------------------------------------ */
 
+/* ------------------------------------------------------------------------ */
+/* The paper's interpolation: barycentric vertex maps (Sec. 3.3) and the     */
+/* 8-cell trilinear blend renormalised over non-empty cells (Sec. 3.4)      */
+/* ------------------------------------------------------------------------ */
+
+int64_t ora_map_entries(int32_t R, int32_t interp) {
+  return interp == ORA_INTERP_PAPER ? (int64_t)(R + 1) * (R + 1) : (int64_t)R * R;
+}
+
+/* Vertex (i, j) of the unfolded grid sits at (i / R, j / R). Points of the
+ * map border that are one direction share one storage slot: the edges
+ * s = 0 and s = 1 are each glued to themselves with t mirrored, the edges
+ * t = 0 and t = 1 with s mirrored, and the four corners are the -z pole. */
+static int32_t vertex_slot(int32_t i, int32_t j, int32_t R) {
+  if (i == 0 || i == R) j = j < R - j ? j : R - j;
+  if (j == 0 || j == R) i = i < R - i ? i : R - i;
+  return j * (R + 1) + i;
+}
+
+/* Each octahedron face, unfolded, is a right isosceles triangle whose
+ * hypotenuse lies on one of the lines |2s - 1| + |2t - 1| = 1 (the equator)
+ * and whose legs lie on the map's border or on its centre lines. Subdividing
+ * every face uniformly gives grid cells split along the diagonal parallel
+ * to their quadrant's equator segment: the anti-diagonal in the quadrants
+ * where s - 1/2 and t - 1/2 have the same sign, the main diagonal in the
+ * other two. The query's cell and half give the triangle; its weights are
+ * the barycentric coordinates of (s R, t R). */
+static void bary_one(double s, double t, int32_t R, int32_t ij[6], double w[3]) {
+  double pu = s * R, pv = t * R;
+  int32_t i = (int32_t)floor(pu), j = (int32_t)floor(pv);
+  if (i > R - 1) i = R - 1;
+  if (j > R - 1) j = R - 1;
+  if (i < 0) i = 0;
+  if (j < 0) j = 0;
+  double fu = pu - i, fv = pv - j;
+  int same_side = (2 * i >= R) == (2 * j >= R);
+  int32_t v[3][2];
+  if (same_side) {
+    if (fu + fv <= 1.0) {
+      v[0][0] = i;     v[0][1] = j;     w[0] = 1.0 - fu - fv;
+      v[1][0] = i + 1; v[1][1] = j;     w[1] = fu;
+      v[2][0] = i;     v[2][1] = j + 1; w[2] = fv;
+    } else {
+      v[0][0] = i + 1; v[0][1] = j + 1; w[0] = fu + fv - 1.0;
+      v[1][0] = i;     v[1][1] = j + 1; w[1] = 1.0 - fu;
+      v[2][0] = i + 1; v[2][1] = j;     w[2] = 1.0 - fv;
+    }
+  } else {
+    if (fu >= fv) {
+      v[0][0] = i;     v[0][1] = j;     w[0] = 1.0 - fu;
+      v[1][0] = i + 1; v[1][1] = j;     w[1] = fu - fv;
+      v[2][0] = i + 1; v[2][1] = j + 1; w[2] = fv;
+    } else {
+      v[0][0] = i;     v[0][1] = j;     w[0] = 1.0 - fv;
+      v[1][0] = i;     v[1][1] = j + 1; w[1] = fv - fu;
+      v[2][0] = i + 1; v[2][1] = j + 1; w[2] = fu;
+    }
+  }
+  for (int k = 0; k < 3; ++k) {
+    ij[2 * k] = v[k][0];
+    ij[2 * k + 1] = v[k][1];
+  }
+}
+
+void ora_bary(const double* st, int64_t B, int32_t R, int32_t* ij_out, double* w_out, int32_t* vidx_out) {
+  for (int64_t b = 0; b < B; ++b) {
+    int32_t ij[6];
+    bary_one(st[2 * b], st[2 * b + 1], R, ij, &w_out[3 * b]);
+    for (int k = 0; k < 3; ++k) {
+      ij_out[6 * b + 2 * k] = ij[2 * k];
+      ij_out[6 * b + 2 * k + 1] = ij[2 * k + 1];
+      vidx_out[3 * b + k] = vertex_slot(ij[2 * k], ij[2 * k + 1], R);
+    }
+  }
+}
+
+/* Node of the level-l cell with integer coordinates c, found by walking
+ * down from the root along the cell's octants; -1 if the cell is outside
+ * the cube or has no node. */
+static int64_t cell_node(const ora_tree* t, int32_t l, const int64_t c[3]) {
+  int64_t n = (int64_t)1 << l;
+  for (int a = 0; a < 3; ++a)
+    if (c[a] < 0 || c[a] >= n) return -1;
+  int64_t cur = 0;
+  for (int32_t k = 1; k <= l; ++k) {
+    uint32_t word = t->nodes[cur];
+    uint32_t mask = word & 0xffu;
+    int o = child_octant(c, l - k);
+    if (!((mask >> o) & 1u)) return -1;
+    cur = (int64_t)(word >> 8) + popcount8(mask & ((1u << o) - 1u));
+  }
+  return cur;
+}
+
+/* Cell centres at level l sit at (c + 1/2) / 2^l. The eight cells whose
+ * centres surround x (clamped to the cube) get the standard trilinear
+ * weights; cells outside the cube or without a node are dropped and the
+ * remaining weights rescaled to sum to 1 (all zero if none remains). */
+static void neighbours_one(const ora_tree* t, const float* x3, int32_t l, int32_t idx[8], int64_t cells[24],
+                           double w[8]) {
+  int64_t base[3];
+  double f[3];
+  for (int a = 0; a < 3; ++a) {
+    double xa = (double)x3[a];
+    if (!(xa >= 0.0)) xa = 0.0;
+    if (xa > 1.0) xa = 1.0;
+    double p = xa * ldexp(1.0, l) - 0.5;
+    double fl = floor(p);
+    base[a] = (int64_t)fl;
+    f[a] = p - fl;
+  }
+  double sum = 0.0;
+  for (int d = 0; d < 8; ++d) {
+    int64_t c[3];
+    double wd = 1.0;
+    for (int a = 0; a < 3; ++a) {
+      int bit = (d >> a) & 1;
+      c[a] = base[a] + bit;
+      wd *= bit ? f[a] : 1.0 - f[a];
+      cells[3 * d + a] = c[a];
+    }
+    idx[d] = (int32_t)cell_node(t, l, c);
+    w[d] = idx[d] >= 0 ? wd : 0.0;
+    sum += w[d];
+  }
+  for (int d = 0; d < 8; ++d) w[d] = sum > 0.0 ? w[d] / sum : 0.0;
+}
+
+void ora_neighbours(const ora_tree* t, const float* x, int64_t B, int32_t l, int32_t* idx_out,
+                    int64_t* cell_out, double* w_out) {
+  for (int64_t b = 0; b < B; ++b) neighbours_one(t, &x[3 * b], l, &idx_out[8 * b], &cell_out[24 * b], &w_out[8 * b]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Encoding: per-level features, concatenated level by level (Sec. 3.4)      */
+/* ------------------------------------------------------------------------ */
+
 typedef struct {
-  int32_t idx[ORA_MAX_LEVELS];
-  int32_t ij[ORA_MAX_LEVELS][8];
+  int32_t idx[ORA_MAX_LEVELS];       /* containing node per level */
+  int32_t ij[ORA_MAX_LEVELS][8];     /* bilinear taps (texel i, j) */
   double w[ORA_MAX_LEVELS][4];
+  int32_t nb[ORA_MAX_LEVELS][8];     /* paper: the 8 neighbouring cells' nodes */
+  double nbw[ORA_MAX_LEVELS][8];     /* their renormalised trilinear weights */
+  int32_t vert[ORA_MAX_LEVELS][3];   /* paper: storage slots of the 3 vertices */
+  double vw[ORA_MAX_LEVELS][3];      /* their barycentric weights */
 } query_taps;
 
 static void query_locate(const ora_tree* t, const float* x3, const float* d3, query_taps* qt) {
   double st[2];
   descend_one(t, x3, qt->idx);
   octa_one(d3, st);
-  for (int32_t l = 0; l < t->n_levels; ++l) taps_one(st[0], st[1], t->res[l], qt->ij[l], qt->w[l]);
+  for (int32_t l = 0; l < t->n_levels; ++l) {
+    if (t->interp == ORA_INTERP_PAPER) {
+      int64_t cells[24];
+      int32_t ij[6];
+      neighbours_one(t, x3, l, qt->nb[l], cells, qt->nbw[l]);
+      bary_one(st[0], st[1], t->res[l], ij, qt->vw[l]);
+      for (int k = 0; k < 3; ++k) qt->vert[l][k] = vertex_slot(ij[2 * k], ij[2 * k + 1], t->res[l]);
+    } else {
+      taps_one(st[0], st[1], t->res[l], qt->ij[l], qt->w[l]);
+    }
+  }
+}
+
+/* Offset of map entry `slot` of node idx at level l. */
+static int64_t entry_base(const ora_tree* t, int32_t l, int32_t idx, int64_t slot) {
+  int64_t local = (int64_t)idx - t->level_offset[l];
+  return (local * ora_map_entries(t->res[l], t->interp) + slot) * t->C;
 }
 
 /* Offset of texel (i, j) of node idx at level l in that level's table. */
@@ -318,12 +477,26 @@ static int64_t texel_base(const ora_tree* t, int32_t l, int32_t idx, int32_t i, 
   return ((local * R + j) * R + i) * t->C;
 }
 
-/* h_l = sum over taps of w * T_l[node][j][i][:]; a level without a node
- * contributes zeros. */
+/* Bilinear scheme: h_l = sum over taps of w * T_l[node][j][i][:]; a level
+ * without a node contributes zeros. Paper scheme: h_l = sum over the 8
+ * neighbouring cells of their renormalised trilinear weight times the
+ * barycentric blend of that cell's three vertices; empty cells contribute
+ * nothing. */
 static void encode_from_taps(const ora_tree* t, const query_taps* qt, double* h) {
   int32_t C = t->C;
   for (int32_t l = 0; l < t->n_levels; ++l) {
     for (int32_t c = 0; c < C; ++c) h[l * C + c] = 0.0;
+    if (t->interp == ORA_INTERP_PAPER) {
+      for (int d = 0; d < 8; ++d) {
+        if (qt->nb[l][d] < 0) continue;
+        for (int k = 0; k < 3; ++k) {
+          int64_t base = entry_base(t, l, qt->nb[l][d], qt->vert[l][k]);
+          double wk = qt->nbw[l][d] * qt->vw[l][k];
+          for (int32_t c = 0; c < C; ++c) h[l * C + c] += wk * (double)t->feat[l][base + c];
+        }
+      }
+      continue;
+    }
     if (qt->idx[l] < 0) continue;
     for (int k = 0; k < 4; ++k) {
       int64_t base = texel_base(t, l, qt->idx[l], qt->ij[l][2 * k], qt->ij[l][2 * k + 1]);
@@ -564,10 +737,23 @@ static void backprop_query(const ora_tree* t, const ora_mlp* m, const float* x3,
 }
 
 /* Adjoint of the level features: each tap's share w_tap * dh_l is added to
- * the texel the tap read, at the node that holds the query at that level. */
+ * the texel the tap read, at the node that holds the query at that level
+ * (paper scheme: each of the 24 cell-vertex reads gets its weight times
+ * dh_l). */
 static void scatter_query(const ora_tree* t, const query_taps* qt, const double* dh, double* const* dfeat) {
   int32_t C = t->C;
   for (int32_t l = 0; l < t->n_levels; ++l) {
+    if (t->interp == ORA_INTERP_PAPER) {
+      for (int d = 0; d < 8; ++d) {
+        if (qt->nb[l][d] < 0) continue;
+        for (int k = 0; k < 3; ++k) {
+          int64_t base = entry_base(t, l, qt->nb[l][d], qt->vert[l][k]);
+          double wk = qt->nbw[l][d] * qt->vw[l][k];
+          for (int32_t c = 0; c < C; ++c) dfeat[l][base + c] += wk * dh[l * C + c];
+        }
+      }
+      continue;
+    }
     if (qt->idx[l] < 0) continue;
     for (int k = 0; k < 4; ++k) {
       int64_t base = texel_base(t, l, qt->idx[l], qt->ij[l][2 * k], qt->ij[l][2 * k + 1]);

@@ -10,7 +10,8 @@
  * Conventions
  *  - Every FP32 input is widened exactly to double; all arithmetic is FP64.
  *  - Feature tables are the FP32 master copies, laid out per level as
- *    [n_l][R_l][R_l][C] (row = t direction, column = s direction).
+ *    [n_l][R_l][R_l][C] texels (row = t direction, column = s direction),
+ *    or with ORA_INTERP_PAPER as [n_l][R_l + 1][R_l + 1][C] map vertices.
  *  - Node words: (first_child << 8) | child_mask, first_child a global node
  *    index, child octant o = bx | by << 1 | bz << 2. Leaves hold 0.
  *  - Levels 0..D; level 0 is the root.
@@ -30,13 +31,20 @@ extern "C" {
 #define ORA_MAX_LEVELS 16
 #define ORA_MAX_LAYERS 7
 
+/* Interpolation schemes of a level feature. */
+#define ORA_INTERP_NODE_BILINEAR 0  /* containing node, bilinear on R x R texels */
+#define ORA_INTERP_PAPER 1          /* 8 neighbouring cells (trilinear,
+                                       renormalised over non-empty cells),
+                                       barycentric on (R+1)^2 vertices */
+
 typedef struct {
   int32_t n_levels;                          /* L = D + 1 */
   int32_t C;                                 /* features per texel */
-  int32_t res[ORA_MAX_LEVELS];               /* R_l texels per side */
+  int32_t res[ORA_MAX_LEVELS];               /* R_l texels (cells) per side */
   int64_t level_offset[ORA_MAX_LEVELS + 1];  /* level l = [off_l, off_{l+1}) */
   const uint32_t* nodes;
   const float* feat[ORA_MAX_LEVELS];         /* FP32 masters */
+  int32_t interp;                            /* ORA_INTERP_* */
 } ora_tree;
 
 typedef struct {
@@ -82,8 +90,27 @@ void ora_octa_decode(const double* st, int64_t B, double* dir_out);
  * weights [B][4]. */
 void ora_taps(const double* st, int64_t B, int32_t R, int32_t* ij_out, double* w_out);
 
+/* Entries of one node's map: R^2 texels, or (R + 1)^2 vertices with
+ * ORA_INTERP_PAPER. */
+int64_t ora_map_entries(int32_t R, int32_t interp);
+
+/* Barycentric vertex lookup (Sec. 3.3) at map resolution R (cells per side):
+ * the three vertices (i, j) of the triangle holding (s, t), as found on the
+ * unfolded grid [B][3][2], their weights [B][3], and each vertex's
+ * canonical storage index j * (R + 1) + i after the seam identification
+ * [B][3]. */
+void ora_bary(const double* st, int64_t B, int32_t R, int32_t* ij_out, double* w_out, int32_t* vidx_out);
+
+/* The eight octree cells around x at level l (Sec. 3.4): global node index
+ * of each (-1 where the cell is empty or outside the cube) [B][8], integer
+ * cell coordinates [B][8][3], and trilinear weights renormalised over the
+ * non-empty cells [B][8] (all zero when every cell is empty). Corner
+ * d = dx | dy << 1 | dz << 2. */
+void ora_neighbours(const ora_tree* t, const float* x, int64_t B, int32_t l, int32_t* idx_out,
+                    int64_t* cell_out, double* w_out);
+
 /* Concatenated per-level features h [B][L*C] and node indices [B][L]
- * (idx_out may be NULL). */
+ * (idx_out may be NULL; the containing node per level in both schemes). */
 void ora_encode(const ora_tree* t, const float* x, const float* dir, int64_t B,
                 double* h_out, int32_t* idx_out);
 

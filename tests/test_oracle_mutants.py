@@ -32,7 +32,19 @@ MUTANTS = {
     "relu_mask_missing": ("if (i > 0 && !(pre[i - 1][k] > 0.0)) s = 0.0;", ""),
     "scatter_wrong_tap_weight": ("dfeat[l][base + c] += qt->w[l][k] * dh[l * C + c];",
                                  "dfeat[l][base + c] += 0.25 * dh[l * C + c];"),
-    "node_offset_dropped": ("int64_t local = (int64_t)idx - t->level_offset[l];", "int64_t local = 0;"),
+    "node_offset_dropped": ("int64_t local = (int64_t)idx - t->level_offset[l];\n  return ((local * R + j) * R + i) * t->C;",
+                            "int64_t local = 0;\n  return ((local * R + j) * R + i) * t->C;"),
+    # the paper's interpolation (Sec. 3.3 vertex maps, Sec. 3.4 8-cell blend)
+    "paper_node_offset_dropped": ("int64_t local = (int64_t)idx - t->level_offset[l];\n  return (local * ora_map_entries",
+                                  "int64_t local = 0;\n  return (local * ora_map_entries"),
+    "bary_diagonal_flipped": ("int same_side = (2 * i >= R) == (2 * j >= R);",
+                              "int same_side = (2 * i >= R) != (2 * j >= R);"),
+    "bary_weight_swapped": ("v[1][0] = i + 1; v[1][1] = j;     w[1] = fu;", "v[1][0] = i + 1; v[1][1] = j;     w[1] = fv;"),
+    "vertex_seam_not_shared": ("  if (i == 0 || i == R) j = j < R - j ? j : R - j;\n", ""),
+    "trilinear_not_renormalised": ("for (int d = 0; d < 8; ++d) w[d] = sum > 0.0 ? w[d] / sum : 0.0;", ""),
+    "trilinear_centre_offset_dropped": ("double p = xa * ldexp(1.0, l) - 0.5;", "double p = xa * ldexp(1.0, l);"),
+    "paper_scatter_wrong_weight": ("          for (int32_t c = 0; c < C; ++c) dfeat[l][base + c] += wk * dh[l * C + c];",
+                                   "          for (int32_t c = 0; c < C; ++c) dfeat[l][base + c] += qt->vw[l][k] * dh[l * C + c];"),
     "scatter_into_first_node": ("int64_t base = texel_base(t, l, qt->idx[l], qt->ij[l][2 * k], qt->ij[l][2 * k + 1]);\n"
                                 "      for (int32_t c = 0; c < C; ++c) dfeat",
                                 "int64_t base = texel_base(t, l, (int32_t)t->level_offset[l], qt->ij[l][2 * k], "
