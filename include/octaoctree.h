@@ -14,12 +14,23 @@
  *    from predictions at secondary hits.
  *  - Sec. 3.6: the target is detached from the gradient.
  *
- * Where the paper leaves a choice open, this library takes these readings:
- *  - Each level reads the node that contains x (no 8-cell trilinear blend).
- *  - Each map has R x R texels, read by a bilinear fetch at texel centres.
- *    The octahedral seams are glued: the edges s = 0 and s = 1 each meet
+ * Two interpolation schemes per level (oo_tree.interp):
+ *  - OO_INTERP_NODE_BILINEAR: each level reads the node that contains x
+ *    (the paper's "no octree interpolation" variant, Sec. 4.4). Each map
+ *    has R x R texels, read by a bilinear fetch at texel centres. The
+ *    octahedral seams are glued: the edges s = 0 and s = 1 each meet
  *    themselves with t mirrored, and the edges t = 0 and t = 1 with s
- *    mirrored. The barycentric vertex lookup is not used.
+ *    mirrored.
+ *  - OO_INTERP_PAPER: the paper's own scheme. The eight octree cells whose
+ *    centres surround x are weighted trilinearly, renormalised over the
+ *    cells that exist (Sec. 3.4, level-feature equation). Each is read by
+ *    the barycentric lookup of Sec. 3.3 on a map of (R+1) x (R+1)
+ *    vertices. Every grid cell of the map is split along the diagonal
+ *    parallel to its quadrant's equator segment, so triangles follow the
+ *    octahedron's faces. Border vertices that are one direction share one
+ *    slot (the lower index along the edge; the four corners use slot 0).
+ *    All eight cells use the same direction: there is no disparity
+ *    predictor.
  *  - The decoder reads h only.
  *  - The BSDF is Lambert plus GGX.
  *
@@ -79,9 +90,16 @@ typedef enum { OO_F32 = 0, OO_F16 = 1, OO_BF16 = 2 } oo_dtype;
  *    word = (first_child << 8) | child_mask. Bit o of the mask is set when
  *    the child in octant o = bx | by << 1 | bz << 2 exists. first_child is
  *    the global index of the lowest existing child. A leaf's word is 0.
- *  - feat[l]: level-l table [n_l][res][res][C] of feat_dtype. Row index is
- *    t (v), column index is s (u), channels contiguous. 16-byte aligned.
+ *  - feat[l]: level-l table of feat_dtype, channels contiguous, 16-byte
+ *    aligned. Row index is t (v), column index is s (u).
+ *    OO_INTERP_NODE_BILINEAR: [n_l][res][res][C] texels.
+ *    OO_INTERP_PAPER: [n_l][res + 1][res + 1][C] vertices. Vertex (i, j)
+ *    sits at (s, t) = (i / res, j / res). A border vertex that repeats
+ *    another's direction is never read.
+ *  - interp: OO_INTERP_NODE_BILINEAR (0) or OO_INTERP_PAPER (1).
  */
+#define OO_INTERP_NODE_BILINEAR 0
+#define OO_INTERP_PAPER 1
 typedef struct {
   int32_t n_levels;
   int32_t C;
@@ -90,6 +108,7 @@ typedef struct {
   const uint32_t* nodes;
   oo_dtype feat_dtype;
   const void* feat[OO_MAX_LEVELS];
+  int32_t interp;
 } oo_tree;
 
 /*
@@ -129,13 +148,16 @@ int oo_build_octree(const float* samples_xyz_host, int64_t n, int32_t max_depth,
                     int64_t* level_offset_out_host, int64_t* n_nodes_out_host);
 
 /*
- * Encoding query: the node containing x at every level, the octahedral
- * coordinate of dir, and a bilinear fetch per level (Sec. 3.3-3.4).
+ * Encoding query (Sec. 3.3-3.4): the octahedral coordinate of dir and, per
+ * level, the interpolated feature of the tree's scheme.
  *  - x, dir: [B][3] FP32.
  *  - h_out: [B][n_levels * C] in h_dtype. Level-major, channels contiguous.
- *    A level without a node contributes zeros.
- *  - node_idx_out: [B][n_levels] global node index per level, -1 where the
- *    tree has no node. May be NULL.
+ *    A level with no node to read contributes zeros.
+ *  - node_idx_out: may be NULL. OO_INTERP_NODE_BILINEAR: [B][n_levels], the
+ *    global node index per level, -1 where the tree has no node.
+ *    OO_INTERP_PAPER: [B][n_levels][8], the nodes of the eight cells around
+ *    x, -1 for an empty cell or one outside the cube. Corner d = dx | dy << 1
+ *    | dz << 2; its cell is floor(x 2^l - 1/2) + (dx, dy, dz).
  */
 int oo_encode_query(const oo_tree* tree, const float* x, const float* dir, int64_t B, void* h_out,
                     oo_dtype h_dtype, int32_t* node_idx_out, hipStream_t stream);
@@ -261,7 +283,9 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
  * level), read back from the workspace in the caller's query order.
  *  - tree, mlp, batch: as passed to the forward; workspace: the one it
  *    filled, unchanged since (its size is checked as in the forward).
- *  - node_idx_out: [Qb][n_levels] int32, -1 where the tree has no node.
+ *  - node_idx_out: [Qb][n_levels] int32, -1 where the tree has no node
+ *    (OO_INTERP_PAPER: [Qb][n_levels][8], the eight neighbouring cells'
+ *    nodes as in oo_encode_query).
  *    Qb = B (the LHS queries) with the target detached, B (1 + N) with
  *    grad_through_rhs (LHS queries first, then query (b, k) at B + b N + k).
  *  - The indices are those the fused query kernel computed during the

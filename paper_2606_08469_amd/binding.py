@@ -35,7 +35,12 @@ class OOError(RuntimeError):
 class _Tree(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("C", C.c_int32), ("res", C.c_int32 * MAX_LEVELS),
                 ("level_offset", C.c_int64 * (MAX_LEVELS + 1)), ("nodes", C.c_void_p),
-                ("feat_dtype", C.c_int32), ("feat", C.c_void_p * MAX_LEVELS)]
+                ("feat_dtype", C.c_int32), ("feat", C.c_void_p * MAX_LEVELS), ("interp", C.c_int32)]
+
+
+# Level-feature interpolation schemes (oo_tree.interp).
+INTERP_NODE_BILINEAR = 0  # containing node, bilinear on R x R texels
+INTERP_PAPER = 1          # 8 cells trilinear (renormalised), barycentric on (R+1)^2 vertices
 
 
 class _MLP(C.Structure):
@@ -139,12 +144,19 @@ def build_octree(samples, max_depth: int, split_threshold: int):
 class Tree:
     """Octree on the device plus one feature table per level."""
 
-    def __init__(self, nodes, level_offset, res, C_, feat):
+    def __init__(self, nodes, level_offset, res, C_, feat, interp=INTERP_NODE_BILINEAR):
         self.nodes = torch.from_numpy(np.asarray(nodes, np.uint32).view(np.int32)).cuda()
         self.level_offset = [int(v) for v in level_offset]
         self.res = [int(r) for r in res]
         self.C = int(C_)
+        self.interp = int(interp)
         self.feat = [f if isinstance(f, torch.Tensor) else _dev(f) for f in feat]
+
+    @property
+    def corners(self):
+        """Node indices per level of one query: 1, or the 8 neighbouring
+        cells in the paper's scheme."""
+        return 8 if self.interp == INTERP_PAPER else 1
 
     @property
     def n_levels(self):
@@ -163,6 +175,7 @@ class Tree:
         t.feat_dtype = DTYPE_CODE[feat[0].dtype]
         for l, f in enumerate(feat):
             t.feat[l] = f.data_ptr() if f.numel() else None
+        t.interp = self.interp
         return t
 
 
@@ -215,7 +228,8 @@ def batch_struct(b: dict):
 def encode_query(tree: Tree, x, d, h_dtype=torch.float32, with_idx=True, feat=None):
     B = x.shape[0]
     h = torch.empty((B, tree.n_levels * tree.C), dtype=h_dtype, device="cuda")
-    idx = torch.empty((B, tree.n_levels), dtype=torch.int32, device="cuda") if with_idx else None
+    shape = (B, tree.n_levels) if tree.corners == 1 else (B, tree.n_levels, tree.corners)
+    idx = torch.empty(shape, dtype=torch.int32, device="cuda") if with_idx else None
     ts = tree.struct(feat)
     _check(lib().oo_encode_query(C.byref(ts), _ptr(x), _ptr(d), B, _ptr(h), DTYPE_CODE[h_dtype], _ptr(idx),
                                  _stream()), "oo_encode_query")
@@ -275,12 +289,14 @@ def residual_bwd(tree: Tree, mlp: MLP, batch: dict, resid, rhs, grad_loss, dfeat
 
 def residual_node_indices(tree: Tree, mlp: MLP, batch: dict, workspace, feat=None, W=None):
     """Node index per level of every backward query, as the forward stored
-    it in the workspace: int32 [Qb][L] in the caller's query order."""
+    it in the workspace: int32 [Qb][L] (paper's scheme: [Qb][L][8]) in the
+    caller's query order."""
     ts, ms, bs = tree.struct(feat), mlp.struct(W), batch_struct(batch)
     B, N = int(bs.B), int(bs.N)
     full = bs.grad_through_rhs and batch.get("target_override") is None and N > 0
     Qb = B * (1 + N) if full else B
-    out = torch.full((Qb, tree.n_levels), -2, dtype=torch.int32, device="cuda")
+    shape = (Qb, tree.n_levels) if tree.corners == 1 else (Qb, tree.n_levels, tree.corners)
+    out = torch.full(shape, -2, dtype=torch.int32, device="cuda")
     _check(lib().oo_residual_node_indices(C.byref(ts), C.byref(ms), C.byref(bs), _ptr(workspace), _nbytes(workspace),
                                           _ptr(out), _stream()), "oo_residual_node_indices")
     return out
@@ -379,7 +395,7 @@ class OctaOctree(torch.nn.Module):
     Masters and working copies each live in one flat buffer with the same
     aligned layout, so a refresh is a single cast launch over the buffer."""
 
-    def __init__(self, nodes, level_offset, res, C_, feat, W, b, dtype=torch.float32):
+    def __init__(self, nodes, level_offset, res, C_, feat, W, b, dtype=torch.float32, interp=INTERP_NODE_BILINEAR):
         super().__init__()
         self.dtype = dtype
         shapes = [tuple(np.shape(f)) for f in feat] + [tuple(np.shape(w)) for w in W]
@@ -395,7 +411,7 @@ class OctaOctree(torch.nn.Module):
         self.feat = torch.nn.ParameterList(views[:nf])
         self.W = torch.nn.ParameterList(views[nf:])
         self.b = torch.nn.ParameterList([torch.nn.Parameter(_dev(v)) for v in b])
-        self.tree = Tree(nodes, level_offset, res, C_, list(self.feat))
+        self.tree = Tree(nodes, level_offset, res, C_, list(self.feat), interp=interp)
         self.mlp = MLP(list(self.W), list(self.b))
         self._ws = None
         self._work = None

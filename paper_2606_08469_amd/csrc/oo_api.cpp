@@ -113,11 +113,14 @@ int check_tree(const oo_tree* t, TreeArgs& A) {
   if (t->feat_dtype != OO_F32 && t->feat_dtype != OO_F16 && t->feat_dtype != OO_BF16)
     return fail(OO_EINVAL, "unknown feat_dtype %d", (int)t->feat_dtype);
   if (!t->nodes) return fail(OO_EINVAL, "nodes is NULL");
+  if (t->interp != OO_INTERP_NODE_BILINEAR && t->interp != OO_INTERP_PAPER)
+    return fail(OO_EINVAL, "interp must be OO_INTERP_NODE_BILINEAR or OO_INTERP_PAPER, got %d", t->interp);
   if (t->level_offset[0] != 0 || t->level_offset[1] != 1)
     return fail(OO_EINVAL, "level_offset must start 0, 1 (one root node)");
   A.L = t->n_levels;
   A.C = t->C;
   A.D = t->n_levels - 1;
+  A.interp = t->interp;
   A.nodes = t->nodes;
   for (int l = 0; l < OO_MAX_LEVELS; ++l) {
     A.res[l] = 2;
@@ -208,7 +211,8 @@ int check_batch(const oo_residual_batch* b, ResidualArgs& A) {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Workspace {
-  size_t Lq, lossp, seeds, nidx, uv, dh, wt[OO_MAX_LAYERS], dwp, order, rank, scount, stotal, sstart, gpad, total;
+  size_t Lq, lossp, seeds, nidx, uv, pos, dh, wt[OO_MAX_LAYERS], dwp, order, rank, scount, stotal, sstart, gpad, total;
+  int K;  // node indices stored per level and backward query: 1, or 8 corners in the paper's scheme
   int64_t pad_off[OO_MAX_LEVELS];  // float offset of each level's pair buffer in gpad, or -1
   int64_t pad_total;               // floats in gpad
   int64_t Qb;
@@ -255,10 +259,16 @@ Workspace workspace_layout(const MlpArgs& M, oo_dtype md, const oo_residual_batc
   w.seeds = o;
   o = align256(o + (size_t)Qb * 3 * sizeof(float));
   w.Qb = Qb;
-  w.nidx = o;  // node index per level of every backward query, written by the forward, [L][Qb]
-  o = align256(o + (size_t)Qb * L * sizeof(int32_t));
+  const bool paper = tree->interp == OO_INTERP_PAPER;
+  w.K = paper ? 8 : 1;
+  // node index per level of every backward query, written by the forward,
+  // [L][Qb] (paper's scheme: the eight corner cells' nodes, [L][8][Qb])
+  w.nidx = o;
+  o = align256(o + (size_t)Qb * L * w.K * sizeof(int32_t));
   w.uv = o;  // octahedral coordinates of every backward query, written by the forward, [Qb]
   o = align256(o + (size_t)Qb * sizeof(float2));
+  w.pos = o;  // paper's scheme: position of every backward query, [Qb]
+  o = align256(o + (paper ? (size_t)Qb * sizeof(float4) : 0));
   w.dh = o;  // dLoss/dh of every backward query, [Qb][K0] FP32
   o = align256(o + (size_t)Qb * M.K0 * sizeof(float));
   const size_t esz = md == OO_F32 ? 4 : 2;
@@ -283,7 +293,7 @@ Workspace workspace_layout(const MlpArgs& M, oo_dtype md, const oo_residual_batc
   // coarse-level pair buffers of the feature-gradient scatter
   w.gpad = o;
   w.pad_total = 0;
-  bool open = tree->C == 8;
+  bool open = tree->C == 8 && !paper;  // the paper's scheme scatters to vertices directly
   for (int l = 0; l < OO_MAX_LEVELS; ++l) {
     w.pad_off[l] = -1;
     if (l >= L || !open) continue;
@@ -480,7 +490,8 @@ int oo_query_fwd(const oo_tree* tree, const oo_mlp* mlp, const float* x, const f
   if (!x || !dir || !rgb_out) return fail(OO_EINVAL, "x, dir and rgb_out are required");
   QuerySrc src{x, dir, B, x, dir};
   ProfScope ps(OO_PROF_QUERY, stream);
-  return hip_status(launch_query(T, tree->feat_dtype, M, mlp->dtype, src, B, rgb_out, nullptr, nullptr, 0, stream),
+  return hip_status(launch_query(T, tree->feat_dtype, M, mlp->dtype, src, B, rgb_out, nullptr, nullptr, nullptr, 0,
+                                 stream),
                     "query_fwd launch");
 }
 
@@ -542,7 +553,7 @@ int oo_radiosity_residual_fwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   {
     ProfScope ps(OO_PROF_QUERY, stream);
     e = launch_query(T, tree->feat_dtype, M, mlp->dtype, sorted, Q, Lq, nidx, reinterpret_cast<float2*>(ws + w.uv),
-                     w.Qb, stream);
+                     reinterpret_cast<float4*>(ws + w.pos), w.Qb, stream);
   }
   if (e != hipSuccess) return hip_status(e, "residual query launch");
   ProfScope ps(OO_PROF_COMBINE, stream);
@@ -607,6 +618,7 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   // octahedral coordinates were stored at those positions
   const int32_t* order = reinterpret_cast<const int32_t*>(ws + w.order);
   const float2* uv = reinterpret_cast<const float2*>(ws + w.uv);
+  const float4* pos = reinterpret_cast<const float4*>(ws + w.pos);
   float* dh = reinterpret_cast<float*>(ws + w.dh);
   const int nc = bwd_chunks(Qb);
   const int64_t chunk = ((Qb + nc - 1) / nc + 63) / 64 * 64;  // whole 64-query tiles
@@ -617,7 +629,7 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
     for (int c = 0; c < nc; ++c) {
       const int64_t q0 = c * chunk, qn = std::min(Qb - q0, chunk);
       if (qn <= 0) break;
-      BwdArgs B{qn, nidx + q0, Qb, uv + q0, seeds, order + q0, Qb, partials, dh + q0 * M.K0, c > 0};
+      BwdArgs B{qn, nidx + q0, Qb, uv + q0, pos + q0, seeds, order + q0, Qb, partials, dh + q0 * M.K0, c > 0};
       {
         ProfScope ps(OO_PROF_BACKWARD, stream);
         e = launch_bwd(T, tree->feat_dtype, M, mlp->dtype, Wt, B, w.PL, w.grid, stream);
@@ -631,7 +643,7 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
       }
       {
         ProfScope ps(OO_PROF_SCATTER, ss);
-        e = launch_scatter(T, qn, nidx + q0, Qb, uv + q0, dh + q0 * M.K0, post_scale, G, ss);
+        e = launch_scatter(T, qn, nidx + q0, Qb, uv + q0, pos + q0, dh + q0 * M.K0, post_scale, G, ss);
       }
       if (e != hipSuccess) return hip_status(e, "scatter launch");
     }
@@ -675,7 +687,7 @@ int oo_residual_node_indices(const oo_tree* tree, const oo_mlp* mlp, const oo_re
   if (!node_idx_out) return fail(OO_EINVAL, "node_idx_out is required");
   const char* ws = static_cast<const char*>(workspace);
   return hip_status(launch_saved_nodes(reinterpret_cast<const int32_t*>(ws + w.nidx),
-                                       reinterpret_cast<const int32_t*>(ws + w.order), w.Qb, tree->n_levels,
+                                       reinterpret_cast<const int32_t*>(ws + w.order), w.Qb, tree->n_levels, w.K,
                                        node_idx_out, stream),
                     "node index readback launch");
 }

@@ -189,7 +189,7 @@ __device__ inline void store_tq(MT* buf, const f32x4 (&acc)[MT2], int m0, int n_
 // W_0^T and W_0 are packed into LDS once per workgroup (their per-tile
 // fragment loads from L2 dominated the layer chains); the output layer's
 // weights are read from L2.
-template <class TT, class MT, int C, int H, bool WL>
+template <class TT, class MT, int C, int H, bool WL, bool PAPER>
 __global__ __launch_bounds__(64 * bwd_waves<MT>()) void bwd_kernel(const TreeArgs T, const MlpArgs M, const MlpArgs Mt,
                                                              const BwdArgs A, const ParamLayout PL) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -275,22 +275,50 @@ __global__ __launch_bounds__(64 * bwd_waves<MT>()) void bwd_kernel(const TreeArg
       // this lane's levels part, part + kLanesPerQuery, ...: all their
       // gathers in flight
       constexpr int G = kMaxLevels / kLanesPerQuery;
-      int lidx[G];
+      if constexpr (PAPER) {
+        // the eight corner nodes per level come from the forward ([L][8][Q]),
+        // the trilinear weights from the stored position
+        const float4 xp = q < Q ? A.pos[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float xq[3] = {xp.x, xp.y, xp.z};
 #pragma unroll
-      for (int gi = 0; gi < G; ++gi) {
-        const int l = part + kLanesPerQuery * gi;
-        int v = (l < L && q < Q) ? nidx[(int64_t)l * ldn + q] : -1;  // nidx is level-major [L][Q]
-        if (l < L && (v < T.off[l] || v >= T.off[l + 1])) v = -1;  // never index outside level l
-        lidx[gi] = v;
-      }
-      float h[G][C];
-      gather_levels<TT, C, G, kLanesPerQuery>(T, part, lidx, s, t, h);
+        for (int gi = 0; gi < G; ++gi) {
+          const int l = part + kLanesPerQuery * gi;
+          if (l < L) {
+            int node[8];
 #pragma unroll
-      for (int gi = 0; gi < G; ++gi) {
-        const int l = part + kLanesPerQuery * gi;
-        if (l < L) {
+            for (int d = 0; d < 8; ++d) {
+              int v = q < Q ? nidx[((int64_t)l * 8 + d) * ldn + q] : -1;
+              node[d] = (v < T.off[l] || v >= T.off[l + 1]) ? -1 : v;  // never index outside level l
+            }
+            int base[3], slot[3];
+            float f[3], wc[8], wv[3], h[C];
 #pragma unroll
-          for (int c = 0; c < C; ++c) act0[tq_index(l * C + c, ql)] = from_f32<MT>(h[gi][c]);
+            for (int a = 0; a < 3; ++a) cell_frac(xq[a], l, base[a], f[a]);
+            corner_weights(f, node, wc);
+            bary(s, t, T.res[l], slot, wv);
+            gather_paper_level<TT, C>(T, l, node, wc, slot, wv, h);
+#pragma unroll
+            for (int c = 0; c < C; ++c) act0[tq_index(l * C + c, ql)] = from_f32<MT>(h[c]);
+          }
+        }
+      } else {
+        int lidx[G];
+#pragma unroll
+        for (int gi = 0; gi < G; ++gi) {
+          const int l = part + kLanesPerQuery * gi;
+          int v = (l < L && q < Q) ? nidx[(int64_t)l * ldn + q] : -1;  // nidx is level-major [L][Q]
+          if (l < L && (v < T.off[l] || v >= T.off[l + 1])) v = -1;  // never index outside level l
+          lidx[gi] = v;
+        }
+        float h[G][C];
+        gather_levels<TT, C, G, kLanesPerQuery>(T, part, lidx, s, t, h);
+#pragma unroll
+        for (int gi = 0; gi < G; ++gi) {
+          const int l = part + kLanesPerQuery * gi;
+          if (l < L) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) act0[tq_index(l * C + c, ql)] = from_f32<MT>(h[gi][c]);
+          }
         }
       }
     }
@@ -651,7 +679,9 @@ static hipError_t launch_bwd_t(const TreeArgs& T, const MlpArgs& M, const MlpArg
                                const ParamLayout& PL, int grid, hipStream_t st) {
   bool wl;
   const size_t lds = bwd_lds_total(M.K0, H, M.n_layers, T.L, (int)sizeof(MT), wl);
-  auto k = wl ? bwd_kernel<TT, MT, C, H, true> : bwd_kernel<TT, MT, C, H, false>;
+  const bool paper = T.interp == OO_INTERP_PAPER;
+  auto k = wl ? (paper ? bwd_kernel<TT, MT, C, H, true, true> : bwd_kernel<TT, MT, C, H, true, false>)
+              : (paper ? bwd_kernel<TT, MT, C, H, false, true> : bwd_kernel<TT, MT, C, H, false, false>);
   hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k, dim3(grid), dim3(64 * bwd_waves<MT>()), lds, st, T, M, Mt, A, PL);
   return hipGetLastError();
@@ -732,10 +762,72 @@ __global__ __launch_bounds__(256) void scatter_kernel(const TreeArgs T, int64_t 
   }
 }
 
+// Feature-gradient scatter of the paper's scheme: 8 C lanes per (query,
+// level), one per (corner, channel), corner-major. A lane adds
+// w_corner * w_vertex * dh[q][l C + c] * post_scale to the three vertices
+// its corner's cell reads. The renormalisation needs to know which of the
+// query's eight corners exist: one ballot over the wave, read at this
+// lane's group of 8 C lanes (all lanes of a group share the query, so they
+// run the loop the same number of times). Corner nodes come from the
+// forward ([L][8][Q], range-checked), positions and octahedral coordinates
+// too; weights are recomputed.
+template <int C>
+__global__ __launch_bounds__(256) void scatter_paper_kernel(const TreeArgs T, int64_t Q,
+                                                            const int32_t* __restrict__ nidx, int64_t ldn,
+                                                            const float2* __restrict__ uv,
+                                                            const float4* __restrict__ pos,
+                                                            const float* __restrict__ dh, float post_scale,
+                                                            const GradArgs G) {
+  constexpr int U = 8 * C;
+  static_assert(64 % U == 0, "a lane group must not straddle waves");
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x, n = Q * U;
+  const int gbase = (int)(threadIdx.x & 63) / U * U;
+  for (int l = 0; l < T.L; ++l) {
+    const int R = T.res[l];
+    const int64_t E = (int64_t)(R + 1) * (R + 1);
+    float* const dst = G.dfeat[l];
+    for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < n; gid += stride) {
+      const int64_t q = gid / U;
+      const int d = (int)(gid / C) & 7;
+      const int c = (int)(gid % C);
+      const int id = nidx[((int64_t)l * 8 + d) * ldn + q];
+      const bool ok = id >= T.off[l] && id < T.off[l + 1];
+      const uint64_t gb = __ballot(ok) >> gbase;
+      int node[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) node[e] = ((gb >> (e * C)) & 1u) ? 0 : -1;
+      if (!ok) continue;
+      const float4 xp = pos[q];
+      const float xq[3] = {xp.x, xp.y, xp.z};
+      int base[3], slot[3];
+      float f[3], wc[8], wv[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) cell_frac(xq[a], l, base[a], f[a]);
+      corner_weights(f, node, wc);
+      const float2 p = uv[q];
+      bary(fminf(fmaxf(p.x, 0.0f), 1.0f), fminf(fmaxf(p.y, 0.0f), 1.0f), R, slot, wv);
+      const float gv = dh[q * (int64_t)(T.L * C) + l * C + c] * post_scale * pick8(wc, d);
+      const int64_t nb = ((int64_t)id - T.off[l]) * E;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) unsafeAtomicAdd(dst + (nb + slot[k]) * C + c, wv[k] * gv);
+    }
+  }
+}
+
 hipError_t launch_scatter(const TreeArgs& T, int64_t Q, const int32_t* nidx, int64_t ldn, const float2* uv,
-                          const float* dh,
-                          float post_scale, const GradArgs& G, hipStream_t st) {
+                          const float4* pos, const float* dh, float post_scale, const GradArgs& G, hipStream_t st) {
   if (Q == 0) return hipSuccess;
+  if (T.interp == OO_INTERP_PAPER) {
+    int64_t blocks = (Q * 8 * T.C + 255) / 256;
+    if (blocks > 256 * 16) blocks = 256 * 16;
+    if (T.C == 4)
+      hipLaunchKernelGGL(scatter_paper_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, st, T, Q, nidx, ldn, uv, pos,
+                         dh, post_scale, G);
+    else
+      hipLaunchKernelGGL(scatter_paper_kernel<8>, dim3((unsigned)blocks), dim3(256), 0, st, T, Q, nidx, ldn, uv, pos,
+                         dh, post_scale, G);
+    return hipGetLastError();
+  }
   // a persistent grid walks every level: block scheduling stays out of the
   // way of the atomic stream
   int64_t blocks = (Q * 4 * T.C + 255) / 256;

@@ -18,6 +18,7 @@ constexpr int kWave = 64;
 // table so that predicated dummy loads stay in bounds).
 struct TreeArgs {
   int32_t L, C, D;
+  int32_t interp;  // OO_INTERP_NODE_BILINEAR or OO_INTERP_PAPER
   int32_t res[kMaxLevels];
   int64_t off[kMaxLevels + 1];
   const uint32_t* nodes;
@@ -374,6 +375,209 @@ __device__ inline void encode_pipelined(const TreeArgs& T, bool valid, const flo
 #pragma unroll
   for (int c = 0; c < C; ++c) z[c] = 0.0f;
   for (; l < L; ++l) put(l, z, -1);
+}
+
+// ---------------------------------------------------------------------------
+// The paper's scheme: the eight cells whose centres surround x, weighted
+// trilinearly and renormalised over the cells that exist, each read by a
+// barycentric lookup on a vertex map
+// ---------------------------------------------------------------------------
+
+// Along one axis at level l: the lower of the two cells around x (cell
+// centres at (c + 1/2) 2^-l) and the trilinear fraction towards the upper
+// one. x is clamped to the cube (fmaxf maps NaN to 0). x 2^l is exact, and
+// so is the subtraction of 1/2 whenever x 2^l >= 1/2; below that the result
+// lies in [-1/2, 0) and its floor is -1 however it rounds.
+__device__ inline void cell_frac(float xa, int l, int& base, float& f) {
+  const float xc = fminf(fmaxf(xa, 0.0f), 1.0f);
+  const float p = xc * (float)(1u << l) - 0.5f;
+  const float fl = floorf(p);
+  base = (int)fl;
+  f = p - fl;
+}
+
+// v[i] for a lane-varying i in [0, 8) without indexing a register array
+// (which would spill it to scratch memory).
+template <class V>
+__device__ inline V pick8(const V v[8], int i) {
+  const V a = (i & 1) ? v[1] : v[0], b = (i & 1) ? v[3] : v[2];
+  const V c = (i & 1) ? v[5] : v[4], d = (i & 1) ? v[7] : v[6];
+  const V ab = (i & 2) ? b : a, cd = (i & 2) ? d : c;
+  return (i & 4) ? cd : ab;
+}
+
+// Nodes of the eight cells around x at level l >= 1 (corner d = dx | dy << 1
+// | dz << 2 is cell base + (dx, dy, dz)), from the previous level's eight:
+// a cell's parent is one of them, at corner ((cell >> 1) - pbase) per axis,
+// which is 0 or 1. pnode/pword: the previous level's nodes (-1 if none) and
+// their node words. Cells outside the cube, or whose parent has no such
+// child, get -1.
+__device__ inline void corners_next(int l, const int base[3], const int pbase[3], const int pnode[8],
+                                    const uint32_t pword[8], int node[8]) {
+  const unsigned n = 1u << l;
+#pragma unroll
+  for (int d = 0; d < 8; ++d) {
+    const int cx = base[0] + (d & 1), cy = base[1] + ((d >> 1) & 1), cz = base[2] + (d >> 2);
+    const bool in = (unsigned)cx < n && (unsigned)cy < n && (unsigned)cz < n;
+    const int pd = (((cx >> 1) - pbase[0]) & 1) | ((((cy >> 1) - pbase[1]) & 1) << 1) | ((((cz >> 1) - pbase[2]) & 1) << 2);
+    const int pn = pick8(pnode, pd);
+    const uint32_t w = pick8(pword, pd);
+    const int o = (cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2);
+    const uint32_t m = w & 0xffu;
+    node[d] = (in && pn >= 0 && ((m >> o) & 1u)) ? (int)(w >> 8) + __popc(m & ((1u << o) - 1u)) : -1;
+  }
+}
+
+// Level-0 corners: only the root cell (0, 0, 0) exists.
+__device__ inline void corners_root(bool valid, const int base[3], int node[8]) {
+#pragma unroll
+  for (int d = 0; d < 8; ++d) {
+    const bool root = base[0] + (d & 1) == 0 && base[1] + ((d >> 1) & 1) == 0 && base[2] + (d >> 2) == 0;
+    node[d] = valid && root ? 0 : -1;
+  }
+}
+
+// Trilinear weights of the corners that have a node, divided by their sum
+// (all zero when none has one).
+__device__ inline void corner_weights(const float f[3], const int node[8], float w[8]) {
+  float sum = 0.0f;
+#pragma unroll
+  for (int d = 0; d < 8; ++d) {
+    const float wx = (d & 1) ? f[0] : 1.0f - f[0];
+    const float wy = ((d >> 1) & 1) ? f[1] : 1.0f - f[1];
+    const float wz = (d >> 2) ? f[2] : 1.0f - f[2];
+    w[d] = node[d] >= 0 ? wx * wy * wz : 0.0f;
+    sum += w[d];
+  }
+  const float inv = sum > 0.0f ? 1.0f / sum : 0.0f;
+#pragma unroll
+  for (int d = 0; d < 8; ++d) w[d] *= inv;
+}
+
+// Storage slot of vertex (i, j) of an (R+1) x (R+1) map: a border vertex
+// that is the same direction as another (edges s = 0 and s = 1 glued to
+// themselves with t mirrored, t = 0 and t = 1 with s mirrored, corners the
+// -z pole) uses the slot of the one with the lower index along the edge.
+__device__ inline int vertex_slot(int i, int j, int R) {
+  if (i == 0 || i == R) j = min(j, R - j);
+  if (j == 0 || j == R) i = min(i, R - i);
+  return j * (R + 1) + i;
+}
+
+// Barycentric lookup at (s, t) in [0, 1]^2 on a map of R x R grid cells:
+// the cell is split along the diagonal parallel to its quadrant's equator
+// segment (anti-diagonal where s - 1/2 and t - 1/2 have the same sign, main
+// diagonal otherwise), so the triangle lies in one octahedron face.
+__device__ inline void bary(float s, float t, int R, int slot[3], float w[3]) {
+  const float pu = s * (float)R, pv = t * (float)R;
+  const int i = min(max((int)floorf(pu), 0), R - 1), j = min(max((int)floorf(pv), 0), R - 1);
+  const float fu = pu - (float)i, fv = pv - (float)j;
+  const bool same = (2 * i >= R) == (2 * j >= R);
+  int i0, j0, i1, j1, i2, j2;
+  if (same) {
+    if (fu + fv <= 1.0f) {
+      i0 = i; j0 = j; w[0] = 1.0f - fu - fv;
+      i1 = i + 1; j1 = j; w[1] = fu;
+      i2 = i; j2 = j + 1; w[2] = fv;
+    } else {
+      i0 = i + 1; j0 = j + 1; w[0] = fu + fv - 1.0f;
+      i1 = i; j1 = j + 1; w[1] = 1.0f - fu;
+      i2 = i + 1; j2 = j; w[2] = 1.0f - fv;
+    }
+  } else {
+    if (fu >= fv) {
+      i0 = i; j0 = j; w[0] = 1.0f - fu;
+      i1 = i + 1; j1 = j; w[1] = fu - fv;
+      i2 = i + 1; j2 = j + 1; w[2] = fv;
+    } else {
+      i0 = i; j0 = j; w[0] = 1.0f - fv;
+      i1 = i; j1 = j + 1; w[1] = fv - fu;
+      i2 = i + 1; j2 = j + 1; w[2] = fu;
+    }
+  }
+  slot[0] = vertex_slot(i0, j0, R);
+  slot[1] = vertex_slot(i1, j1, R);
+  slot[2] = vertex_slot(i2, j2, R);
+}
+
+// Level feature of the paper's scheme: sum over the corners and the three
+// vertices of w_corner * w_vertex * T[node][slot]. Loads go out a batch of
+// corners at a time (12 entries of 16 bytes, or 6 of 32 bytes); corners
+// without a node read entry 0 of the level with weight 0.
+template <class TT, int C>
+__device__ inline void gather_paper_level(const TreeArgs& T, int l, const int node[8], const float wc[8],
+                                          const int slot[3], const float wv[3], float* h) {
+  typedef typename Texel<TT, C>::raw Raw;
+  constexpr int CB = sizeof(TT) * C > 16 ? 2 : 4;  // corners per batch
+  const int R = T.res[l];
+  const int64_t E = (int64_t)(R + 1) * (R + 1);
+  const TT* base = reinterpret_cast<const TT*>(T.feat[l]);
+#pragma unroll
+  for (int c = 0; c < C; ++c) h[c] = 0.0f;
+#pragma unroll
+  for (int b0 = 0; b0 < 8; b0 += CB) {
+    Raw r[CB][3];
+#pragma unroll
+    for (int dd = 0; dd < CB; ++dd) {
+      const int d = b0 + dd;
+      const bool ok = node[d] >= 0;
+      const int64_t nb = ok ? ((int64_t)node[d] - T.off[l]) * E : 0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) Texel<TT, C>::load(base + (ok ? (nb + slot[k]) * C : 0), r[dd][k]);
+    }
+#pragma unroll
+    for (int dd = 0; dd < CB; ++dd)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) Texel<TT, C>::acc(r[dd][k], wc[b0 + dd] * wv[k], h);
+  }
+}
+
+// Encoding of one query in the paper's scheme, level by level: the eight
+// corners' nodes follow from the previous level's (their node words are
+// loaded while this level's entries are gathered). put(l, h, node) receives
+// each level's C features and the eight corner nodes. Once no lane of the
+// wave has a corner left, deeper levels are empty too (their cells' parents
+// are among this level's corners) and get zeros.
+template <class TT, int C, class Put>
+__device__ inline void encode_paper(const TreeArgs& T, bool valid, const float x[3], float s, float t, Put&& put) {
+  const int L = T.L, D = T.D;
+  int base[3], pbase[3], node[8], pnode[8];
+  uint32_t pword[8];
+  float f[3];
+  int l = 0;
+  for (; l < L; ++l) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) cell_frac(x[a], l, base[a], f[a]);
+    if (l == 0)
+      corners_root(valid, base, node);
+    else
+      corners_next(l, base, pbase, pnode, pword, node);
+    bool any = false;
+#pragma unroll
+    for (int d = 0; d < 8; ++d) any |= node[d] >= 0;
+    if (!__any(any)) break;
+    // node words for the next level, then this level's entries
+#pragma unroll
+    for (int d = 0; d < 8; ++d) pword[d] = (l < D && node[d] >= 0) ? T.nodes[node[d]] : 0u;
+    float wc[8], wv[3];
+    int slot[3];
+    corner_weights(f, node, wc);
+    bary(s, t, T.res[l], slot, wv);
+    float h[C];
+    gather_paper_level<TT, C>(T, l, node, wc, slot, wv, h);
+    put(l, h, node);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) pbase[a] = base[a];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) pnode[d] = node[d];
+  }
+  float z[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) z[c] = 0.0f;
+  int none[8];
+#pragma unroll
+  for (int d = 0; d < 8; ++d) none[d] = -1;
+  for (; l < L; ++l) put(l, z, none);
 }
 
 // ---------------------------------------------------------------------------

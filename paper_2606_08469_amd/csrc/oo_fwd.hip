@@ -11,7 +11,7 @@ namespace oo {
 // ---------------------------------------------------------------------------
 // Standalone encoding: one thread per query, h written row-major to memory.
 // ---------------------------------------------------------------------------
-template <class TT, class HT, int C>
+template <class TT, class HT, int C, bool PAPER>
 __global__ __launch_bounds__(256) void encode_kernel(const TreeArgs T, const float* __restrict__ x,
                                                      const float* __restrict__ dir, int64_t B,
                                                      HT* __restrict__ h_out, int32_t* __restrict__ idx_out) {
@@ -24,6 +24,27 @@ __global__ __launch_bounds__(256) void encode_kernel(const TreeArgs T, const flo
       xq[a] = x[3 * q + a];
       dq[a] = dir[3 * q + a];
     }
+  }
+  typedef HT vC __attribute__((ext_vector_type(C)));
+  if constexpr (PAPER) {
+    // the eight cells around x per level, barycentric vertex maps
+    float s, t;
+    octa(dq, s, t);
+    const int L = T.L;
+    HT* hrow = h_out + (valid ? q : 0) * (int64_t)(L * C);
+    encode_paper<TT, C>(T, valid, xq, s, t, [&](int l, const float (&h)[C], const int (&node)[8]) {
+      if (!valid) return;
+      vC v;
+#pragma unroll
+      for (int c = 0; c < C; ++c) v[c] = from_f32<HT>(h[c]);
+      *reinterpret_cast<vC*>(hrow + l * C) = v;
+      if (idx_out) {
+        int4* o = reinterpret_cast<int4*>(idx_out + (q * L + l) * 8);
+        o[0] = make_int4(node[0], node[1], node[2], node[3]);
+        o[1] = make_int4(node[4], node[5], node[6], node[7]);
+      }
+    });
+    return;
   }
   int idx[kMaxLevels];
   descend(T, valid, xq, idx);
@@ -41,7 +62,6 @@ __global__ __launch_bounds__(256) void encode_kernel(const TreeArgs T, const flo
     for (int gi = 0; gi < 4; ++gi) {
       const int l = l0 + gi;
       if (l < L) {
-        typedef HT vC __attribute__((ext_vector_type(C)));
         vC v;
 #pragma unroll
         for (int c = 0; c < C; ++c) v[c] = from_f32<HT>(h[gi][c]);
@@ -208,10 +228,14 @@ __device__ inline void store_rgb(const f32x4 out[NT], int t0, int64_t q_base, in
 // Queries q < n_idx also store their node index per level in idx_out
 // (level-major [L][n_idx]) and their octahedral coordinates in uv_out, which
 // the residual backward reads instead of descending and mapping again.
-template <class TT, class MT, int C, int H, bool WLDS>
+// In the paper's scheme the stored indices are the eight corner cells'
+// nodes per level ([L][8][n_idx]) and the query's position is kept too
+// (pos_out, [n_idx]); the backward recomputes the trilinear weights from it.
+template <class TT, class MT, int C, int H, bool WLDS, bool PAPER>
 __global__ __launch_bounds__(512) void query_kernel(const TreeArgs T, const MlpArgs M, const QuerySrc src,
                                                     int64_t Q, float* __restrict__ rgb, int32_t* __restrict__ idx_out,
-                                                    float2* __restrict__ uv_out, int64_t n_idx) {
+                                                    float2* __restrict__ uv_out, float4* __restrict__ pos_out,
+                                                    int64_t n_idx) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   constexpr int NT = 2;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63, waves = blockDim.x >> 6;
@@ -237,11 +261,22 @@ __global__ __launch_bounds__(512) void query_kernel(const TreeArgs T, const MlpA
     octa(d, s, t);
     const bool keep = q < n_idx;
     if (keep) uv_out[q] = make_float2(s, t);
-    encode_pipelined<TT, C>(T, valid, x, s, t, [&](int l, const float* h, int node) {
+    if constexpr (PAPER) {
+      if (keep) pos_out[q] = make_float4(x[0], x[1], x[2], 0.0f);
+      encode_paper<TT, C>(T, valid, x, s, t, [&](int l, const float (&h)[C], const int (&node)[8]) {
 #pragma unroll
-      for (int c = 0; c < C; c += 4) htile_put4<MT>(htile, KB0, lane, l * C + c, &h[c]);
-      if (keep) idx_out[l * n_idx + q] = node;  // level-major: coalesced across lanes
-    });
+        for (int c = 0; c < C; c += 4) htile_put4<MT>(htile, KB0, lane, l * C + c, &h[c]);
+        if (keep)
+#pragma unroll
+          for (int d = 0; d < 8; ++d) idx_out[(l * 8 + d) * n_idx + q] = node[d];  // coalesced across lanes
+      });
+    } else {
+      encode_pipelined<TT, C>(T, valid, x, s, t, [&](int l, const float* h, int node) {
+#pragma unroll
+        for (int c = 0; c < C; c += 4) htile_put4<MT>(htile, KB0, lane, l * C + c, &h[c]);
+        if (keep) idx_out[l * n_idx + q] = node;  // level-major: coalesced across lanes
+      });
+    }
     wave_lds_sync();
 #pragma unroll
     for (int t0 = 0; t0 < 4; t0 += NT) {
@@ -463,14 +498,17 @@ __global__ __launch_bounds__(256) void cast_kernel(const float* __restrict__ src
 // Node indices the residual forward stored for its backward queries
 // ([L][Qb], sorted positions), returned per source query ([Qb][L]). Sorted
 // position p holds source query order[p]; a value outside [0, Qb) is skipped.
+// With K = 8 (the paper's scheme) each level holds the eight corners:
+// [L][8][Qb] in, [Qb][L][8] out.
 __global__ __launch_bounds__(256) void saved_nodes_kernel(const int32_t* __restrict__ nidx,
-                                                          const int32_t* __restrict__ order, int64_t Qb, int L,
+                                                          const int32_t* __restrict__ order, int64_t Qb, int L, int K,
                                                           int32_t* __restrict__ out) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= Qb) return;
   const int64_t q = order[p];
   if (q < 0 || q >= Qb) return;
-  for (int l = 0; l < L; ++l) out[q * L + l] = nidx[(int64_t)l * Qb + p];
+  for (int l = 0; l < L; ++l)
+    for (int k = 0; k < K; ++k) out[(q * L + l) * K + k] = nidx[((int64_t)l * K + k) * Qb + p];
 }
 
 // ---------------------------------------------------------------------------
@@ -503,8 +541,12 @@ template <class TT, class HT, int C>
 static hipError_t launch_encode_t(const TreeArgs& T, const float* x, const float* d, int64_t B, void* h,
                                   int32_t* idx, hipStream_t st) {
   const int64_t blocks = (B + 255) / 256;
-  hipLaunchKernelGGL((encode_kernel<TT, HT, C>), dim3((unsigned)blocks), dim3(256), 0, st, T, x, d, B,
-                     reinterpret_cast<HT*>(h), idx);
+  if (T.interp == OO_INTERP_PAPER)
+    hipLaunchKernelGGL((encode_kernel<TT, HT, C, true>), dim3((unsigned)blocks), dim3(256), 0, st, T, x, d, B,
+                       reinterpret_cast<HT*>(h), idx);
+  else
+    hipLaunchKernelGGL((encode_kernel<TT, HT, C, false>), dim3((unsigned)blocks), dim3(256), 0, st, T, x, d, B,
+                       reinterpret_cast<HT*>(h), idx);
   return hipGetLastError();
 }
 
@@ -558,40 +600,49 @@ static void tile_launch_shape(const MlpArgs& M, int64_t Q, bool& wlds, int& wave
   grid = (int)(g > 0 ? g : 1);
 }
 
-template <class TT, class MT, int C, int H>
-static hipError_t launch_query_t(const TreeArgs& T, const MlpArgs& M, const QuerySrc& src, int64_t Q, float* rgb,
-                                 int32_t* idx_out, float2* uv_out, int64_t n_idx, hipStream_t st) {
+template <class TT, class MT, int C, int H, bool PAPER>
+static hipError_t launch_query_p(const TreeArgs& T, const MlpArgs& M, const QuerySrc& src, int64_t Q, float* rgb,
+                                 int32_t* idx_out, float2* uv_out, float4* pos_out, int64_t n_idx, hipStream_t st) {
   bool wlds;
   int waves, grid;
   size_t lds;
   tile_launch_shape<MT>(M, Q, wlds, waves, lds, grid);
   if (wlds) {
-    auto k = query_kernel<TT, MT, C, H, true>;
+    auto k = query_kernel<TT, MT, C, H, true, PAPER>;
     hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, st, T, M, src, Q, rgb, idx_out, uv_out, n_idx);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, st, T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx);
   } else {
-    auto k = query_kernel<TT, MT, C, H, false>;
+    auto k = query_kernel<TT, MT, C, H, false, PAPER>;
     hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, st, T, M, src, Q, rgb, idx_out, uv_out, n_idx);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, st, T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx);
   }
   return hipGetLastError();
 }
 
+template <class TT, class MT, int C, int H>
+static hipError_t launch_query_t(const TreeArgs& T, const MlpArgs& M, const QuerySrc& src, int64_t Q, float* rgb,
+                                 int32_t* idx_out, float2* uv_out, float4* pos_out, int64_t n_idx, hipStream_t st) {
+  return T.interp == OO_INTERP_PAPER
+             ? launch_query_p<TT, MT, C, H, true>(T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx, st)
+             : launch_query_p<TT, MT, C, H, false>(T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx, st);
+}
+
 template <class TT, class MT, int C>
 static hipError_t launch_query_c(const TreeArgs& T, const MlpArgs& M, const QuerySrc& src, int64_t Q, float* rgb,
-                                 int32_t* idx_out, float2* uv_out, int64_t n_idx, hipStream_t st) {
-  return M.H == 64 ? launch_query_t<TT, MT, C, 64>(T, M, src, Q, rgb, idx_out, uv_out, n_idx, st)
-                   : launch_query_t<TT, MT, C, 128>(T, M, src, Q, rgb, idx_out, uv_out, n_idx, st);
+                                 int32_t* idx_out, float2* uv_out, float4* pos_out, int64_t n_idx, hipStream_t st) {
+  return M.H == 64 ? launch_query_t<TT, MT, C, 64>(T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx, st)
+                   : launch_query_t<TT, MT, C, 128>(T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx, st);
 }
 
 hipError_t launch_query(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, const QuerySrc& src,
-                        int64_t Q, float* rgb, int32_t* idx_out, float2* uv_out, int64_t n_idx, hipStream_t st) {
+                        int64_t Q, float* rgb, int32_t* idx_out, float2* uv_out, float4* pos_out, int64_t n_idx,
+                        hipStream_t st) {
   if (Q == 0) return hipSuccess;
   if (td == OO_F32)
-    return T.C == 4 ? launch_query_c<float, float, 4>(T, M, src, Q, rgb, idx_out, uv_out, n_idx, st)
-                    : launch_query_c<float, float, 8>(T, M, src, Q, rgb, idx_out, uv_out, n_idx, st);
-  if (td == OO_F16) return launch_query_c<f16, f16, 8>(T, M, src, Q, rgb, idx_out, uv_out, n_idx, st);
-  return launch_query_c<bf16, bf16, 8>(T, M, src, Q, rgb, idx_out, uv_out, n_idx, st);
+    return T.C == 4 ? launch_query_c<float, float, 4>(T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx, st)
+                    : launch_query_c<float, float, 8>(T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx, st);
+  if (td == OO_F16) return launch_query_c<f16, f16, 8>(T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx, st);
+  return launch_query_c<bf16, bf16, 8>(T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx, st);
   (void)md;
 }
 
@@ -638,11 +689,11 @@ hipError_t launch_combine(const ResidualArgs& A, const float* Lq, const int32_t*
   return hipGetLastError();
 }
 
-hipError_t launch_saved_nodes(const int32_t* nidx, const int32_t* order, int64_t Qb, int L, int32_t* out,
+hipError_t launch_saved_nodes(const int32_t* nidx, const int32_t* order, int64_t Qb, int L, int K, int32_t* out,
                               hipStream_t st) {
   if (Qb == 0) return hipSuccess;
   hipLaunchKernelGGL(saved_nodes_kernel, dim3((unsigned)((Qb + 255) / 256)), dim3(256), 0, st, nidx, order, Qb, L,
-                     out);
+                     K, out);
   return hipGetLastError();
 }
 

@@ -52,9 +52,12 @@ hipError_t launch_encode(const TreeArgs& T, oo_dtype td, const float* x, const f
                          oo_dtype hd, int32_t* idx, hipStream_t st);
 hipError_t launch_mlp(const MlpArgs& M, oo_dtype md, const void* h, int64_t Q, float* rgb, hipStream_t st);
 // Queries q < n_idx also store their node index per level (idx_out,
-// [L][n_idx]) and octahedral coordinates (uv_out, [n_idx]).
+// [L][n_idx]; the paper's scheme: the eight corner nodes, [L][8][n_idx], and
+// the position, pos_out [n_idx]) and octahedral coordinates (uv_out,
+// [n_idx]).
 hipError_t launch_query(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, const QuerySrc& src,
-                        int64_t Q, float* rgb, int32_t* idx_out, float2* uv_out, int64_t n_idx, hipStream_t st);
+                        int64_t Q, float* rgb, int32_t* idx_out, float2* uv_out, float4* pos_out, int64_t n_idx,
+                        hipStream_t st);
 
 // Spatial bucketing of the residual queries: NB chunks, K buckets (octree
 // cell level c). Workspace: counts [NB][K], total [K], start [K] int32;
@@ -72,7 +75,7 @@ int combine_blocks(int64_t B, int N);
 hipError_t launch_combine(const ResidualArgs& A, const float* Lq, const int32_t* rank, float* lhs, float* rhs,
                           float* resid, double* partials, double* loss, hipStream_t st);
 hipError_t launch_cast(const float* src, void* dst, oo_dtype dt, int64_t n, hipStream_t st);
-hipError_t launch_saved_nodes(const int32_t* nidx, const int32_t* order, int64_t Qb, int L, int32_t* out,
+hipError_t launch_saved_nodes(const int32_t* nidx, const int32_t* order, int64_t Qb, int L, int K, int32_t* out,
                               hipStream_t st);
 
 // Backward.
@@ -88,9 +91,10 @@ hipError_t launch_transpose_weights(const MlpArgs& M, oo_dtype md, void* const* 
 // accumulate is set).
 struct BwdArgs {
   int64_t Q;
-  const int32_t* nidx;
+  const int32_t* nidx;  // [L][ldn], or [L][8][ldn] in the paper's scheme
   int64_t ldn;
   const float2* uv;
+  const float4* pos;    // the paper's scheme: query positions, [Q]
   const float* seeds;
   const int32_t* order;
   int64_t n_seed;
@@ -101,7 +105,7 @@ struct BwdArgs {
 hipError_t launch_bwd(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, void* const* Wt,
                       const BwdArgs& A, const ParamLayout& PL, int grid, hipStream_t st);
 hipError_t launch_scatter(const TreeArgs& T, int64_t Q, const int32_t* nidx, int64_t ldn, const float2* uv,
-                          const float* dh, float post_scale, const GradArgs& G, hipStream_t st);
+                          const float4* pos, const float* dh, float post_scale, const GradArgs& G, hipStream_t st);
 hipError_t launch_dw_reduce(const float* partials, int grid, const ParamLayout& PL, const ReduceDst& D, float scale,
                             hipStream_t st);
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t st);

@@ -381,10 +381,12 @@ def train_batch(cfg: Config):
     return out
 
 
-def init_tables(cfg: Config, level_counts):
-    """FP32 feature tables N(0, 0.1), [n_l][R_l][R_l][C] per level."""
+def init_tables(cfg: Config, level_counts, vertices: bool = False):
+    """FP32 feature tables N(0, 0.1), [n_l][R_l][R_l][C] per level, or
+    [n_l][R_l + 1][R_l + 1][C] for vertex-stored maps."""
     g = rng(cfg.idx, 3)
-    return [g.normal(0.0, 0.1, (int(n), R, R, cfg.C)).astype(np.float32)
+    e = 1 if vertices else 0
+    return [g.normal(0.0, 0.1, (int(n), R + e, R + e, cfg.C)).astype(np.float32)
             for n, R in zip(level_counts, cfg.res)]
 
 

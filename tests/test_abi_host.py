@@ -190,3 +190,27 @@ def test_dot_and_node_readback_validation(L):
     n[0] = -3
     a[0] = 16
     assert L.oo_dot_f64(a, None, n, 1, out, out, None) == -1                 # negative size
+
+
+def test_interp_scheme_validation_and_workspace(L):
+    """An unknown interpolation scheme is refused before any device work;
+    the paper's scheme stores eight corner nodes and a position per backward
+    query, and uses no pair buffers, which the workspace size reflects."""
+    t, m = _tree(), _mlp()
+    x = C.c_void_p(0x4000)
+    bad = _tree()
+    bad.interp = 2
+    assert L.oo_encode_query(C.byref(bad), x, x, 4, x, 0, None, None) == -1
+    assert b"interp" in L.oo_last_error()
+    assert L.oo_query_fwd(C.byref(bad), C.byref(m), x, x, 16, x, None) == -1
+    b = binding._Batch()
+    b.B, b.N = 1000, 0
+    b.x = b.dir = b.Le = 0x5000
+    n0, n1 = C.c_size_t(0), C.c_size_t(0)
+    assert L.oo_residual_workspace_bytes(C.byref(t), C.byref(m), C.byref(b), C.byref(n0)) == 0
+    paper = _tree()
+    paper.interp = 1
+    assert L.oo_residual_workspace_bytes(C.byref(paper), C.byref(m), C.byref(b), C.byref(n1)) == 0
+    # 7 more node indices per level (3 levels, int32) and 16 B of position per query, 256-byte rounding aside
+    extra = 1000 * (3 * 7 * 4 + 16)
+    assert extra - 512 <= n1.value - n0.value <= extra + 512, (n0.value, n1.value)

@@ -1,0 +1,221 @@
+"""GPU parity of the paper's own interpolation (Sec. 3.3 barycentric vertex
+maps, Sec. 3.4 eight-cell trilinear blend renormalised over non-empty
+cells) against the FP64 oracle, through the C-ABI: the eight corner nodes
+per level bit-exact, features, the fused query, and the residual step's
+forward and backward (including the four-chunk schedule on FP16)."""
+import dataclasses
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2606_08469_amd import binding, synth
+from _gpu import (cosine, kink_margin_ok_tree, oracle_tree_for, rel_l2, render_queries, report, subset_batch, to_np,
+                  train_batch, tree_for)
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+MIX_TOL = 1e-2
+MIX_COS = 0.999
+PAPER = binding.INTERP_PAPER
+
+
+@functools.lru_cache(maxsize=None)
+def paper_params(ci: int):
+    cfg = synth.CONFIGS[ci]
+    _, lo = oracle_tree_for(cfg.tree_cfg)
+    feat = synth.init_tables(cfg, np.diff(lo), vertices=True)
+    W, b = synth.init_mlp(cfg)
+    return feat, W, b
+
+
+def paper_oracle(ci: int):
+    cfg = synth.CONFIGS[ci]
+    nodes, lo = oracle_tree_for(cfg.tree_cfg)
+    feat, W, b = paper_params(ci)
+    return oracle.Tree(nodes, lo, list(cfg.res), cfg.C, feat, interp=oracle.INTERP_PAPER), oracle.MLP(W, b)
+
+
+def paper_gpu(ci: int, dtype=torch.float32):
+    cfg = synth.CONFIGS[ci]
+    _, nodes, lo = tree_for(cfg.tree_cfg)
+    feat, W, b = paper_params(ci)
+    return binding.OctaOctree(nodes, lo, list(cfg.res), cfg.C, feat, W, b, dtype=dtype, interp=PAPER)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def edge_queries(n=300, seed=0):
+    g = np.random.default_rng(seed)
+    x = np.concatenate([g.uniform(-0.2, 1.2, (n, 3)), g.choice([0.0, 0.25, 0.5, 0.75, 1.0], (n, 3)),
+                        np.array([[1.0, 1.0, 1.0], [0.0, 0.0, 0.0], [0.999999940395, 0.5, 0.5]])]).astype(np.float32)
+    d = g.normal(size=(len(x), 3)).astype(np.float32)
+    d[:8] = [[0, 0, 1], [0, 0, -1], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 0], [1, 1, -1]]
+    d[8:20, 2] = 0.0  # equator
+    d[20:40, 0] = 0.0  # lower-hemisphere seam
+    d[20:40, 2] = -np.abs(d[20:40, 2])
+    return x, d
+
+
+def some_queries(ci, n):
+    cfg = synth.CONFIGS[ci]
+    if cfg.kind == "render":
+        x, d = render_queries(ci)
+    else:
+        b = train_batch(ci, n)
+        x, d = b["x"], b["dir"]
+    sel = np.random.default_rng(ci).choice(len(x), size=min(n, len(x)), replace=False)
+    ex, ed = edge_queries()
+    return np.concatenate([x[sel], ex]), np.concatenate([d[sel], ed])
+
+
+def oracle_corners(otree, x):
+    """[B][L][8] corner nodes from the oracle's neighbour search."""
+    return np.stack([oracle.neighbours(otree, x, l)[0] for l in range(otree.n_levels)], axis=1)
+
+
+@pytest.mark.parametrize("ci,n", [(1, 4096), (2, 20000), (4, 20000)])
+def test_paper_encode_corners_bit_exact_and_features(ci, n):
+    x, d = some_queries(ci, n)
+    model = paper_gpu(ci)
+    otree, _ = paper_oracle(ci)
+    print(f"[case] paper encode cfg{ci} B={len(x)}", flush=True)
+    h, idx = binding.encode_query(model.tree, dev(x), dev(d), torch.float32)
+    want_idx = oracle_corners(otree, x)
+    got_idx = idx.cpu().numpy()
+    want_h, _ = oracle.encode(otree, x, d)
+    e = rel_l2(to_np(h), want_h)
+    report(f"paper encode cfg{ci}", B=len(x), corner_mismatches=int((got_idx != want_idx).sum()),
+           present=int((want_idx >= 0).sum()), h_rel_l2=e,
+           h_max_abs=float(np.abs(to_np(h) - want_h).max()))
+    np.testing.assert_array_equal(got_idx, want_idx)
+    assert e <= FP32_TOL
+    # 16-bit features from the same FP32 tables
+    h16, _ = binding.encode_query(model.tree, dev(x), dev(d), torch.float16)
+    assert rel_l2(to_np(h16), want_h) <= 1e-3
+
+
+@pytest.mark.parametrize("ci,dtype,tol", [(1, torch.float32, FP32_TOL), (2, torch.float32, FP32_TOL),
+                                          (2, torch.float16, MIX_TOL), (4, torch.bfloat16, MIX_TOL),
+                                          (4, torch.float32, FP32_TOL)])
+def test_paper_query_fwd(ci, dtype, tol):
+    x, d = some_queries(ci, 8192)
+    model = paper_gpu(ci, dtype)
+    otree, omlp = paper_oracle(ci)
+    print(f"[case] paper query cfg{ci} {dtype} B={len(x)}", flush=True)
+    got = to_np(model(dev(x), dev(d)))
+    want = oracle.query_fwd(otree, omlp, x, d)
+    e = rel_l2(got, want)
+    report(f"paper query cfg{ci} {dtype}", rel_l2=e)
+    assert e <= tol
+
+
+def kink_safe(otree, W, b, batch, full):
+    ok = kink_margin_ok_tree(otree, W, b, batch["x"], batch["dir"])
+    N = int(batch.get("N", 0))
+    if full and N > 0:
+        ok2 = kink_margin_ok_tree(otree, W, b, batch["x2"].reshape(-1, 3), batch["dir2"].reshape(-1, 3))
+        ok &= ok2.reshape(-1, N).all(axis=1)
+    return subset_batch(batch, np.nonzero(ok)[0]), int((~ok).sum())
+
+
+def run_residual(model, batch_np):
+    b = binding.device_batch(batch_np)
+    for p in model.parameters():
+        p.grad = None
+    loss = model.residual(b)
+    loss.backward()
+    out = dict(loss=float(loss.item()),
+               dfeat=[to_np(p.grad) if p.grad is not None else np.zeros(p.shape) for p in model.feat],
+               dW=[to_np(p.grad) for p in model.W], db=[to_np(p.grad) for p in model.b])
+    ws = model.workspace(b)
+    lhs, rhs, res, _ = binding.residual_fwd(model.tree, model.mlp, b, ws, feat=model.work_feat, W=model.work_W)
+    out.update(lhs=to_np(lhs), rhs=to_np(rhs), resid=to_np(res), ws=ws, b=b)
+    return out
+
+
+def compare_grads(name, got, otree, omlp, batch, tol=None, cos=None):
+    dfeat, dW, db = oracle.residual_bwd(otree, omlp, batch)
+    for l, (g, w) in enumerate(zip(got["dfeat"], dfeat)):
+        if w.size == 0 or not np.any(w):
+            continue
+        e, c = rel_l2(g, w), cosine(g, w)
+        report(f"{name} dfeat[{l}]", rel_l2=e, cos=c)
+        if tol is not None:
+            assert e <= tol, (l, e)
+        if cos is not None:
+            assert c >= cos, (l, c)
+    for i, (gw, ow, gb, ob) in enumerate(zip(got["dW"], dW, got["db"], db)):
+        e1, e2, c1, c2 = rel_l2(gw, ow), rel_l2(gb, ob), cosine(gw, ow), cosine(gb, ob)
+        report(f"{name} W[{i}]", rel_l2=e1, cos=c1)
+        report(f"{name} b[{i}]", rel_l2=e2, cos=c2)
+        if tol is not None:
+            assert e1 <= tol and e2 <= tol, (i, e1, e2)
+        if cos is not None:
+            assert c1 >= cos and c2 >= cos, (i, c1, c2)
+
+
+@pytest.mark.parametrize("ci,B,mode", [(1, None, "l2"), (3, 2048, "l2"), (3, 1000, "relative"), (3, 512, "full"),
+                                       (3, 70000, "l2")])
+def test_paper_residual_fp32(ci, B, mode):
+    """Residual outputs, loss and every gradient group element-wise within
+    1e-5 (points whose ReLU pattern FP32 could flip are dropped)."""
+    batch = dict(train_batch(ci) if B is None else train_batch(ci, B))
+    if mode == "relative":
+        batch.update(loss_kind=1, eps=1e-2)
+    if mode == "full":
+        batch["grad_through_rhs"] = 1
+    otree, omlp = paper_oracle(ci)
+    _, W, b = paper_params(ci)
+    batch, dropped = kink_safe(otree, W, b, batch, mode == "full")
+    model = paper_gpu(ci)
+    print(f"[case] paper residual fp32 cfg{ci} B={len(batch['x'])} {mode} (kink-dropped {dropped})", flush=True)
+    got = run_residual(model, batch)
+    lhs, rhs, res, loss = oracle.residual_fwd(otree, omlp, batch)
+    for k, w in (("lhs", lhs), ("rhs", rhs), ("resid", res)):
+        e = rel_l2(got[k], w)
+        report(f"paper residual cfg{ci} {mode} {k}", rel_l2=e)
+        assert e <= FP32_TOL
+    el = abs(got["loss"] - loss) / abs(loss)
+    report(f"paper residual cfg{ci} {mode} loss", rel=el)
+    assert el <= FP32_TOL
+    compare_grads(f"paper cfg{ci} {mode}", got, otree, omlp, batch, tol=FP32_TOL)
+
+
+def test_paper_four_chunk_fp16_backward_and_corners():
+    """The training step on the depth-10 tree with FP16 vertex maps and
+    decoder 88-128-128-3: 131,072 LHS points (four backward chunks, scatter
+    on the second stream, partials accumulated). Radiance and loss within
+    1e-2, every gradient group at cosine >= 0.999, and the corner nodes the
+    fused kernel stored for the backward bit-identical to the oracle's."""
+    ci, B = 5, 131072
+    batch = train_batch(ci, B)
+    otree, omlp = paper_oracle(ci)
+    model = paper_gpu(ci, torch.float16)
+    print(f"[case] paper four-chunk fp16 cfg{ci} B={B}", flush=True)
+    got = run_residual(model, batch)
+    corners = binding.residual_node_indices(model.tree, model.mlp, got["b"], got["ws"], feat=model.work_feat,
+                                            W=model.work_W).cpu().numpy()
+    want_c = oracle_corners(otree, batch["x"])
+    report("paper four-chunk corners", mismatches=int((corners != want_c).sum()), present=int((want_c >= 0).sum()))
+    np.testing.assert_array_equal(corners, want_c)
+    lhs, rhs, res, loss = oracle.residual_fwd(otree, omlp, batch)
+    e, el = rel_l2(got["lhs"], lhs), abs(got["loss"] - loss) / abs(loss)
+    report("paper four-chunk fp16 lhs", rel_l2=e)
+    report("paper four-chunk fp16 loss", rel=el)
+    assert e <= MIX_TOL and el <= MIX_TOL
+    compare_grads("paper four-chunk fp16", got, otree, omlp, batch, cos=MIX_COS)
+
+
+def test_paper_refuses_bad_scheme():
+    """An unknown scheme value is refused before any launch."""
+    model = paper_gpu(1)
+    model.tree.interp = 2
+    x, d = some_queries(1, 16)
+    with pytest.raises(binding.OOError, match="interp"):
+        binding.encode_query(model.tree, dev(x), dev(d), torch.float32)
