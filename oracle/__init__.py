@@ -99,6 +99,7 @@ def lib():
         L.ora_map_entries.restype = C.c_int64
         L.ora_bary.argtypes = [vp, i64, i32, vp, vp, vp]
         L.ora_neighbours.argtypes = [vp, vp, i64, i32, vp, vp, vp]
+        L.ora_adam.argtypes = [vp, vp, vp, vp, i64, vp, i64, i32, C.c_double, C.c_double, C.c_double, C.c_double]
         _lib = L
     return _lib
 
@@ -347,3 +348,15 @@ def residual_bwd(tree: Tree, mlp: MLP, batch: dict, grad_loss=1.0, nthreads=0):
     if rc != 0:
         raise RuntimeError(f"ora_residual_bwd failed: {rc}")
     return dfeat, dW, db
+
+
+def adam(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.99, eps=1e-15, touched=None, block=1):
+    """One Adam step (Kingma and Ba, Algorithm 1) on copies of FP32 arrays:
+    returns (p, m, v) as FP32. touched: per-block flags (uint32) that limit
+    the update to blocks of `block` entries some query read."""
+    p, m, v = _f32(p).copy(), _f32(m).copy(), _f32(v).copy()
+    g = _f32(g)
+    tf = None if touched is None else np.ascontiguousarray(touched, dtype=np.uint32)
+    lib().ora_adam(_p(p), _p(g), _p(m), _p(v), p.size, _p(tf), int(block), int(t), float(lr), float(b1),
+                   float(b2), float(eps))
+    return p, m, v

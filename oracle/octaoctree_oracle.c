@@ -885,3 +885,25 @@ done:
   free(dhs);
   return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Optimiser step over the FP32 masters                                      */
+/* ------------------------------------------------------------------------ */
+
+/* Adam as stated by Kingma and Ba (Algorithm 1), with the bias corrections
+ * written out; blocks of a feature table whose node no query read are left
+ * alone (their gradient is zero, and their moments are not decayed). */
+void ora_adam(float* p, const float* g, float* m, float* v, int64_t n, const uint32_t* touched, int64_t block,
+              int32_t t, double lr, double b1, double b2, double eps) {
+  double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
+  for (int64_t i = 0; i < n; ++i) {
+    if (touched && !touched[i / block]) continue;
+    double gi = (double)g[i];
+    double mi = b1 * (double)m[i] + (1.0 - b1) * gi;
+    double vi = b2 * (double)v[i] + (1.0 - b2) * gi * gi;
+    double step = lr * (mi / c1) / (sqrt(vi / c2) + eps);
+    m[i] = (float)mi;
+    v[i] = (float)vi;
+    p[i] = (float)((double)p[i] - step);
+  }
+}

@@ -135,6 +135,17 @@ int ora_residual_bwd(const ora_tree* t, const ora_mlp* m, const ora_batch* bt, d
                      double* const* dfeat, double* const* dW, double* const* db,
                      int32_t nthreads);
 
+/* One Adam step (Kingma and Ba, Algorithm 1) over n FP32 parameters with
+ * FP32 moments, all updated in place after widening to FP64:
+ *   m <- b1 m + (1 - b1) g,  v <- b2 v + (1 - b2) g^2,
+ *   p <- p - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+ * With `touched` set, the array is split into blocks of `block` entries and
+ * only blocks whose flag is non-zero are updated (a node's map that no query
+ * of the batch read keeps its parameters and moments); touched == NULL
+ * updates every entry. Results are rounded back to FP32 (p, m, v). */
+void ora_adam(float* p, const float* g, float* m, float* v, int64_t n, const uint32_t* touched, int64_t block,
+              int32_t t, double lr, double b1, double b2, double eps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -45,6 +45,12 @@ MUTANTS = {
     "trilinear_centre_offset_dropped": ("double p = xa * ldexp(1.0, l) - 0.5;", "double p = xa * ldexp(1.0, l);"),
     "paper_scatter_wrong_weight": ("          for (int32_t c = 0; c < C; ++c) dfeat[l][base + c] += wk * dh[l * C + c];",
                                    "          for (int32_t c = 0; c < C; ++c) dfeat[l][base + c] += qt->vw[l][k] * dh[l * C + c];"),
+    # the optimiser step
+    "adam_no_bias_correction": ("double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);",
+                                "double c1 = 1.0, c2 = 1.0 - pow(b2, (double)t);"),
+    "adam_untouched_updated": ("    if (touched && !touched[i / block]) continue;\n", ""),
+    "adam_second_moment_unsquared": ("double vi = b2 * (double)v[i] + (1.0 - b2) * gi * gi;",
+                                     "double vi = b2 * (double)v[i] + (1.0 - b2) * fabs(gi);"),
     "scatter_into_first_node": ("int64_t base = texel_base(t, l, qt->idx[l], qt->ij[l][2 * k], qt->ij[l][2 * k + 1]);\n"
                                 "      for (int32_t c = 0; c < C; ++c) dfeat",
                                 "int64_t base = texel_base(t, l, (int32_t)t->level_offset[l], qt->ij[l][2 * k], "
