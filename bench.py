@@ -17,6 +17,7 @@ batch also runs on the FP32 plain path, and the render forwards at 1280x720
 Prints one JSON line.
 """
 import argparse
+import dataclasses
 import json
 import math
 import os
@@ -83,44 +84,53 @@ def main():
 
     mixed = binding.OctaOctree(nodes, lo, list(cfg.res), cfg.C, feat, W, b, dtype=torch.float16)
     batch = binding.device_batch(batch_np)
-    # FP32 gradient accumulators in one flat buffer (aligned views), zeroed
-    # with a single fill per step
-    gshapes = [tuple(t.shape) for t in list(mixed.feat) + list(mixed.W) + list(mixed.b)]
-    goffs, gtotal = binding._flat_layout(gshapes)
-    gflat = torch.zeros(gtotal, dtype=torch.float32, device=dev)
-    gviews = [gflat[o:o + int(np.prod(sh))].view(sh) for sh, o in zip(gshapes, goffs)]
-    nf, nw = len(mixed.feat), len(mixed.W)
-    grads = {"dfeat": gviews[:nf], "dW": gviews[nf:nf + nw], "db": gviews[nf + nw:]}
-    ws_mixed = mixed.workspace(batch)
     outs = tuple(torch.empty((B, 3), dtype=torch.float32, device=dev) for _ in range(3)) + (
         torch.empty((), dtype=torch.float64, device=dev),)
     gl = torch.ones((), dtype=torch.float64, device=dev)
+    grad_bufs = {}
 
-    def step(model, ev=None):
+    def grads_for(model):
+        """FP32 gradient accumulators of a model in one flat buffer (aligned
+        views), zeroed with a single fill per step."""
+        key = id(model)
+        if key not in grad_bufs:
+            gshapes = [tuple(t.shape) for t in list(model.feat) + list(model.W) + list(model.b)]
+            goffs, gtotal = binding._flat_layout(gshapes)
+            gflat = torch.zeros(gtotal, dtype=torch.float32, device=dev)
+            gviews = [gflat[o:o + int(np.prod(sh))].view(sh) for sh, o in zip(gshapes, goffs)]
+            nf, nw = len(model.feat), len(model.W)
+            grad_bufs.clear()  # one model's buffers at a time
+            grad_bufs[key] = (gflat, {"dfeat": gviews[:nf], "dW": gviews[nf:nf + nw], "db": gviews[nf + nw:]})
+        return grad_bufs[key]
+
+    def step(model, ev=None, bt=None, o=None):
+        bt = batch if bt is None else bt
+        o = outs if o is None else o
+        gflat, grads = grads_for(model)
         if ev:
             ev[3].record()
         model.refresh()
         gflat.zero_()
         if ev:
             ev[0].record()
-        ws = model.workspace(batch)  # sized for this model's dtypes
-        lhs, rhs, res, loss = binding.residual_fwd(model.tree, model.mlp, batch, ws, feat=model.work_feat,
-                                                   W=model.work_W, outs=outs)
+        ws = model.workspace(bt)  # sized for this model's dtypes
+        lhs, rhs, res, loss = binding.residual_fwd(model.tree, model.mlp, bt, ws, feat=model.work_feat,
+                                                   W=model.work_W, outs=o)
         if ev:
             ev[1].record()
-        binding.residual_bwd(model.tree, model.mlp, batch, res, rhs, gl, grads["dfeat"], grads["dW"], grads["db"],
+        binding.residual_bwd(model.tree, model.mlp, bt, res, rhs, gl, grads["dfeat"], grads["dW"], grads["db"],
                              ws, feat=model.work_feat, W=model.work_W)
         if ev:
             ev[2].record()
             ev[4].record()
         return loss
 
-    def timed(model, steps, warmup, kernels=False):
+    def timed(model, steps, warmup, kernels=False, bt=None, o=None):
         """Wall time per step over the timed steps, their mean forward and
         backward event times, and (kernels=True) the library's own per-launch
         event timings of every kernel group in the timed region."""
         for _ in range(warmup):
-            step(model)
+            step(model, bt=bt, o=o)
         torch.cuda.synchronize()
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
         if kernels:
@@ -128,7 +138,7 @@ def main():
         torch.cuda.synchronize()
         t = time.perf_counter()
         for i in range(steps):
-            step(model, evs[i])
+            step(model, evs[i], bt=bt, o=o)
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t) / steps
         per = None
@@ -147,6 +157,12 @@ def main():
     log(f"mixed: {ms:.3f} ms/step (fwd {fwd_ms:.3f} ms, bwd {bwd_ms:.3f} ms); step events median "
         f"{st_mixed['median']:.3f} p10 {st_mixed['p10']:.3f} p90 {st_mixed['p90']:.3f} ms")
     log("per launch (ms): " + ", ".join(f"{k} {v[0]:.4f}" for k, v in per_kernel.items()))
+
+    # ---------------- optimiser step (NEXT to the hot path) ------------------
+    # the last timed step's gradients: mark the nodes the batch read, then
+    # one lazy fused Adam step (refresh of the working copy and clear of the
+    # gradients included), as a training loop would run after the backward
+    opt = optimizer_bench(torch, binding, mixed, batch, grads_for(mixed)[1], args)
 
     # ---------------- algorithmic bytes / FLOPs ----------------------------
     # Levels present per query: the descent stops at the first missing child.
@@ -195,6 +211,30 @@ def main():
         del fp32
         torch.cuda.empty_cache()
         extra["render"] = render_bench(torch, binding, synth, args)
+        # the paper's interpolation (8-cell trilinear blend over barycentric
+        # vertex maps) on the same tree, batch and decoder
+        del mixed
+        grad_bufs.clear()
+        torch.cuda.empty_cache()
+        vfeat = synth.init_tables(cfg, counts, vertices=True)
+        paper = binding.OctaOctree(nodes, lo, list(cfg.res), cfg.C, vfeat, W, b, dtype=torch.float16,
+                                   interp=binding.INTERP_PAPER)
+        log("timing paper-scheme mixed step")
+        msp, fp_, bp_, perp, stp = timed(paper, max(5, args.steps // 4), 2, kernels=True)
+        extra["paper_scheme"] = {
+            "workload": "same training step with the paper's level feature: 8 neighbouring cells (trilinear, "
+                        "renormalised) x 3 barycentric vertices per level, (R+1)^2-vertex FP16 maps",
+            "ms_per_step": round(msp, 4), "fwd_ms": round(fp_, 4), "bwd_ms": round(bp_, 4),
+            "step_event_ms": {k: round(v, 4) for k, v in stp.items()},
+            "value": round(Q / (msp * 1e-3) / 1e6, 2), "unit": "Mqueries/s",
+            "ms_per_launch": {k: round(v[0], 4) for k, v in perp.items()},
+            "launches_per_step": {k: round(v[1], 2) for k, v in perp.items()}}
+        log(f"paper scheme: {msp:.3f} ms/step (fwd {fp_:.3f}, bwd {bp_:.3f})")
+        del paper
+        grad_bufs.clear()
+        torch.cuda.empty_cache()
+        extra["paper_scheme"]["render"] = render_bench(torch, binding, synth, args, interp=binding.INTERP_PAPER)
+        extra["paper_config"] = paper_config_bench(torch, binding, synth, args, timed, grad_bufs)
 
     # ---------------- CPU baseline (oracle) --------------------------------
     cpu = None
@@ -229,8 +269,92 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    line["optimizer_step"] = opt
     line.update(extra)
     print(json.dumps(line), flush=True)
+
+
+def paper_config_bench(torch, binding, synth, args, timed, grad_bufs):
+    """The paper's network and loss on its batch schedule: 8 levels x 4 FP16
+    channels on vertex maps (257^2 .. 3^2), eight-cell blend, the 13 surface
+    attributes (+3 zero columns), four hidden layers of width 128, relative
+    L2, mirror-direction lookup. One timed training step (forward and
+    backward) per schedule stage (B LHS points x M samples)."""
+    cfg = synth.CONFIGS[6]
+    t0 = time.time()
+    nodes, lo = binding.build_octree(synth.tree_samples(cfg), cfg.D, cfg.tau)
+    counts = np.diff(lo)
+    feat = synth.init_tables(cfg, counts, vertices=True)
+    W, b = synth.init_mlp(cfg)
+    model = binding.OctaOctree(nodes, lo, list(cfg.res), cfg.C, feat, W, b, dtype=torch.float16,
+                               interp=binding.INTERP_PAPER)
+    out = {"workload": "paper network and loss: depth-7 octree (%d nodes), 8 levels x 4 FP16 channels on "
+                       "(R+1)^2 vertex maps R = 256..2, 13 surface attributes (+3 zero), decoder "
+                       "48-128-128-128-128-3 FP16 MFMA, relative L2, detached target" % len(nodes),
+           "stages": []}
+    log(f"paper config: tree built in {time.time() - t0:.1f}s, nodes={len(nodes)} levels={counts.tolist()}")
+    for B, N in synth.PAPER_SCHEDULE:
+        bt_np = synth.train_batch(dataclasses.replace(cfg, B=B, N=N))
+        bt = binding.device_batch(bt_np)
+        del bt_np
+        o = tuple(torch.empty((B, 3), dtype=torch.float32, device="cuda") for _ in range(3)) + (
+            torch.empty((), dtype=torch.float64, device="cuda"),)
+        grad_bufs.clear()
+        msc, fc, bc, perc, stc = timed(model, max(5, args.steps // 5), 2, kernels=True, bt=bt, o=o)
+        Q = B * (1 + N)
+        out["stages"].append({
+            "lhs_points": B, "samples_per_point": N, "queries_per_step": Q, "ms_per_step": round(msc, 4),
+            "fwd_ms": round(fc, 4), "bwd_ms": round(bc, 4), "value": round(Q / (msc * 1e-3) / 1e6, 2),
+            "unit": "Mqueries/s", "step_event_ms": {k: round(v, 4) for k, v in stc.items()},
+            "ms_per_launch": {k: round(v[0], 4) for k, v in perc.items()},
+            "launches_per_step": {k: round(v[1], 2) for k, v in perc.items()}})
+        log(f"paper config B={B} M={N}: {msc:.3f} ms/step (fwd {fc:.3f}, bwd {bc:.3f}), "
+            f"{Q / (msc * 1e-3) / 1e6:.1f} Mqueries/s")
+        del bt, o
+        torch.cuda.empty_cache()
+    del model
+    grad_bufs.clear()
+    torch.cuda.empty_cache()
+    return out
+
+
+def optimizer_bench(torch, binding, model, batch, grads, args):
+    """Times the node marking and the fused lazy Adam step (FP16 working
+    copy) on the gradients of one backward, and reports the share of the
+    feature tables it touched and the bytes it moved (per updated element:
+    parameter, gradient, both moments read; parameter and moments written,
+    the working copy written, the gradient cleared)."""
+    ws = model.workspace(batch)
+    n_nodes = model.tree.level_offset[-1]
+    touched = torch.zeros(n_nodes, dtype=torch.int32, device="cuda")
+    flat = [grads["dfeat"][i] for i in range(len(model.feat))] + list(grads["dW"]) + list(grads["db"])
+    state = model.new_adam_state()
+    reps = max(5, args.steps // 5)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
+    for i in range(reps):
+        evs[i][0].record()
+        touched.zero_()
+        binding.touched_nodes(model.tree, model.mlp, batch, ws, touched, feat=model.work_feat, W=model.work_W)
+        evs[i][1].record()
+        binding.adam_step(model.adam_segments(flat, state, touched), i + 1, lr=1e-3, work_dtype=model.dtype)
+        evs[i][2].record()
+    torch.cuda.synchronize()
+    mark = float(np.median([e[0].elapsed_time(e[1]) for e in evs]))
+    step = float(np.median([e[1].elapsed_time(e[2]) for e in evs]))
+    lo = model.tree.level_offset
+    t = touched.cpu().numpy().astype(bool)
+    upd = sum(int(t[lo[l]:lo[l + 1]].sum()) * (p.numel() // max(lo[l + 1] - lo[l], 1))
+              for l, p in enumerate(model.feat)) + sum(w.numel() for w in model.W) + sum(v.numel() for v in model.b)
+    total = sum(p.numel() for p in model.parameters())
+    nbytes = upd * (16 + 12 + 2 + 4)
+    log(f"optimizer: mark {mark:.4f} ms, lazy Adam {step:.4f} ms over {upd} of {total} elements "
+        f"({nbytes / (step * 1e-3) / 1e9:.0f} GB/s)")
+    return {"mark_touched_ms": round(mark, 4), "adam_ms": round(step, 4), "updated_elements": upd,
+            "total_elements": total, "touched_nodes": int(t.sum()), "nodes": int(n_nodes),
+            "bytes_moved": int(nbytes), "achieved_GBs": round(nbytes / (step * 1e-3) / 1e9, 1),
+            "frac_of_hbm_peak": round(nbytes / (step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "note": "lazy Adam (untouched nodes' maps skipped) fused with the FP16 refresh and gradient clear; "
+                    "in a training loop it replaces the full refresh and the full gradient clear of the step"}
 
 
 def _event_times(torch, run, reps):
@@ -249,19 +373,20 @@ def _event_times(torch, run, reps):
     return float(np.median(t)), float(np.percentile(t, 10)), float(np.percentile(t, 90)), out_
 
 
-def render_bench(torch, binding, synth, args):
+def render_bench(torch, binding, synth, args, interp=0):
     """Render-query forwards (one query per pixel) on the FP32 plain path
     (encode to memory + decoder kernel) and the 16-bit fused path, with the
-    fused path's roofline; and the standalone 16-bit decoder (oo_mlp_fwd on
-    materialised features) at config 4's 88-128-128-3, the one place where
-    the decoder alone can approach the matrix cores' peak."""
+    fused path's roofline; and (bilinear scheme only) the standalone 16-bit
+    decoder (oo_mlp_fwd on materialised features) at config 4's
+    88-128-128-3, the one place where the decoder alone can approach the
+    matrix cores' peak. interp selects the level-feature scheme."""
     out = {}
     reps = max(20, args.steps)
     for ci, dtypes in ((2, (torch.float32, torch.float16)), (4, (torch.float32, torch.bfloat16))):
         cfg = synth.CONFIGS[ci]
         s = synth.tree_samples(cfg)
         nodes, lo = binding.build_octree(s, cfg.D, cfg.tau)
-        feat = synth.init_tables(cfg, np.diff(lo))
+        feat = synth.init_tables(cfg, np.diff(lo), vertices=bool(interp))
         W, b = synth.init_mlp(cfg)
         x, d = synth.render_queries(cfg)
         xt = torch.from_numpy(x).cuda()
@@ -270,14 +395,17 @@ def render_bench(torch, binding, synth, args):
         ref = None
         lv = None
         for dtype in dtypes:
-            m = binding.OctaOctree(nodes, lo, list(cfg.res), cfg.C, feat, W, b, dtype=dtype)
+            m = binding.OctaOctree(nodes, lo, list(cfg.res), cfg.C, feat, W, b, dtype=dtype, interp=interp)
             if dtype == torch.float32:
                 def run():
                     h, _ = binding.encode_query(m.tree, xt, dt, torch.float32, with_idx=False)
                     return binding.mlp_fwd(m.mlp, h)
                 name = "fp32_plain_unfused"
                 _, idx = binding.encode_query(m.tree, xt, dt, torch.float32)
+                # node words read and map entries gathered: one word and 4 texels
+                # per present level, or one word and 3 vertices per present corner
                 lv = float((idx >= 0).sum().item())
+                entries = lv * (3 if interp else 4)
                 del idx
             else:
                 run = lambda: m(xt, dt)
@@ -289,11 +417,11 @@ def render_bench(torch, binding, synth, args):
             rec = {"ms": round(med, 4), "p10_ms": round(p10, 4), "p90_ms": round(p90, 4),
                    "Mqueries_s": round(len(x) / (med * 1e-3) / 1e6, 1), "rel_l2_vs_fp32": err}
             if dtype != torch.float32:
-                rec["roofline"] = render_roofline(cfg, len(x), lv, med, 2)
+                rec["roofline"] = render_roofline(cfg, len(x), entries, lv, med, 2)
             res[name] = rec
             log(f"render cfg{ci} {name}: {med:.4f} ms (p10 {p10:.4f}, p90 {p90:.4f}), "
                 f"{len(x) / (med * 1e-3) / 1e6:.0f} Mq/s, err {err:.2e}")
-            if ci == 4 and dtype == torch.float32:
+            if ci == 4 and dtype == torch.float32 and not interp:
                 # standalone decoder on materialised 16-bit features
                 for hd in (torch.float16, torch.bfloat16):
                     m16 = binding.OctaOctree(nodes, lo, list(cfg.res), cfg.C, feat, W, b, dtype=hd)
@@ -382,14 +510,14 @@ def kernel_rooflines(cfg, B, Q, lv_all, lv_lhs, per_kernel):
     return out
 
 
-def render_roofline(cfg, n_queries, lv, ms, elem_bytes):
-    """Algorithmic bytes of the fused render forward (per query: 4 taps x C
-    x element size per present level, a 4 B node word per present level,
-    24 B position and direction, 12 B radiance) and its decoder FLOPs,
-    against the measured time."""
+def render_roofline(cfg, n_queries, entries, words, ms, elem_bytes):
+    """Algorithmic bytes of the fused render forward (C x element size per
+    map entry gathered, 4 B per node word read, 24 B position and direction
+    and 12 B radiance per query) and its decoder FLOPs, against the measured
+    time."""
     C, K0, H = cfg.C, cfg.mlp[0], cfg.mlp[1]
     mlp_flop = 2 * (K0 * H + (len(cfg.mlp) - 3) * H * H + H * 3)
-    nbytes = lv * (4 * C * elem_bytes + 4) + n_queries * 36
+    nbytes = entries * C * elem_bytes + words * 4 + n_queries * 36
     t = ms * 1e-3
     return {"bound": "hbm", "achieved": round(nbytes / t / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_bytes": int(nbytes),

@@ -114,9 +114,15 @@ typedef struct {
 /*
  * The decoder MLP (Sec. 3.5). Hidden layers use ReLU; the output layer is
  * linear.
- *  - n_layers: number of Linear layers, 2..5.
- *  - dims[0] = n_levels * C (at most 128). dims[n_layers] = 3. Every hidden
- *    width is the same: 64 or 128.
+ *  - n_layers: number of Linear layers, 2..5 (the paper's decoder has four
+ *    hidden layers of width 128: n_layers = 5).
+ *  - dims[0] = n_levels * C + E, a multiple of 4, at most 128. The decoder
+ *    reads [h, g]: the n_levels * C level features, then E >= 0 surface
+ *    attributes per query (Sec. 3.5: position, mirror direction, normal,
+ *    albedo, roughness: 13 values; the caller pads g with zero columns to
+ *    make dims[0] a multiple of 4, which leaves the function unchanged and
+ *    gives the padding weights zero gradient). E = 0 decodes h alone.
+ *    dims[n_layers] = 3. Every hidden width is the same: 64 or 128.
  *  - W[i]: [dims[i+1]][dims[i]] row-major in `dtype`. Also the operand type
  *    of the matrix cores. Accumulation is always FP32.
  *  - b[i]: [dims[i+1]] FP32.
@@ -175,11 +181,13 @@ int oo_mlp_fwd(const oo_mlp* mlp, const void* h, oo_dtype h_dtype, int64_t B, fl
  * (Sec. 3.6, rendering: one query and one decoder evaluation per visible
  * point).
  *  - x, dir: [B][3] FP32. rgb_out: [B][3] FP32.
+ *  - attr: [B][E] FP32, the decoder's surface attributes g (E = dims[0] -
+ *    n_levels * C); NULL when E = 0, required otherwise.
  *  - Supported type pairs (tree->feat_dtype, mlp->dtype): (F32, F32),
  *    (F16, F16), (BF16, BF16).
  */
-int oo_query_fwd(const oo_tree* tree, const oo_mlp* mlp, const float* x, const float* dir, int64_t B,
-                 float* rgb_out, hipStream_t stream);
+int oo_query_fwd(const oo_tree* tree, const oo_mlp* mlp, const float* x, const float* dir, const float* attr,
+                 int64_t B, float* rgb_out, hipStream_t stream);
 
 /*
  * One batch of the neural-radiosity residual (Sec. 3.2 Monte-Carlo RHS;
@@ -191,6 +199,10 @@ int oo_query_fwd(const oo_tree* tree, const oo_mlp* mlp, const float* x, const f
  *  - Per sample, [B][N][3] FP32: x2 (secondary hit), dir2 (lookup
  *    direction at the hit), wi (sampled incident direction).
  *  - pdf: [B][N] FP32, or NULL for 1.
+ *  - attr: [B][E] FP32, the decoder's surface attributes g of the LHS
+ *    queries; attr2: [B][N][E] those of the secondary hits (E = dims[0] -
+ *    n_levels * C). Both NULL when E = 0; attr2 is not read with
+ *    target_override.
  *  - target_override: [B][3] FP32. When set, it replaces the RHS estimate
  *    and no RHS query is made. Finite-difference checks use this to freeze
  *    the target.
@@ -215,6 +227,7 @@ typedef struct {
   int32_t loss_kind;
   float eps;
   int32_t grad_through_rhs;
+  const float *attr, *attr2;
 } oo_residual_batch;
 
 /* Workspace size in bytes that the residual forward and backward need for
@@ -332,6 +345,57 @@ int oo_dot_f64(const float* const* a, const float* const* b, const int64_t* n, i
  */
 int oo_dot_f64_noalloc(const float* const* a, const float* const* b, const int64_t* n, int32_t n_groups,
                        double* out, hipStream_t stream);
+
+/*
+ * Optimiser step over the FP32 masters. The paper trains its tables and
+ * networks jointly by gradient descent on the residual loss (Sec. 3.6, 4.1)
+ * but does not name the optimiser; this is Adam (Kingma and Ba,
+ * Algorithm 1), fused with the refresh of the 16-bit working copy and the
+ * clearing of the gradient, and lazy over feature-map blocks that no query
+ * of the batch read.
+ *  - segments: host array of n_segs <= OO_ADAM_MAX_SEGMENTS descriptors, each
+ *    a contiguous parameter array (a level's table, a layer's W or b):
+ *    param, grad, m, v are device FP32 arrays of n elements; work is the
+ *    working copy (n elements of cfg->work_dtype) or NULL; touched is NULL
+ *    (update every element) or a device array of per-block flags with
+ *    `block` elements per flag (a node's map: res^2 C, or (res+1)^2 C in the
+ *    paper's scheme), of which only blocks with a non-zero flag are touched.
+ *  - For every updated element, in FP32:
+ *      m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
+ *      param -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps),
+ *    then work = RNE(param) and grad = 0. Elements of untouched blocks are
+ *    not read or written.
+ *  - cfg->step is t >= 1. param, grad, m, v and work must not overlap.
+ */
+#define OO_ADAM_MAX_SEGMENTS 32
+typedef struct {
+  float lr, beta1, beta2, eps;
+  int32_t step;
+  oo_dtype work_dtype;
+} oo_adam_config;
+typedef struct {
+  float* param;
+  float* grad;
+  float* m;
+  float* v;
+  void* work;
+  int64_t n;
+  const uint32_t* touched;
+  int64_t block;
+} oo_adam_segment;
+int oo_adam_step(const oo_adam_config* cfg, const oo_adam_segment* segments, int32_t n_segs, hipStream_t stream);
+
+/*
+ * Marks the nodes the residual forward's backward queries read: for each
+ * stored node index (the node per level, or the eight corner cells' nodes in
+ * the paper's scheme), touched[node] = 1. touched: device [n_nodes] uint32,
+ * global node indices; the caller clears it first. tree, mlp, batch,
+ * workspace: as passed to the forward, unchanged since. The flags of a
+ * level, offset by its first node, are the `touched` blocks of that level's
+ * table in oo_adam_step.
+ */
+int oo_touched_nodes(const oo_tree* tree, const oo_mlp* mlp, const oo_residual_batch* batch, const void* workspace,
+                     size_t workspace_bytes, uint32_t* touched, hipStream_t stream);
 
 /* FP32 -> FP16/BF16 (round to nearest even) or FP32 copy, n elements. Used
  * to refresh working copies from FP32 masters. */

@@ -66,6 +66,7 @@ class _Batch(C.Structure):
         ("loss_kind", C.c_int32),
         ("eps", C.c_double),
         ("grad_through_rhs", C.c_int32),
+        ("attr", C.c_void_p), ("attr2", C.c_void_p),
     ]
 
 
@@ -89,7 +90,7 @@ def lib():
         L.ora_taps.argtypes = [vp, i64, i32, vp, vp]
         L.ora_encode.argtypes = [vp, vp, vp, i64, vp, vp]
         L.ora_mlp_fwd.argtypes = [vp, vp, i64, vp]
-        L.ora_query_fwd.argtypes = [vp, vp, vp, vp, i64, vp, i32]
+        L.ora_query_fwd.argtypes = [vp, vp, vp, vp, vp, i64, vp, i32]
         L.ora_bsdf_weight.argtypes = [vp, vp]
         L.ora_residual_fwd.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32]
         L.ora_residual_fwd.restype = C.c_int
@@ -172,7 +173,7 @@ def _batch_struct(bt: dict, keep: list):
     s.B = int(bt["x"].shape[0])
     s.N = int(bt.get("N", 0))
     for name in ("x", "dir", "n", "wo", "albedo", "Le", "rough", "x2", "dir2", "wi", "pdf",
-                 "target_override"):
+                 "target_override", "attr", "attr2"):
         a = bt.get(name)
         if a is not None:
             a = _f32(a)
@@ -299,13 +300,15 @@ def mlp_fwd(mlp: MLP, h):
     return out
 
 
-def query_fwd(tree: Tree, mlp: MLP, x, d, nthreads=0):
-    """Encode + decode: RGB radiance [B][3]."""
+def query_fwd(tree: Tree, mlp: MLP, x, d, nthreads=0, attr=None):
+    """Encode + decode: RGB radiance [B][3]. attr: [B][E] decoder attributes
+    appended after h (Sec. 3.5), when the MLP's input is wider than L*C."""
     x = _f32(x).reshape(-1, 3)
     d = _f32(d).reshape(-1, 3)
+    e = None if attr is None else _f32(attr).reshape(x.shape[0], -1)
     ts, ms = tree._struct(), mlp._struct()
     out = np.zeros((x.shape[0], 3), np.float64)
-    lib().ora_query_fwd(C.byref(ts), C.byref(ms), _p(x), _p(d), x.shape[0], _p(out), int(nthreads))
+    lib().ora_query_fwd(C.byref(ts), C.byref(ms), _p(x), _p(d), _p(e), x.shape[0], _p(out), int(nthreads))
     return out
 
 

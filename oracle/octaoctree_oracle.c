@@ -549,20 +549,31 @@ void ora_mlp_fwd(const ora_mlp* m, const double* h, int64_t B, double* out) {
   for (int64_t b = 0; b < B; ++b) mlp_row(m, &h[din * b], act, pre, &out[dout * b]);
 }
 
-void ora_query_fwd(const ora_tree* t, const ora_mlp* m, const float* x, const float* dir,
+/* Number of decoder attributes after the level features. */
+static int32_t attr_dims(const ora_tree* t, const ora_mlp* m) { return m->dims[0] - t->n_levels * t->C; }
+
+/* Decoder input of one query: the level features, then its attributes. */
+static void decoder_input(const ora_tree* t, const ora_mlp* m, const query_taps* qt, const float* e, double* h) {
+  encode_from_taps(t, qt, h);
+  int32_t LC = t->n_levels * t->C, E = attr_dims(t, m);
+  for (int32_t k = 0; k < E; ++k) h[LC + k] = (double)e[k];
+}
+
+void ora_query_fwd(const ora_tree* t, const ora_mlp* m, const float* x, const float* dir, const float* attr,
                    int64_t B, double* rgb_out, int32_t nthreads) {
   int32_t dout = m->dims[m->n_layers];
+  int32_t E = attr_dims(t, m);
 #ifdef _OPENMP
   int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
 #pragma omp parallel for schedule(static) num_threads(nt)
 #endif
   for (int64_t b = 0; b < B; ++b) {
-    double h[ORA_MAX_LEVELS * 16];
+    double h[ORA_MAX_WIDTH];
     double act[ORA_MAX_LAYERS + 1][ORA_MAX_WIDTH];
     double pre[ORA_MAX_LAYERS][ORA_MAX_WIDTH];
     query_taps qt;
     query_locate(t, &x[3 * b], &dir[3 * b], &qt);
-    encode_from_taps(t, &qt, h);
+    decoder_input(t, m, &qt, E > 0 ? &attr[E * b] : NULL, h);
     mlp_row(m, h, act, pre, &rgb_out[dout * b]);
   }
   (void)nthreads;
@@ -636,7 +647,7 @@ static int residual_parts(const ora_tree* t, const ora_mlp* m, const ora_batch* 
                           double* T, double* r, int32_t nthreads) {
   int64_t B = bt->B;
   int32_t N = bt->N;
-  ora_query_fwd(t, m, bt->x, bt->dir, B, lhs, nthreads);
+  ora_query_fwd(t, m, bt->x, bt->dir, bt->attr, B, lhs, nthreads);
   if (bt->target_override) {
     for (int64_t i = 0; i < 3 * B; ++i) T[i] = (double)bt->target_override[i];
   } else {
@@ -649,7 +660,7 @@ static int residual_parts(const ora_tree* t, const ora_mlp* m, const ora_batch* 
         free(w);
         return -5;
       }
-      ora_query_fwd(t, m, bt->x2, bt->dir2, B * N, rhsq, nthreads);
+      ora_query_fwd(t, m, bt->x2, bt->dir2, bt->attr2, B * N, rhsq, nthreads);
       ora_bsdf_weight(bt, w);
       for (int64_t b = 0; b < B; ++b)
         for (int c = 0; c < 3; ++c) {
@@ -676,10 +687,12 @@ static int check_inputs(const ora_tree* t, const ora_mlp* m, const ora_batch* bt
   if (!t || !m || !bt || bt->B < 0 || bt->N < 0) return -1;
   if (t->n_levels < 1 || t->n_levels > ORA_MAX_LEVELS) return -1;
   if (m->n_layers < 1 || m->n_layers > ORA_MAX_LAYERS) return -1;
-  if (m->dims[0] != t->n_levels * t->C || m->dims[m->n_layers] != 3) return -1;
+  if (attr_dims(t, m) < 0 || m->dims[m->n_layers] != 3) return -1;
+  if (attr_dims(t, m) > 0 && bt->B > 0 && (!bt->attr || (bt->N > 0 && !bt->target_override && !bt->attr2)))
+    return -1;
   for (int32_t i = 0; i <= m->n_layers; ++i)
     if (m->dims[i] < 1 || m->dims[i] > ORA_MAX_WIDTH) return -1;
-  if (t->n_levels * t->C > ORA_MAX_LEVELS * 16) return -1;
+  if (m->dims[0] > ORA_MAX_WIDTH) return -1;
   return 0;
 }
 
@@ -704,16 +717,16 @@ int ora_residual_fwd(const ora_tree* t, const ora_mlp* m, const ora_batch* bt, d
  * gradients (ReLU'(0) = 0) added to dW/db, then dh = W_1^T delta_1 written
  * to dh_out, and the query's node indices, taps and weights to qt, from which
  * scatter_query later adds each tap's share of dh to the texel it read. */
-static void backprop_query(const ora_tree* t, const ora_mlp* m, const float* x3, const float* d3,
+static void backprop_query(const ora_tree* t, const ora_mlp* m, const float* x3, const float* d3, const float* e,
                            const double g[3], double* const* dW, double* const* db, query_taps* qt,
                            double* dh_out) {
-  double h[ORA_MAX_LEVELS * 16];
+  double h[ORA_MAX_WIDTH];
   double act[ORA_MAX_LAYERS + 1][ORA_MAX_WIDTH];
   double pre[ORA_MAX_LAYERS][ORA_MAX_WIDTH];
   double out[ORA_MAX_WIDTH];
   double delta[ORA_MAX_WIDTH], prev[ORA_MAX_WIDTH];
   query_locate(t, x3, d3, qt);
-  encode_from_taps(t, qt, h);
+  decoder_input(t, m, qt, e, h);
   mlp_row(m, h, act, pre, out);
 
   int32_t nl = m->n_layers;
@@ -765,9 +778,9 @@ static void scatter_query(const ora_tree* t, const query_taps* qt, const double*
 /* Seed of backward query q (q < B: the LHS query of point q; otherwise the
  * RHS query (b, k) of point b = (q - B) / N, only with the gradient through
  * the target). */
-static void query_seed(const ora_batch* bt, const double* lhs, const double* T, const double* r,
+static void query_seed(const ora_batch* bt, int32_t E, const double* lhs, const double* T, const double* r,
                        const double* w, double grad_loss, int64_t q, double g[3], const float** x3,
-                       const float** d3) {
+                       const float** d3, const float** e) {
   int64_t B = bt->B;
   int64_t b = q < B ? q : (q - B) / bt->N;
   for (int c = 0; c < 3; ++c) {
@@ -781,12 +794,14 @@ static void query_seed(const ora_batch* bt, const double* lhs, const double* T, 
   if (q < B) {
     *x3 = &bt->x[3 * q];
     *d3 = &bt->dir[3 * q];
+    *e = E > 0 ? &bt->attr[E * q] : NULL;
     return;
   }
   int64_t bk = q - B;
   for (int c = 0; c < 3; ++c) g[c] = -g[c] * w[3 * bk + c] / (double)bt->N;
   *x3 = &bt->x2[3 * bk];
   *d3 = &bt->dir2[3 * bk];
+  *e = E > 0 ? &bt->attr2[E * bk] : NULL;
 }
 
 /* Gradient of the loss scaled by grad_loss. With the target detached (the
@@ -857,9 +872,9 @@ int ora_residual_bwd(const ora_tree* t, const ora_mlp* m, const ora_batch* bt, d
 #endif
       for (int64_t j = 0; j < nq; ++j) {
         double g[3];
-        const float *x3, *d3;
-        query_seed(bt, lhs, T, r, w, grad_loss, q0 + j, g, &x3, &d3);
-        backprop_query(t, m, x3, d3, g, pdW, pdb, &qts[j], &dhs[j * K0]);
+        const float *x3, *d3, *e;
+        query_seed(bt, attr_dims(t, m), lhs, T, r, w, grad_loss, q0 + j, g, &x3, &d3, &e);
+        backprop_query(t, m, x3, d3, e, g, pdW, pdb, &qts[j], &dhs[j * K0]);
       }
     }
     for (int64_t j = 0; j < nq; ++j) scatter_query(t, &qts[j], &dhs[j * K0], dfeat);

@@ -47,9 +47,12 @@ typedef struct {
   int32_t interp;                            /* ORA_INTERP_* */
 } ora_tree;
 
+/* The decoder reads [h, g]: the L*C level features, then E = dims[0] - L*C
+ * per-query surface attributes g (Sec. 3.5: position, mirror direction,
+ * normal, albedo, roughness; E = 0 reads h only). */
 typedef struct {
   int32_t n_layers;                          /* number of Linear layers */
-  int32_t dims[ORA_MAX_LAYERS + 1];          /* dims[0] = L*C, dims[n_layers] = 3 */
+  int32_t dims[ORA_MAX_LAYERS + 1];          /* dims[0] = L*C + E, dims[n_layers] = 3 */
   const float* W[ORA_MAX_LAYERS];            /* [dims[i+1]][dims[i]] row-major */
   const float* b[ORA_MAX_LAYERS];            /* [dims[i+1]] */
 } ora_mlp;
@@ -66,6 +69,8 @@ typedef struct {
   int32_t loss_kind;                           /* 0 mean L2, 1 relative L2 */
   double eps;
   int32_t grad_through_rhs;                    /* 0 detached target, 1 full */
+  const float* attr;                           /* [B][E] decoder attributes of the LHS queries */
+  const float* attr2;                          /* [B][N][E] those of the secondary queries */
 } ora_batch;
 
 /* Octree construction from surface samples (refinement rule: a node at level
@@ -117,8 +122,9 @@ void ora_encode(const ora_tree* t, const float* x, const float* dir, int64_t B,
 /* Decoder MLP on FP64 inputs h [B][dims[0]] -> out [B][dims[n_layers]]. */
 void ora_mlp_fwd(const ora_mlp* m, const double* h, int64_t B, double* out);
 
-/* Encode + MLP, queries processed in parallel over nthreads (<= 0: all). */
-void ora_query_fwd(const ora_tree* t, const ora_mlp* m, const float* x, const float* dir,
+/* Encode + MLP, queries processed in parallel over nthreads (<= 0: all).
+ * attr: [B][E] decoder attributes appended after h (NULL when E = 0). */
+void ora_query_fwd(const ora_tree* t, const ora_mlp* m, const float* x, const float* dir, const float* attr,
                    int64_t B, double* rgb_out, int32_t nthreads);
 
 /* BSDF sample weight f_r * |n . wi| / pdf for every (b, k): [B][N][3]. */

@@ -54,8 +54,20 @@ class _Batch(C.Structure):
                 ("albedo", C.c_void_p), ("Le", C.c_void_p), ("rough", C.c_void_p),
                 ("x2", C.c_void_p), ("dir2", C.c_void_p), ("wi", C.c_void_p), ("pdf", C.c_void_p),
                 ("target_override", C.c_void_p), ("F0", C.c_float), ("loss_kind", C.c_int32),
-                ("eps", C.c_float), ("grad_through_rhs", C.c_int32)]
+                ("eps", C.c_float), ("grad_through_rhs", C.c_int32), ("attr", C.c_void_p), ("attr2", C.c_void_p)]
 
+
+class _AdamCfg(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("step", C.c_int32), ("work_dtype", C.c_int32)]
+
+
+class _AdamSeg(C.Structure):
+    _fields_ = [("param", C.c_void_p), ("grad", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p),
+                ("work", C.c_void_p), ("n", C.c_int64), ("touched", C.c_void_p), ("block", C.c_int64)]
+
+
+ADAM_MAX_SEGMENTS = 32
 
 _lib = None
 
@@ -70,7 +82,7 @@ def lib():
         L.oo_build_octree.argtypes = [vp, i64, i32, i32, vp, i64, vp, vp]
         L.oo_encode_query.argtypes = [vp, vp, vp, i64, vp, i32, vp, vp]
         L.oo_mlp_fwd.argtypes = [vp, vp, i32, i64, vp, vp]
-        L.oo_query_fwd.argtypes = [vp, vp, vp, vp, i64, vp, vp]
+        L.oo_query_fwd.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
         L.oo_residual_workspace_bytes.argtypes = [vp, vp, vp, C.POINTER(C.c_size_t)]
         sz = C.c_size_t
         L.oo_radiosity_residual_fwd.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
@@ -79,6 +91,8 @@ def lib():
         L.oo_residual_node_indices.argtypes = [vp, vp, vp, vp, sz, vp, vp]
         L.oo_dot_f64.argtypes = [vp, vp, vp, i32, vp, vp, vp]
         L.oo_dot_f64_noalloc.argtypes = [vp, vp, vp, i32, vp, vp]
+        L.oo_adam_step.argtypes = [vp, vp, i32, vp]
+        L.oo_touched_nodes.argtypes = [vp, vp, vp, vp, sz, vp, vp]
         L.oo_profile_begin.argtypes = [i32]
         L.oo_profile_end.argtypes = [vp, vp]
         L.oo_profile_kind_name.argtypes = [i32]
@@ -87,7 +101,7 @@ def lib():
         for f in ("oo_build_octree", "oo_encode_query", "oo_mlp_fwd", "oo_query_fwd",
                   "oo_residual_workspace_bytes", "oo_radiosity_residual_fwd", "oo_radiosity_residual_bwd",
                   "oo_cast_params", "oo_profile_begin", "oo_profile_end", "oo_residual_node_indices",
-                  "oo_dot_f64", "oo_dot_f64_noalloc"):
+                  "oo_dot_f64", "oo_dot_f64_noalloc", "oo_adam_step", "oo_touched_nodes"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -197,7 +211,8 @@ class MLP:
         return m
 
 
-_BATCH_ARRAYS = ("x", "dir", "n", "wo", "albedo", "Le", "rough", "x2", "dir2", "wi", "pdf", "target_override")
+_BATCH_ARRAYS = ("x", "dir", "n", "wo", "albedo", "Le", "rough", "x2", "dir2", "wi", "pdf", "target_override",
+                 "attr", "attr2")
 
 
 def device_batch(batch: dict) -> dict:
@@ -244,11 +259,12 @@ def mlp_fwd(mlp: MLP, h, W=None):
     return rgb
 
 
-def query_fwd(tree: Tree, mlp: MLP, x, d, feat=None, W=None, out=None):
+def query_fwd(tree: Tree, mlp: MLP, x, d, feat=None, W=None, out=None, attr=None):
+    """attr: [B][E] FP32 surface attributes when the decoder reads them."""
     B = x.shape[0]
     rgb = torch.empty((B, 3), dtype=torch.float32, device="cuda") if out is None else out
     ts, ms = tree.struct(feat), mlp.struct(W)
-    _check(lib().oo_query_fwd(C.byref(ts), C.byref(ms), _ptr(x), _ptr(d), B, _ptr(rgb), _stream()),
+    _check(lib().oo_query_fwd(C.byref(ts), C.byref(ms), _ptr(x), _ptr(d), _ptr(attr), B, _ptr(rgb), _stream()),
            "oo_query_fwd")
     return rgb
 
@@ -348,6 +364,38 @@ def dot_f64_noalloc(a, b=None, out=None):
     return out[:G]
 
 
+def touched_nodes(tree: Tree, mlp: MLP, batch: dict, workspace, touched, feat=None, W=None):
+    """Sets touched[node] = 1 (uint32 device tensor [n_nodes], cleared by
+    the caller) for every node the forward's backward queries read."""
+    ts, ms, bs = tree.struct(feat), mlp.struct(W), batch_struct(batch)
+    assert touched.dtype == torch.int32 and touched.numel() == tree.level_offset[-1]
+    _check(lib().oo_touched_nodes(C.byref(ts), C.byref(ms), C.byref(bs), _ptr(workspace), _nbytes(workspace),
+                                  _ptr(touched), _stream()), "oo_touched_nodes")
+    return touched
+
+
+def adam_step(segments, step, lr=1e-3, beta1=0.9, beta2=0.99, eps=1e-15, work_dtype=torch.float32):
+    """One fused Adam step. segments: list of dicts with FP32 device tensors
+    param, grad, m, v, optional work (working copy) and optional touched
+    (int32 per-block flags, block entries each)."""
+    if len(segments) > ADAM_MAX_SEGMENTS:
+        raise OOError(f"at most {ADAM_MAX_SEGMENTS} segments")
+    arr = (_AdamSeg * max(1, len(segments)))()
+    for i, sg in enumerate(segments):
+        for k in ("param", "grad", "m", "v"):
+            t = sg[k]
+            if t.dtype != torch.float32 or not t.is_contiguous():
+                raise OOError(f"segment {i}: {k} must be a contiguous FP32 tensor")
+        arr[i].param, arr[i].grad = sg["param"].data_ptr(), sg["grad"].data_ptr()
+        arr[i].m, arr[i].v = sg["m"].data_ptr(), sg["v"].data_ptr()
+        arr[i].work = sg["work"].data_ptr() if sg.get("work") is not None else None
+        arr[i].n = sg["param"].numel()
+        arr[i].touched = sg["touched"].data_ptr() if sg.get("touched") is not None else None
+        arr[i].block = int(sg.get("block", 0))
+    cfg = _AdamCfg(float(lr), float(beta1), float(beta2), float(eps), int(step), DTYPE_CODE[work_dtype])
+    _check(lib().oo_adam_step(C.byref(cfg), arr, len(segments), _stream()), "oo_adam_step")
+
+
 PROF_KINDS = 11
 
 
@@ -434,9 +482,10 @@ class OctaOctree(torch.nn.Module):
                 self.work_feat, self.work_W = views[:nf], views[nf:]
             cast_params(self._master, self._work)
 
-    def forward(self, x, d):
-        """Radiance at (x, d) [B][3] (inference; no autograd)."""
-        return query_fwd(self.tree, self.mlp, x, d, feat=self.work_feat, W=self.work_W)
+    def forward(self, x, d, attr=None):
+        """Radiance at (x, d) [B][3] (inference; no autograd); attr: the
+        decoder's surface attributes [B][E] when it reads them."""
+        return query_fwd(self.tree, self.mlp, x, d, feat=self.work_feat, W=self.work_W, attr=attr)
 
     def workspace(self, batch):
         """A workspace for explicit residual_fwd / residual_bwd calls on this
@@ -455,6 +504,29 @@ class OctaOctree(torch.nn.Module):
     def residual(self, batch):
         """Loss of the residual step (0-dim FP64) with autograd to the masters."""
         return RadiosityResidual.apply(self, batch, *self.feat, *self.W, *self.b)
+
+    def adam_segments(self, grads, state, touched=None):
+        """oo_adam_step segments for this model's tables and layers: each
+        level's table lazy over its nodes' flags (touched: int32 [n_nodes],
+        or None for a dense step), weights and biases dense. grads and
+        state['m'] / state['v']: lists shaped like feat + W + b."""
+        params = list(self.feat) + list(self.W) + list(self.b)
+        works = (list(self.work_feat) + list(self.work_W) if self.dtype != torch.float32
+                 else [None] * (len(self.feat) + len(self.W))) + [None] * len(self.b)
+        lo = self.tree.level_offset
+        segs = []
+        for i, p in enumerate(params):
+            sg = dict(param=p.data.view(-1), grad=grads[i].view(-1), m=state["m"][i].view(-1),
+                      v=state["v"][i].view(-1), work=None if works[i] is None else works[i].view(-1))
+            if i < len(self.feat) and touched is not None and lo[i + 1] > lo[i]:
+                sg.update(touched=touched[lo[i]:lo[i + 1]], block=p.numel() // (lo[i + 1] - lo[i]))
+            segs.append(sg)
+        return segs
+
+    def new_adam_state(self):
+        params = list(self.feat) + list(self.W) + list(self.b)
+        return {"m": [torch.zeros_like(p.data) for p in params], "v": [torch.zeros_like(p.data) for p in params],
+                "t": 0}
 
 
 class RadiosityResidual(torch.autograd.Function):

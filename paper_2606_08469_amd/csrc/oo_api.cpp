@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -148,23 +149,27 @@ int check_tree(const oo_tree* t, TreeArgs& A) {
   return OO_OK;
 }
 
-int check_mlp(const oo_mlp* m, int K0, MlpArgs& A) {
+// LC: the level features' width n_levels * C; the rest of dims[0] are the
+// decoder's surface attributes.
+int check_mlp(const oo_mlp* m, int LC, MlpArgs& A) {
   if (!m) return fail(OO_EINVAL, "mlp is NULL");
   if (m->n_layers < 2 || m->n_layers > 5) return fail(OO_EUNSUPPORTED, "n_layers must be in [2, 5], got %d", m->n_layers);
   if (m->dtype != OO_F32 && m->dtype != OO_F16 && m->dtype != OO_BF16)
     return fail(OO_EINVAL, "unknown mlp dtype %d", (int)m->dtype);
-  if (m->dims[0] != K0) return fail(OO_EINVAL, "dims[0] = %d must equal n_levels * C = %d", m->dims[0], K0);
+  const int K0 = m->dims[0];
+  if (K0 < LC) return fail(OO_EINVAL, "dims[0] = %d is smaller than n_levels * C = %d", K0, LC);
   if (K0 > 128) return fail(OO_EUNSUPPORTED, "input width %d > 128", K0);
+  if (K0 % 4) return fail(OO_EUNSUPPORTED, "input width %d must be a multiple of 4 (pad the attributes)", K0);
   if (m->dims[m->n_layers] != 3) return fail(OO_EINVAL, "last dim must be 3, got %d", m->dims[m->n_layers]);
   const int H = m->dims[1];
   for (int i = 1; i < m->n_layers; ++i)
     if (m->dims[i] != H) return fail(OO_EUNSUPPORTED, "hidden widths must all be equal");
   if (H != 64 && H != 128) return fail(OO_EUNSUPPORTED, "hidden width must be 64 or 128, got %d", H);
-  if (H == 128 && m->n_layers > 3) return fail(OO_EUNSUPPORTED, "width 128 supports at most 2 hidden layers");
   for (int i = 0; i < m->n_layers; ++i)
     if (!m->W[i] || !m->b[i]) return fail(OO_EINVAL, "W[%d] or b[%d] is NULL", i, i);
   A.n_layers = m->n_layers;
   A.K0 = K0;
+  A.E = K0 - LC;
   A.H = H;
   for (int i = 0; i < OO_MAX_LAYERS; ++i) {
     A.W[i] = i < m->n_layers ? m->W[i] : nullptr;
@@ -176,7 +181,6 @@ int check_mlp(const oo_mlp* m, int K0, MlpArgs& A) {
 int check_pair(const oo_tree* t, const oo_mlp* m) {
   if (t->feat_dtype != m->dtype)
     return fail(OO_EUNSUPPORTED, "feature dtype %d and MLP dtype %d must match", (int)t->feat_dtype, (int)m->dtype);
-  if (t->feat_dtype != OO_F32 && t->C != 8) return fail(OO_EUNSUPPORTED, "16-bit tables need C = 8");
   return OO_OK;
 }
 
@@ -205,6 +209,15 @@ int check_batch(const oo_residual_batch* b, ResidualArgs& A) {
   A.F0 = b->F0;
   A.loss_kind = b->loss_kind;
   A.eps = b->eps;
+  return OO_OK;
+}
+
+// The surface attributes that the decoder reads: of the LHS queries, and of
+// the secondary hits when the RHS is estimated.
+int check_attrs(const oo_residual_batch* b, const ResidualArgs& A, const MlpArgs& M) {
+  if (M.E == 0 || A.B == 0) return OO_OK;
+  if (!b->attr) return fail(OO_EINVAL, "attr is required: the decoder reads %d surface attributes", M.E);
+  if (A.N > 0 && !b->attr2) return fail(OO_EINVAL, "attr2 is required when N > 0 without target_override");
   return OO_OK;
 }
 
@@ -269,8 +282,8 @@ Workspace workspace_layout(const MlpArgs& M, oo_dtype md, const oo_residual_batc
   o = align256(o + (size_t)Qb * sizeof(float2));
   w.pos = o;  // paper's scheme: position of every backward query, [Qb]
   o = align256(o + (paper ? (size_t)Qb * sizeof(float4) : 0));
-  w.dh = o;  // dLoss/dh of every backward query, [Qb][K0] FP32
-  o = align256(o + (size_t)Qb * M.K0 * sizeof(float));
+  w.dh = o;  // dLoss/dh of every backward query, [Qb][L C] FP32
+  o = align256(o + (size_t)Qb * L * tree->C * sizeof(float));
   const size_t esz = md == OO_F32 ? 4 : 2;
   for (int i = 0; i < M.n_layers; ++i) {
     w.wt[i] = o;
@@ -468,7 +481,6 @@ int oo_mlp_fwd(const oo_mlp* mlp, const void* h, oo_dtype h_dtype, int64_t B, fl
   int rc = check_mlp(mlp, mlp->dims[0], M);
   if (rc) return rc;
   if (h_dtype != mlp->dtype) return fail(OO_EINVAL, "h_dtype must equal mlp->dtype");
-  if (mlp->dims[0] % 4) return fail(OO_EUNSUPPORTED, "input width must be a multiple of 4");
   if (B < 0) return fail(OO_EINVAL, "B must be >= 0");
   if (B == 0) return OO_OK;
   if (!h || !rgb_out) return fail(OO_EINVAL, "h and rgb_out are required");
@@ -476,8 +488,8 @@ int oo_mlp_fwd(const oo_mlp* mlp, const void* h, oo_dtype h_dtype, int64_t B, fl
   return hip_status(launch_mlp(M, mlp->dtype, h, B, rgb_out, stream), "mlp_fwd launch");
 }
 
-int oo_query_fwd(const oo_tree* tree, const oo_mlp* mlp, const float* x, const float* dir, int64_t B, float* rgb_out,
-                 hipStream_t stream) {
+int oo_query_fwd(const oo_tree* tree, const oo_mlp* mlp, const float* x, const float* dir, const float* attr, int64_t B,
+                 float* rgb_out, hipStream_t stream) {
   g_err[0] = 0;
   TreeArgs T;
   MlpArgs M;
@@ -488,7 +500,10 @@ int oo_query_fwd(const oo_tree* tree, const oo_mlp* mlp, const float* x, const f
   if (B < 0) return fail(OO_EINVAL, "B must be >= 0");
   if (B == 0) return OO_OK;
   if (!x || !dir || !rgb_out) return fail(OO_EINVAL, "x, dir and rgb_out are required");
+  if (M.E > 0 && !attr) return fail(OO_EINVAL, "attr is required: the decoder reads %d surface attributes", M.E);
   QuerySrc src{x, dir, B, x, dir};
+  src.gA = src.gB = attr;
+  src.E = M.E;
   ProfScope ps(OO_PROF_QUERY, stream);
   return hip_status(launch_query(T, tree->feat_dtype, M, mlp->dtype, src, B, rgb_out, nullptr, nullptr, nullptr, 0,
                                  stream),
@@ -522,6 +537,7 @@ int oo_radiosity_residual_fwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   if ((rc = check_mlp(mlp, tree->n_levels * tree->C, M))) return rc;
   if ((rc = check_pair(tree, mlp))) return rc;
   if ((rc = check_batch(batch, A))) return rc;
+  if ((rc = check_attrs(batch, A, M))) return rc;
   if (!loss_out || !workspace) return fail(OO_EINVAL, "loss_out and workspace are required");
   if (A.B > 0 && (!lhs_out || !rhs_out || !resid_out)) return fail(OO_EINVAL, "lhs_out, rhs_out, resid_out are required");
   const Workspace w = workspace_layout(M, mlp->dtype, batch, tree);
@@ -535,6 +551,9 @@ int oo_radiosity_residual_fwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   const int64_t Q = A.B * (1 + A.N);
   if (Q > INT32_MAX) return fail(OO_EUNSUPPORTED, "B (1 + N) = %lld exceeds 2^31 - 1 queries", (long long)Q);
   QuerySrc src{batch->x, batch->dir, A.B, A.N > 0 ? batch->x2 : batch->x, A.N > 0 ? batch->dir2 : batch->dir};
+  src.gA = batch->attr;
+  src.gB = A.N > 0 ? batch->attr2 : batch->attr;
+  src.E = M.E;
   // bucket the queries by octree cell (LHS first) and evaluate them in that
   // order: Lq and the stored node indices are in sorted order
   int32_t* order = reinterpret_cast<int32_t*>(ws + w.order);
@@ -573,6 +592,7 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   if ((rc = check_mlp(mlp, tree->n_levels * tree->C, M))) return rc;
   if ((rc = check_pair(tree, mlp))) return rc;
   if ((rc = check_batch(batch, A))) return rc;
+  if ((rc = check_attrs(batch, A, M))) return rc;
   if (!grad_loss || !dfeat || !dW || !db || !workspace) return fail(OO_EINVAL, "NULL argument");
   if (A.B == 0) return OO_OK;
   if (!resid || !rhs) return fail(OO_EINVAL, "resid and rhs are required");
@@ -629,7 +649,12 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
     for (int c = 0; c < nc; ++c) {
       const int64_t q0 = c * chunk, qn = std::min(Qb - q0, chunk);
       if (qn <= 0) break;
-      BwdArgs B{qn, nidx + q0, Qb, uv + q0, pos + q0, seeds, order + q0, Qb, partials, dh + q0 * M.K0, c > 0};
+      const int64_t LC = (int64_t)tree->n_levels * tree->C;
+      BwdArgs B{qn, nidx + q0, Qb, uv + q0, pos + q0, seeds, order + q0, Qb, partials, dh + q0 * LC, c > 0};
+      B.gA = batch->attr;
+      B.gB = A.N > 0 ? batch->attr2 : batch->attr;
+      B.nA = A.B;
+      B.n_src = A.B * (1 + A.N);
       {
         ProfScope ps(OO_PROF_BACKWARD, stream);
         e = launch_bwd(T, tree->feat_dtype, M, mlp->dtype, Wt, B, w.PL, w.grid, stream);
@@ -643,7 +668,7 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
       }
       {
         ProfScope ps(OO_PROF_SCATTER, ss);
-        e = launch_scatter(T, qn, nidx + q0, Qb, uv + q0, pos + q0, dh + q0 * M.K0, post_scale, G, ss);
+        e = launch_scatter(T, qn, nidx + q0, Qb, uv + q0, pos + q0, dh + q0 * LC, post_scale, G, ss);
       }
       if (e != hipSuccess) return hip_status(e, "scatter launch");
     }
@@ -744,6 +769,65 @@ int oo_dot_f64_noalloc(const float* const* a, const float* const* b, const int64
   if (e != hipSuccess) return hip_status(e, "static partials lookup");
   // every partial is overwritten by the launch: nothing to clear
   return hip_status(launch_dot(D, n_groups, partials, out, stream), "dot launch");
+}
+
+int oo_adam_step(const oo_adam_config* cfg, const oo_adam_segment* segs, int32_t n_segs, hipStream_t stream) {
+  g_err[0] = 0;
+  if (!cfg) return fail(OO_EINVAL, "cfg is NULL");
+  if (n_segs < 0 || n_segs > OO_ADAM_MAX_SEGMENTS)
+    return fail(OO_EINVAL, "n_segs must be in [0, %d], got %d", OO_ADAM_MAX_SEGMENTS, n_segs);
+  if (cfg->step < 1) return fail(OO_EINVAL, "step must be >= 1, got %d", cfg->step);
+  if (!(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) || !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f))
+    return fail(OO_EINVAL, "beta1 and beta2 must be in [0, 1)");
+  if (!(cfg->eps >= 0.0f) || !(cfg->lr >= 0.0f)) return fail(OO_EINVAL, "lr and eps must be >= 0");
+  if (cfg->work_dtype != OO_F32 && cfg->work_dtype != OO_F16 && cfg->work_dtype != OO_BF16)
+    return fail(OO_EINVAL, "unknown work_dtype");
+  if (n_segs == 0) return OO_OK;
+  if (!segs) return fail(OO_EINVAL, "segments is NULL");
+  AdamArgs A;
+  A.n_segs = n_segs;
+  A.first[0] = 0;
+  for (int s = 0; s < n_segs; ++s) {
+    const oo_adam_segment& S = segs[s];
+    if (S.n < 0) return fail(OO_EINVAL, "segment %d: n must be >= 0", s);
+    if (S.n > 0 && (!S.param || !S.grad || !S.m || !S.v))
+      return fail(OO_EINVAL, "segment %d: param, grad, m and v are required", s);
+    if (S.touched && (S.block <= 0 || S.block % 4))
+      return fail(OO_EINVAL, "segment %d: block must be a positive multiple of 4 with touched flags", s);
+    A.seg[s] = AdamSeg{S.param, S.grad, S.m, S.v, S.work, S.n, S.touched, S.block};
+    A.first[s + 1] = A.first[s] + (S.n + 3) / 4;
+  }
+  A.lr = cfg->lr;
+  A.b1 = cfg->beta1;
+  A.b2 = cfg->beta2;
+  A.eps = cfg->eps;
+  A.inv_c1 = (float)(1.0 / (1.0 - std::pow((double)cfg->beta1, (double)cfg->step)));
+  A.inv_c2 = (float)(1.0 / (1.0 - std::pow((double)cfg->beta2, (double)cfg->step)));
+  return hip_status(launch_adam(A, cfg->work_dtype, stream), "adam launch");
+}
+
+int oo_touched_nodes(const oo_tree* tree, const oo_mlp* mlp, const oo_residual_batch* batch, const void* workspace,
+                     size_t workspace_bytes, uint32_t* touched, hipStream_t stream) {
+  g_err[0] = 0;
+  TreeArgs T;
+  MlpArgs M;
+  ResidualArgs A;
+  int rc = check_tree(tree, T);
+  if (rc) return rc;
+  if ((rc = check_mlp(mlp, tree->n_levels * tree->C, M))) return rc;
+  if ((rc = check_pair(tree, mlp))) return rc;
+  if ((rc = check_batch(batch, A))) return rc;
+  if (!workspace) return fail(OO_EINVAL, "workspace is required");
+  const Workspace w = workspace_layout(M, mlp->dtype, batch, tree);
+  if (workspace_bytes < w.total)
+    return fail(OO_EINVAL, "workspace of %zu bytes is smaller than the %zu this problem needs", workspace_bytes,
+                w.total);
+  if (w.Qb == 0) return OO_OK;
+  if (!touched) return fail(OO_EINVAL, "touched is required");
+  const char* ws = static_cast<const char*>(workspace);
+  return hip_status(launch_touched(reinterpret_cast<const int32_t*>(ws + w.nidx), w.Qb, (int64_t)tree->n_levels * w.K,
+                                   tree->level_offset[tree->n_levels], touched, stream),
+                    "touched nodes launch");
 }
 
 int oo_cast_params(const float* src, void* dst, oo_dtype dst_dtype, int64_t n, hipStream_t stream) {

@@ -189,7 +189,10 @@ __device__ inline void store_tq(MT* buf, const f32x4 (&acc)[MT2], int m0, int n_
 // W_0^T and W_0 are packed into LDS once per workgroup (their per-tile
 // fragment loads from L2 dominated the layer chains); the output layer's
 // weights are read from L2.
-template <class TT, class MT, int C, int H, bool WL, bool PAPER>
+// NHH: hidden-to-hidden layers whose dW the kernel accumulates in registers
+// (up to 3 at width 64; at width 128 one, or three for a four-hidden-layer
+// decoder).
+template <class TT, class MT, int C, int H, bool WL, bool PAPER, int NHH>
 __global__ __launch_bounds__(64 * bwd_waves<MT>()) void bwd_kernel(const TreeArgs T, const MlpArgs M, const MlpArgs Mt,
                                                              const BwdArgs A, const ParamLayout PL) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -207,11 +210,10 @@ __global__ __launch_bounds__(64 * bwd_waves<MT>()) void bwd_kernel(const TreeArg
   constexpr int MH = H / 16, MH2 = MH / kMSplit;
   constexpr int U0 = (MH * 8 + NW - 1) / NW, UH = (MH * MH + NW - 1) / NW;
   constexpr int UO = (MH + NW - 1) / NW;
-  constexpr int NHH = H == 128 ? 1 : 3;  // hidden-to-hidden layers supported
   const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, r16 = lane & 15;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: scalar branches
   const int nt = wave & 3, mh = wave >> 2, col = 16 * nt + r16;  // mh = 0 with 4 waves
-  const int K0 = M.K0, NL = M.n_layers, L = T.L;
+  const int K0 = M.K0, NL = M.n_layers, L = T.L, LC = L * C;
   const BwdLayout lay = bwd_layout(K0, H, NL, L, (int)sizeof(MT));
   const int KB0 = lay.KB0, R0 = lay.R0;
   MT* const act0 = reinterpret_cast<MT*>(smem + lay.act0);
@@ -320,6 +322,15 @@ __global__ __launch_bounds__(64 * bwd_waves<MT>()) void bwd_kernel(const TreeArg
             for (int c = 0; c < C; ++c) act0[tq_index(l * C + c, ql)] = from_f32<MT>(h[gi][c]);
           }
         }
+      }
+      // the decoder's surface attributes, rows L C .. K0 - 1, read in the
+      // caller's query order
+      if (M.E > 0) {
+        int64_t qs = q < Q ? (order ? (int64_t)order[q] : q) : -1;
+        const float* gp = (qs < 0 || qs >= A.n_src) ? nullptr : (qs < A.nA ? A.gA + M.E * qs : A.gB + M.E * (qs - A.nA));
+        for (int k = 4 * part; k < M.E; k += 4 * kLanesPerQuery)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) act0[tq_index(LC + k + c, ql)] = from_f32<MT>(gp ? gp[k + c] : 0.0f);
       }
     }
     __syncthreads();
@@ -436,8 +447,10 @@ __global__ __launch_bounds__(64 * bwd_waves<MT>()) void bwd_kernel(const TreeArg
         __syncthreads();  // every wave has read din(i) and a_i
         store_tq<MT, MH2>(act(i), dacc, mh * MH2, MH, H, nt, ln, false);
       } else {
-        constexpr int MK2 = 8 / kMSplit;  // up to 8 row tiles of dh (K0 <= 128)
-        const int MK = (K0 + 15) / 16;
+        // dh = W_0^T delta_1 over the level-feature rows only: the surface
+        // attributes are inputs, not parameters
+        constexpr int MK2 = 8 / kMSplit;  // up to 8 row tiles of dh (L C <= 128)
+        const int MK = (LC + 15) / 16;
         f32x4 dacc[MK2];
 #pragma unroll
         for (int mi = 0; mi < MK2; ++mi) dacc[mi] = z4;
@@ -457,8 +470,8 @@ __global__ __launch_bounds__(64 * bwd_waves<MT>()) void bwd_kernel(const TreeArg
 #pragma unroll
           for (int mi = 0; mi < MK2; ++mi) {
             const int k = 16 * (mh * MK2 + mi) + 4 * gs;
-            if (mh * MK2 + mi < MK && k < K0)
-              *reinterpret_cast<float4*>(dh_out + q * K0 + k) = make_float4(dacc[mi][0], dacc[mi][1], dacc[mi][2], dacc[mi][3]);
+            if (mh * MK2 + mi < MK && k < LC)
+              *reinterpret_cast<float4*>(dh_out + q * LC + k) = make_float4(dacc[mi][0], dacc[mi][1], dacc[mi][2], dacc[mi][3]);
           }
         }
       }
@@ -680,8 +693,11 @@ static hipError_t launch_bwd_t(const TreeArgs& T, const MlpArgs& M, const MlpArg
   bool wl;
   const size_t lds = bwd_lds_total(M.K0, H, M.n_layers, T.L, (int)sizeof(MT), wl);
   const bool paper = T.interp == OO_INTERP_PAPER;
-  auto k = wl ? (paper ? bwd_kernel<TT, MT, C, H, true, true> : bwd_kernel<TT, MT, C, H, true, false>)
-              : (paper ? bwd_kernel<TT, MT, C, H, false, true> : bwd_kernel<TT, MT, C, H, false, false>);
+  constexpr int NH = H == 128 ? 1 : 3;
+  auto k = wl ? (paper ? bwd_kernel<TT, MT, C, H, true, true, NH> : bwd_kernel<TT, MT, C, H, true, false, NH>)
+              : (paper ? bwd_kernel<TT, MT, C, H, false, true, NH> : bwd_kernel<TT, MT, C, H, false, false, NH>);
+  if (H == 128 && M.n_layers > 3)  // four hidden layers: their weights do not fit in LDS
+    k = paper ? bwd_kernel<TT, MT, C, H, false, true, 3> : bwd_kernel<TT, MT, C, H, false, false, 3>;
   hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k, dim3(grid), dim3(64 * bwd_waves<MT>()), lds, st, T, M, Mt, A, PL);
   return hipGetLastError();
@@ -702,8 +718,10 @@ hipError_t launch_bwd(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype
   if (td == OO_F32)
     return T.C == 4 ? launch_bwd_c<float, float, 4>(T, M, Mt, A, PL, grid, st)
                     : launch_bwd_c<float, float, 8>(T, M, Mt, A, PL, grid, st);
-  if (td == OO_F16) return launch_bwd_c<f16, f16, 8>(T, M, Mt, A, PL, grid, st);
-  return launch_bwd_c<bf16, bf16, 8>(T, M, Mt, A, PL, grid, st);
+  if (td == OO_F16)
+    return T.C == 4 ? launch_bwd_c<f16, f16, 4>(T, M, Mt, A, PL, grid, st) : launch_bwd_c<f16, f16, 8>(T, M, Mt, A, PL, grid, st);
+  return T.C == 4 ? launch_bwd_c<bf16, bf16, 4>(T, M, Mt, A, PL, grid, st)
+                  : launch_bwd_c<bf16, bf16, 8>(T, M, Mt, A, PL, grid, st);
   (void)md;
 }
 

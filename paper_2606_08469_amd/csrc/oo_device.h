@@ -28,7 +28,8 @@ struct TreeArgs {
 // Kernel-argument copy of oo_mlp.
 struct MlpArgs {
   int32_t n_layers;  // Linear layers; n_layers - 1 hidden layers of width H
-  int32_t K0;        // input width (levels * C)
+  int32_t K0;        // input width: levels * C features, then E surface attributes
+  int32_t E;
   int32_t H;
   const void* W[kMaxLayers];  // [out][in] row-major, MT
   const float* b[kMaxLayers];
@@ -45,8 +46,12 @@ struct QuerySrc {
   const float* dB;
   // When set, query i is the source query idx[i] (a permutation into the
   // n queries above); an index outside [0, n) reads as x = 0, dir = +z.
-  const int32_t* idx;
-  int64_t n;
+  const int32_t* idx = nullptr;
+  int64_t n = 0;
+  // the decoder's E surface attributes per query, [nA][E] and [.][E]
+  const float* gA = nullptr;
+  const float* gB = nullptr;
+  int32_t E = 0;
 };
 
 __device__ inline int64_t source_query(const QuerySrc& s, int64_t i) {
@@ -81,6 +86,15 @@ __device__ inline void load_query(const QuerySrc& s, int64_t i, float x[3], floa
     x[a] = xp[a];
     d[a] = dp[a];
   }
+}
+
+// Surface attributes k .. k + 3 of query i (zeros for an index outside the
+// sources).
+__device__ inline void load_attr4(const QuerySrc& s, int64_t i, int k, float v[4]) {
+  const int64_t q = source_query(s, i);
+  const float* gp = q < 0 ? nullptr : (q < s.nA ? s.gA + s.E * q : s.gB + s.E * (q - s.nA));
+#pragma unroll
+  for (int c = 0; c < 4; ++c) v[c] = gp ? gp[k + c] : 0.0f;
 }
 
 // ---------------------------------------------------------------------------

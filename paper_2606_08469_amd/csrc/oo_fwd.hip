@@ -277,6 +277,12 @@ __global__ __launch_bounds__(512) void query_kernel(const TreeArgs T, const MlpA
         if (keep) idx_out[l * n_idx + q] = node;  // level-major: coalesced across lanes
       });
     }
+    // the decoder's surface attributes follow the level features
+    for (int k = 0; k < M.E; k += 4) {
+      float g4[4] = {0.f, 0.f, 0.f, 0.f};
+      if (valid) load_attr4(src, q, k, g4);
+      htile_put4<MT>(htile, KB0, lane, M.K0 - M.E + k, g4);
+    }
     wave_lds_sync();
 #pragma unroll
     for (int t0 = 0; t0 < 4; t0 += NT) {
@@ -641,8 +647,11 @@ hipError_t launch_query(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dty
   if (td == OO_F32)
     return T.C == 4 ? launch_query_c<float, float, 4>(T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx, st)
                     : launch_query_c<float, float, 8>(T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx, st);
-  if (td == OO_F16) return launch_query_c<f16, f16, 8>(T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx, st);
-  return launch_query_c<bf16, bf16, 8>(T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx, st);
+  if (td == OO_F16)
+    return T.C == 4 ? launch_query_c<f16, f16, 4>(T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx, st)
+                    : launch_query_c<f16, f16, 8>(T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx, st);
+  return T.C == 4 ? launch_query_c<bf16, bf16, 4>(T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx, st)
+                  : launch_query_c<bf16, bf16, 8>(T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx, st);
   (void)md;
 }
 

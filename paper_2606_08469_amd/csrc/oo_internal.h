@@ -99,8 +99,13 @@ struct BwdArgs {
   const int32_t* order;
   int64_t n_seed;
   float* partials;
-  float* dh;
+  float* dh;            // [Q][L C]: dLoss/dh of the level features
   int accumulate;
+  // the decoder's surface attributes in the caller's query order: [nA][E]
+  // for the first nA queries, [n_src - nA][E] for the rest
+  const float* gA = nullptr;
+  const float* gB = nullptr;
+  int64_t nA = 0, n_src = 0;
 };
 hipError_t launch_bwd(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, void* const* Wt,
                       const BwdArgs& A, const ParamLayout& PL, int grid, hipStream_t st);
@@ -125,5 +130,24 @@ hipError_t launch_dot(const DotArgs& D, int n_groups, double* partials, double* 
 constexpr int kMaxDevices = 64;
 hipError_t dot_scratch(double** partials);
 hipError_t launch_pad_fold(const TreeArgs& T, const GradArgs& G, hipStream_t st);
+
+// Optimiser step: segments and the thread range each owns (4 elements per
+// thread), hyper-parameters with the bias corrections folded in.
+struct AdamSeg {
+  float *param, *grad, *m, *v;
+  void* work;
+  int64_t n;
+  const uint32_t* touched;
+  int64_t block;
+};
+struct AdamArgs {
+  int32_t n_segs;
+  AdamSeg seg[OO_ADAM_MAX_SEGMENTS];
+  int64_t first[OO_ADAM_MAX_SEGMENTS + 1];
+  float lr, b1, b2, eps, inv_c1, inv_c2;
+};
+hipError_t launch_adam(const AdamArgs& A, oo_dtype work_dtype, hipStream_t st);
+hipError_t launch_touched(const int32_t* nidx, int64_t n, int64_t rows, int64_t n_nodes, uint32_t* touched,
+                          hipStream_t st);
 
 }  // namespace oo

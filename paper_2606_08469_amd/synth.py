@@ -12,7 +12,12 @@ network or residual). It only produces FP32 inputs and FP32 initial
 parameters, identical for the GPU library and the CPU oracle. All randomness
 comes from ``numpy.random.default_rng(1000 * config + k)`` with k = 0 scene,
 1 tree samples, 2 queries, 3 feature tables, 4 BSDF inputs and targets,
-5 MLP weights, 6 index subsets.
+5 MLP weights, 6 index subsets, 7 materials of rendered pixels.
+
+Configs with ``gbuf`` feed the decoder the paper's surface attributes
+g = [x, w_r, n, a, alpha] (Sec. 3.5) after the level features: 13 values per
+query, stored with 3 zero columns (``G_WIDTH``) so that the decoder's input
+width stays a multiple of 4.
 """
 from __future__ import annotations
 
@@ -46,6 +51,10 @@ class Config:
     table_dtype: str = "f32"
     mlp_dtype: str = "f32"
     hot: float = 1.0         # extra sample density on four detailed objects
+    gbuf: bool = False       # decoder also reads the surface attributes g
+    lookup: str = "wo"       # lookup direction: "wo" (outgoing) or "mirror" (w_r)
+    loss_kind: int = 0       # 0 mean L2, 1 relative L2
+    interp: int = 0          # 0 node + bilinear texels, 1 the paper's (8 cells, vertex maps)
 
 
 CONFIGS = {
@@ -64,7 +73,22 @@ CONFIGS = {
               (64, 64, 64, 32, 32, 32, 16, 8, 4, 2, 2), 8, 32, 9_500_000, 0.7,
               (88, 128, 128, 3), "train", 1 << 20, 8, rough=(0.02, 0.2),
               table_dtype="f16", mlp_dtype="f16", hot=8.0),
+    # The paper's network and loss (Sec. 3.5, Sec. 3.6, Sec. 4 implementation
+    # details): 8 levels of 4 channels with vertex maps from 257^2 down to
+    # 3^2, the 13 surface attributes, four hidden layers of width 128,
+    # relative L2, lookup along the mirror direction, 65536 LHS points with
+    # 32 secondary samples each (the first quarter of its schedule).
+    6: Config(6, "train-paper-decoder", "room16", 6, 7, (256, 128, 64, 32, 16, 8, 4, 2), 4, 32,
+              9_500_000, 0.7, (8 * 4 + 16, 128, 128, 128, 128, 3), "train", 1 << 16, 32, rough=(0.02, 0.2),
+              table_dtype="f16", mlp_dtype="f16", hot=8.0, gbuf=True, lookup="mirror", loss_kind=1, interp=1),
 }
+
+G_ATTRS = 13   # x, w_r, n, albedo, roughness
+G_WIDTH = 16   # stored width: the attributes, then zeros
+
+# The paper's batch schedule (Sec. 4): every quarter of training halves the
+# LHS points and doubles the secondary samples per point.
+PAPER_SCHEDULE = ((1 << 16, 32), (1 << 15, 64), (1 << 14, 128), (1 << 13, 256))
 
 
 def rng(cfg: int, k: int) -> np.random.Generator:
@@ -303,6 +327,16 @@ def reflect(wo, n):
     return 2.0 * np.einsum("ij,ij->i", wo, n)[:, None] * n - wo
 
 
+def gbuffer(x, wr, n, albedo, rough):
+    """Surface attributes [x, w_r, n, a, alpha] per query, FP32 [m][G_WIDTH]
+    (the last G_WIDTH - G_ATTRS columns zero)."""
+    m = len(x)
+    g = np.zeros((m, G_WIDTH), np.float32)
+    g[:, 0:3], g[:, 3:6], g[:, 6:9] = x, wr, n
+    g[:, 9:12], g[:, 12] = albedo, np.asarray(rough).reshape(m)
+    return g
+
+
 # --------------------------------------------------------------------------
 # Workloads
 # --------------------------------------------------------------------------
@@ -341,6 +375,22 @@ def render_queries(cfg: Config):
     return np.clip(p, 0.0, 1.0).astype(np.float32), wr.astype(np.float32)
 
 
+def render_gbuffer(cfg: Config):
+    """Queries and surface attributes of the rendered pixels: (x, w_r, g),
+    with a seeded albedo and roughness per pixel."""
+    scene = make_scene(CONFIGS[cfg.tree_cfg])
+    eye = np.array([0.5, 0.06, 0.45])
+    d = camera_rays(cfg.width, cfg.height, eye, [0.5, 0.9, 0.4])
+    p, n, t = cast(scene, np.tile(eye, (len(d), 1)), d)
+    assert np.isfinite(t).all()
+    x = np.clip(p, 0.0, 1.0).astype(np.float32)
+    wr = _unit(reflect(-d, n)).astype(np.float32)
+    gm = rng(cfg.idx, 7)
+    albedo = gm.uniform(0.05, 0.95, (len(x), 3))
+    rough = gm.uniform(cfg.rough[0], cfg.rough[1], len(x))
+    return x, wr, gbuffer(x, wr, n, albedo, rough)
+
+
 def train_batch(cfg: Config):
     """Neural-radiosity training batch: LHS points with BSDF inputs and, when
     N > 0, N cosine-sampled secondary hits each; config 1 instead carries
@@ -356,9 +406,9 @@ def train_batch(cfg: Config):
     else:
         wo, _ = cosine_hemisphere(n, g, 1)
         wo = wo[:, 0]
-        d = wo
+        d = _unit(reflect(wo, n)) if cfg.lookup == "mirror" else wo
     out = dict(x=x.astype(np.float32), dir=d.astype(np.float32), n=n.astype(np.float32),
-               wo=wo.astype(np.float32), N=N, F0=0.04, loss_kind=0, eps=1e-2, grad_through_rhs=0)
+               wo=wo.astype(np.float32), N=N, F0=0.04, loss_kind=cfg.loss_kind, eps=1e-2, grad_through_rhs=0)
     out["albedo"] = gb.uniform(0.05, 0.95, (B, 3)).astype(np.float32)
     out["rough"] = gb.uniform(cfg.rough[0], cfg.rough[1], B).astype(np.float32)
     le = np.zeros((B, 3))
@@ -368,16 +418,27 @@ def train_batch(cfg: Config):
     if N == 0:
         out["target_override"] = gb.uniform(0.0, 1.0, (B, 3)).astype(np.float32)
         out["x2"] = out["dir2"] = out["wi"] = out["pdf"] = None
+        if cfg.gbuf:
+            out["attr"] = gbuffer(x, d, n, out["albedo"], out["rough"])
         return out
     wi, cos = cosine_hemisphere(n, g, N)                       # [B][N][3]
     o = np.repeat(x + 1e-4 * n, N, axis=0)
-    p, _, t = cast(scene, o, wi.reshape(-1, 3))
+    p, n2, t = cast(scene, o, wi.reshape(-1, 3))
     assert np.isfinite(t).all()
-    out["x2"] = np.clip(p, 0.0, 1.0).reshape(B, N, 3).astype(np.float32)
-    out["dir2"] = (-wi).astype(np.float32)
+    x2 = np.clip(p, 0.0, 1.0)
+    # at the hit the outgoing direction points back along the sample
+    wo2 = -wi.reshape(-1, 3)
+    d2 = _unit(reflect(wo2, n2)) if cfg.lookup == "mirror" else wo2
+    out["x2"] = x2.reshape(B, N, 3).astype(np.float32)
+    out["dir2"] = d2.reshape(B, N, 3).astype(np.float32)
     out["wi"] = wi.astype(np.float32)
     out["pdf"] = (cos / math.pi).astype(np.float32)
     out["target_override"] = None
+    if cfg.gbuf:
+        albedo2 = gb.uniform(0.05, 0.95, (B * N, 3))
+        rough2 = gb.uniform(cfg.rough[0], cfg.rough[1], B * N)
+        out["attr"] = gbuffer(x, d, n, out["albedo"], out["rough"])
+        out["attr2"] = gbuffer(x2, d2, n2, albedo2, rough2).reshape(B, N, -1)
     return out
 
 

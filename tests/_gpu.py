@@ -111,8 +111,11 @@ def kink_margin_ok(ci: int, x, d, band=KINK_BAND):
     return kink_margin_ok_tree(otree, W, b, x, d, band)
 
 
-def kink_margin_ok_tree(otree, W, b, x, d, band=KINK_BAND):
+def kink_margin_ok_tree(otree, W, b, x, d, band=KINK_BAND, attr=None):
+    """attr: [B][E] surface attributes the decoder reads after h."""
     a = oracle.encode(otree, x, d)[0].astype(np.float64)
+    if attr is not None:
+        a = np.concatenate([a, np.asarray(attr, np.float64).reshape(len(a), -1)], axis=1)
     ok = np.ones(len(a), bool)
     for i in range(len(W) - 1):
         Wi, bi = np.asarray(W[i], np.float64), np.asarray(b[i], np.float64)

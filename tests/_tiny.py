@@ -8,13 +8,16 @@ from paper_2606_08469_amd import synth
 
 
 def tiny_problem(seed=0, D=3, res=(4, 4, 2, 2), C=4, widths=(64, 64), B=64, N=3, tau=4,
-                 n_samples=600, bias_scale=0.0):
+                 n_samples=600, bias_scale=0.0, n_attr=0):
+    """n_attr > 0: the decoder also reads that many surface attributes per
+    query (drawn from a generator of their own, so the rest of the problem
+    is the same as without them)."""
     g = np.random.default_rng(seed)
     samples = (g.uniform(0, 1, (n_samples, 3)) ** 1.5).astype(np.float32)
     nodes, lo = oracle.build_octree(samples, D, tau)
     counts = np.diff(lo)
     feat = [g.normal(0, 0.1, (int(n), R, R, C)).astype(np.float32) for n, R in zip(counts, res)]
-    dims = (len(res) * C,) + tuple(widths) + (3,)
+    dims = (len(res) * C + n_attr,) + tuple(widths) + (3,)
     W = [g.uniform(-1, 1, (o, i)).astype(np.float32) * np.float32(math.sqrt(6 / (i + o)))
          for i, o in zip(dims[:-1], dims[1:])]
     b = [(bias_scale * g.normal(size=o)).astype(np.float32) for o in dims[1:]]
@@ -35,6 +38,11 @@ def tiny_problem(seed=0, D=3, res=(4, 4, 2, 2), C=4, widths=(64, 64), B=64, N=3,
         batch["dir2"] = (-wi).astype(np.float32)
     else:
         batch["wi"] = batch["pdf"] = batch["x2"] = batch["dir2"] = None
+    if n_attr:
+        ga = np.random.default_rng(seed + 7919)
+        batch["attr"] = ga.uniform(-1, 1, (B, n_attr)).astype(np.float32)
+        if N > 0:
+            batch["attr2"] = ga.uniform(-1, 1, (B, N, n_attr)).astype(np.float32)
     tree = oracle.Tree(nodes, lo, list(res), C, feat)
     mlp = oracle.MLP(W, b)
     return tree, mlp, batch

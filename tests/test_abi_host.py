@@ -26,7 +26,7 @@ def L():
 def test_exports_every_declared_symbol(L):
     hdr = open(os.path.join(ROOT, "include", "octaoctree.h")).read()
     names = set(re.findall(r"^\s*(?:int|const char\*)\s+(oo_\w+)\s*\(", hdr, re.M))
-    assert len(names) == 15, names
+    assert len(names) == 17, names
     for n in sorted(names):
         assert hasattr(L, n), n
 
@@ -98,24 +98,24 @@ def test_validation_errors(L):
     stream = None
     x = C.c_void_p(0x4000)
     # B = 0 is a no-op
-    assert L.oo_query_fwd(C.byref(t), C.byref(m), x, x, 0, x, stream) == 0
+    assert L.oo_query_fwd(C.byref(t), C.byref(m), x, x, None, 0, x, stream) == 0
     bad = _tree()
     bad.C = 5
-    assert L.oo_query_fwd(C.byref(bad), C.byref(m), x, x, 16, x, stream) == -1
+    assert L.oo_query_fwd(C.byref(bad), C.byref(m), x, x, None, 16, x, stream) == -1
     bad = _tree()
     bad.res[1] = 3
-    assert L.oo_query_fwd(C.byref(bad), C.byref(m), x, x, 16, x, stream) == -1
+    assert L.oo_query_fwd(C.byref(bad), C.byref(m), x, x, None, 16, x, stream) == -1
     bad = _tree()
     bad.feat[1] = 0x10008  # not 16-byte aligned
-    assert L.oo_query_fwd(C.byref(bad), C.byref(m), x, x, 16, x, stream) == -1
+    assert L.oo_query_fwd(C.byref(bad), C.byref(m), x, x, None, 16, x, stream) == -1
     bad = _tree()
     bad.n_levels = 0
     assert L.oo_encode_query(C.byref(bad), x, x, 4, x, 0, None, stream) == -1
-    assert L.oo_query_fwd(C.byref(t), C.byref(_mlp(K0=20)), x, x, 16, x, stream) == -1     # dims[0] != L*C
-    assert L.oo_query_fwd(C.byref(t), C.byref(_mlp(H=96)), x, x, 16, x, stream) == -4      # width unsupported
-    assert L.oo_query_fwd(C.byref(t), C.byref(_mlp(H=128, n_layers=4)), x, x, 16, x, stream) == -4
-    assert L.oo_query_fwd(C.byref(t), C.byref(_mlp(dtype=binding.BF16)), x, x, 16, x, stream) == -4  # dtype pair
-    assert L.oo_query_fwd(C.byref(t), C.byref(m), x, x, -1, x, stream) == -1
+    assert L.oo_query_fwd(C.byref(t), C.byref(_mlp(K0=20)), x, x, None, 16, x, stream) == -1     # dims[0] != L*C
+    assert L.oo_query_fwd(C.byref(t), C.byref(_mlp(H=96)), x, x, None, 16, x, stream) == -4      # width unsupported
+    assert L.oo_query_fwd(C.byref(t), C.byref(_mlp(H=128, n_layers=6)), x, x, None, 16, x, stream) == -4  # > 5 layers
+    assert L.oo_query_fwd(C.byref(t), C.byref(_mlp(dtype=binding.BF16)), x, x, None, 16, x, stream) == -4  # dtype pair
+    assert L.oo_query_fwd(C.byref(t), C.byref(m), x, x, None, -1, x, stream) == -1
     assert L.oo_cast_params(x, x, 7, 4, stream) == -1
     assert L.oo_cast_params(x, x, 1, -2, stream) == -1
     assert b"" != L.oo_last_error()
@@ -175,6 +175,40 @@ def test_residual_rejects_small_workspace(L):
     assert rc == -1 and b"workspace" in L.oo_last_error()
 
 
+def test_surface_attribute_validation(L):
+    """A decoder wider than the level features reads E = dims[0] - L C
+    surface attributes per query: the query and residual calls refuse a
+    missing attr (and attr2 when the RHS is estimated) before any device
+    work, and an input width that is not a multiple of 4."""
+    t = _tree()
+    x = C.c_void_p(0x4000)
+    wide = _mlp(K0=24 + 16)
+    assert L.oo_query_fwd(C.byref(t), C.byref(wide), x, x, None, 16, x, None) == -1
+    assert b"attr" in L.oo_last_error()
+    assert L.oo_query_fwd(C.byref(t), C.byref(_mlp(K0=24 + 13)), x, x, x, 16, x, None) == -4  # not a multiple of 4
+    assert b"multiple of 4" in L.oo_last_error()
+    assert L.oo_query_fwd(C.byref(t), C.byref(_mlp(K0=132)), x, x, x, 16, x, None) == -4      # wider than 128
+    b = binding._Batch()
+    b.B, b.N = 8, 2
+    b.x = b.dir = b.Le = b.n = b.wo = b.albedo = b.rough = b.x2 = b.dir2 = b.wi = 0x5000
+    n = C.c_size_t(0)
+    assert L.oo_residual_workspace_bytes(C.byref(t), C.byref(wide), C.byref(b), C.byref(n)) == 0
+    p = C.c_void_p(0x5000)
+    ptrs = (C.c_void_p * 8)(*([0x5000] * 8))
+    for attr, attr2, word in ((0, 0, b"attr is"), (0x5000, 0, b"attr2")):
+        b.attr, b.attr2 = attr, attr2
+        rc = L.oo_radiosity_residual_fwd(C.byref(t), C.byref(wide), C.byref(b), p, p, p, p, p, n.value, None)
+        assert rc == -1 and word in L.oo_last_error()
+        rc = L.oo_radiosity_residual_bwd(C.byref(t), C.byref(wide), C.byref(b), p, p, p, ptrs, ptrs, ptrs, p,
+                                         n.value, None)
+        assert rc == -1 and word in L.oo_last_error()
+    # with the target frozen no secondary query is made: attr2 is not needed
+    b.target_override = 0x5000
+    b.attr, b.attr2 = 0x5000, 0
+    rc = L.oo_radiosity_residual_fwd(C.byref(t), C.byref(wide), C.byref(b), p, p, p, p, None, n.value, None)
+    assert rc == -1 and b"loss_out" in L.oo_last_error()
+
+
 def test_dot_and_node_readback_validation(L):
     """Argument checks of oo_dot_f64 and oo_residual_node_indices that fail
     before any device work."""
@@ -202,7 +236,7 @@ def test_interp_scheme_validation_and_workspace(L):
     bad.interp = 2
     assert L.oo_encode_query(C.byref(bad), x, x, 4, x, 0, None, None) == -1
     assert b"interp" in L.oo_last_error()
-    assert L.oo_query_fwd(C.byref(bad), C.byref(m), x, x, 16, x, None) == -1
+    assert L.oo_query_fwd(C.byref(bad), C.byref(m), x, x, None, 16, x, None) == -1
     b = binding._Batch()
     b.B, b.N = 1000, 0
     b.x = b.dir = b.Le = 0x5000
@@ -214,3 +248,23 @@ def test_interp_scheme_validation_and_workspace(L):
     # 7 more node indices per level (3 levels, int32) and 16 B of position per query, 256-byte rounding aside
     extra = 1000 * (3 * 7 * 4 + 16)
     assert extra - 512 <= n1.value - n0.value <= extra + 512, (n0.value, n1.value)
+
+
+def test_adam_validation(L):
+    """oo_adam_step refuses bad hyper-parameters and segments before any
+    launch."""
+    cfg = binding._AdamCfg(1e-3, 0.9, 0.99, 1e-15, 1, binding.F16)
+    segs = (binding._AdamSeg * 2)()
+    for sg in segs:
+        sg.param = sg.grad = sg.m = sg.v = 0x1000
+        sg.n = 64
+    assert L.oo_adam_step(C.byref(cfg), segs, 0, None) == 0                       # nothing to do
+    assert L.oo_adam_step(C.byref(cfg), segs, binding.ADAM_MAX_SEGMENTS + 1, None) == -1
+    bad = binding._AdamCfg(1e-3, 0.9, 0.99, 1e-15, 0, binding.F16)
+    assert L.oo_adam_step(C.byref(bad), segs, 2, None) == -1 and b"step" in L.oo_last_error()
+    bad = binding._AdamCfg(1e-3, 1.0, 0.99, 1e-15, 1, binding.F16)
+    assert L.oo_adam_step(C.byref(bad), segs, 2, None) == -1
+    segs[1].touched, segs[1].block = 0x2000, 6                                     # block not a multiple of 4
+    assert L.oo_adam_step(C.byref(cfg), segs, 2, None) == -1 and b"block" in L.oo_last_error()
+    segs[1].touched, segs[1].param = None, None
+    assert L.oo_adam_step(C.byref(cfg), segs, 2, None) == -1 and b"required" in L.oo_last_error()

@@ -1,0 +1,196 @@
+"""GPU parity of the paper's decoder (Sec. 3.5: the level features followed by
+the surface attributes g = [x, w_r, n, a, alpha], four hidden layers of
+width 128) and loss (Sec. 3.6 relative L2) against the FP64 oracle, through
+the C-ABI: the fused query, the residual step's outputs and every gradient
+group, both interpolation schemes, FP32 element-wise and 16-bit within the
+mixed-precision bars, and the full-size batch of the paper's schedule on
+sampled outputs."""
+import dataclasses
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2606_08469_amd import binding, synth
+from _gpu import (cosine, kink_margin_ok_tree, oracle_tree_for, rel_l2, report, subset_batch, to_np, tree_for)
+from test_gpu_paper import compare_grads, dev, run_residual
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+MIX_TOL = 1e-2
+MIX_COS = 0.999
+PAPER_CI = 6
+
+
+@functools.lru_cache(maxsize=None)
+def setup(scheme: str):
+    """(cfg, feat, W, b, interp) of a decoder that reads the surface
+    attributes: the paper's config (vertex maps, eight cells), or the
+    node + bilinear scheme on the nine-level tree with the same decoder
+    shape."""
+    if scheme == "paper":
+        cfg, interp = synth.CONFIGS[PAPER_CI], binding.INTERP_PAPER
+    else:
+        base = synth.CONFIGS[3]
+        cfg = dataclasses.replace(base, mlp=(len(base.res) * base.C + synth.G_WIDTH, 128, 128, 128, 128, 3),
+                                  gbuf=True, lookup="mirror", loss_kind=1)
+        interp = binding.INTERP_NODE_BILINEAR
+    _, lo = oracle_tree_for(cfg.tree_cfg)
+    feat = synth.init_tables(cfg, np.diff(lo), vertices=interp == binding.INTERP_PAPER)
+    W, b = synth.init_mlp(cfg)
+    return cfg, feat, W, b, interp
+
+
+def models(scheme, dtype=torch.float32, W=None):
+    cfg, feat, W0, b, interp = setup(scheme)
+    W = W0 if W is None else W
+    _, nodes, lo = tree_for(cfg.tree_cfg)
+    onodes, olo = oracle_tree_for(cfg.tree_cfg)
+    gpu = binding.OctaOctree(nodes, lo, list(cfg.res), cfg.C, feat, W, b, dtype=dtype, interp=interp)
+    otree = oracle.Tree(onodes, olo, list(cfg.res), cfg.C, feat, interp=interp)
+    return gpu, otree, oracle.MLP(W, b)
+
+
+@functools.lru_cache(maxsize=None)
+def batch_for(scheme: str, B: int, N: int | None = None):
+    cfg = setup(scheme)[0]
+    cfg = dataclasses.replace(cfg, B=B, N=cfg.N if N is None else N)
+    return synth.train_batch(cfg)
+
+
+def kink_safe(otree, W, b, batch, full):
+    ok = kink_margin_ok_tree(otree, W, b, batch["x"], batch["dir"], attr=batch["attr"])
+    N = int(batch.get("N", 0))
+    if full and N > 0:
+        ok2 = kink_margin_ok_tree(otree, W, b, batch["x2"].reshape(-1, 3), batch["dir2"].reshape(-1, 3),
+                                  attr=batch["attr2"].reshape(-1, synth.G_WIDTH))
+        ok &= ok2.reshape(-1, N).all(axis=1)
+    return subset_batch(batch, np.nonzero(ok)[0]), int((~ok).sum())
+
+
+@pytest.mark.parametrize("scheme,dtype,tol", [("paper", torch.float32, FP32_TOL), ("paper", torch.float16, MIX_TOL),
+                                              ("paper", torch.bfloat16, MIX_TOL),
+                                              ("bilinear", torch.float32, FP32_TOL),
+                                              ("bilinear", torch.float16, MIX_TOL)])
+def test_query_with_surface_attributes(scheme, dtype, tol):
+    """LHS and secondary queries of a training batch with their attributes;
+    the same queries with the attributes zeroed differ on both sides alike
+    (the kernel reads them, in their order)."""
+    batch = batch_for(scheme, 512, 8)
+    x = np.concatenate([batch["x"], batch["x2"].reshape(-1, 3)])
+    d = np.concatenate([batch["dir"], batch["dir2"].reshape(-1, 3)])
+    g = np.concatenate([batch["attr"], batch["attr2"].reshape(-1, synth.G_WIDTH)])
+    gpu, otree, omlp = models(scheme, dtype)
+    print(f"[case] attribute query {scheme} {dtype} B={len(x)}", flush=True)
+    for name, gg in (("attributes", g), ("reversed", np.ascontiguousarray(g[:, ::-1]))):
+        got = to_np(gpu(dev(x), dev(d), attr=dev(gg)))
+        want = oracle.query_fwd(otree, omlp, x, d, attr=gg)
+        e = rel_l2(got, want)
+        report(f"attribute query {scheme} {dtype} {name}", B=len(x), rel_l2=e)
+        assert e <= tol
+    with pytest.raises(binding.OOError, match="attr"):
+        gpu(dev(x), dev(d))
+
+
+@pytest.mark.parametrize("scheme,B,mode", [("paper", 1024, "relative"), ("paper", 1024, "l2"),
+                                           ("paper", 256, "full"), ("bilinear", 2048, "relative"),
+                                           ("bilinear", 512, "full")])
+def test_residual_with_surface_attributes_fp32(scheme, B, mode):
+    """Residual outputs, loss and every gradient group (W_0's attribute
+    columns included) element-wise within 1e-5; points whose ReLU pattern
+    FP32 could flip are dropped."""
+    batch = dict(batch_for(scheme, B))
+    if mode == "l2":
+        batch["loss_kind"] = 0
+    if mode == "full":
+        batch["grad_through_rhs"] = 1
+    gpu, otree, omlp = models(scheme)
+    _, _, W, b, _ = setup(scheme)
+    batch, dropped = kink_safe(otree, W, b, batch, mode == "full")
+    print(f"[case] attribute residual fp32 {scheme} B={len(batch['x'])} N={batch['N']} {mode} "
+          f"(kink-dropped {dropped})", flush=True)
+    got = run_residual(gpu, batch)
+    lhs, rhs, res, loss = oracle.residual_fwd(otree, omlp, batch)
+    for k, w in (("lhs", lhs), ("rhs", rhs), ("resid", res)):
+        e = rel_l2(got[k], w)
+        report(f"attribute residual {scheme} {mode} {k}", rel_l2=e)
+        assert e <= FP32_TOL
+    el = abs(got["loss"] - loss) / abs(loss)
+    report(f"attribute residual {scheme} {mode} loss", rel=el)
+    assert el <= FP32_TOL
+    compare_grads(f"attribute {scheme} {mode}", got, otree, omlp, batch, tol=FP32_TOL)
+
+
+def test_padded_attributes_match_unpadded_oracle():
+    """The caller pads the 13 attributes with 3 zero columns: the GPU's
+    16-attribute decoder, with arbitrary weights on the padding columns,
+    matches the oracle's 13-attribute decoder (outputs and gradients), and
+    the padding columns' dW is exactly zero."""
+    scheme = "paper"
+    cfg, feat, W, b, _ = setup(scheme)
+    LC = len(cfg.res) * cfg.C
+    Wp = [w.copy() for w in W]
+    Wp[0][:, LC + synth.G_ATTRS:] = np.random.default_rng(5).uniform(-1, 1, (W[0].shape[0], 3))
+    gpu, otree, _ = models(scheme, W=Wp)
+    omlp13 = oracle.MLP([np.ascontiguousarray(Wp[0][:, :LC + synth.G_ATTRS])] + Wp[1:], b)
+    batch = dict(batch_for(scheme, 512), grad_through_rhs=1)
+    batch, dropped = kink_safe(otree, Wp, b, batch, True)
+    b13 = dict(batch, attr=np.ascontiguousarray(batch["attr"][:, :synth.G_ATTRS]),
+               attr2=np.ascontiguousarray(batch["attr2"][:, :, :synth.G_ATTRS]))
+    print(f"[case] padded attributes B={len(batch['x'])} (kink-dropped {dropped})", flush=True)
+    got = run_residual(gpu, batch)
+    lhs, rhs, _, loss = oracle.residual_fwd(otree, omlp13, b13)
+    dfeat, dW, db = oracle.residual_bwd(otree, omlp13, b13)
+    e = max(rel_l2(got["lhs"], lhs), rel_l2(got["rhs"], rhs), abs(got["loss"] - loss) / abs(loss))
+    e_w0 = rel_l2(got["dW"][0][:, :LC + synth.G_ATTRS], dW[0])
+    report("padded attributes", out_rel=e, dW0_rel=e_w0, pad_dW_max=float(np.abs(got["dW"][0][:, LC + 13:]).max()))
+    assert e <= FP32_TOL and e_w0 <= FP32_TOL
+    assert np.all(got["dW"][0][:, LC + synth.G_ATTRS:] == 0.0)
+    for l, (g_, w_) in enumerate(zip(got["dfeat"], dfeat)):
+        if np.any(w_):
+            assert rel_l2(g_, w_) <= FP32_TOL, l
+
+
+def test_paper_config_fp16_step():
+    """The paper's configuration in FP16 (vertex maps and decoder) on 4096
+    LHS points x 32 samples, relative L2: radiance and loss within 1e-2,
+    every gradient group at cosine >= 0.999."""
+    batch = batch_for("paper", 4096)
+    gpu, otree, omlp = models("paper", torch.float16)
+    print(f"[case] paper config fp16 B=4096 N={batch['N']}", flush=True)
+    got = run_residual(gpu, batch)
+    lhs, rhs, _, loss = oracle.residual_fwd(otree, omlp, batch)
+    e1, e2, el = rel_l2(got["lhs"], lhs), rel_l2(got["rhs"], rhs), abs(got["loss"] - loss) / abs(loss)
+    report("paper config fp16", lhs_rel=e1, rhs_rel=e2, loss_rel=el)
+    assert max(e1, e2, el) <= MIX_TOL
+    compare_grads("paper config fp16", got, otree, omlp, batch, cos=MIX_COS)
+
+
+@pytest.mark.parametrize("B,N", synth.PAPER_SCHEDULE)
+def test_paper_schedule_full_size_sampled(B, N):
+    """Each stage of the paper's batch schedule at full size in FP16, as the
+    benchmark launches it: the residual of 512 sampled points against the
+    oracle's (their LHS and RHS queries evaluated one by one), and the
+    reported loss against the FP64 sum over the GPU's own residuals."""
+    batch = batch_for("paper", B, N)
+    gpu, otree, omlp = models("paper", torch.float16)
+    print(f"[case] paper schedule B={B} N={N}", flush=True)
+    b = binding.device_batch(batch)
+    ws = gpu.workspace(b)
+    lhs, rhs, res, loss = binding.residual_fwd(gpu.tree, gpu.mlp, b, ws, feat=gpu.work_feat, W=gpu.work_W)
+    torch.cuda.synchronize()
+    sel = synth.subset(B, 512, PAPER_CI)
+    sub = subset_batch(batch, sel)
+    olhs, orhs, _, _ = oracle.residual_fwd(otree, omlp, sub)
+    e1, e2 = rel_l2(to_np(lhs)[sel], olhs), rel_l2(to_np(rhs)[sel], orhs)
+    r = to_np(res).astype(np.float64)
+    T = to_np(rhs).astype(np.float64)
+    rho = np.maximum(to_np(lhs).astype(np.float64) + T, 0.0) + batch["eps"]
+    want_loss = float(((r / rho) ** 2).sum() / (3 * B))
+    el = abs(float(loss.item()) - want_loss) / want_loss
+    report(f"paper schedule B={B} N={N}", lhs_rel=e1, rhs_rel=e2, loss_vs_own_residuals=el)
+    assert e1 <= MIX_TOL and e2 <= MIX_TOL
+    assert el <= 1e-5

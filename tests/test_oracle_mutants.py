@@ -51,6 +51,13 @@ MUTANTS = {
     "adam_untouched_updated": ("    if (touched && !touched[i / block]) continue;\n", ""),
     "adam_second_moment_unsquared": ("double vi = b2 * (double)v[i] + (1.0 - b2) * gi * gi;",
                                      "double vi = b2 * (double)v[i] + (1.0 - b2) * fabs(gi);"),
+    # the decoder's surface attributes (Sec. 3.5)
+    "attribute_order_reversed": ("for (int32_t k = 0; k < E; ++k) h[LC + k] = (double)e[k];",
+                                 "for (int32_t k = 0; k < E; ++k) h[LC + E - 1 - k] = (double)e[k];"),
+    "rhs_backward_reads_lhs_attributes": ("*e = E > 0 ? &bt->attr2[E * bk] : NULL;",
+                                          "*e = E > 0 ? &bt->attr[E * b] : NULL;"),
+    "backward_reads_first_point_attributes": ("*e = E > 0 ? &bt->attr[E * q] : NULL;",
+                                              "*e = E > 0 ? &bt->attr[0] : NULL;"),
     "scatter_into_first_node": ("int64_t base = texel_base(t, l, qt->idx[l], qt->ij[l][2 * k], qt->ij[l][2 * k + 1]);\n"
                                 "      for (int32_t c = 0; c < C; ++c) dfeat",
                                 "int64_t base = texel_base(t, l, (int32_t)t->level_offset[l], qt->ij[l][2 * k], "
