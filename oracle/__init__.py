@@ -26,6 +26,29 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboo_oracle.so")
 
 
+class _MLP(C.Structure):
+    _fields_ = [
+        ("n_layers", C.c_int32),
+        ("dims", C.c_int32 * (MAX_LAYERS + 1)),
+        ("W", C.c_void_p * MAX_LAYERS),
+        ("b", C.c_void_p * MAX_LAYERS),
+    ]
+
+
+HASH_MAX_LEVELS = 16
+
+
+class _Disparity(C.Structure):
+    _fields_ = [
+        ("n_levels", C.c_int32),
+        ("F", C.c_int32),
+        ("log2_T", C.c_int32),
+        ("res", C.c_int32 * HASH_MAX_LEVELS),
+        ("tables", C.c_void_p),
+        ("mlp", _MLP),
+    ]
+
+
 class _Tree(C.Structure):
     _fields_ = [
         ("n_levels", C.c_int32),
@@ -35,21 +58,13 @@ class _Tree(C.Structure):
         ("nodes", C.c_void_p),
         ("feat", C.c_void_p * MAX_LEVELS),
         ("interp", C.c_int32),
+        ("disp", C.POINTER(_Disparity)),
     ]
 
 
 # Level-feature interpolation schemes.
 INTERP_NODE_BILINEAR = 0  # containing node, bilinear on R x R texels
 INTERP_PAPER = 1          # 8-cell trilinear (renormalised), barycentric on (R+1)^2 vertices
-
-
-class _MLP(C.Structure):
-    _fields_ = [
-        ("n_layers", C.c_int32),
-        ("dims", C.c_int32 * (MAX_LAYERS + 1)),
-        ("W", C.c_void_p * MAX_LAYERS),
-        ("b", C.c_void_p * MAX_LAYERS),
-    ]
 
 
 class _Batch(C.Structure):
@@ -94,7 +109,9 @@ def lib():
         L.ora_bsdf_weight.argtypes = [vp, vp]
         L.ora_residual_fwd.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32]
         L.ora_residual_fwd.restype = C.c_int
-        L.ora_residual_bwd.argtypes = [vp, vp, vp, C.c_double, vp, vp, vp, i32]
+        L.ora_residual_bwd.argtypes = [vp, vp, vp, C.c_double, vp, vp, vp, vp, vp, vp, i32]
+        L.ora_hash_encode.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.ora_disparity_fwd.argtypes = [vp, vp, vp, i64, vp]
         L.ora_residual_bwd.restype = C.c_int
         L.ora_map_entries.argtypes = [i32, i32]
         L.ora_map_entries.restype = C.c_int64
@@ -118,6 +135,33 @@ def _f64(a):
 
 
 @dataclass
+class Disparity:
+    """The disparity predictor (Sec. 3.3, Sec. 3.5): hash-grid tables
+    [n_levels][2^log2_T][F] FP32 with N_i cells per side at level i, and
+    an MLP on [encoding, unit(w_r), 0] with one output."""
+
+    res: list                         # N_i per hash level
+    F: int
+    log2_T: int
+    tables: np.ndarray
+    W: list
+    b: list
+
+    def _struct(self):
+        g = _Disparity()
+        g.n_levels = len(self.res)
+        g.F = int(self.F)
+        g.log2_T = int(self.log2_T)
+        for i, n in enumerate(self.res):
+            g.res[i] = int(n)
+        self._tables = _f32(self.tables)
+        g.tables = self._tables.ctypes.data
+        self._mlp = MLP(self.W, self.b)
+        g.mlp = self._mlp._struct()
+        return g
+
+
+@dataclass
 class Tree:
     """Octree + FP32 master feature tables, as the oracle reads them."""
 
@@ -128,6 +172,7 @@ class Tree:
     feat: list = field(default_factory=list)  # float32 [n_l][R_l][R_l][C] per level
     # INTERP_PAPER: feat[l] is [n_l][R_l + 1][R_l + 1][C] (map vertices)
     interp: int = INTERP_NODE_BILINEAR
+    disp: "Disparity | None" = None   # INTERP_PAPER only: shifts each cell's lookup direction
 
     @property
     def n_levels(self):
@@ -147,6 +192,9 @@ class Tree:
         for l, f in enumerate(self._feat):
             t.feat[l] = f.ctypes.data
         t.interp = int(self.interp)
+        if self.disp is not None:
+            self._disp = self.disp._struct()
+            t.disp = C.pointer(self._disp)
         return t
 
 
@@ -337,8 +385,10 @@ def residual_fwd(tree: Tree, mlp: MLP, batch: dict, nthreads=0):
     return lhs, rhs, res, float(loss[0])
 
 
-def residual_bwd(tree: Tree, mlp: MLP, batch: dict, grad_loss=1.0, nthreads=0):
-    """FP64 gradients (dfeat per level, dW, db) of the loss times grad_loss."""
+def residual_bwd(tree: Tree, mlp: MLP, batch: dict, grad_loss=1.0, nthreads=0, disp_out=None):
+    """FP64 gradients (dfeat per level, dW, db) of the loss times grad_loss.
+    With a disparity predictor on the tree, its gradients (keys "tables",
+    "W", "b") go into the dict disp_out when given."""
     keep = []
     bs = _batch_struct(batch, keep)
     ts, ms = tree._struct(), mlp._struct()
@@ -346,11 +396,43 @@ def residual_bwd(tree: Tree, mlp: MLP, batch: dict, grad_loss=1.0, nthreads=0):
     dW = [np.zeros(np.shape(w), np.float64) for w in mlp.W]
     db = [np.zeros(np.shape(b), np.float64) for b in mlp.b]
     arr = lambda lst: (C.c_void_p * max(1, len(lst)))(*[a.ctypes.data for a in lst])
+    gt = gW = gb = None
+    if tree.disp is not None and tree.interp == INTERP_PAPER:
+        g = tree.disp
+        gt = np.zeros(np.shape(g.tables), np.float64)
+        gW = [np.zeros(np.shape(w), np.float64) for w in g.W]
+        gb = [np.zeros(np.shape(b), np.float64) for b in g.b]
     rc = lib().ora_residual_bwd(C.byref(ts), C.byref(ms), C.byref(bs), float(grad_loss),
-                                arr(dfeat), arr(dW), arr(db), int(nthreads))
+                                arr(dfeat), arr(dW), arr(db), _p(gt), None if gW is None else arr(gW),
+                                None if gb is None else arr(gb), int(nthreads))
     if rc != 0:
         raise RuntimeError(f"ora_residual_bwd failed: {rc}")
+    if disp_out is not None and gt is not None:
+        disp_out.update(tables=gt, W=gW, b=gb)
     return dfeat, dW, db
+
+
+def hash_encode(disp: Disparity, x):
+    """Hash encoding of x (Sec. 3.5, Instant-NGP style): (enc [B][L F],
+    vertex entries [B][L][8], trilinear weights [B][L][8])."""
+    x = _f32(x).reshape(-1, 3)
+    B, L = x.shape[0], len(disp.res)
+    enc = np.zeros((B, L * disp.F), np.float64)
+    idx = np.zeros((B, L, 8), np.int64)
+    w = np.zeros((B, L, 8), np.float64)
+    gs = disp._struct()
+    lib().ora_hash_encode(C.byref(gs), _p(x), B, _p(enc), _p(idx), _p(w))
+    return enc, idx, w
+
+
+def disparity(disp: Disparity, x, d):
+    """Predicted disparity d(x, w_r) per query [B] (Sec. 3.3)."""
+    x = _f32(x).reshape(-1, 3)
+    d = _f32(d).reshape(-1, 3)
+    out = np.zeros(x.shape[0], np.float64)
+    gs = disp._struct()
+    lib().ora_disparity_fwd(C.byref(gs), _p(x), _p(d), x.shape[0], _p(out))
+    return out
 
 
 def adam(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.99, eps=1e-15, touched=None, block=1):

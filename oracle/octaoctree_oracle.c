@@ -25,6 +25,8 @@
  */
 #include "octaoctree_oracle.h"
 
+#define ORA_MAX_WIDTH 256  /* widest layer of either MLP */
+
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -216,7 +218,7 @@ static double sign_pos(double v) { return v < 0.0 ? -1.0 : 1.0; } /* sign(0) = +
 /* u = (wx, wy) / (|wx| + |wy| + |wz|); for wz < 0 the lower hemisphere is
  * folded with both new coordinates computed from the unfolded u; then
  * (s, t) = (u + 1) / 2. The zero vector maps to the map centre. */
-static void octa_one(const float* d, double* st) {
+static void octa_vec(const double* d, double* st) {
   double dx = d[0], dy = d[1], dz = d[2];
   double S = fabs(dx) + fabs(dy) + fabs(dz);
   double ux = 0.0, uy = 0.0;
@@ -232,6 +234,38 @@ static void octa_one(const float* d, double* st) {
   }
   st[0] = 0.5 * (ux + 1.0);
   st[1] = 0.5 * (uy + 1.0);
+}
+
+static void octa_one(const float* d, double* st) {
+  double v[3] = {d[0], d[1], d[2]};
+  octa_vec(v, st);
+}
+
+/* Derivative of (s, t) = octa(v) with respect to v, J[2][3], differentiated
+ * piece by piece on the piece octa(v) evaluates (|a|' = sign(a) with
+ * sign(0) = +1, as in the map). Upper hemisphere:
+ * d u_a / d v_b = [a == b] / S - v_a sign(v_b) / S^2 with S = |v|_1. The
+ * lower fold (1 - |u_y|) sign(u_x), (1 - |u_x|) sign(u_y) swaps and
+ * negates: d f_x = -sign(u_x) sign(u_y) d u_y, d f_y = -sign(u_x) sign(u_y)
+ * d u_x. Then (s, t) = (u + 1) / 2. */
+static void octa_jacobian(const double* v, double J[2][3]) {
+  double S = fabs(v[0]) + fabs(v[1]) + fabs(v[2]);
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 3; ++b) J[a][b] = 0.0;
+  if (!(S > 0.0)) return;
+  double du[2][3];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 3; ++b) du[a][b] = (a == b ? 1.0 / S : 0.0) - v[a] * sign_pos(v[b]) / (S * S);
+  if (v[2] < 0.0) {
+    double sx = sign_pos(v[0] / S), sy = sign_pos(v[1] / S);
+    for (int b = 0; b < 3; ++b) {
+      double fx = -sx * sy * du[1][b], fy = -sx * sy * du[0][b];
+      du[0][b] = fx;
+      du[1][b] = fy;
+    }
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 3; ++b) J[a][b] = 0.5 * du[a][b];
 }
 
 void ora_octa(const float* dir, int64_t B, double* st_out) {
@@ -376,6 +410,34 @@ void ora_bary(const double* st, int64_t B, int32_t R, int32_t* ij_out, double* w
   }
 }
 
+static double det3(const double a[3][3]) {
+  return a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) - a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+         a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+}
+
+/* Derivatives of the barycentric weights with respect to (pu, pv) = (s R,
+ * t R) inside the triangle with grid vertices ij: the weights solve
+ * sum_k w_k (i_k, j_k, 1) = (pu, pv, 1), so each derivative is that system
+ * solved for a unit right-hand side (Cramer's rule). */
+static void bary_grad(const int32_t ij[6], double dw_du[3], double dw_dv[3]) {
+  double M[3][3];
+  for (int k = 0; k < 3; ++k) {
+    M[0][k] = ij[2 * k];
+    M[1][k] = ij[2 * k + 1];
+    M[2][k] = 1.0;
+  }
+  double det = det3(M);
+  for (int r = 0; r < 2; ++r) {
+    double* out = r == 0 ? dw_du : dw_dv;
+    for (int k = 0; k < 3; ++k) {
+      double A[3][3];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) A[a][b] = b == k ? (a == r ? 1.0 : 0.0) : M[a][b];
+      out[k] = det3(A) / det;
+    }
+  }
+}
+
 /* Node of the level-l cell with integer coordinates c, found by walking
  * down from the root along the cell's octants; -1 if the cell is outside
  * the cube or has no node. */
@@ -443,23 +505,75 @@ typedef struct {
   double w[ORA_MAX_LEVELS][4];
   int32_t nb[ORA_MAX_LEVELS][8];     /* paper: the 8 neighbouring cells' nodes */
   double nbw[ORA_MAX_LEVELS][8];     /* their renormalised trilinear weights */
-  int32_t vert[ORA_MAX_LEVELS][3];   /* paper: storage slots of the 3 vertices */
-  double vw[ORA_MAX_LEVELS][3];      /* their barycentric weights */
+  int32_t vert[ORA_MAX_LEVELS][8][3]; /* paper: storage slots of each cell's 3 vertices */
+  double vw[ORA_MAX_LEVELS][8][3];    /* their barycentric weights */
+  double dvw[ORA_MAX_LEVELS][8][3];   /* their derivatives with respect to the disparity */
+  /* with a disparity predictor: the query's disparity, its hash-grid
+   * vertices and weights, and (backward) the gradient at the encoding */
+  double disp;
+  int64_t hidx[ORA_HASH_MAX_LEVELS][8];
+  double hw[ORA_HASH_MAX_LEVELS][8];
+  double denc[ORA_HASH_MAX_LEVELS * ORA_HASH_MAX_F];
 } query_taps;
 
+static double disparity_one(const ora_disparity* g, const float* x3, const float* d3, int64_t hidx[][8],
+                            double hw[][8], double act[][ORA_MAX_WIDTH], double pre[][ORA_MAX_WIDTH]);
+static void unit_dir(const float* d3, double u[3]);
+
+/* Everything a query reads, per level. Paper scheme with a disparity
+ * predictor: cell j (integer coordinates c, centre (c + 1/2) / 2^l) is read
+ * along v_j = (x - centre) d + unit(w_r), with x clamped to the cube as for
+ * the cells; d (v_j) / d d = x - centre, carried through the octahedral
+ * map and the triangle's barycentric weights to dvw. */
 static void query_locate(const ora_tree* t, const float* x3, const float* d3, query_taps* qt) {
   double st[2];
   descend_one(t, x3, qt->idx);
   octa_one(d3, st);
+  int shift = t->interp == ORA_INTERP_PAPER && t->disp != NULL;
+  double xc[3] = {0.0, 0.0, 0.0}, u[3] = {0.0, 0.0, 0.0};
+  qt->disp = 0.0;
+  if (shift) {
+    double act[ORA_MAX_LAYERS + 1][ORA_MAX_WIDTH], pre[ORA_MAX_LAYERS][ORA_MAX_WIDTH];
+    qt->disp = disparity_one(t->disp, x3, d3, qt->hidx, qt->hw, act, pre);
+    unit_dir(d3, u);
+    for (int a = 0; a < 3; ++a) {
+      double xa = (double)x3[a];
+      if (!(xa >= 0.0)) xa = 0.0;
+      if (xa > 1.0) xa = 1.0;
+      xc[a] = xa;
+    }
+  }
   for (int32_t l = 0; l < t->n_levels; ++l) {
+    int32_t R = t->res[l];
     if (t->interp == ORA_INTERP_PAPER) {
       int64_t cells[24];
-      int32_t ij[6];
       neighbours_one(t, x3, l, qt->nb[l], cells, qt->nbw[l]);
-      bary_one(st[0], st[1], t->res[l], ij, qt->vw[l]);
-      for (int k = 0; k < 3; ++k) qt->vert[l][k] = vertex_slot(ij[2 * k], ij[2 * k + 1], t->res[l]);
+      for (int d = 0; d < 8; ++d) {
+        double sd[2] = {st[0], st[1]}, dv[3] = {0.0, 0.0, 0.0}, J[2][3];
+        if (shift) {
+          double v[3];
+          for (int a = 0; a < 3; ++a) {
+            dv[a] = xc[a] - ((double)cells[3 * d + a] + 0.5) / ldexp(1.0, l);
+            v[a] = dv[a] * qt->disp + u[a];
+          }
+          octa_vec(v, sd);
+          octa_jacobian(v, J);
+        }
+        int32_t ij[6];
+        bary_one(sd[0], sd[1], R, ij, qt->vw[l][d]);
+        for (int k = 0; k < 3; ++k) qt->vert[l][d][k] = vertex_slot(ij[2 * k], ij[2 * k + 1], R);
+        double gu[3] = {0.0, 0.0, 0.0}, gv[3] = {0.0, 0.0, 0.0}, ds = 0.0, dt = 0.0;
+        if (shift) {
+          bary_grad(ij, gu, gv);
+          for (int a = 0; a < 3; ++a) {
+            ds += J[0][a] * dv[a];
+            dt += J[1][a] * dv[a];
+          }
+        }
+        for (int k = 0; k < 3; ++k) qt->dvw[l][d][k] = R * (gu[k] * ds + gv[k] * dt);
+      }
     } else {
-      taps_one(st[0], st[1], t->res[l], qt->ij[l], qt->w[l]);
+      taps_one(st[0], st[1], R, qt->ij[l], qt->w[l]);
     }
   }
 }
@@ -490,8 +604,8 @@ static void encode_from_taps(const ora_tree* t, const query_taps* qt, double* h)
       for (int d = 0; d < 8; ++d) {
         if (qt->nb[l][d] < 0) continue;
         for (int k = 0; k < 3; ++k) {
-          int64_t base = entry_base(t, l, qt->nb[l][d], qt->vert[l][k]);
-          double wk = qt->nbw[l][d] * qt->vw[l][k];
+          int64_t base = entry_base(t, l, qt->nb[l][d], qt->vert[l][d][k]);
+          double wk = qt->nbw[l][d] * qt->vw[l][d][k];
           for (int32_t c = 0; c < C; ++c) h[l * C + c] += wk * (double)t->feat[l][base + c];
         }
       }
@@ -521,7 +635,6 @@ void ora_encode(const ora_tree* t, const float* x, const float* dir, int64_t B, 
 /* Decoder MLP (Sec. 3.5): ReLU hidden layers, linear output                 */
 /* ------------------------------------------------------------------------ */
 
-#define ORA_MAX_WIDTH 256
 
 /* Forward pass of one row. act[i] receives the input of layer i (act[0] = h)
  * and pre[i] the pre-activation of layer i. */
@@ -547,6 +660,131 @@ void ora_mlp_fwd(const ora_mlp* m, const double* h, int64_t B, double* out) {
   static __thread double pre[ORA_MAX_LAYERS][ORA_MAX_WIDTH];
   int32_t din = m->dims[0], dout = m->dims[m->n_layers];
   for (int64_t b = 0; b < B; ++b) mlp_row(m, &h[din * b], act, pre, &out[dout * b]);
+}
+
+/* Reverse pass through the dense layers for the output gradient in delta:
+ * dW/db accumulate delta_{i+1} a_i^T and delta_{i+1}, the gradient moves
+ * through W_i^T and the ReLU mask (ReLU'(0) = 0); delta ends as the gradient
+ * at the input. */
+static void mlp_backprop(const ora_mlp* m, double act[][ORA_MAX_WIDTH], double pre[][ORA_MAX_WIDTH],
+                         double* delta, double* const* dW, double* const* db) {
+  double prev[ORA_MAX_WIDTH];
+  for (int32_t i = m->n_layers - 1; i >= 0; --i) {
+    int32_t fin = m->dims[i], fout = m->dims[i + 1];
+    for (int32_t o = 0; o < fout; ++o) {
+      db[i][o] += delta[o];
+      for (int32_t k = 0; k < fin; ++k) dW[i][(int64_t)o * fin + k] += delta[o] * act[i][k];
+    }
+    for (int32_t k = 0; k < fin; ++k) {
+      double s = 0.0;
+      for (int32_t o = 0; o < fout; ++o) s += (double)m->W[i][(int64_t)o * fin + k] * delta[o];
+      if (i > 0 && !(pre[i - 1][k] > 0.0)) s = 0.0;
+      prev[k] = s;
+    }
+    for (int32_t k = 0; k < fin; ++k) delta[k] = prev[k];
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Disparity predictor: hash encoding + small MLP (Sec. 3.3, Sec. 3.5)       */
+/* ------------------------------------------------------------------------ */
+
+/* Entry of grid vertex c of hash level i: dense when the level's
+ * (N + 1)^3 vertices fit in the table, else the spatial hash of Instant-NGP
+ * (per-axis primes 1, 2654435761, 805459861, xor, 32-bit wrap-around),
+ * modulo the table size. */
+static int64_t hash_slot(const ora_disparity* g, int32_t i, const int64_t c[3]) {
+  int64_t N1 = (int64_t)g->res[i] + 1;
+  int64_t T = (int64_t)1 << g->log2_T;
+  if (N1 * N1 * N1 <= T) return c[0] + N1 * (c[1] + N1 * c[2]);
+  uint32_t h = ((uint32_t)c[0] * 1u) ^ ((uint32_t)c[1] * 2654435761u) ^ ((uint32_t)c[2] * 805459861u);
+  return (int64_t)(h & (uint32_t)(T - 1));
+}
+
+/* Level i: x (clamped to the cube) scaled by N_i lies in cell
+ * floor(x N_i) (the last cell closed at x = 1); its eight vertices get the
+ * trilinear weights of the fraction. enc[i F + f] = sum_d w_d T_i[slot_d][f]. */
+static void hash_encode_one(const ora_disparity* g, const float* x3, double* enc, int64_t idx[][8],
+                            double w[][8]) {
+  int64_t T = (int64_t)1 << g->log2_T;
+  for (int32_t i = 0; i < g->n_levels; ++i) {
+    int64_t N = g->res[i], base[3];
+    double f[3];
+    for (int a = 0; a < 3; ++a) {
+      double xa = (double)x3[a];
+      if (!(xa >= 0.0)) xa = 0.0;
+      if (xa > 1.0) xa = 1.0;
+      double p = xa * (double)N;
+      double fl = floor(p);
+      if (fl > (double)(N - 1)) fl = (double)(N - 1);
+      base[a] = (int64_t)fl;
+      f[a] = p - fl;
+    }
+    for (int32_t e = 0; e < g->F; ++e) enc[i * g->F + e] = 0.0;
+    for (int d = 0; d < 8; ++d) {
+      int64_t c[3];
+      double wd = 1.0;
+      for (int a = 0; a < 3; ++a) {
+        int bit = (d >> a) & 1;
+        c[a] = base[a] + bit;
+        wd *= bit ? f[a] : 1.0 - f[a];
+      }
+      int64_t slot = hash_slot(g, i, c);
+      idx[i][d] = slot;
+      w[i][d] = wd;
+      const float* row = g->tables + ((int64_t)i * T + slot) * g->F;
+      for (int32_t e = 0; e < g->F; ++e) enc[i * g->F + e] += wd * (double)row[e];
+    }
+  }
+}
+
+void ora_hash_encode(const ora_disparity* g, const float* x, int64_t B, double* enc_out, int64_t* idx_out,
+                     double* w_out) {
+  int64_t E = (int64_t)g->n_levels * g->F;
+  for (int64_t b = 0; b < B; ++b) {
+    double enc[ORA_HASH_MAX_LEVELS * ORA_HASH_MAX_F];
+    int64_t idx[ORA_HASH_MAX_LEVELS][8];
+    double w[ORA_HASH_MAX_LEVELS][8];
+    hash_encode_one(g, &x[3 * b], enc, idx, w);
+    for (int64_t e = 0; e < E; ++e)
+      if (enc_out) enc_out[E * b + e] = enc[e];
+    for (int32_t i = 0; i < g->n_levels; ++i)
+      for (int d = 0; d < 8; ++d) {
+        if (idx_out) idx_out[(b * g->n_levels + i) * 8 + d] = idx[i][d];
+        if (w_out) w_out[(b * g->n_levels + i) * 8 + d] = w[i][d];
+      }
+  }
+}
+
+/* Unit vector of a direction (the zero vector stays zero). */
+static void unit_dir(const float* d3, double u[3]) {
+  double n = sqrt((double)d3[0] * d3[0] + (double)d3[1] * d3[1] + (double)d3[2] * d3[2]);
+  for (int a = 0; a < 3; ++a) u[a] = n > 0.0 ? (double)d3[a] / n : 0.0;
+}
+
+/* d = MLP([hash encoding of x, unit(w_r), 0]); act / pre are the MLP's
+ * activations for the backward. */
+static double disparity_one(const ora_disparity* g, const float* x3, const float* d3, int64_t hidx[][8],
+                            double hw[][8], double act[][ORA_MAX_WIDTH], double pre[][ORA_MAX_WIDTH]) {
+  double in[ORA_MAX_WIDTH], out[ORA_MAX_WIDTH], u[3];
+  int32_t E = g->n_levels * g->F;
+  hash_encode_one(g, x3, in, hidx, hw);
+  unit_dir(d3, u);
+  in[E] = u[0];
+  in[E + 1] = u[1];
+  in[E + 2] = u[2];
+  in[E + 3] = 0.0;
+  mlp_row(&g->mlp, in, act, pre, out);
+  return out[0];
+}
+
+void ora_disparity_fwd(const ora_disparity* g, const float* x, const float* dir, int64_t B, double* d_out) {
+  for (int64_t b = 0; b < B; ++b) {
+    int64_t hidx[ORA_HASH_MAX_LEVELS][8];
+    double hw[ORA_HASH_MAX_LEVELS][8];
+    double act[ORA_MAX_LAYERS + 1][ORA_MAX_WIDTH], pre[ORA_MAX_LAYERS][ORA_MAX_WIDTH];
+    d_out[b] = disparity_one(g, &x[3 * b], &dir[3 * b], hidx, hw, act, pre);
+  }
 }
 
 /* Number of decoder attributes after the level features. */
@@ -693,6 +931,18 @@ static int check_inputs(const ora_tree* t, const ora_mlp* m, const ora_batch* bt
   for (int32_t i = 0; i <= m->n_layers; ++i)
     if (m->dims[i] < 1 || m->dims[i] > ORA_MAX_WIDTH) return -1;
   if (m->dims[0] > ORA_MAX_WIDTH) return -1;
+  const ora_disparity* g = t->disp;
+  if (g && t->interp == ORA_INTERP_PAPER) {
+    if (g->n_levels < 1 || g->n_levels > ORA_HASH_MAX_LEVELS || g->F < 1 || g->F > ORA_HASH_MAX_F) return -1;
+    if (g->log2_T < 1 || g->log2_T > 30 || !g->tables) return -1;
+    for (int32_t i = 0; i < g->n_levels; ++i)
+      if (g->res[i] < 1 || g->res[i] > (1 << 20)) return -1;
+    const ora_mlp* gm = &g->mlp;
+    if (gm->n_layers < 1 || gm->n_layers > ORA_MAX_LAYERS) return -1;
+    if (gm->dims[0] != g->n_levels * g->F + 4 || gm->dims[gm->n_layers] != 1) return -1;
+    for (int32_t i = 0; i <= gm->n_layers; ++i)
+      if (gm->dims[i] < 1 || gm->dims[i] > ORA_MAX_WIDTH) return -1;
+  }
   return 0;
 }
 
@@ -718,50 +968,71 @@ int ora_residual_fwd(const ora_tree* t, const ora_mlp* m, const ora_batch* bt, d
  * to dh_out, and the query's node indices, taps and weights to qt, from which
  * scatter_query later adds each tap's share of dh to the texel it read. */
 static void backprop_query(const ora_tree* t, const ora_mlp* m, const float* x3, const float* d3, const float* e,
-                           const double g[3], double* const* dW, double* const* db, query_taps* qt,
-                           double* dh_out) {
+                           const double g[3], double* const* dW, double* const* db, double* const* gdW,
+                           double* const* gdb, query_taps* qt, double* dh_out) {
   double h[ORA_MAX_WIDTH];
   double act[ORA_MAX_LAYERS + 1][ORA_MAX_WIDTH];
   double pre[ORA_MAX_LAYERS][ORA_MAX_WIDTH];
   double out[ORA_MAX_WIDTH];
-  double delta[ORA_MAX_WIDTH], prev[ORA_MAX_WIDTH];
+  double delta[ORA_MAX_WIDTH];
   query_locate(t, x3, d3, qt);
   decoder_input(t, m, qt, e, h);
   mlp_row(m, h, act, pre, out);
 
   int32_t nl = m->n_layers;
   for (int32_t o = 0; o < m->dims[nl]; ++o) delta[o] = g[o];
-  for (int32_t i = nl - 1; i >= 0; --i) {
-    int32_t fin = m->dims[i], fout = m->dims[i + 1];
-    for (int32_t o = 0; o < fout; ++o) {
-      db[i][o] += delta[o];
-      for (int32_t k = 0; k < fin; ++k) dW[i][(int64_t)o * fin + k] += delta[o] * act[i][k];
-    }
-    for (int32_t k = 0; k < fin; ++k) {
-      double s = 0.0;
-      for (int32_t o = 0; o < fout; ++o) s += (double)m->W[i][(int64_t)o * fin + k] * delta[o];
-      if (i > 0 && !(pre[i - 1][k] > 0.0)) s = 0.0;
-      prev[k] = s;
-    }
-    for (int32_t k = 0; k < fin; ++k) delta[k] = prev[k];
-  }
+  mlp_backprop(m, act, pre, delta, dW, db);
   /* delta now holds dL/dh. */
   for (int32_t k = 0; k < m->dims[0]; ++k) dh_out[k] = delta[k];
+  if (!(t->interp == ORA_INTERP_PAPER && t->disp)) return;
+  /* dL/dd = sum over levels, cells and vertices of
+   * w_cell * (d w_vertex / d d) * <T[cell][vertex], dL/dh_l>, then through
+   * the predictor's MLP to its weights and its input; the encoding part of
+   * the input gradient is kept for the hash-table scatter. */
+  const ora_disparity* gp = t->disp;
+  int32_t C = t->C;
+  double dd = 0.0;
+  for (int32_t l = 0; l < t->n_levels; ++l)
+    for (int d = 0; d < 8; ++d) {
+      if (qt->nb[l][d] < 0) continue;
+      for (int k = 0; k < 3; ++k) {
+        int64_t base = entry_base(t, l, qt->nb[l][d], qt->vert[l][d][k]);
+        double s = 0.0;
+        for (int32_t c = 0; c < C; ++c) s += (double)t->feat[l][base + c] * dh_out[l * C + c];
+        dd += qt->nbw[l][d] * qt->dvw[l][d][k] * s;
+      }
+    }
+  double gact[ORA_MAX_LAYERS + 1][ORA_MAX_WIDTH], gpre[ORA_MAX_LAYERS][ORA_MAX_WIDTH];
+  disparity_one(gp, x3, d3, qt->hidx, qt->hw, gact, gpre);
+  double gdelta[ORA_MAX_WIDTH];
+  gdelta[0] = dd;
+  mlp_backprop(&gp->mlp, gact, gpre, gdelta, gdW, gdb);
+  for (int32_t k = 0; k < gp->n_levels * gp->F; ++k) qt->denc[k] = gdelta[k];
 }
 
 /* Adjoint of the level features: each tap's share w_tap * dh_l is added to
  * the texel the tap read, at the node that holds the query at that level
  * (paper scheme: each of the 24 cell-vertex reads gets its weight times
  * dh_l). */
-static void scatter_query(const ora_tree* t, const query_taps* qt, const double* dh, double* const* dfeat) {
+static void scatter_query(const ora_tree* t, const query_taps* qt, const double* dh, double* const* dfeat,
+                          double* dtables) {
   int32_t C = t->C;
+  if (t->interp == ORA_INTERP_PAPER && t->disp) {
+    /* hash-table entries: each vertex's trilinear share of dL/d enc */
+    const ora_disparity* g = t->disp;
+    int64_t T = (int64_t)1 << g->log2_T;
+    for (int32_t i = 0; i < g->n_levels; ++i)
+      for (int d = 0; d < 8; ++d)
+        for (int32_t e = 0; e < g->F; ++e)
+          dtables[((int64_t)i * T + qt->hidx[i][d]) * g->F + e] += qt->hw[i][d] * qt->denc[i * g->F + e];
+  }
   for (int32_t l = 0; l < t->n_levels; ++l) {
     if (t->interp == ORA_INTERP_PAPER) {
       for (int d = 0; d < 8; ++d) {
         if (qt->nb[l][d] < 0) continue;
         for (int k = 0; k < 3; ++k) {
-          int64_t base = entry_base(t, l, qt->nb[l][d], qt->vert[l][k]);
-          double wk = qt->nbw[l][d] * qt->vw[l][k];
+          int64_t base = entry_base(t, l, qt->nb[l][d], qt->vert[l][d][k]);
+          double wk = qt->nbw[l][d] * qt->vw[l][d][k];
           for (int32_t c = 0; c < C; ++c) dfeat[l][base + c] += wk * dh[l * C + c];
         }
       }
@@ -816,7 +1087,7 @@ static void query_seed(const ora_batch* bt, int32_t E, const double* lhs, const 
 #define ORA_BWD_BLOCK 16384
 int ora_residual_bwd(const ora_tree* t, const ora_mlp* m, const ora_batch* bt, double grad_loss,
                      double* const* dfeat, double* const* dW, double* const* db,
-                     int32_t nthreads) {
+                     double* dtables, double* const* gdW, double* const* gdb, int32_t nthreads) {
   int rc = check_inputs(t, m, bt);
   if (rc) return rc;
   int64_t B = bt->B;
@@ -827,8 +1098,13 @@ int ora_residual_bwd(const ora_tree* t, const ora_mlp* m, const ora_batch* bt, d
   nt = nthreads > 0 ? nthreads : omp_get_max_threads();
 #endif
   (void)nthreads;
-  int64_t P = 0;
+  const ora_mlp* gm = (t->interp == ORA_INTERP_PAPER && t->disp) ? &t->disp->mlp : NULL;
+  if (gm && (!dtables || !gdW || !gdb)) return -1;
+  int64_t P = 0, PG = 0;
   for (int32_t i = 0; i < m->n_layers; ++i) P += (int64_t)m->dims[i + 1] * (m->dims[i] + 1);
+  if (gm)
+    for (int32_t i = 0; i < gm->n_layers; ++i) PG += (int64_t)gm->dims[i + 1] * (gm->dims[i] + 1);
+  P += PG;
   int32_t K0 = m->dims[0];
   double* lhs = (double*)malloc((size_t)(3 * B) * sizeof(double));
   double* T = (double*)malloc((size_t)(3 * B) * sizeof(double));
@@ -860,12 +1136,20 @@ int ora_residual_bwd(const ora_tree* t, const ora_mlp* m, const ora_batch* bt, d
       double* mine = priv + (int64_t)tid * P;
       double* pdW[ORA_MAX_LAYERS];
       double* pdb[ORA_MAX_LAYERS];
+      double* pgW[ORA_MAX_LAYERS];
+      double* pgb[ORA_MAX_LAYERS];
       int64_t o = 0;
       for (int32_t i = 0; i < m->n_layers; ++i) {
         pdW[i] = mine + o;
         o += (int64_t)m->dims[i + 1] * m->dims[i];
         pdb[i] = mine + o;
         o += m->dims[i + 1];
+      }
+      for (int32_t i = 0; gm && i < gm->n_layers; ++i) {
+        pgW[i] = mine + o;
+        o += (int64_t)gm->dims[i + 1] * gm->dims[i];
+        pgb[i] = mine + o;
+        o += gm->dims[i + 1];
       }
 #ifdef _OPENMP
 #pragma omp for schedule(static)
@@ -874,10 +1158,10 @@ int ora_residual_bwd(const ora_tree* t, const ora_mlp* m, const ora_batch* bt, d
         double g[3];
         const float *x3, *d3, *e;
         query_seed(bt, attr_dims(t, m), lhs, T, r, w, grad_loss, q0 + j, g, &x3, &d3, &e);
-        backprop_query(t, m, x3, d3, e, g, pdW, pdb, &qts[j], &dhs[j * K0]);
+        backprop_query(t, m, x3, d3, e, g, pdW, pdb, pgW, pgb, &qts[j], &dhs[j * K0]);
       }
     }
-    for (int64_t j = 0; j < nq; ++j) scatter_query(t, &qts[j], &dhs[j * K0], dfeat);
+    for (int64_t j = 0; j < nq; ++j) scatter_query(t, &qts[j], &dhs[j * K0], dfeat, dtables);
   }
   for (int th = 0; th < nt; ++th) {
     const double* mine = priv + (int64_t)th * P;
@@ -888,6 +1172,13 @@ int ora_residual_bwd(const ora_tree* t, const ora_mlp* m, const ora_batch* bt, d
       o += nw;
       for (int32_t e = 0; e < m->dims[i + 1]; ++e) db[i][e] += mine[o + e];
       o += m->dims[i + 1];
+    }
+    for (int32_t i = 0; gm && i < gm->n_layers; ++i) {
+      int64_t nw = (int64_t)gm->dims[i + 1] * gm->dims[i];
+      for (int64_t e = 0; e < nw; ++e) gdW[i][e] += mine[o + e];
+      o += nw;
+      for (int32_t e = 0; e < gm->dims[i + 1]; ++e) gdb[i][e] += mine[o + e];
+      o += gm->dims[i + 1];
     }
   }
 done:

@@ -37,16 +37,6 @@ extern "C" {
                                        renormalised over non-empty cells),
                                        barycentric on (R+1)^2 vertices */
 
-typedef struct {
-  int32_t n_levels;                          /* L = D + 1 */
-  int32_t C;                                 /* features per texel */
-  int32_t res[ORA_MAX_LEVELS];               /* R_l texels (cells) per side */
-  int64_t level_offset[ORA_MAX_LEVELS + 1];  /* level l = [off_l, off_{l+1}) */
-  const uint32_t* nodes;
-  const float* feat[ORA_MAX_LEVELS];         /* FP32 masters */
-  int32_t interp;                            /* ORA_INTERP_* */
-} ora_tree;
-
 /* The decoder reads [h, g]: the L*C level features, then E = dims[0] - L*C
  * per-query surface attributes g (Sec. 3.5: position, mirror direction,
  * normal, albedo, roughness; E = 0 reads h only). */
@@ -56,6 +46,45 @@ typedef struct {
   const float* W[ORA_MAX_LAYERS];            /* [dims[i+1]][dims[i]] row-major */
   const float* b[ORA_MAX_LAYERS];            /* [dims[i+1]] */
 } ora_mlp;
+
+/* The disparity predictor g_psi (Sec. 3.3 disparity equation, Sec. 3.5): a
+ * multi-resolution hash encoding of x (Instant-NGP style) followed by a
+ * small MLP on [encoding, unit w_r, 0] with one linear output, d.
+ *  - Level i has N_i cells per side (Instant-NGP's geometric series
+ *    floor(N_0 b^i), evaluated by the caller). Its eight grid vertices
+ *    around x N_i (x clamped to the cube; the last cell is closed) are read
+ *    with the trilinear weights of x N_i's fraction in the cell.
+ *  - Level i's table has 2^log2_T entries of F features. Vertex (a, b, c)
+ *    is entry a + (N_i + 1) (b + (N_i + 1) c) when (N_i + 1)^3 <= 2^log2_T,
+ *    else the spatial hash (a * 1) xor (b * 2654435761) xor (c * 805459861)
+ *    in 32-bit arithmetic, modulo 2^log2_T.
+ *  - mlp.dims[0] = n_levels F + 4, mlp.dims[mlp.n_layers] = 1. */
+#define ORA_HASH_MAX_LEVELS 16
+#define ORA_HASH_MAX_F 8
+typedef struct {
+  int32_t n_levels;                          /* hash-grid levels, <= ORA_HASH_MAX_LEVELS */
+  int32_t F;                                 /* features per entry */
+  int32_t log2_T;                            /* entries per level = 2^log2_T */
+  int32_t res[ORA_HASH_MAX_LEVELS];          /* N_i cells per side */
+  const float* tables;                       /* [n_levels][2^log2_T][F] */
+  ora_mlp mlp;
+} ora_disparity;
+
+typedef struct {
+  int32_t n_levels;                          /* L = D + 1 */
+  int32_t C;                                 /* features per texel */
+  int32_t res[ORA_MAX_LEVELS];               /* R_l texels (cells) per side */
+  int64_t level_offset[ORA_MAX_LEVELS + 1];  /* level l = [off_l, off_{l+1}) */
+  const uint32_t* nodes;
+  const float* feat[ORA_MAX_LEVELS];         /* FP32 masters */
+  int32_t interp;                            /* ORA_INTERP_* */
+  /* ORA_INTERP_PAPER only: the disparity predictor, or NULL for none (the
+   * "no direction offset" lookup along w_r). With it, neighbouring cell j
+   * of a level (centre c_j) is read along v_j = (x - c_j) d + w_r / |w_r|
+   * (Sec. 3.3, shifted-direction equation, second form), where d is the
+   * query's predicted disparity and w_r its lookup direction. */
+  const ora_disparity* disp;
+} ora_tree;
 
 typedef struct {
   int64_t B;
@@ -119,6 +148,15 @@ void ora_neighbours(const ora_tree* t, const float* x, int64_t B, int32_t l, int
 void ora_encode(const ora_tree* t, const float* x, const float* dir, int64_t B,
                 double* h_out, int32_t* idx_out);
 
+/* Hash encoding of x [B][n_levels F], with each level's eight vertex
+ * entries [B][n_levels][8] and trilinear weights [B][n_levels][8] (either
+ * output may be NULL). Vertex d = dx | dy << 1 | dz << 2. */
+void ora_hash_encode(const ora_disparity* g, const float* x, int64_t B, double* enc_out, int64_t* idx_out,
+                     double* w_out);
+
+/* Predicted disparity d(x, w_r) of each query [B]. */
+void ora_disparity_fwd(const ora_disparity* g, const float* x, const float* dir, int64_t B, double* d_out);
+
 /* Decoder MLP on FP64 inputs h [B][dims[0]] -> out [B][dims[n_layers]]. */
 void ora_mlp_fwd(const ora_mlp* m, const double* h, int64_t B, double* out);
 
@@ -136,10 +174,13 @@ int ora_residual_fwd(const ora_tree* t, const ora_mlp* m, const ora_batch* bt,
                      int32_t nthreads);
 
 /* Residual backward for upstream gradient grad_loss. Gradients accumulate
- * (+=) into dfeat[l] ([n_l][R_l][R_l][C]), dW[i], db[i], all FP64. */
+ * (+=) into dfeat[l] ([n_l][R_l][R_l][C]), dW[i], db[i], all FP64. With a
+ * disparity predictor (t->disp) its gradients accumulate into dtables
+ * ([n_levels][2^log2_T][F]), gdW[i] and gdb[i]; these may be NULL
+ * otherwise. */
 int ora_residual_bwd(const ora_tree* t, const ora_mlp* m, const ora_batch* bt, double grad_loss,
                      double* const* dfeat, double* const* dW, double* const* db,
-                     int32_t nthreads);
+                     double* dtables, double* const* gdW, double* const* gdb, int32_t nthreads);
 
 /* One Adam step (Kingma and Ba, Algorithm 1) over n FP32 parameters with
  * FP32 moments, all updated in place after widening to FP64:

@@ -44,7 +44,7 @@ MUTANTS = {
     "trilinear_not_renormalised": ("for (int d = 0; d < 8; ++d) w[d] = sum > 0.0 ? w[d] / sum : 0.0;", ""),
     "trilinear_centre_offset_dropped": ("double p = xa * ldexp(1.0, l) - 0.5;", "double p = xa * ldexp(1.0, l);"),
     "paper_scatter_wrong_weight": ("          for (int32_t c = 0; c < C; ++c) dfeat[l][base + c] += wk * dh[l * C + c];",
-                                   "          for (int32_t c = 0; c < C; ++c) dfeat[l][base + c] += qt->vw[l][k] * dh[l * C + c];"),
+                                   "          for (int32_t c = 0; c < C; ++c) dfeat[l][base + c] += qt->vw[l][d][k] * dh[l * C + c];"),
     # the optimiser step
     "adam_no_bias_correction": ("double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);",
                                 "double c1 = 1.0, c2 = 1.0 - pow(b2, (double)t);"),
@@ -58,6 +58,27 @@ MUTANTS = {
                                           "*e = E > 0 ? &bt->attr[E * b] : NULL;"),
     "backward_reads_first_point_attributes": ("*e = E > 0 ? &bt->attr[E * q] : NULL;",
                                               "*e = E > 0 ? &bt->attr[0] : NULL;"),
+    # the disparity-shifted lookup (Sec. 3.3) and its predictor (Sec. 3.5)
+    "shift_centre_offset_dropped": ("dv[a] = xc[a] - ((double)cells[3 * d + a] + 0.5) / ldexp(1.0, l);",
+                                    "dv[a] = xc[a] - ((double)cells[3 * d + a]) / ldexp(1.0, l);"),
+    "shift_sign_flipped": ("v[a] = dv[a] * qt->disp + u[a];", "v[a] = -dv[a] * qt->disp + u[a];"),
+    "shift_direction_not_unit": ("    unit_dir(d3, u);\n    for (int a = 0; a < 3; ++a) {\n      double xa",
+                                 "    for (int a = 0; a < 3; ++a) u[a] = d3[a];\n    for (int a = 0; a < 3; ++a) {\n"
+                                 "      double xa"),
+    "octa_jacobian_fold_sign": ("double fx = -sx * sy * du[1][b], fy = -sx * sy * du[0][b];",
+                                "double fx = sx * sy * du[1][b], fy = sx * sy * du[0][b];"),
+    "bary_derivative_axes_swapped": ("qt->dvw[l][d][k] = R * (gu[k] * ds + gv[k] * dt);",
+                                     "qt->dvw[l][d][k] = R * (gu[k] * dt + gv[k] * ds);"),
+    "hash_primes_swapped": ("((uint32_t)c[1] * 2654435761u) ^ ((uint32_t)c[2] * 805459861u)",
+                            "((uint32_t)c[1] * 805459861u) ^ ((uint32_t)c[2] * 2654435761u)"),
+    "hash_dense_stride_dropped": ("return c[0] + N1 * (c[1] + N1 * c[2]);", "return c[0] + N1 * (c[1] + c[2]);"),
+    "hash_weight_swapped": ("        wd *= bit ? f[a] : 1.0 - f[a];\n      }\n      int64_t slot = hash_slot",
+                            "        wd *= bit ? 1.0 - f[a] : f[a];\n      }\n      int64_t slot = hash_slot"),
+    "disparity_gradient_without_cell_weight": ("dd += qt->nbw[l][d] * qt->dvw[l][d][k] * s;",
+                                               "dd += qt->dvw[l][d][k] * s;"),
+    "hash_scatter_without_vertex_weight": ("+= qt->hw[i][d] * qt->denc[i * g->F + e];",
+                                           "+= qt->denc[i * g->F + e];"),
+    "predictor_direction_not_unit": ("  unit_dir(d3, u);\n  in[E] = u[0];", "  for (int a = 0; a < 3; ++a) u[a] = d3[a];\n  in[E] = u[0];"),
     "scatter_into_first_node": ("int64_t base = texel_base(t, l, qt->idx[l], qt->ij[l][2 * k], qt->ij[l][2 * k + 1]);\n"
                                 "      for (int32_t c = 0; c < C; ++c) dfeat",
                                 "int64_t base = texel_base(t, l, (int32_t)t->level_offset[l], qt->ij[l][2 * k], "
