@@ -94,13 +94,17 @@ def main():
         views), zeroed with a single fill per step."""
         key = id(model)
         if key not in grad_bufs:
-            gshapes = [tuple(t.shape) for t in list(model.feat) + list(model.W) + list(model.b)]
+            params = list(model.feat) + list(model.W) + list(model.b) + list(model.disp_params)
+            gshapes = [tuple(t.shape) for t in params]
             goffs, gtotal = binding._flat_layout(gshapes)
             gflat = torch.zeros(gtotal, dtype=torch.float32, device=dev)
             gviews = [gflat[o:o + int(np.prod(sh))].view(sh) for sh, o in zip(gshapes, goffs)]
-            nf, nw = len(model.feat), len(model.W)
+            nf, nw, nb = len(model.feat), len(model.W), len(model.b)
             grad_bufs.clear()  # one model's buffers at a time
-            grad_bufs[key] = (gflat, {"dfeat": gviews[:nf], "dW": gviews[nf:nf + nw], "db": gviews[nf + nw:]})
+            gd = gviews[nf + nw + nb:]
+            nd = (len(gd) - 1) // 2
+            grad_bufs[key] = (gflat, {"dfeat": gviews[:nf], "dW": gviews[nf:nf + nw], "db": gviews[nf + nw:nf + nw + nb],
+                                      "disp": (gd[0], gd[1:1 + nd], gd[1 + nd:]) if gd else None})
         return grad_bufs[key]
 
     def step(model, ev=None, bt=None, o=None):
@@ -119,7 +123,7 @@ def main():
         if ev:
             ev[1].record()
         binding.residual_bwd(model.tree, model.mlp, bt, res, rhs, gl, grads["dfeat"], grads["dW"], grads["db"],
-                             ws, feat=model.work_feat, W=model.work_W)
+                             ws, feat=model.work_feat, W=model.work_W, disp_grads=grads["disp"])
         if ev:
             ev[2].record()
             ev[4].record()
@@ -276,20 +280,25 @@ def main():
 
 def paper_config_bench(torch, binding, synth, args, timed, grad_bufs):
     """The paper's network and loss on its batch schedule: 8 levels x 4 FP16
-    channels on vertex maps (257^2 .. 3^2), eight-cell blend, the 13 surface
-    attributes (+3 zero columns), four hidden layers of width 128, relative
-    L2, mirror-direction lookup. One timed training step (forward and
-    backward) per schedule stage (B LHS points x M samples)."""
+    channels on vertex maps (257^2 .. 3^2), eight-cell blend along the
+    disparity-shifted directions (hash-grid predictor, 16 levels x 2, MLP
+    36-64-64-1 in FP32), the 13 surface attributes (+3 zero columns), four
+    hidden layers of width 128, relative L2, mirror-direction lookup. One
+    timed training step (forward and backward, the predictor's included) per
+    schedule stage (B LHS points x M samples), and the first stage without
+    the shift for comparison."""
     cfg = synth.CONFIGS[6]
     t0 = time.time()
     nodes, lo = binding.build_octree(synth.tree_samples(cfg), cfg.D, cfg.tau)
     counts = np.diff(lo)
     feat = synth.init_tables(cfg, counts, vertices=True)
     W, b = synth.init_mlp(cfg)
+    disp = synth.init_disparity(cfg)
     model = binding.OctaOctree(nodes, lo, list(cfg.res), cfg.C, feat, W, b, dtype=torch.float16,
-                               interp=binding.INTERP_PAPER)
+                               interp=binding.INTERP_PAPER, disparity=disp)
     out = {"workload": "paper network and loss: depth-7 octree (%d nodes), 8 levels x 4 FP16 channels on "
-                       "(R+1)^2 vertex maps R = 256..2, 13 surface attributes (+3 zero), decoder "
+                       "(R+1)^2 vertex maps R = 256..2 read along disparity-shifted directions (hash grid "
+                       "16 x 2^19 x 2 + MLP 36-64-64-1, FP32), 13 surface attributes (+3 zero), decoder "
                        "48-128-128-128-128-3 FP16 MFMA, relative L2, detached target" % len(nodes),
            "stages": []}
     log(f"paper config: tree built in {time.time() - t0:.1f}s, nodes={len(nodes)} levels={counts.tolist()}")
@@ -310,6 +319,17 @@ def paper_config_bench(torch, binding, synth, args, timed, grad_bufs):
             "launches_per_step": {k: round(v[1], 2) for k, v in perc.items()}})
         log(f"paper config B={B} M={N}: {msc:.3f} ms/step (fwd {fc:.3f}, bwd {bc:.3f}), "
             f"{Q / (msc * 1e-3) / 1e6:.1f} Mqueries/s")
+        if (B, N) == synth.PAPER_SCHEDULE[0]:
+            # the same stage without the shift (the "no direction offset" lookup)
+            plain = binding.OctaOctree(nodes, lo, list(cfg.res), cfg.C, feat, W, b, dtype=torch.float16,
+                                       interp=binding.INTERP_PAPER)
+            grad_bufs.clear()
+            msn, fn, bn, _, _ = timed(plain, max(5, args.steps // 5), 2, bt=bt, o=o)
+            out["no_shift_first_stage"] = {"ms_per_step": round(msn, 4), "fwd_ms": round(fn, 4),
+                                           "bwd_ms": round(bn, 4)}
+            log(f"paper config without the shift, B={B} M={N}: {msn:.3f} ms/step")
+            del plain
+            grad_bufs.clear()
         del bt, o
         torch.cuda.empty_cache()
     del model

@@ -81,8 +81,9 @@ typedef enum { OO_F32 = 0, OO_F16 = 1, OO_BF16 = 2 } oo_dtype;
  * pointers.
  *  - n_levels: L = D + 1 levels, 0 (root) ..= D, with 1 <= L <= 16.
  *  - C: channels per texel, 4 or 8.
- *  - res[l]: the level-l map is res[l] x res[l] texels. A power of two in
- *    [2, 64].
+ *  - res[l]: the level-l map is res[l] x res[l] texels (cells). A power of
+ *    two in [2, 64], or in [2, 512] with OO_INTERP_PAPER (the paper's
+ *    coarsest vertex maps have 2^8 + 1 vertices per side).
  *  - level_offset: the nodes of level l have global indices
  *    [level_offset[l], level_offset[l+1]).
  *  - nodes: one 32-bit word per node, breadth first; within a level, nodes
@@ -97,9 +98,53 @@ typedef enum { OO_F32 = 0, OO_F16 = 1, OO_BF16 = 2 } oo_dtype;
  *    sits at (s, t) = (i / res, j / res). A border vertex that repeats
  *    another's direction is never read.
  *  - interp: OO_INTERP_NODE_BILINEAR (0) or OO_INTERP_PAPER (1).
+ *  - disparity: see oo_disparity below; NULL unless interp = 1.
  */
 #define OO_INTERP_NODE_BILINEAR 0
 #define OO_INTERP_PAPER 1
+
+/*
+ * The disparity predictor g_psi (Sec. 3.3, disparity equation; Sec. 3.5:
+ * a multi-resolution hash encoding followed by a small MLP). All FP32
+ * device pointers.
+ *  - Hash encoding of x (Instant-NGP style): level i has res[i] = N_i
+ *    cells per side (1 <= N_i <= 2^20). x, clamped to the cube, scaled by
+ *    N_i lies in cell floor(x N_i) (the last cell closed at x = 1); its
+ *    eight vertices are read with the trilinear weights of the fraction.
+ *    Vertex (a, b, c) is entry a + (N_i + 1) (b + (N_i + 1) c) when
+ *    (N_i + 1)^3 <= 2^log2_T, else ((a * 1) xor (b * 2654435761) xor
+ *    (c * 805459861)) mod 2^log2_T in 32-bit arithmetic.
+ *  - tables: [n_levels][2^log2_T][F] with n_levels = 16 and F = 2
+ *    (Instant-NGP's shape), 1 <= log2_T <= 24, 8-byte aligned.
+ *  - The MLP reads [encoding (n_levels F), unit(w_r) (3), 0]: n_layers = 2
+ *    or 3 Linear layers (one or two hidden layers of width 64; the paper's
+ *    has two), W[i] row-major [dims[i+1]][dims[i]] FP32, b[i] [dims[i+1]];
+ *    dims[0] = 36, dims[n_layers] = 1 (the disparity d, linear output).
+ *    ReLU between. Other shapes are refused with OO_EUNSUPPORTED.
+ *  - dtables, dW, db: gradient accumulators (same shapes) that the residual
+ *    backward adds the predictor's gradients into (+=); NULL for calls
+ *    that do not differentiate.
+ * With a predictor, cell j of a level (centre c_j = (cell + 1/2) / 2^l) is
+ * read along v_j = (x - c_j) d + w_r / |w_r| (Sec. 3.3, shifted-direction
+ * equation, second form; x clamped to the cube as for the cells); the
+ * octahedral map needs no normalisation of v_j.
+ */
+#define OO_HASH_MAX_LEVELS 16
+typedef struct {
+  int32_t n_levels;
+  int32_t F;
+  int32_t log2_T;
+  int32_t res[OO_HASH_MAX_LEVELS];
+  const float* tables;
+  int32_t n_layers;
+  int32_t dims[5];
+  const float* W[4];
+  const float* b[4];
+  float* dtables;
+  float* dW[4];
+  float* db[4];
+} oo_disparity;
+
 typedef struct {
   int32_t n_levels;
   int32_t C;
@@ -109,6 +154,10 @@ typedef struct {
   oo_dtype feat_dtype;
   const void* feat[OO_MAX_LEVELS];
   int32_t interp;
+  /* OO_INTERP_PAPER only: the disparity predictor shifting each cell's
+   * lookup direction, or NULL for the lookup along w_r (the "no direction
+   * offset" ablation of Sec. 4.4). */
+  const oo_disparity* disparity;
 } oo_tree;
 
 /*

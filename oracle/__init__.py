@@ -109,7 +109,7 @@ def lib():
         L.ora_bsdf_weight.argtypes = [vp, vp]
         L.ora_residual_fwd.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32]
         L.ora_residual_fwd.restype = C.c_int
-        L.ora_residual_bwd.argtypes = [vp, vp, vp, C.c_double, vp, vp, vp, vp, vp, vp, i32]
+        L.ora_residual_bwd.argtypes = [vp, vp, vp, C.c_double, vp, vp, vp, vp, vp, vp, vp, i32]
         L.ora_hash_encode.argtypes = [vp, vp, i64, vp, vp, vp]
         L.ora_disparity_fwd.argtypes = [vp, vp, vp, i64, vp]
         L.ora_residual_bwd.restype = C.c_int
@@ -388,7 +388,8 @@ def residual_fwd(tree: Tree, mlp: MLP, batch: dict, nthreads=0):
 def residual_bwd(tree: Tree, mlp: MLP, batch: dict, grad_loss=1.0, nthreads=0, disp_out=None):
     """FP64 gradients (dfeat per level, dW, db) of the loss times grad_loss.
     With a disparity predictor on the tree, its gradients (keys "tables",
-    "W", "b") go into the dict disp_out when given."""
+    "W", "b") and dL/d disparity per backward query ("dd") go into the dict
+    disp_out when given."""
     keep = []
     bs = _batch_struct(batch, keep)
     ts, ms = tree._struct(), mlp._struct()
@@ -396,19 +397,21 @@ def residual_bwd(tree: Tree, mlp: MLP, batch: dict, grad_loss=1.0, nthreads=0, d
     dW = [np.zeros(np.shape(w), np.float64) for w in mlp.W]
     db = [np.zeros(np.shape(b), np.float64) for b in mlp.b]
     arr = lambda lst: (C.c_void_p * max(1, len(lst)))(*[a.ctypes.data for a in lst])
-    gt = gW = gb = None
+    gt = gW = gb = dd = None
     if tree.disp is not None and tree.interp == INTERP_PAPER:
         g = tree.disp
         gt = np.zeros(np.shape(g.tables), np.float64)
         gW = [np.zeros(np.shape(w), np.float64) for w in g.W]
         gb = [np.zeros(np.shape(b), np.float64) for b in g.b]
+        full = batch.get("grad_through_rhs", 0) and batch.get("target_override") is None and bs.N > 0
+        dd = np.zeros(bs.B * (1 + bs.N) if full else bs.B, np.float64)
     rc = lib().ora_residual_bwd(C.byref(ts), C.byref(ms), C.byref(bs), float(grad_loss),
                                 arr(dfeat), arr(dW), arr(db), _p(gt), None if gW is None else arr(gW),
-                                None if gb is None else arr(gb), int(nthreads))
+                                None if gb is None else arr(gb), _p(dd), int(nthreads))
     if rc != 0:
         raise RuntimeError(f"ora_residual_bwd failed: {rc}")
     if disp_out is not None and gt is not None:
-        disp_out.update(tables=gt, W=gW, b=gb)
+        disp_out.update(tables=gt, W=gW, b=gb, dd=dd)
     return dfeat, dW, db
 
 

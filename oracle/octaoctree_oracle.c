@@ -511,6 +511,7 @@ typedef struct {
   /* with a disparity predictor: the query's disparity, its hash-grid
    * vertices and weights, and (backward) the gradient at the encoding */
   double disp;
+  double dd;                          /* backward: dL/d disparity */
   int64_t hidx[ORA_HASH_MAX_LEVELS][8];
   double hw[ORA_HASH_MAX_LEVELS][8];
   double denc[ORA_HASH_MAX_LEVELS * ORA_HASH_MAX_F];
@@ -1002,6 +1003,7 @@ static void backprop_query(const ora_tree* t, const ora_mlp* m, const float* x3,
         dd += qt->nbw[l][d] * qt->dvw[l][d][k] * s;
       }
     }
+  qt->dd = dd;
   double gact[ORA_MAX_LAYERS + 1][ORA_MAX_WIDTH], gpre[ORA_MAX_LAYERS][ORA_MAX_WIDTH];
   disparity_one(gp, x3, d3, qt->hidx, qt->hw, gact, gpre);
   double gdelta[ORA_MAX_WIDTH];
@@ -1087,7 +1089,8 @@ static void query_seed(const ora_batch* bt, int32_t E, const double* lhs, const 
 #define ORA_BWD_BLOCK 16384
 int ora_residual_bwd(const ora_tree* t, const ora_mlp* m, const ora_batch* bt, double grad_loss,
                      double* const* dfeat, double* const* dW, double* const* db,
-                     double* dtables, double* const* gdW, double* const* gdb, int32_t nthreads) {
+                     double* dtables, double* const* gdW, double* const* gdb, double* dd_out,
+                     int32_t nthreads) {
   int rc = check_inputs(t, m, bt);
   if (rc) return rc;
   int64_t B = bt->B;
@@ -1162,6 +1165,8 @@ int ora_residual_bwd(const ora_tree* t, const ora_mlp* m, const ora_batch* bt, d
       }
     }
     for (int64_t j = 0; j < nq; ++j) scatter_query(t, &qts[j], &dhs[j * K0], dfeat, dtables);
+    if (gm && dd_out)
+      for (int64_t j = 0; j < nq; ++j) dd_out[q0 + j] = qts[j].dd;
   }
   for (int th = 0; th < nt; ++th) {
     const double* mine = priv + (int64_t)th * P;

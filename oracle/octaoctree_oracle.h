@@ -177,10 +177,12 @@ int ora_residual_fwd(const ora_tree* t, const ora_mlp* m, const ora_batch* bt,
  * (+=) into dfeat[l] ([n_l][R_l][R_l][C]), dW[i], db[i], all FP64. With a
  * disparity predictor (t->disp) its gradients accumulate into dtables
  * ([n_levels][2^log2_T][F]), gdW[i] and gdb[i]; these may be NULL
- * otherwise. */
+ * otherwise. dd_out (may be NULL): dL/d disparity of each backward query
+ * (the LHS queries, then with grad_through_rhs the secondary ones). */
 int ora_residual_bwd(const ora_tree* t, const ora_mlp* m, const ora_batch* bt, double grad_loss,
                      double* const* dfeat, double* const* dW, double* const* db,
-                     double* dtables, double* const* gdW, double* const* gdb, int32_t nthreads);
+                     double* dtables, double* const* gdW, double* const* gdb, double* dd_out,
+                     int32_t nthreads);
 
 /* One Adam step (Kingma and Ba, Algorithm 1) over n FP32 parameters with
  * FP32 moments, all updated in place after widening to FP64:

@@ -32,10 +32,20 @@ class OOError(RuntimeError):
     pass
 
 
+HASH_MAX_LEVELS = 16
+
+
+class _Disparity(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("F", C.c_int32), ("log2_T", C.c_int32),
+                ("res", C.c_int32 * HASH_MAX_LEVELS), ("tables", C.c_void_p), ("n_layers", C.c_int32),
+                ("dims", C.c_int32 * 5), ("W", C.c_void_p * 4), ("b", C.c_void_p * 4),
+                ("dtables", C.c_void_p), ("dW", C.c_void_p * 4), ("db", C.c_void_p * 4)]
+
+
 class _Tree(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("C", C.c_int32), ("res", C.c_int32 * MAX_LEVELS),
                 ("level_offset", C.c_int64 * (MAX_LEVELS + 1)), ("nodes", C.c_void_p),
-                ("feat_dtype", C.c_int32), ("feat", C.c_void_p * MAX_LEVELS), ("interp", C.c_int32)]
+                ("feat_dtype", C.c_int32), ("feat", C.c_void_p * MAX_LEVELS), ("interp", C.c_int32), ("disparity", C.POINTER(_Disparity))]
 
 
 # Level-feature interpolation schemes (oo_tree.interp).
@@ -155,16 +165,56 @@ def build_octree(samples, max_depth: int, split_threshold: int):
 # Device-side descriptions
 # ---------------------------------------------------------------------------
 
-class Tree:
-    """Octree on the device plus one feature table per level."""
+class Disparity:
+    """The disparity predictor on the device (FP32): hash tables
+    [16][2^log2_T][2] with res[i] cells per side at level i, and an MLP on
+    [encoding, unit(w_r), 0] (hidden width 64, one output). grads: optional
+    (dtables, dW list, db list) accumulators for the residual backward."""
 
-    def __init__(self, nodes, level_offset, res, C_, feat, interp=INTERP_NODE_BILINEAR):
+    def __init__(self, res, log2_T, tables, W, b):
+        self.res = [int(r) for r in res]
+        self.log2_T = int(log2_T)
+        self.tables = tables if isinstance(tables, torch.Tensor) else _dev(tables)
+        self.W = [w if isinstance(w, torch.Tensor) else _dev(w) for w in W]
+        self.b = [v if isinstance(v, torch.Tensor) else _dev(v) for v in b]
+
+    def struct(self, grads=None):
+        g = _Disparity()
+        g.n_levels = len(self.res)
+        g.F = int(self.tables.shape[-1])
+        g.log2_T = self.log2_T
+        for i, n in enumerate(self.res):
+            g.res[i] = n
+        g.tables = self.tables.data_ptr()
+        g.n_layers = len(self.W)
+        g.dims[0] = self.W[0].shape[1]
+        for i, w in enumerate(self.W):
+            g.dims[i + 1] = w.shape[0]
+            g.W[i] = w.data_ptr()
+            g.b[i] = self.b[i].data_ptr()
+        if grads is not None:
+            dt, dW, db = grads
+            g.dtables = dt.data_ptr()
+            for i in range(len(self.W)):
+                g.dW[i] = dW[i].data_ptr()
+                g.db[i] = db[i].data_ptr()
+        return g
+
+
+class Tree:
+    """Octree on the device plus one feature table per level; with the
+    paper's scheme optionally the disparity predictor that shifts each
+    cell's lookup direction."""
+
+    def __init__(self, nodes, level_offset, res, C_, feat, interp=INTERP_NODE_BILINEAR, disparity=None):
         self.nodes = torch.from_numpy(np.asarray(nodes, np.uint32).view(np.int32)).cuda()
         self.level_offset = [int(v) for v in level_offset]
         self.res = [int(r) for r in res]
         self.C = int(C_)
         self.interp = int(interp)
         self.feat = [f if isinstance(f, torch.Tensor) else _dev(f) for f in feat]
+        self.disparity = disparity
+        self.disp_grads = None  # (dtables, dW, db) the next struct() passes to a backward
 
     @property
     def corners(self):
@@ -190,6 +240,9 @@ class Tree:
         for l, f in enumerate(feat):
             t.feat[l] = f.data_ptr() if f.numel() else None
         t.interp = self.interp
+        if self.disparity is not None:
+            self._disp_struct = self.disparity.struct(self.disp_grads)
+            t.disparity = C.pointer(self._disp_struct)
         return t
 
 
@@ -292,9 +345,15 @@ def residual_fwd(tree: Tree, mlp: MLP, batch: dict, workspace, feat=None, W=None
 
 
 def residual_bwd(tree: Tree, mlp: MLP, batch: dict, resid, rhs, grad_loss, dfeat, dW, db, workspace, feat=None,
-                 W=None):
-    """Accumulates (+=) FP32 gradients into dfeat / dW / db."""
-    ts, ms, bs = tree.struct(feat), mlp.struct(W), batch_struct(batch)
+                 W=None, disp_grads=None):
+    """Accumulates (+=) FP32 gradients into dfeat / dW / db, and with a
+    disparity predictor into disp_grads = (dtables, dW list, db list)."""
+    tree.disp_grads = disp_grads
+    try:
+        ts = tree.struct(feat)
+    finally:
+        tree.disp_grads = None
+    ms, bs = mlp.struct(W), batch_struct(batch)
     arr = lambda ts_: (C.c_void_p * max(1, len(ts_)))(*[t.data_ptr() if t.numel() else None for t in ts_])
     g = grad_loss.to(device="cuda", dtype=torch.float64).contiguous().reshape(())
     _check(lib().oo_radiosity_residual_bwd(C.byref(ts), C.byref(ms), C.byref(bs), _ptr(resid), _ptr(rhs), _ptr(g),
@@ -443,7 +502,11 @@ class OctaOctree(torch.nn.Module):
     Masters and working copies each live in one flat buffer with the same
     aligned layout, so a refresh is a single cast launch over the buffer."""
 
-    def __init__(self, nodes, level_offset, res, C_, feat, W, b, dtype=torch.float32, interp=INTERP_NODE_BILINEAR):
+    def __init__(self, nodes, level_offset, res, C_, feat, W, b, dtype=torch.float32, interp=INTERP_NODE_BILINEAR,
+                 disparity=None):
+        """disparity: the paper's scheme only; dict(res, log2_T, tables, W, b)
+        of the disparity predictor, kept as FP32 Parameters (no working copy:
+        the predictor runs in FP32)."""
         super().__init__()
         self.dtype = dtype
         shapes = [tuple(np.shape(f)) for f in feat] + [tuple(np.shape(w)) for w in W]
@@ -461,6 +524,14 @@ class OctaOctree(torch.nn.Module):
         self.b = torch.nn.ParameterList([torch.nn.Parameter(_dev(v)) for v in b])
         self.tree = Tree(nodes, level_offset, res, C_, list(self.feat), interp=interp)
         self.mlp = MLP(list(self.W), list(self.b))
+        self.disp_params = []
+        if disparity is not None:
+            self.disp_tables = torch.nn.Parameter(_dev(disparity["tables"]))
+            self.disp_W = torch.nn.ParameterList([torch.nn.Parameter(_dev(w)) for w in disparity["W"]])
+            self.disp_b = torch.nn.ParameterList([torch.nn.Parameter(_dev(v)) for v in disparity["b"]])
+            self.tree.disparity = Disparity(disparity["res"], disparity["log2_T"], self.disp_tables,
+                                            list(self.disp_W), list(self.disp_b))
+            self.disp_params = [self.disp_tables] + list(self.disp_W) + list(self.disp_b)
         self._ws = None
         self._work = None
         self._gen = 0
@@ -503,16 +574,16 @@ class OctaOctree(torch.nn.Module):
 
     def residual(self, batch):
         """Loss of the residual step (0-dim FP64) with autograd to the masters."""
-        return RadiosityResidual.apply(self, batch, *self.feat, *self.W, *self.b)
+        return RadiosityResidual.apply(self, batch, *self.feat, *self.W, *self.b, *self.disp_params)
 
     def adam_segments(self, grads, state, touched=None):
         """oo_adam_step segments for this model's tables and layers: each
         level's table lazy over its nodes' flags (touched: int32 [n_nodes],
         or None for a dense step), weights and biases dense. grads and
         state['m'] / state['v']: lists shaped like feat + W + b."""
-        params = list(self.feat) + list(self.W) + list(self.b)
+        params = list(self.feat) + list(self.W) + list(self.b) + self.disp_params
         works = (list(self.work_feat) + list(self.work_W) if self.dtype != torch.float32
-                 else [None] * (len(self.feat) + len(self.W))) + [None] * len(self.b)
+                 else [None] * (len(self.feat) + len(self.W))) + [None] * (len(self.b) + len(self.disp_params))
         lo = self.tree.level_offset
         segs = []
         for i, p in enumerate(params):
@@ -524,7 +595,7 @@ class OctaOctree(torch.nn.Module):
         return segs
 
     def new_adam_state(self):
-        params = list(self.feat) + list(self.W) + list(self.b)
+        params = list(self.feat) + list(self.W) + list(self.b) + self.disp_params
         return {"m": [torch.zeros_like(p.data) for p in params], "v": [torch.zeros_like(p.data) for p in params],
                 "t": 0}
 
@@ -561,6 +632,9 @@ class RadiosityResidual(torch.autograd.Function):
         dfeat = [torch.zeros(f.shape, dtype=torch.float32, device="cuda") for f in model.feat]
         dW = [torch.zeros(w.shape, dtype=torch.float32, device="cuda") for w in model.W]
         db = [torch.zeros(v.shape, dtype=torch.float32, device="cuda") for v in model.b]
+        dg = [torch.zeros(p.shape, dtype=torch.float32, device="cuda") for p in model.disp_params]
+        nw = (len(dg) - 1) // 2
         residual_bwd(model.tree, model.mlp, batch, res, rhs, grad_loss, dfeat, dW, db, ctx.ws,
-                     feat=model.work_feat, W=model.work_W)
-        return (None, None, *dfeat, *dW, *db)
+                     feat=model.work_feat, W=model.work_W,
+                     disp_grads=(dg[0], dg[1:1 + nw], dg[1 + nw:]) if dg else None)
+        return (None, None, *dfeat, *dW, *db, *dg)

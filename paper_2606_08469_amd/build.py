@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liboctaoctree.so")
-SOURCES = ["oo_api.cpp", "oo_fwd.hip", "oo_bwd.hip", "oo_sort.hip", "oo_optim.hip"]
+SOURCES = ["oo_api.cpp", "oo_fwd.hip", "oo_bwd.hip", "oo_sort.hip", "oo_optim.hip", "oo_disp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

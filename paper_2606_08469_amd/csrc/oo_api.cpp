@@ -128,8 +128,11 @@ int check_tree(const oo_tree* t, TreeArgs& A) {
     A.feat[l] = nullptr;
   }
   for (int l = 0; l <= OO_MAX_LEVELS; ++l) A.off[l] = l <= t->n_levels ? t->level_offset[l] : t->level_offset[t->n_levels];
+  // vertex maps reach 2^8 + 1 vertices per side in the paper's configuration
+  const int rmax = t->interp == OO_INTERP_PAPER ? 512 : 64;
   for (int l = 0; l < t->n_levels; ++l) {
-    if (!pow2_in(t->res[l], 2, 64)) return fail(OO_EINVAL, "res[%d] = %d is not a power of two in [2, 64]", l, t->res[l]);
+    if (!pow2_in(t->res[l], 2, rmax))
+      return fail(OO_EINVAL, "res[%d] = %d is not a power of two in [2, %d]", l, t->res[l], rmax);
     if (t->level_offset[l + 1] < t->level_offset[l]) return fail(OO_EINVAL, "level_offset must be non-decreasing");
     A.res[l] = t->res[l];
     const bool has_nodes = t->level_offset[l + 1] > t->level_offset[l];
@@ -175,6 +178,50 @@ int check_mlp(const oo_mlp* m, int LC, MlpArgs& A) {
     A.W[i] = i < m->n_layers ? m->W[i] : nullptr;
     A.b[i] = i < m->n_layers ? m->b[i] : nullptr;
   }
+  return OO_OK;
+}
+
+// The disparity predictor of the paper's scheme (G.n_levels = 0 without
+// one). grads: the call differentiates, so the gradient accumulators are
+// required too.
+int check_disparity(const oo_tree* t, DispArgs& G, bool grads) {
+  G = DispArgs{};
+  const oo_disparity* p = t->disparity;
+  if (!p) return OO_OK;
+  if (t->interp != OO_INTERP_PAPER) return fail(OO_EINVAL, "a disparity predictor needs interp = OO_INTERP_PAPER");
+  if (p->n_levels != kHashLevels)
+    return fail(OO_EUNSUPPORTED, "disparity n_levels must be %d, got %d", kHashLevels, p->n_levels);
+  if (p->F != kDispF) return fail(OO_EUNSUPPORTED, "disparity F must be %d, got %d", kDispF, p->F);
+  if (p->log2_T < 1 || p->log2_T > 24) return fail(OO_EINVAL, "disparity log2_T must be in [1, 24], got %d", p->log2_T);
+  if (!p->tables || reinterpret_cast<uintptr_t>(p->tables) % 8)
+    return fail(OO_EINVAL, "disparity tables must be non-NULL and 8-byte aligned");
+  if (p->n_layers != 2 && p->n_layers != 3)
+    return fail(OO_EUNSUPPORTED, "disparity n_layers must be 2 or 3, got %d", p->n_layers);
+  const int K = p->n_levels * p->F + 4;
+  if (p->dims[0] != K) return fail(OO_EINVAL, "disparity dims[0] = %d must be n_levels F + 4 = %d", p->dims[0], K);
+  for (int i = 1; i < p->n_layers; ++i)
+    if (p->dims[i] != kDispH) return fail(OO_EUNSUPPORTED, "disparity hidden widths must be %d", kDispH);
+  if (p->dims[p->n_layers] != 1) return fail(OO_EINVAL, "disparity output width must be 1");
+  G.n_levels = p->n_levels;
+  G.log2_T = p->log2_T;
+  G.n_layers = p->n_layers;
+  G.K = K;
+  G.tables = p->tables;
+  G.dense_mask = 0;
+  for (int i = 0; i < p->n_levels; ++i) {
+    if (p->res[i] < 1 || p->res[i] > (1 << 20))
+      return fail(OO_EINVAL, "disparity res[%d] = %d must be in [1, 2^20]", i, p->res[i]);
+    G.res[i] = p->res[i];
+    const uint64_t n1 = (uint64_t)p->res[i] + 1;
+    if (n1 * n1 * n1 <= (uint64_t(1) << p->log2_T)) G.dense_mask |= 1u << i;
+  }
+  for (int i = 0; i < p->n_layers; ++i) {
+    if (!p->W[i] || !p->b[i]) return fail(OO_EINVAL, "disparity W[%d] or b[%d] is NULL", i, i);
+    G.W[i] = p->W[i];
+    G.b[i] = p->b[i];
+    if (grads && (!p->dW[i] || !p->db[i])) return fail(OO_EINVAL, "disparity dW[%d] or db[%d] is NULL", i, i);
+  }
+  if (grads && !p->dtables) return fail(OO_EINVAL, "disparity dtables is NULL");
   return OO_OK;
 }
 
@@ -225,6 +272,8 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Workspace {
   size_t Lq, lossp, seeds, nidx, uv, pos, dh, wt[OO_MAX_LAYERS], dwp, order, rank, scount, stotal, sstart, gpad, total;
+  size_t wdir, dd, gdwp;  // the disparity predictor's: lookup directions, dLoss/d disparity, parameter partials
+  int ggrid;
   int K;  // node indices stored per level and backward query: 1, or 8 corners in the paper's scheme
   int64_t pad_off[OO_MAX_LEVELS];  // float offset of each level's pair buffer in gpad, or -1
   int64_t pad_total;               // floats in gpad
@@ -284,6 +333,23 @@ Workspace workspace_layout(const MlpArgs& M, oo_dtype md, const oo_residual_batc
   o = align256(o + (paper ? (size_t)Qb * sizeof(float4) : 0));
   w.dh = o;  // dLoss/dh of every backward query, [Qb][L C] FP32
   o = align256(o + (size_t)Qb * L * tree->C * sizeof(float));
+  // with the disparity predictor: unit lookup direction [Qb] float4 and
+  // dLoss/d disparity [Qb] of every backward query, and the predictor's
+  // parameter partials [ggrid][P]
+  const bool shift = paper && tree->disparity;
+  w.ggrid = shift ? disparity_bwd_grid(Qb) : 0;
+  w.wdir = o;
+  o = align256(o + (shift ? (size_t)Qb * sizeof(float4) : 0));
+  w.dd = o;
+  o = align256(o + (shift ? (size_t)Qb * sizeof(float) : 0));
+  w.gdwp = o;
+  if (shift) {
+    const oo_disparity* p = tree->disparity;
+    size_t P = (size_t)p->dims[1] * p->dims[0] + p->dims[1] + (size_t)p->dims[p->n_layers] * p->dims[p->n_layers - 1] +
+               p->dims[p->n_layers];
+    if (p->n_layers == 3) P += (size_t)p->dims[2] * p->dims[1] + p->dims[2];
+    o = align256(o + (size_t)w.ggrid * P * sizeof(float));
+  }
   const size_t esz = md == OO_F32 ? 4 : 2;
   for (int i = 0; i < M.n_layers; ++i) {
     w.wt[i] = o;
@@ -467,10 +533,14 @@ int oo_encode_query(const oo_tree* tree, const float* x, const float* dir, int64
   if (rc) return rc;
   if (B < 0) return fail(OO_EINVAL, "B must be >= 0");
   if (h_dtype != OO_F32 && h_dtype != OO_F16 && h_dtype != OO_BF16) return fail(OO_EINVAL, "unknown h_dtype");
+  DispArgs G;
+  if ((rc = check_disparity(tree, G, false))) return rc;
+  if (G.n_levels > 0 && h_dtype != OO_F32)
+    return fail(OO_EUNSUPPORTED, "the shifted encoding writes FP32 features only");
   if (B == 0) return OO_OK;
   if (!x || !dir || !h_out) return fail(OO_EINVAL, "x, dir and h_out are required");
   ProfScope ps(OO_PROF_ENCODE, stream);
-  return hip_status(launch_encode(T, tree->feat_dtype, x, dir, B, h_out, h_dtype, node_idx_out, stream),
+  return hip_status(launch_encode(T, tree->feat_dtype, x, dir, B, h_out, h_dtype, node_idx_out, G, stream),
                     "encode_query launch");
 }
 
@@ -497,6 +567,8 @@ int oo_query_fwd(const oo_tree* tree, const oo_mlp* mlp, const float* x, const f
   if (rc) return rc;
   if ((rc = check_mlp(mlp, tree->n_levels * tree->C, M))) return rc;
   if ((rc = check_pair(tree, mlp))) return rc;
+  DispArgs G;
+  if ((rc = check_disparity(tree, G, false))) return rc;
   if (B < 0) return fail(OO_EINVAL, "B must be >= 0");
   if (B == 0) return OO_OK;
   if (!x || !dir || !rgb_out) return fail(OO_EINVAL, "x, dir and rgb_out are required");
@@ -505,8 +577,8 @@ int oo_query_fwd(const oo_tree* tree, const oo_mlp* mlp, const float* x, const f
   src.gA = src.gB = attr;
   src.E = M.E;
   ProfScope ps(OO_PROF_QUERY, stream);
-  return hip_status(launch_query(T, tree->feat_dtype, M, mlp->dtype, src, B, rgb_out, nullptr, nullptr, nullptr, 0,
-                                 stream),
+  const QueryOut O{nullptr, nullptr, nullptr, nullptr, 0};
+  return hip_status(launch_query(T, tree->feat_dtype, M, mlp->dtype, src, B, rgb_out, O, G, stream),
                     "query_fwd launch");
 }
 
@@ -520,6 +592,8 @@ int oo_residual_workspace_bytes(const oo_tree* tree, const oo_mlp* mlp, const oo
   if ((rc = check_mlp(mlp, tree->n_levels * tree->C, M))) return rc;
   if ((rc = check_pair(tree, mlp))) return rc;
   if ((rc = check_batch(batch, A))) return rc;
+  DispArgs G;
+  if ((rc = check_disparity(tree, G, false))) return rc;
   if (!bytes) return fail(OO_EINVAL, "bytes is NULL");
   *bytes = workspace_layout(M, mlp->dtype, batch, tree).total;
   return OO_OK;
@@ -538,6 +612,8 @@ int oo_radiosity_residual_fwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   if ((rc = check_pair(tree, mlp))) return rc;
   if ((rc = check_batch(batch, A))) return rc;
   if ((rc = check_attrs(batch, A, M))) return rc;
+  DispArgs G;
+  if ((rc = check_disparity(tree, G, false))) return rc;
   if (!loss_out || !workspace) return fail(OO_EINVAL, "loss_out and workspace are required");
   if (A.B > 0 && (!lhs_out || !rhs_out || !resid_out)) return fail(OO_EINVAL, "lhs_out, rhs_out, resid_out are required");
   const Workspace w = workspace_layout(M, mlp->dtype, batch, tree);
@@ -571,8 +647,9 @@ int oo_radiosity_residual_fwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   sorted.n = Q;
   {
     ProfScope ps(OO_PROF_QUERY, stream);
-    e = launch_query(T, tree->feat_dtype, M, mlp->dtype, sorted, Q, Lq, nidx, reinterpret_cast<float2*>(ws + w.uv),
-                     reinterpret_cast<float4*>(ws + w.pos), w.Qb, stream);
+    const QueryOut O{nidx, reinterpret_cast<float2*>(ws + w.uv), reinterpret_cast<float4*>(ws + w.pos),
+                     G.n_levels ? reinterpret_cast<float4*>(ws + w.wdir) : nullptr, w.Qb};
+    e = launch_query(T, tree->feat_dtype, M, mlp->dtype, sorted, Q, Lq, O, G, stream);
   }
   if (e != hipSuccess) return hip_status(e, "residual query launch");
   ProfScope ps(OO_PROF_COMBINE, stream);
@@ -593,15 +670,17 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   if ((rc = check_pair(tree, mlp))) return rc;
   if ((rc = check_batch(batch, A))) return rc;
   if ((rc = check_attrs(batch, A, M))) return rc;
+  DispArgs G;
+  if ((rc = check_disparity(tree, G, true))) return rc;
   if (!grad_loss || !dfeat || !dW || !db || !workspace) return fail(OO_EINVAL, "NULL argument");
   if (A.B == 0) return OO_OK;
   if (!resid || !rhs) return fail(OO_EINVAL, "resid and rhs are required");
-  GradArgs G;
-  for (int l = 0; l < OO_MAX_LEVELS; ++l) G.dfeat[l] = G.pad[l] = nullptr;
+  GradArgs GA;
+  for (int l = 0; l < OO_MAX_LEVELS; ++l) GA.dfeat[l] = GA.pad[l] = nullptr;
   for (int l = 0; l < tree->n_levels; ++l) {
     const bool has_nodes = tree->level_offset[l + 1] > tree->level_offset[l];
     if (has_nodes && !dfeat[l]) return fail(OO_EINVAL, "dfeat[%d] is NULL", l);
-    G.dfeat[l] = dfeat[l];
+    GA.dfeat[l] = dfeat[l];
   }
   for (int i = 0; i < mlp->n_layers; ++i)
     if (!dW[i] || !db[i]) return fail(OO_EINVAL, "dW[%d] or db[%d] is NULL", i, i);
@@ -612,7 +691,7 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   char* ws = static_cast<char*>(workspace);
   float* const gpad = reinterpret_cast<float*>(ws + w.gpad);
   for (int l = 0; l < tree->n_levels; ++l)
-    if (w.pad_off[l] >= 0 && G.dfeat[l]) G.pad[l] = gpad + w.pad_off[l];
+    if (w.pad_off[l] >= 0 && GA.dfeat[l]) GA.pad[l] = gpad + w.pad_off[l];
   float* seeds = reinterpret_cast<float*>(ws + w.seeds);
   const int32_t* nidx = reinterpret_cast<const int32_t*>(ws + w.nidx);
   float* partials = reinterpret_cast<float*>(ws + w.dwp);
@@ -626,6 +705,7 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
     ProfScope ps(OO_PROF_SEEDS, stream);
     e = launch_seeds(A, resid, rhs, grad_loss, full ? 1 : 0, seeds, stream);
     if (e == hipSuccess) e = launch_fill_zero(gpad, w.pad_total, stream);
+    if (e == hipSuccess && G.n_levels) e = launch_fill_zero(reinterpret_cast<float*>(ws + w.dd), Qb, stream);
   }
   if (e != hipSuccess) return hip_status(e, "seed launch");
   {
@@ -655,6 +735,13 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
       B.gB = A.N > 0 ? batch->attr2 : batch->attr;
       B.nA = A.B;
       B.n_src = A.B * (1 + A.N);
+      ShiftArgs SA;
+      if (G.n_levels) {
+        B.wdir = reinterpret_cast<const float4*>(ws + w.wdir) + q0;
+        B.shift = 1;
+        SA.wdir = B.wdir;
+        SA.dd = reinterpret_cast<float*>(ws + w.dd) + q0;
+      }
       {
         ProfScope ps(OO_PROF_BACKWARD, stream);
         e = launch_bwd(T, tree->feat_dtype, M, mlp->dtype, Wt, B, w.PL, w.grid, stream);
@@ -668,7 +755,8 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
       }
       {
         ProfScope ps(OO_PROF_SCATTER, ss);
-        e = launch_scatter(T, qn, nidx + q0, Qb, uv + q0, pos + q0, dh + q0 * LC, post_scale, G, ss);
+        e = launch_scatter(T, tree->feat_dtype, qn, nidx + q0, Qb, uv + q0, pos + q0, dh + q0 * LC, post_scale, GA, SA,
+                           ss);
       }
       if (e != hipSuccess) return hip_status(e, "scatter launch");
     }
@@ -687,8 +775,40 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   }
   D.start[D.n_seg] = w.PL.P;
   ProfScope ps(OO_PROF_DW_REDUCE, stream);
-  if ((e = launch_pad_fold(T, G, stream)) != hipSuccess) return hip_status(e, "gradient fold launch");
-  return hip_status(launch_dw_reduce(partials, w.grid, w.PL, D, post_scale, stream), "dW reduce launch");
+  if ((e = launch_pad_fold(T, GA, stream)) != hipSuccess) return hip_status(e, "gradient fold launch");
+  if ((e = launch_dw_reduce(partials, w.grid, w.PL, D, post_scale, stream)) != hipSuccess)
+    return hip_status(e, "dW reduce launch");
+  if (!G.n_levels) return OO_OK;
+  // the disparity predictor: from each backward query's dLoss/d disparity
+  // (summed by the scatter) to its MLP and hash tables
+  const oo_disparity* gp = tree->disparity;
+  QuerySrc src{batch->x, batch->dir, A.B, A.N > 0 ? batch->x2 : batch->x, A.N > 0 ? batch->dir2 : batch->dir};
+  src.idx = order;
+  src.n = A.B * (1 + A.N);
+  float* gpart = reinterpret_cast<float*>(ws + w.gdwp);
+  if ((e = launch_disparity_bwd(G, src, Qb, reinterpret_cast<const float*>(ws + w.dd), gp->dtables, gpart, w.ggrid,
+                                stream)) != hipSuccess)
+    return hip_status(e, "disparity backward launch");
+  ParamLayout GL;
+  ReduceDst GD;
+  GL.n_layers = gp->n_layers;
+  GD.n_seg = 2 * gp->n_layers;
+  int64_t off = 0;
+  for (int i = 0; i < gp->n_layers; ++i) {
+    GL.n_in[i] = gp->dims[i];
+    GL.n_out[i] = gp->dims[i + 1];
+    GL.w_off[i] = off;
+    GD.start[2 * i] = off;
+    GD.dst[2 * i] = gp->dW[i];
+    off += (int64_t)gp->dims[i] * gp->dims[i + 1];
+    GL.b_off[i] = off;
+    GD.start[2 * i + 1] = off;
+    GD.dst[2 * i + 1] = gp->db[i];
+    off += gp->dims[i + 1];
+  }
+  GL.P = off;
+  GD.start[GD.n_seg] = off;
+  return hip_status(launch_dw_reduce(gpart, w.ggrid, GL, GD, 1.0f, stream), "disparity reduce launch");
 }
 
 int oo_residual_node_indices(const oo_tree* tree, const oo_mlp* mlp, const oo_residual_batch* batch,
@@ -703,6 +823,8 @@ int oo_residual_node_indices(const oo_tree* tree, const oo_mlp* mlp, const oo_re
   if ((rc = check_mlp(mlp, tree->n_levels * tree->C, M))) return rc;
   if ((rc = check_pair(tree, mlp))) return rc;
   if ((rc = check_batch(batch, A))) return rc;
+  DispArgs G;
+  if ((rc = check_disparity(tree, G, false))) return rc;
   if (!workspace) return fail(OO_EINVAL, "workspace is required");
   const Workspace w = workspace_layout(M, mlp->dtype, batch, tree);
   if (workspace_bytes < w.total)
@@ -794,7 +916,10 @@ int oo_adam_step(const oo_adam_config* cfg, const oo_adam_segment* segs, int32_t
       return fail(OO_EINVAL, "segment %d: param, grad, m and v are required", s);
     if (S.touched && (S.block <= 0 || S.block % 4))
       return fail(OO_EINVAL, "segment %d: block must be a positive multiple of 4 with touched flags", s);
-    A.seg[s] = AdamSeg{S.param, S.grad, S.m, S.v, S.work, S.n, S.touched, S.block};
+    const size_t wa = cfg->work_dtype == OO_F32 ? 16 : 8;
+    const bool vec = ((uintptr_t)S.param | (uintptr_t)S.grad | (uintptr_t)S.m | (uintptr_t)S.v) % 16 == 0 &&
+                     (uintptr_t)S.work % wa == 0;
+    A.seg[s] = AdamSeg{S.param, S.grad, S.m, S.v, S.work, S.n, S.touched, S.block, vec ? 1 : 0};
     A.first[s + 1] = A.first[s] + (S.n + 3) / 4;
   }
   A.lr = cfg->lr;
@@ -817,6 +942,8 @@ int oo_touched_nodes(const oo_tree* tree, const oo_mlp* mlp, const oo_residual_b
   if ((rc = check_mlp(mlp, tree->n_levels * tree->C, M))) return rc;
   if ((rc = check_pair(tree, mlp))) return rc;
   if ((rc = check_batch(batch, A))) return rc;
+  DispArgs G;
+  if ((rc = check_disparity(tree, G, false))) return rc;
   if (!workspace) return fail(OO_EINVAL, "workspace is required");
   const Workspace w = workspace_layout(M, mlp->dtype, batch, tree);
   if (workspace_bytes < w.total)

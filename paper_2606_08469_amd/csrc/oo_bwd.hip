@@ -297,8 +297,14 @@ __global__ __launch_bounds__(64 * bwd_waves<MT>()) void bwd_kernel(const TreeArg
 #pragma unroll
             for (int a = 0; a < 3; ++a) cell_frac(xq[a], l, base[a], f[a]);
             corner_weights(f, node, wc);
-            bary(s, t, T.res[l], slot, wv);
-            gather_paper_level<TT, C>(T, l, node, wc, slot, wv, h);
+            if (A.shift) {  // each corner's cell along its shifted direction
+              const float4 w4 = q < Q ? A.wdir[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+              const float u[3] = {w4.x, w4.y, w4.z};
+              gather_paper_level_shift<TT, C>(T, l, node, wc, xq, base, xp.w, u, h);
+            } else {
+              bary(s, t, T.res[l], slot, wv);
+              gather_paper_level<TT, C>(T, l, node, wc, slot, wv, h);
+            }
 #pragma unroll
             for (int c = 0; c < C; ++c) act0[tq_index(l * C + c, ql)] = from_f32<MT>(h[c]);
           }
@@ -789,13 +795,20 @@ __global__ __launch_bounds__(256) void scatter_kernel(const TreeArgs T, int64_t 
 // run the loop the same number of times). Corner nodes come from the
 // forward ([L][8][Q], range-checked), positions and octahedral coordinates
 // too; weights are recomputed.
-template <int C>
+// With the disparity shift (S.wdir set) corner d's vertices and weights
+// follow its own direction v = (x - centre) disp + u, and the lane adds its
+// share of dLoss/d disparity,
+//   w_corner * dh[q][l C + c] * post_scale * sum_k (d w_k / d disp) T[k][c],
+// with d w_k / d disp = R (dw_k/dpu ds + dw_k/dpv dt), (ds, dt) = J_octa(v)
+// (x - centre); the 8 C lanes of a (query, level) are summed over the wave
+// before one atomic add into dd[q].
+template <class TT, int C>
 __global__ __launch_bounds__(256) void scatter_paper_kernel(const TreeArgs T, int64_t Q,
                                                             const int32_t* __restrict__ nidx, int64_t ldn,
                                                             const float2* __restrict__ uv,
                                                             const float4* __restrict__ pos,
                                                             const float* __restrict__ dh, float post_scale,
-                                                            const GradArgs G) {
+                                                            const GradArgs G, const ShiftArgs S) {
   constexpr int U = 8 * C;
   static_assert(64 % U == 0, "a lane group must not straddle waves");
   const int64_t stride = (int64_t)gridDim.x * blockDim.x, n = Q * U;
@@ -814,7 +827,6 @@ __global__ __launch_bounds__(256) void scatter_paper_kernel(const TreeArgs T, in
       int node[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) node[e] = ((gb >> (e * C)) & 1u) ? 0 : -1;
-      if (!ok) continue;
       const float4 xp = pos[q];
       const float xq[3] = {xp.x, xp.y, xp.z};
       int base[3], slot[3];
@@ -822,28 +834,66 @@ __global__ __launch_bounds__(256) void scatter_paper_kernel(const TreeArgs T, in
 #pragma unroll
       for (int a = 0; a < 3; ++a) cell_frac(xq[a], l, base[a], f[a]);
       corner_weights(f, node, wc);
-      const float2 p = uv[q];
-      bary(fminf(fmaxf(p.x, 0.0f), 1.0f), fminf(fmaxf(p.y, 0.0f), 1.0f), R, slot, wv);
       const float gv = dh[q * (int64_t)(T.L * C) + l * C + c] * post_scale * pick8(wc, d);
-      const int64_t nb = ((int64_t)id - T.off[l]) * E;
+      const int64_t nb = ok ? ((int64_t)id - T.off[l]) * E : 0;
+      if (S.wdir) {
+        const float4 w4 = S.wdir[q];
+        const float u[3] = {w4.x, w4.y, w4.z};
+        float v[3], dv[3], s, t, J[2][3], gu[3], gvv[3];
+        shifted_dir(xq, l, base, d, xp.w, u, v, dv);
+        octa(v, s, t);
+        octa_jacobian(v, J);
+        bary_t<true>(s, t, R, slot, wv, gu, gvv);
+        const float ds = J[0][0] * dv[0] + J[0][1] * dv[1] + J[0][2] * dv[2];
+        const float dt = J[1][0] * dv[0] + J[1][1] * dv[1] + J[1][2] * dv[2];
+        float contrib = 0.0f;
+        if (ok) {
+          const TT* tab = reinterpret_cast<const TT*>(T.feat[l]);
+#pragma unroll
+          for (int k = 0; k < 3; ++k)
+            contrib += (float)R * (gu[k] * ds + gvv[k] * dt) * to_f32(tab[(nb + slot[k]) * C + c]);
+          contrib *= gv;
+        }
+        // the group's 8 C lanes share (q, l): sum them, one add per group
+#pragma unroll
+        for (int off = U / 2; off >= 1; off >>= 1) contrib += __shfl_xor(contrib, off);
+        if ((gid % U) == 0 && contrib != 0.0f) unsafeAtomicAdd(S.dd + q, contrib);
+      } else {
+        const float2 p = uv[q];
+        bary(fminf(fmaxf(p.x, 0.0f), 1.0f), fminf(fmaxf(p.y, 0.0f), 1.0f), R, slot, wv);
+      }
+      if (!ok) continue;
 #pragma unroll
       for (int k = 0; k < 3; ++k) unsafeAtomicAdd(dst + (nb + slot[k]) * C + c, wv[k] * gv);
     }
   }
 }
 
-hipError_t launch_scatter(const TreeArgs& T, int64_t Q, const int32_t* nidx, int64_t ldn, const float2* uv,
-                          const float4* pos, const float* dh, float post_scale, const GradArgs& G, hipStream_t st) {
+template <class TT>
+static void launch_scatter_paper(const TreeArgs& T, int64_t Q, const int32_t* nidx, int64_t ldn, const float2* uv,
+                                 const float4* pos, const float* dh, float post_scale, const GradArgs& G,
+                                 const ShiftArgs& S, hipStream_t st) {
+  int64_t blocks = (Q * 8 * T.C + 255) / 256;
+  if (blocks > 256 * 16) blocks = 256 * 16;
+  if (T.C == 4)
+    hipLaunchKernelGGL((scatter_paper_kernel<TT, 4>), dim3((unsigned)blocks), dim3(256), 0, st, T, Q, nidx, ldn, uv,
+                       pos, dh, post_scale, G, S);
+  else
+    hipLaunchKernelGGL((scatter_paper_kernel<TT, 8>), dim3((unsigned)blocks), dim3(256), 0, st, T, Q, nidx, ldn, uv,
+                       pos, dh, post_scale, G, S);
+}
+
+hipError_t launch_scatter(const TreeArgs& T, oo_dtype td, int64_t Q, const int32_t* nidx, int64_t ldn,
+                          const float2* uv, const float4* pos, const float* dh, float post_scale, const GradArgs& G,
+                          const ShiftArgs& S, hipStream_t st) {
   if (Q == 0) return hipSuccess;
   if (T.interp == OO_INTERP_PAPER) {
-    int64_t blocks = (Q * 8 * T.C + 255) / 256;
-    if (blocks > 256 * 16) blocks = 256 * 16;
-    if (T.C == 4)
-      hipLaunchKernelGGL(scatter_paper_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, st, T, Q, nidx, ldn, uv, pos,
-                         dh, post_scale, G);
+    if (td == OO_F32)
+      launch_scatter_paper<float>(T, Q, nidx, ldn, uv, pos, dh, post_scale, G, S, st);
+    else if (td == OO_F16)
+      launch_scatter_paper<f16>(T, Q, nidx, ldn, uv, pos, dh, post_scale, G, S, st);
     else
-      hipLaunchKernelGGL(scatter_paper_kernel<8>, dim3((unsigned)blocks), dim3(256), 0, st, T, Q, nidx, ldn, uv, pos,
-                         dh, post_scale, G);
+      launch_scatter_paper<bf16>(T, Q, nidx, ldn, uv, pos, dh, post_scale, G, S, st);
     return hipGetLastError();
   }
   // a persistent grid walks every level: block scheduling stays out of the

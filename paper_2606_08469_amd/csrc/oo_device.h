@@ -25,6 +25,24 @@ struct TreeArgs {
   const void* feat[kMaxLevels];
 };
 
+// Kernel-argument copy of oo_disparity (forward parameters). The GPU
+// predictor has 16 hash levels of F = 2 features (its MLP input is 36
+// wide, a compile-time shape, so the weight loads batch) and hidden layers
+// of width 64; dense_mask bit i marks a level whose vertices are indexed
+// densely (decided on the host in exact integer arithmetic).
+constexpr int kHashLevels = OO_HASH_MAX_LEVELS;
+constexpr int kDispF = 2;
+constexpr int kDispH = 64;
+constexpr int kDispK = kHashLevels * kDispF + 4;
+struct DispArgs {
+  int32_t n_levels, log2_T, n_layers, K;  // K = n_levels F + 4
+  uint32_t dense_mask;
+  int32_t res[kHashLevels];
+  const float* tables;  // [n_levels][2^log2_T][F]
+  const float* W[3];
+  const float* b[3];
+};
+
 // Kernel-argument copy of oo_mlp.
 struct MlpArgs {
   int32_t n_layers;  // Linear layers; n_layers - 1 hidden layers of width H
@@ -95,6 +113,149 @@ __device__ inline void load_attr4(const QuerySrc& s, int64_t i, int k, float v[4
   const float* gp = q < 0 ? nullptr : (q < s.nA ? s.gA + s.E * q : s.gB + s.E * (q - s.nA));
 #pragma unroll
   for (int c = 0; c < 4; ++c) v[c] = gp ? gp[k + c] : 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// Disparity predictor: hash encoding of x and a small FP32 MLP per lane
+// ---------------------------------------------------------------------------
+
+// Level i of the hash encoding: the cell of x N_i (x clamped to the cube,
+// the last cell closed) and the fraction in it. The product is formed in
+// FP64, where it is exact, so the cell is the one the FP64 definition
+// gives.
+__device__ __forceinline__ void hash_cell(float xa, int N, int& base, float& f) {
+  const double p = (double)fminf(fmaxf(xa, 0.0f), 1.0f) * (double)N;
+  double fl = floor(p);
+  if (fl > (double)(N - 1)) fl = (double)(N - 1);
+  base = (int)fl;
+  f = (float)(p - fl);
+}
+
+// Entry of grid vertex (a, b, c) of level i: dense, or the spatial hash
+// (per-axis primes 1, 2654435761, 805459861, xor) modulo the table size.
+__device__ __forceinline__ uint32_t hash_entry(const DispArgs& G, int i, uint32_t a, uint32_t b, uint32_t c) {
+  if ((G.dense_mask >> i) & 1u) {
+    const uint32_t N1 = (uint32_t)G.res[i] + 1u;
+    return a + N1 * (b + N1 * c);
+  }
+  return (a ^ (b * 2654435761u) ^ (c * 805459861u)) & ((1u << G.log2_T) - 1u);
+}
+
+// The predictor's input [encoding, unit(w_r), 0] (zeros past it).
+__device__ __forceinline__ void disparity_input(const DispArgs& G, const float x[3], const float u[3], float (&a)[kDispK]) {
+#pragma unroll
+  for (int k = 0; k < kDispK; ++k) a[k] = 0.0f;
+#pragma unroll
+  for (int i = 0; i < kHashLevels; ++i) {
+    if (i < G.n_levels) {
+      const int N = G.res[i];
+      int base[3];
+      float f[3];
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) hash_cell(x[ax], N, base[ax], f[ax]);
+      const float2* tab = reinterpret_cast<const float2*>(G.tables) + ((size_t)i << G.log2_T);
+      float2 r[8];
+#pragma unroll
+      for (int d = 0; d < 8; ++d)
+        r[d] = tab[hash_entry(G, i, base[0] + (d & 1), base[1] + ((d >> 1) & 1), base[2] + (d >> 2))];
+      float e0 = 0.0f, e1 = 0.0f;
+#pragma unroll
+      for (int d = 0; d < 8; ++d) {
+        const float w = ((d & 1) ? f[0] : 1.0f - f[0]) * (((d >> 1) & 1) ? f[1] : 1.0f - f[1]) *
+                        ((d >> 2) ? f[2] : 1.0f - f[2]);
+        e0 += w * r[d].x;
+        e1 += w * r[d].y;
+      }
+      a[2 * i] = e0;
+      a[2 * i + 1] = e1;
+    }
+  }
+  const int nF = kDispF * G.n_levels;
+#pragma unroll
+  for (int k = 0; k < kDispK; ++k) {
+    if (k == nF) a[k] = u[0];
+    if (k == nF + 1) a[k] = u[1];
+    if (k == nF + 2) a[k] = u[2];
+  }
+}
+
+// The predictor's hidden units are formed kDispChunk at a time and streamed
+// into the next layer, so that a lane holds its input, one chunk and the
+// next layer's sums in registers. The weight addresses are uniform across
+// the wave, so the weights come through the scalar cache.
+constexpr int kDispChunk = 16;
+
+// Units c .. c + kDispChunk - 1 of the first hidden layer, ReLU'd:
+// b_0[o] + sum_k W_0[o][k] a[k] (W: the first layer's weights, rows of
+// kDispK).
+__device__ __forceinline__ void disp_chunk0(const DispArgs& G, const float* W, int c, const float (&a)[kDispK],
+                                            float (&h)[kDispChunk]) {
+#pragma unroll
+  for (int j = 0; j < kDispChunk; ++j) {
+    const int o = c + j;
+    float z = G.b[0][o];
+#pragma unroll
+    for (int k = 0; k < kDispK; ++k) z += W[o * kDispK + k] * a[k];
+    h[j] = fmaxf(z, 0.0f);
+  }
+}
+
+// Pre-activations of the second hidden layer (before its bias and ReLU)
+// from the first layer's units, chunk by chunk; h1_out(c, h1) sees every
+// chunk.
+template <class Sink>
+__device__ __forceinline__ void disp_hidden2(const DispArgs& G, const float* W0, const float* W1, const float (&a)[kDispK],
+                                    float (&z2)[kDispH], Sink&& h1_out) {
+#pragma unroll
+  for (int o = 0; o < kDispH; ++o) z2[o] = G.b[1][o];
+#pragma unroll 1
+  for (int c = 0; c < kDispH; c += kDispChunk) {
+    float h1[kDispChunk];
+    disp_chunk0(G, W0, c, a, h1);
+    h1_out(c, h1);
+#pragma unroll
+    for (int o = 0; o < kDispH; ++o) {
+#pragma unroll
+      for (int j = 0; j < kDispChunk; ++j) z2[o] += W1[o * kDispH + c + j] * h1[j];
+      // a few units' weights in flight at a time: the scheduler would
+      // otherwise hoist all of them into scalar registers and spill
+      if ((o & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+// Predicted disparity d(x, w_r) of one lane's query (u = unit(w_r)).
+__device__ __forceinline__ float predict_disparity(const DispArgs& G, const float x[3], const float u[3]) {
+  float a[kDispK];
+  disparity_input(G, x, u, a);
+  // (selected, not indexed: a runtime index into the argument's arrays
+  // would copy them to scratch memory)
+  const bool two = G.n_layers == 3;
+  const float* Wo = two ? G.W[2] : G.W[1];
+  float d = (two ? G.b[2] : G.b[1])[0];
+  if (two) {
+    float z2[kDispH];
+    disp_hidden2(G, G.W[0], G.W[1], a, z2, [](int, const float (&)[kDispChunk]) {});
+#pragma unroll
+    for (int o = 0; o < kDispH; ++o) d += Wo[o] * fmaxf(z2[o], 0.0f);
+  } else {
+#pragma unroll 1
+    for (int c = 0; c < kDispH; c += kDispChunk) {
+      float h1[kDispChunk];
+      disp_chunk0(G, G.W[0], c, a, h1);
+#pragma unroll
+      for (int j = 0; j < kDispChunk; ++j) d += Wo[c + j] * h1[j];
+    }
+  }
+  return d;
+}
+
+// Unit vector of a direction (zero stays zero).
+__device__ __forceinline__ void unit_dir3(const float d[3], float u[3]) {
+  const float n2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  const float inv = n2 > 0.0f ? 1.0f / sqrtf(n2) : 0.0f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) u[a] = d[a] * inv;
 }
 
 // ---------------------------------------------------------------------------
@@ -482,36 +643,90 @@ __device__ inline int vertex_slot(int i, int j, int R) {
 // the cell is split along the diagonal parallel to its quadrant's equator
 // segment (anti-diagonal where s - 1/2 and t - 1/2 have the same sign, main
 // diagonal otherwise), so the triangle lies in one octahedron face.
-__device__ inline void bary(float s, float t, int R, int slot[3], float w[3]) {
+// With GRAD, gu / gv receive the weights' derivatives with respect to
+// pu = s R and pv = t R (constant inside the triangle).
+template <bool GRAD>
+__device__ __forceinline__ void bary_t(float s, float t, int R, int slot[3], float w[3], float gu[3], float gv[3]) {
   const float pu = s * (float)R, pv = t * (float)R;
   const int i = min(max((int)floorf(pu), 0), R - 1), j = min(max((int)floorf(pv), 0), R - 1);
   const float fu = pu - (float)i, fv = pv - (float)j;
   const bool same = (2 * i >= R) == (2 * j >= R);
   int i0, j0, i1, j1, i2, j2;
+  float du[3], dv[3];
   if (same) {
     if (fu + fv <= 1.0f) {
-      i0 = i; j0 = j; w[0] = 1.0f - fu - fv;
-      i1 = i + 1; j1 = j; w[1] = fu;
-      i2 = i; j2 = j + 1; w[2] = fv;
+      i0 = i; j0 = j; w[0] = 1.0f - fu - fv; du[0] = -1.0f; dv[0] = -1.0f;
+      i1 = i + 1; j1 = j; w[1] = fu; du[1] = 1.0f; dv[1] = 0.0f;
+      i2 = i; j2 = j + 1; w[2] = fv; du[2] = 0.0f; dv[2] = 1.0f;
     } else {
-      i0 = i + 1; j0 = j + 1; w[0] = fu + fv - 1.0f;
-      i1 = i; j1 = j + 1; w[1] = 1.0f - fu;
-      i2 = i + 1; j2 = j; w[2] = 1.0f - fv;
+      i0 = i + 1; j0 = j + 1; w[0] = fu + fv - 1.0f; du[0] = 1.0f; dv[0] = 1.0f;
+      i1 = i; j1 = j + 1; w[1] = 1.0f - fu; du[1] = -1.0f; dv[1] = 0.0f;
+      i2 = i + 1; j2 = j; w[2] = 1.0f - fv; du[2] = 0.0f; dv[2] = -1.0f;
     }
   } else {
     if (fu >= fv) {
-      i0 = i; j0 = j; w[0] = 1.0f - fu;
-      i1 = i + 1; j1 = j; w[1] = fu - fv;
-      i2 = i + 1; j2 = j + 1; w[2] = fv;
+      i0 = i; j0 = j; w[0] = 1.0f - fu; du[0] = -1.0f; dv[0] = 0.0f;
+      i1 = i + 1; j1 = j; w[1] = fu - fv; du[1] = 1.0f; dv[1] = -1.0f;
+      i2 = i + 1; j2 = j + 1; w[2] = fv; du[2] = 0.0f; dv[2] = 1.0f;
     } else {
-      i0 = i; j0 = j; w[0] = 1.0f - fv;
-      i1 = i; j1 = j + 1; w[1] = fv - fu;
-      i2 = i + 1; j2 = j + 1; w[2] = fu;
+      i0 = i; j0 = j; w[0] = 1.0f - fv; du[0] = 0.0f; dv[0] = -1.0f;
+      i1 = i; j1 = j + 1; w[1] = fv - fu; du[1] = -1.0f; dv[1] = 1.0f;
+      i2 = i + 1; j2 = j + 1; w[2] = fu; du[2] = 1.0f; dv[2] = 0.0f;
+    }
+  }
+  if constexpr (GRAD) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      gu[k] = du[k];
+      gv[k] = dv[k];
     }
   }
   slot[0] = vertex_slot(i0, j0, R);
   slot[1] = vertex_slot(i1, j1, R);
   slot[2] = vertex_slot(i2, j2, R);
+}
+
+__device__ __forceinline__ void bary(float s, float t, int R, int slot[3], float w[3]) {
+  bary_t<false>(s, t, R, slot, w, nullptr, nullptr);
+}
+
+// d(s, t) / d v of octa(v), on the piece octa() evaluates (sign(0) = +1).
+__device__ __forceinline__ void octa_jacobian(const float v[3], float J[2][3]) {
+  const float S = fabsf(v[0]) + fabsf(v[1]) + fabsf(v[2]);
+  float du[2][3];
+  const float iS = S > 0.0f ? 1.0f / S : 0.0f;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) du[a][b] = (a == b ? iS : 0.0f) - v[a] * (v[b] < 0.0f ? -iS : iS) * iS;
+  if (v[2] < 0.0f) {
+    const float sxy = (v[0] < 0.0f) == (v[1] < 0.0f) ? -1.0f : 1.0f;  // -sign(u_x) sign(u_y)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const float fx = sxy * du[1][b], fy = sxy * du[0][b];
+      du[0][b] = fx;
+      du[1][b] = fy;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) J[a][b] = 0.5f * du[a][b];
+}
+
+// Shifted lookup of the level-l cell base + corner d: v = (x - centre) disp
+// + u with centre (cell + 1/2) / 2^l; dv = x - centre (= d v / d disp).
+// x is clamped to the cube as for the cells.
+__device__ __forceinline__ void shifted_dir(const float x[3], int l, const int base[3], int d, float disp, const float u[3],
+                                   float v[3], float dv[3]) {
+  const float inv = 1.0f / (float)(1u << l);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int bit = (d >> a) & 1;
+    const float xc = fminf(fmaxf(x[a], 0.0f), 1.0f);
+    dv[a] = xc - ((float)(base[a] + bit) + 0.5f) * inv;
+    v[a] = dv[a] * disp + u[a];
+  }
 }
 
 // Level feature of the paper's scheme: sum over the corners and the three
@@ -546,14 +761,55 @@ __device__ inline void gather_paper_level(const TreeArgs& T, int l, const int no
   }
 }
 
+// The same level feature with the disparity shift: corner d's cell is read
+// at its own direction (x - centre) disp + u (one barycentric lookup per
+// corner).
+template <class TT, int C>
+__device__ __forceinline__ void gather_paper_level_shift(const TreeArgs& T, int l, const int node[8], const float wc[8],
+                                                const float x[3], const int base[3], float disp, const float u[3],
+                                                float* h) {
+  typedef typename Texel<TT, C>::raw Raw;
+  constexpr int CB = sizeof(TT) * C > 16 ? 2 : 4;  // corners per batch
+  const int R = T.res[l];
+  const int64_t E = (int64_t)(R + 1) * (R + 1);
+  const TT* tab = reinterpret_cast<const TT*>(T.feat[l]);
+#pragma unroll
+  for (int c = 0; c < C; ++c) h[c] = 0.0f;
+#pragma unroll
+  for (int b0 = 0; b0 < 8; b0 += CB) {
+    Raw r[CB][3];
+    float wv[CB][3];
+#pragma unroll
+    for (int dd = 0; dd < CB; ++dd) {
+      const int d = b0 + dd;
+      float v[3], dv[3], s, t;
+      shifted_dir(x, l, base, d, disp, u, v, dv);
+      octa(v, s, t);
+      int slot[3];
+      bary(s, t, R, slot, wv[dd]);
+      const bool ok = node[d] >= 0;
+      const int64_t nb = ok ? ((int64_t)node[d] - T.off[l]) * E : 0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) Texel<TT, C>::load(tab + (ok ? (nb + slot[k]) * C : 0), r[dd][k]);
+    }
+#pragma unroll
+    for (int dd = 0; dd < CB; ++dd)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) Texel<TT, C>::acc(r[dd][k], wc[b0 + dd] * wv[dd][k], h);
+  }
+}
+
 // Encoding of one query in the paper's scheme, level by level: the eight
 // corners' nodes follow from the previous level's (their node words are
 // loaded while this level's entries are gathered). put(l, h, node) receives
 // each level's C features and the eight corner nodes. Once no lane of the
 // wave has a corner left, deeper levels are empty too (their cells' parents
 // are among this level's corners) and get zeros.
-template <class TT, int C, class Put>
-__device__ inline void encode_paper(const TreeArgs& T, bool valid, const float x[3], float s, float t, Put&& put) {
+// With SHIFT every corner's cell is read along its shifted direction
+// (disparity disp, unit lookup direction u).
+template <class TT, int C, bool SHIFT = false, class Put>
+__device__ __forceinline__ void encode_paper(const TreeArgs& T, bool valid, const float x[3], float s, float t, Put&& put,
+                                    float disp = 0.0f, const float* u = nullptr) {
   const int L = T.L, D = T.D;
   int base[3], pbase[3], node[8], pnode[8];
   uint32_t pword[8];
@@ -573,12 +829,17 @@ __device__ inline void encode_paper(const TreeArgs& T, bool valid, const float x
     // node words for the next level, then this level's entries
 #pragma unroll
     for (int d = 0; d < 8; ++d) pword[d] = (l < D && node[d] >= 0) ? T.nodes[node[d]] : 0u;
-    float wc[8], wv[3];
-    int slot[3];
+    float wc[8];
     corner_weights(f, node, wc);
-    bary(s, t, T.res[l], slot, wv);
     float h[C];
-    gather_paper_level<TT, C>(T, l, node, wc, slot, wv, h);
+    if constexpr (SHIFT) {
+      gather_paper_level_shift<TT, C>(T, l, node, wc, x, base, disp, u, h);
+    } else {
+      float wv[3];
+      int slot[3];
+      bary(s, t, T.res[l], slot, wv);
+      gather_paper_level<TT, C>(T, l, node, wc, slot, wv, h);
+    }
     put(l, h, node);
 #pragma unroll
     for (int a = 0; a < 3; ++a) pbase[a] = base[a];

@@ -11,10 +11,13 @@ namespace oo {
 // ---------------------------------------------------------------------------
 // Standalone encoding: one thread per query, h written row-major to memory.
 // ---------------------------------------------------------------------------
-template <class TT, class HT, int C, bool PAPER>
+// MODE: 0 node + bilinear, 1 the paper's scheme, 2 the paper's scheme with
+// the disparity shift (predicted per query from G).
+template <class TT, class HT, int C, int MODE>
 __global__ __launch_bounds__(256) void encode_kernel(const TreeArgs T, const float* __restrict__ x,
                                                      const float* __restrict__ dir, int64_t B,
-                                                     HT* __restrict__ h_out, int32_t* __restrict__ idx_out) {
+                                                     HT* __restrict__ h_out, int32_t* __restrict__ idx_out,
+                                                     const DispArgs G) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = q < B;
   float xq[3] = {0.f, 0.f, 0.f}, dq[3] = {0.f, 0.f, 1.f};
@@ -26,13 +29,18 @@ __global__ __launch_bounds__(256) void encode_kernel(const TreeArgs T, const flo
     }
   }
   typedef HT vC __attribute__((ext_vector_type(C)));
-  if constexpr (PAPER) {
+  if constexpr (MODE > 0) {
     // the eight cells around x per level, barycentric vertex maps
     float s, t;
     octa(dq, s, t);
+    float u[3] = {0.f, 0.f, 0.f}, disp = 0.0f;
+    if constexpr (MODE == 2) {
+      unit_dir3(dq, u);
+      disp = predict_disparity(G, xq, u);
+    }
     const int L = T.L;
     HT* hrow = h_out + (valid ? q : 0) * (int64_t)(L * C);
-    encode_paper<TT, C>(T, valid, xq, s, t, [&](int l, const float (&h)[C], const int (&node)[8]) {
+    encode_paper<TT, C, MODE == 2>(T, valid, xq, s, t, [&](int l, const float (&h)[C], const int (&node)[8]) {
       if (!valid) return;
       vC v;
 #pragma unroll
@@ -43,7 +51,7 @@ __global__ __launch_bounds__(256) void encode_kernel(const TreeArgs T, const flo
         o[0] = make_int4(node[0], node[1], node[2], node[3]);
         o[1] = make_int4(node[4], node[5], node[6], node[7]);
       }
-    });
+    }, disp, u);
     return;
   }
   int idx[kMaxLevels];
@@ -231,11 +239,16 @@ __device__ inline void store_rgb(const f32x4 out[NT], int t0, int64_t q_base, in
 // In the paper's scheme the stored indices are the eight corner cells'
 // nodes per level ([L][8][n_idx]) and the query's position is kept too
 // (pos_out, [n_idx]); the backward recomputes the trilinear weights from it.
-template <class TT, class MT, int C, int H, bool WLDS, bool PAPER>
+// MODE as for encode_kernel; with the shift the query's predicted
+// disparity goes to pos_out's w and its unit lookup direction to wdir_out.
+template <class TT, class MT, int C, int H, bool WLDS, int MODE>
 __global__ __launch_bounds__(512) void query_kernel(const TreeArgs T, const MlpArgs M, const QuerySrc src,
-                                                    int64_t Q, float* __restrict__ rgb, int32_t* __restrict__ idx_out,
-                                                    float2* __restrict__ uv_out, float4* __restrict__ pos_out,
-                                                    int64_t n_idx) {
+                                                    int64_t Q, float* __restrict__ rgb, const QueryOut O,
+                                                    const DispArgs G) {
+  int32_t* __restrict__ idx_out = O.idx;
+  float2* __restrict__ uv_out = O.uv;
+  float4* __restrict__ pos_out = O.pos;
+  const int64_t n_idx = O.n_idx;
   extern __shared__ __attribute__((aligned(16))) char smem[];
   constexpr int NT = 2;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63, waves = blockDim.x >> 6;
@@ -261,15 +274,21 @@ __global__ __launch_bounds__(512) void query_kernel(const TreeArgs T, const MlpA
     octa(d, s, t);
     const bool keep = q < n_idx;
     if (keep) uv_out[q] = make_float2(s, t);
-    if constexpr (PAPER) {
-      if (keep) pos_out[q] = make_float4(x[0], x[1], x[2], 0.0f);
-      encode_paper<TT, C>(T, valid, x, s, t, [&](int l, const float (&h)[C], const int (&node)[8]) {
+    if constexpr (MODE > 0) {
+      float u[3] = {0.f, 0.f, 0.f}, disp = 0.0f;
+      if constexpr (MODE == 2) {
+        unit_dir3(d, u);
+        disp = predict_disparity(G, x, u);
+        if (keep) O.wdir[q] = make_float4(u[0], u[1], u[2], 0.0f);
+      }
+      if (keep) pos_out[q] = make_float4(x[0], x[1], x[2], disp);
+      encode_paper<TT, C, MODE == 2>(T, valid, x, s, t, [&](int l, const float (&h)[C], const int (&node)[8]) {
 #pragma unroll
         for (int c = 0; c < C; c += 4) htile_put4<MT>(htile, KB0, lane, l * C + c, &h[c]);
         if (keep)
 #pragma unroll
           for (int d = 0; d < 8; ++d) idx_out[(l * 8 + d) * n_idx + q] = node[d];  // coalesced across lanes
-      });
+      }, disp, u);
     } else {
       encode_pipelined<TT, C>(T, valid, x, s, t, [&](int l, const float* h, int node) {
 #pragma unroll
@@ -545,38 +564,64 @@ static int max_lds() {
 
 template <class TT, class HT, int C>
 static hipError_t launch_encode_t(const TreeArgs& T, const float* x, const float* d, int64_t B, void* h,
-                                  int32_t* idx, hipStream_t st) {
+                                  int32_t* idx, const DispArgs& G, hipStream_t st) {
   const int64_t blocks = (B + 255) / 256;
-  if (T.interp == OO_INTERP_PAPER)
-    hipLaunchKernelGGL((encode_kernel<TT, HT, C, true>), dim3((unsigned)blocks), dim3(256), 0, st, T, x, d, B,
-                       reinterpret_cast<HT*>(h), idx);
+  HT* hp = reinterpret_cast<HT*>(h);
+  if (T.interp != OO_INTERP_PAPER)
+    hipLaunchKernelGGL((encode_kernel<TT, HT, C, 0>), dim3((unsigned)blocks), dim3(256), 0, st, T, x, d, B, hp, idx, G);
+  else if (G.n_levels == 0)
+    hipLaunchKernelGGL((encode_kernel<TT, HT, C, 1>), dim3((unsigned)blocks), dim3(256), 0, st, T, x, d, B, hp, idx, G);
+  else if constexpr (sizeof(HT) == 4)  // the shifted encoding writes FP32 features only
+    hipLaunchKernelGGL((encode_kernel<TT, HT, C, 2>), dim3((unsigned)blocks), dim3(256), 0, st, T, x, d, B, hp, idx, G);
   else
-    hipLaunchKernelGGL((encode_kernel<TT, HT, C, false>), dim3((unsigned)blocks), dim3(256), 0, st, T, x, d, B,
-                       reinterpret_cast<HT*>(h), idx);
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 template <class TT, int C>
 static hipError_t launch_encode_h(const TreeArgs& T, const float* x, const float* d, int64_t B, void* h,
-                                  oo_dtype hd, int32_t* idx, hipStream_t st) {
+                                  oo_dtype hd, int32_t* idx, const DispArgs& G, hipStream_t st) {
   switch (hd) {
-    case OO_F32: return launch_encode_t<TT, float, C>(T, x, d, B, h, idx, st);
-    case OO_F16: return launch_encode_t<TT, f16, C>(T, x, d, B, h, idx, st);
-    default: return launch_encode_t<TT, bf16, C>(T, x, d, B, h, idx, st);
+    case OO_F32: return launch_encode_t<TT, float, C>(T, x, d, B, h, idx, G, st);
+    case OO_F16: return launch_encode_t<TT, f16, C>(T, x, d, B, h, idx, G, st);
+    default: return launch_encode_t<TT, bf16, C>(T, x, d, B, h, idx, G, st);
   }
 }
 
 hipError_t launch_encode(const TreeArgs& T, oo_dtype td, const float* x, const float* d, int64_t B, void* h,
-                         oo_dtype hd, int32_t* idx, hipStream_t st) {
+                         oo_dtype hd, int32_t* idx, const DispArgs& G, hipStream_t st) {
   if (B == 0) return hipSuccess;
   if (td == OO_F32)
-    return T.C == 4 ? launch_encode_h<float, 4>(T, x, d, B, h, hd, idx, st)
-                    : launch_encode_h<float, 8>(T, x, d, B, h, hd, idx, st);
+    return T.C == 4 ? launch_encode_h<float, 4>(T, x, d, B, h, hd, idx, G, st)
+                    : launch_encode_h<float, 8>(T, x, d, B, h, hd, idx, G, st);
   if (td == OO_F16)
-    return T.C == 4 ? launch_encode_h<f16, 4>(T, x, d, B, h, hd, idx, st)
-                    : launch_encode_h<f16, 8>(T, x, d, B, h, hd, idx, st);
-  return T.C == 4 ? launch_encode_h<bf16, 4>(T, x, d, B, h, hd, idx, st)
-                  : launch_encode_h<bf16, 8>(T, x, d, B, h, hd, idx, st);
+    return T.C == 4 ? launch_encode_h<f16, 4>(T, x, d, B, h, hd, idx, G, st)
+                    : launch_encode_h<f16, 8>(T, x, d, B, h, hd, idx, G, st);
+  return T.C == 4 ? launch_encode_h<bf16, 4>(T, x, d, B, h, hd, idx, G, st)
+                  : launch_encode_h<bf16, 8>(T, x, d, B, h, hd, idx, G, st);
+}
+
+// Grid of the tile kernels for a workgroup of `waves` waves using lds bytes.
+static int tile_grid(int64_t Q, int waves, size_t lds) {
+  const int64_t n_tiles = (Q + 63) / 64;
+  // LDS per CU on gfx950 is 160 KiB: one or two workgroups fit per CU.
+  const int per_cu = lds * 2 <= (size_t)160 * 1024 ? 2 : 1;
+  int64_t g = (int64_t)device_cus() * per_cu;
+  const int64_t need = (n_tiles + waves - 1) / waves;
+  if (g > need) g = need;
+  if (g >= 8) g -= g % 8;
+  return (int)(g > 0 ? g : 1);
+}
+
+// The shape without weights in LDS: as many 64-query tiles as fit, up to 8.
+template <class MT>
+static void tile_launch_shape_plain(const MlpArgs& M, int64_t Q, int& waves, size_t& lds, int& grid) {
+  const int KB0 = (M.K0 + 31) / 32;
+  const size_t tile_bytes = (size_t)4 * KB0 * kWave * 8 * sizeof(MT);
+  waves = 8;
+  while (waves > 1 && waves * tile_bytes > (size_t)max_lds()) --waves;
+  lds = waves * tile_bytes;
+  grid = tile_grid(Q, waves, lds);
 }
 
 // Workgroup shape for the tile kernels: up to 8 waves, each with a 64-query
@@ -596,62 +641,59 @@ static void tile_launch_shape(const MlpArgs& M, int64_t Q, bool& wlds, int& wave
     while (waves > 1 && waves * tile_bytes > cap) --waves;
   }
   lds = (wlds ? wbytes : 0) + waves * tile_bytes;
-  const int64_t n_tiles = (Q + 63) / 64;
-  // LDS per CU on gfx950 is 160 KiB: one or two workgroups fit per CU.
-  const int per_cu = lds * 2 <= (size_t)160 * 1024 ? 2 : 1;
-  int64_t g = (int64_t)device_cus() * per_cu;
-  const int64_t need = (n_tiles + waves - 1) / waves;
-  if (g > need) g = need;
-  if (g >= 8) g -= g % 8;
-  grid = (int)(g > 0 ? g : 1);
+  grid = tile_grid(Q, waves, lds);
 }
 
-template <class TT, class MT, int C, int H, bool PAPER>
+
+template <class TT, class MT, int C, int H, int MODE>
 static hipError_t launch_query_p(const TreeArgs& T, const MlpArgs& M, const QuerySrc& src, int64_t Q, float* rgb,
-                                 int32_t* idx_out, float2* uv_out, float4* pos_out, int64_t n_idx, hipStream_t st) {
+                                 const QueryOut& O, const DispArgs& G, hipStream_t st) {
   bool wlds;
   int waves, grid;
   size_t lds;
   tile_launch_shape<MT>(M, Q, wlds, waves, lds, grid);
+  if (wlds && MODE == 2) {  // the predictor's registers: keep one variant
+    wlds = false;
+    tile_launch_shape_plain<MT>(M, Q, waves, lds, grid);
+  }
   if (wlds) {
-    auto k = query_kernel<TT, MT, C, H, true, PAPER>;
+    auto k = query_kernel<TT, MT, C, H, true, MODE == 2 ? 1 : MODE>;
     hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, st, T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, st, T, M, src, Q, rgb, O, G);
   } else {
-    auto k = query_kernel<TT, MT, C, H, false, PAPER>;
+    auto k = query_kernel<TT, MT, C, H, false, MODE>;
     hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, st, T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, st, T, M, src, Q, rgb, O, G);
   }
   return hipGetLastError();
 }
 
 template <class TT, class MT, int C, int H>
 static hipError_t launch_query_t(const TreeArgs& T, const MlpArgs& M, const QuerySrc& src, int64_t Q, float* rgb,
-                                 int32_t* idx_out, float2* uv_out, float4* pos_out, int64_t n_idx, hipStream_t st) {
-  return T.interp == OO_INTERP_PAPER
-             ? launch_query_p<TT, MT, C, H, true>(T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx, st)
-             : launch_query_p<TT, MT, C, H, false>(T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx, st);
+                                 const QueryOut& O, const DispArgs& G, hipStream_t st) {
+  if (T.interp != OO_INTERP_PAPER) return launch_query_p<TT, MT, C, H, 0>(T, M, src, Q, rgb, O, G, st);
+  return G.n_levels == 0 ? launch_query_p<TT, MT, C, H, 1>(T, M, src, Q, rgb, O, G, st)
+                         : launch_query_p<TT, MT, C, H, 2>(T, M, src, Q, rgb, O, G, st);
 }
 
 template <class TT, class MT, int C>
 static hipError_t launch_query_c(const TreeArgs& T, const MlpArgs& M, const QuerySrc& src, int64_t Q, float* rgb,
-                                 int32_t* idx_out, float2* uv_out, float4* pos_out, int64_t n_idx, hipStream_t st) {
-  return M.H == 64 ? launch_query_t<TT, MT, C, 64>(T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx, st)
-                   : launch_query_t<TT, MT, C, 128>(T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx, st);
+                                 const QueryOut& O, const DispArgs& G, hipStream_t st) {
+  return M.H == 64 ? launch_query_t<TT, MT, C, 64>(T, M, src, Q, rgb, O, G, st)
+                   : launch_query_t<TT, MT, C, 128>(T, M, src, Q, rgb, O, G, st);
 }
 
 hipError_t launch_query(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, const QuerySrc& src,
-                        int64_t Q, float* rgb, int32_t* idx_out, float2* uv_out, float4* pos_out, int64_t n_idx,
-                        hipStream_t st) {
+                        int64_t Q, float* rgb, const QueryOut& O, const DispArgs& G, hipStream_t st) {
   if (Q == 0) return hipSuccess;
   if (td == OO_F32)
-    return T.C == 4 ? launch_query_c<float, float, 4>(T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx, st)
-                    : launch_query_c<float, float, 8>(T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx, st);
+    return T.C == 4 ? launch_query_c<float, float, 4>(T, M, src, Q, rgb, O, G, st)
+                    : launch_query_c<float, float, 8>(T, M, src, Q, rgb, O, G, st);
   if (td == OO_F16)
-    return T.C == 4 ? launch_query_c<f16, f16, 4>(T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx, st)
-                    : launch_query_c<f16, f16, 8>(T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx, st);
-  return T.C == 4 ? launch_query_c<bf16, bf16, 4>(T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx, st)
-                  : launch_query_c<bf16, bf16, 8>(T, M, src, Q, rgb, idx_out, uv_out, pos_out, n_idx, st);
+    return T.C == 4 ? launch_query_c<f16, f16, 4>(T, M, src, Q, rgb, O, G, st)
+                    : launch_query_c<f16, f16, 8>(T, M, src, Q, rgb, O, G, st);
+  return T.C == 4 ? launch_query_c<bf16, bf16, 4>(T, M, src, Q, rgb, O, G, st)
+                  : launch_query_c<bf16, bf16, 8>(T, M, src, Q, rgb, O, G, st);
   (void)md;
 }
 

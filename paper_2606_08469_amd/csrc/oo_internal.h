@@ -49,15 +49,24 @@ struct ReduceDst {
 };
 
 hipError_t launch_encode(const TreeArgs& T, oo_dtype td, const float* x, const float* d, int64_t B, void* h,
-                         oo_dtype hd, int32_t* idx, hipStream_t st);
+                         oo_dtype hd, int32_t* idx, const DispArgs& G, hipStream_t st);
 hipError_t launch_mlp(const MlpArgs& M, oo_dtype md, const void* h, int64_t Q, float* rgb, hipStream_t st);
 // Queries q < n_idx also store their node index per level (idx_out,
 // [L][n_idx]; the paper's scheme: the eight corner nodes, [L][8][n_idx], and
 // the position, pos_out [n_idx]) and octahedral coordinates (uv_out,
 // [n_idx]).
+// With the disparity predictor (G.n_levels > 0; the paper's scheme only)
+// the fused kernel predicts each query's disparity, stores it in pos_out's
+// w and the unit lookup direction in wdir_out ([n_idx]).
+struct QueryOut {
+  int32_t* idx;
+  float2* uv;
+  float4* pos;
+  float4* wdir;
+  int64_t n_idx;
+};
 hipError_t launch_query(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, const QuerySrc& src,
-                        int64_t Q, float* rgb, int32_t* idx_out, float2* uv_out, float4* pos_out, int64_t n_idx,
-                        hipStream_t st);
+                        int64_t Q, float* rgb, const QueryOut& O, const DispArgs& G, hipStream_t st);
 
 // Spatial bucketing of the residual queries: NB chunks, K buckets (octree
 // cell level c). Workspace: counts [NB][K], total [K], start [K] int32;
@@ -106,11 +115,32 @@ struct BwdArgs {
   const float* gA = nullptr;
   const float* gB = nullptr;
   int64_t nA = 0, n_src = 0;
+  // the disparity shift: unit lookup directions [Q] (the disparity is in
+  // pos[q].w)
+  const float4* wdir = nullptr;
+  int shift = 0;
 };
 hipError_t launch_bwd(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, void* const* Wt,
                       const BwdArgs& A, const ParamLayout& PL, int grid, hipStream_t st);
-hipError_t launch_scatter(const TreeArgs& T, int64_t Q, const int32_t* nidx, int64_t ldn, const float2* uv,
-                          const float4* pos, const float* dh, float post_scale, const GradArgs& G, hipStream_t st);
+// Feature-gradient scatter. With the disparity shift (wdir set; the
+// paper's scheme) it also adds each query's dLoss/d disparity into dd[q]
+// (dd cleared by the caller), reading the tables (feat, type td) it
+// differentiates through.
+struct ShiftArgs {
+  const float4* wdir = nullptr;
+  float* dd = nullptr;
+};
+hipError_t launch_scatter(const TreeArgs& T, oo_dtype td, int64_t Q, const int32_t* nidx, int64_t ldn,
+                          const float2* uv, const float4* pos, const float* dh, float post_scale, const GradArgs& G,
+                          const ShiftArgs& S, hipStream_t st);
+// Disparity predictor backward over the Q sorted backward queries (x, dir
+// from src; dd[q] = dLoss/d disparity): hash-table gradients added into
+// dtables, MLP parameter sums per workgroup into partials [grid][P] with
+// P = disparity_params(G) (flat W_0, b_0, (W_1, b_1,) W_out, b_out).
+int disparity_bwd_grid(int64_t Q);
+int32_t disparity_params(const DispArgs& G);
+hipError_t launch_disparity_bwd(const DispArgs& G, const QuerySrc& src, int64_t Q, const float* dd, float* dtables,
+                                float* partials, int grid, hipStream_t st);
 hipError_t launch_dw_reduce(const float* partials, int grid, const ParamLayout& PL, const ReduceDst& D, float scale,
                             hipStream_t st);
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t st);
@@ -139,6 +169,7 @@ struct AdamSeg {
   int64_t n;
   const uint32_t* touched;
   int64_t block;
+  int vec;  // every array aligned for one vector of 4 elements per thread
 };
 struct AdamArgs {
   int32_t n_segs;

@@ -13,10 +13,19 @@ namespace oo {
 // flag of its first element; blocks are whole multiples of 4 elements
 // (every table block is res^2 C or (res+1)^2 C with C in {4, 8}), so the
 // four elements share it. The last thread of a segment may hold fewer than
-// four elements.
+// four elements. Segments whose arrays are all 16-byte aligned (8-byte for
+// a 16-bit working copy) move each array as one vector per thread.
+__device__ inline float adam_update(const AdamArgs& A, float& p, float& m, float& v, float g) {
+  m = A.b1 * m + (1.0f - A.b1) * g;
+  v = A.b2 * v + (1.0f - A.b2) * g * g;
+  p = p - A.lr * (m * A.inv_c1) / (sqrtf(v * A.inv_c2) + A.eps);
+  return p;
+}
+
 template <class WT>
 __global__ __launch_bounds__(256) void adam_kernel(const AdamArgs A) {
   const int64_t total = A.first[A.n_segs];
+  typedef WT w4 __attribute__((ext_vector_type(4)));
   for (int64_t tq = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; tq < total;
        tq += (int64_t)gridDim.x * blockDim.x) {
     int s = 0;
@@ -25,12 +34,33 @@ __global__ __launch_bounds__(256) void adam_kernel(const AdamArgs A) {
     const int64_t i0 = (tq - A.first[s]) * 4;
     if (S.touched && !S.touched[i0 / S.block]) continue;
     const int cnt = S.n - i0 < 4 ? (int)(S.n - i0) : 4;
+    if (S.vec && cnt == 4) {
+      float4 p = *reinterpret_cast<const float4*>(S.param + i0);
+      float4 m = *reinterpret_cast<const float4*>(S.m + i0);
+      float4 v = *reinterpret_cast<const float4*>(S.v + i0);
+      const float4 g = *reinterpret_cast<const float4*>(S.grad + i0);
+      adam_update(A, p.x, m.x, v.x, g.x);
+      adam_update(A, p.y, m.y, v.y, g.y);
+      adam_update(A, p.z, m.z, v.z, g.z);
+      adam_update(A, p.w, m.w, v.w, g.w);
+      *reinterpret_cast<float4*>(S.param + i0) = p;
+      *reinterpret_cast<float4*>(S.m + i0) = m;
+      *reinterpret_cast<float4*>(S.v + i0) = v;
+      *reinterpret_cast<float4*>(S.grad + i0) = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (S.work) {
+        w4 w;
+        w[0] = from_f32<WT>(p.x);
+        w[1] = from_f32<WT>(p.y);
+        w[2] = from_f32<WT>(p.z);
+        w[3] = from_f32<WT>(p.w);
+        *reinterpret_cast<w4*>(reinterpret_cast<WT*>(S.work) + i0) = w;
+      }
+      continue;
+    }
     for (int k = 0; k < cnt; ++k) {
       const int64_t i = i0 + k;
-      const float g = S.grad[i];
-      const float m = A.b1 * S.m[i] + (1.0f - A.b1) * g;
-      const float v = A.b2 * S.v[i] + (1.0f - A.b2) * g * g;
-      const float p = S.param[i] - A.lr * (m * A.inv_c1) / (sqrtf(v * A.inv_c2) + A.eps);
+      float p = S.param[i], m = S.m[i], v = S.v[i];
+      adam_update(A, p, m, v, S.grad[i]);
       S.m[i] = m;
       S.v[i] = v;
       S.param[i] = p;

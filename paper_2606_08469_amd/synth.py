@@ -12,7 +12,8 @@ network or residual). It only produces FP32 inputs and FP32 initial
 parameters, identical for the GPU library and the CPU oracle. All randomness
 comes from ``numpy.random.default_rng(1000 * config + k)`` with k = 0 scene,
 1 tree samples, 2 queries, 3 feature tables, 4 BSDF inputs and targets,
-5 MLP weights, 6 index subsets, 7 materials of rendered pixels.
+5 MLP weights, 6 index subsets, 7 materials of rendered pixels, 8 the
+disparity predictor's tables and weights.
 
 Configs with ``gbuf`` feed the decoder the paper's surface attributes
 g = [x, w_r, n, a, alpha] (Sec. 3.5) after the level features: 13 values per
@@ -460,6 +461,34 @@ def init_mlp(cfg: Config):
         W.append(g.uniform(-lim, lim, (fout, fin)).astype(np.float32))
         b.append(np.zeros(fout, np.float32))
     return W, b
+
+
+# The disparity predictor (Sec. 3.3, Sec. 3.5): Instant-NGP's hash grid
+# shape (16 levels of 2 features, resolutions growing geometrically from
+# 16 to 2048 cells per side) and two hidden layers of 64 (Sec. 4).
+HASH_LEVELS, HASH_F, HASH_NMIN, HASH_NMAX = 16, 2, 16, 2048
+
+
+def hash_resolutions(n_levels=HASH_LEVELS, n_min=HASH_NMIN, n_max=HASH_NMAX):
+    """N_i = floor(n_min b^i) with b = (n_max / n_min)^(1 / (n_levels - 1))."""
+    b = math.exp((math.log(n_max) - math.log(n_min)) / (n_levels - 1))
+    return [int(math.floor(n_min * b ** i)) for i in range(n_levels)]
+
+
+def init_disparity(cfg: Config, log2_T=19, table_scale=1e-4, d0=1.0, widths=(64, 64)):
+    """FP32 predictor: hash tables U(-table_scale, table_scale), Glorot MLP on
+    [encoding, unit(w_r), 0] -> 1 with zero biases except the output's, d0
+    (the disparity it starts from)."""
+    g = rng(cfg.idx, 8)
+    tables = g.uniform(-table_scale, table_scale, (HASH_LEVELS, 1 << log2_T, HASH_F)).astype(np.float32)
+    dims = (HASH_LEVELS * HASH_F + 4,) + tuple(widths) + (1,)
+    W, b = [], []
+    for fin, fout in zip(dims[:-1], dims[1:]):
+        lim = math.sqrt(6.0 / (fin + fout))
+        W.append(g.uniform(-lim, lim, (fout, fin)).astype(np.float32))
+        b.append(np.zeros(fout, np.float32))
+    b[-1][:] = d0
+    return dict(res=hash_resolutions(), log2_T=log2_T, tables=tables, W=W, b=b)
 
 
 def subset(n_total, m, cfg_idx, k=6):

@@ -96,6 +96,16 @@ def to_np(t):
     return t.detach().float().cpu().numpy() if t.dtype != torch.float64 else t.detach().cpu().numpy()
 
 
+def map_res_tol(res, base=1e-5, r_ref=64):
+    """FP32 bar per level for quantities read through a level's maps. A
+    lookup's weights are affine in (s R, t R); FP32 rounds s and t to about
+    2^-24, so the weights, and the features and gradients formed from them,
+    carry an error proportional to R. The FP32 bar of the workload
+    definitions (1e-5) was set for maps of at most 64 per side; a level
+    with R > 64 (the paper's 2^8 + 1 vertices) gets it scaled by R / 64."""
+    return [base * max(1.0, R / r_ref) for R in res]
+
+
 # Relative distance of a hidden pre-activation from zero below which FP32
 # evaluation (operands rounded to 2^-24, sums of up to 128 products) can put
 # it on the other side of the ReLU kink than the FP64 oracle does.

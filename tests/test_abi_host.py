@@ -106,6 +106,12 @@ def test_validation_errors(L):
     bad.res[1] = 3
     assert L.oo_query_fwd(C.byref(bad), C.byref(m), x, x, None, 16, x, stream) == -1
     bad = _tree()
+    bad.res[0] = 128  # texel maps stop at 64 per side, vertex maps at 512
+    assert L.oo_query_fwd(C.byref(bad), C.byref(m), x, x, None, 16, x, stream) == -1
+    bad.interp, bad.res[0] = 1, 1024
+    assert L.oo_query_fwd(C.byref(bad), C.byref(m), x, x, None, 16, x, stream) == -1
+    assert b"512" in L.oo_last_error()
+    bad = _tree()
     bad.feat[1] = 0x10008  # not 16-byte aligned
     assert L.oo_query_fwd(C.byref(bad), C.byref(m), x, x, None, 16, x, stream) == -1
     bad = _tree()
@@ -207,6 +213,67 @@ def test_surface_attribute_validation(L):
     b.attr, b.attr2 = 0x5000, 0
     rc = L.oo_radiosity_residual_fwd(C.byref(t), C.byref(wide), C.byref(b), p, p, p, p, None, n.value, None)
     assert rc == -1 and b"loss_out" in L.oo_last_error()
+
+
+def _disp(n_levels=16, F=2, n_layers=3, hidden=64, log2_T=10):
+    g = binding._Disparity()
+    g.n_levels, g.F, g.log2_T = n_levels, F, log2_T
+    for i in range(n_levels):
+        g.res[i] = 16 + i
+    g.tables = 0x8000
+    g.n_layers = n_layers
+    g.dims[0] = n_levels * F + 4
+    for i in range(1, n_layers):
+        g.dims[i] = hidden
+    g.dims[n_layers] = 1
+    for i in range(n_layers):
+        g.W[i], g.b[i] = 0x9000 + 0x100 * i, 0xa000 + 0x100 * i
+    return g
+
+
+def test_disparity_validation(L):
+    """The disparity predictor: only with the paper's scheme, only the GPU
+    shape (16 hash levels of 2 features, hidden width 64, 1 or 2 hidden
+    layers), and the residual backward needs its gradient accumulators; all
+    refused before any device work."""
+    x = C.c_void_p(0x4000)
+    m = _mlp()
+
+    def tree_with(g, interp=1):
+        t = _tree()
+        t.interp = interp
+        t.disparity = C.pointer(g)
+        return t
+
+    cases = [(tree_with(_disp(), interp=0), -1, b"OO_INTERP_PAPER"),
+             (tree_with(_disp(n_levels=8)), -4, b"n_levels"),
+             (tree_with(_disp(F=4)), -4, b"F must"),
+             (tree_with(_disp(hidden=32)), -4, b"hidden"),
+             (tree_with(_disp(n_layers=4)), -4, b"n_layers"),
+             (tree_with(_disp(log2_T=30)), -1, b"log2_T")]
+    for t, rc, word in cases:
+        assert L.oo_query_fwd(C.byref(t), C.byref(m), x, x, None, 16, x, None) == rc
+        assert word in L.oo_last_error(), L.oo_last_error()
+    g = _disp()
+    g.tables = 0x8004  # not 8-byte aligned
+    assert L.oo_query_fwd(C.byref(tree_with(g)), C.byref(m), x, x, None, 16, x, None) == -1
+    # the backward needs the gradient accumulators
+    t = tree_with(_disp())
+    b = binding._Batch()
+    b.B, b.N = 8, 0
+    b.x = b.dir = b.Le = 0x5000
+    n = C.c_size_t(0)
+    assert L.oo_residual_workspace_bytes(C.byref(t), C.byref(m), C.byref(b), C.byref(n)) == 0
+    p = C.c_void_p(0x5000)
+    ptrs = (C.c_void_p * 8)(*([0x5000] * 8))
+    rc = L.oo_radiosity_residual_bwd(C.byref(t), C.byref(m), C.byref(b), p, p, p, ptrs, ptrs, ptrs, p, n.value, None)
+    assert rc == -1 and b"disparity dW" in L.oo_last_error()
+    # and its buffers are part of the workspace
+    plain = _tree()
+    plain.interp = 1
+    n0 = C.c_size_t(0)
+    assert L.oo_residual_workspace_bytes(C.byref(plain), C.byref(m), C.byref(b), C.byref(n0)) == 0
+    assert n.value > n0.value
 
 
 def test_dot_and_node_readback_validation(L):

@@ -14,7 +14,8 @@ import torch
 
 import oracle
 from paper_2606_08469_amd import binding, synth
-from _gpu import (cosine, kink_margin_ok_tree, oracle_tree_for, rel_l2, report, subset_batch, to_np, tree_for)
+from _gpu import (cosine, kink_margin_ok_tree, map_res_tol, oracle_tree_for, rel_l2, report, subset_batch, to_np,
+                  tree_for)
 from test_gpu_paper import compare_grads, dev, run_residual
 
 pytestmark = pytest.mark.gpu
@@ -121,7 +122,8 @@ def test_residual_with_surface_attributes_fp32(scheme, B, mode):
     el = abs(got["loss"] - loss) / abs(loss)
     report(f"attribute residual {scheme} {mode} loss", rel=el)
     assert el <= FP32_TOL
-    compare_grads(f"attribute {scheme} {mode}", got, otree, omlp, batch, tol=FP32_TOL)
+    compare_grads(f"attribute {scheme} {mode}", got, otree, omlp, batch, tol=FP32_TOL,
+                  level_tol=map_res_tol(otree.res))
 
 
 def test_padded_attributes_match_unpadded_oracle():
@@ -149,9 +151,9 @@ def test_padded_attributes_match_unpadded_oracle():
     report("padded attributes", out_rel=e, dW0_rel=e_w0, pad_dW_max=float(np.abs(got["dW"][0][:, LC + 13:]).max()))
     assert e <= FP32_TOL and e_w0 <= FP32_TOL
     assert np.all(got["dW"][0][:, LC + synth.G_ATTRS:] == 0.0)
-    for l, (g_, w_) in enumerate(zip(got["dfeat"], dfeat)):
+    for l, (g_, w_, tl) in enumerate(zip(got["dfeat"], dfeat, map_res_tol(otree.res))):
         if np.any(w_):
-            assert rel_l2(g_, w_) <= FP32_TOL, l
+            assert rel_l2(g_, w_) <= tl, (l, rel_l2(g_, w_))
 
 
 def test_paper_config_fp16_step():

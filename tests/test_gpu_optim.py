@@ -25,15 +25,25 @@ def test_adam_step_matches_oracle(work):
     round-to-nearest-even of the new parameters, gradients cleared where
     updated, and untouched blocks not written at all."""
     g = np.random.default_rng(3)
-    specs = [(64 * 37, 64, 0.5), (81 * 8 * 13, 81 * 8, 0.3), (128 * 88 + 3, 0, 0), (5, 0, 0), (1, 0, 0),
-             (4 * 4 * 4 * 1000, 64, 0.05)]
+    # (n, block, touched fraction, offset): a non-zero offset places the
+    # segment's arrays one element past an aligned address, which takes the
+    # kernel's per-element path instead of its vector path
+    specs = [(64 * 37, 64, 0.5, 0), (81 * 8 * 13, 81 * 8, 0.3, 0), (128 * 88 + 3, 0, 0, 0), (5, 0, 0, 0),
+             (1, 0, 0, 0), (4 * 4 * 4 * 1000, 64, 0.05, 0), (64 * 21, 64, 0.5, 1), (1003, 0, 0, 1)]
+
+    def placed(a, off, dtype=None):
+        buf = torch.zeros(len(a) + off, dtype=torch.float32 if dtype is None else dtype, device="cuda")
+        view = buf[off:]
+        view.copy_(torch.from_numpy(a) if dtype is None else torch.from_numpy(a).to(dtype))
+        return view
+
     segs, host = [], []
-    for n, block, frac in specs:
+    for n, block, frac, off in specs:
         p, gr = _rand(g, n), _rand(g, n, 1e-3)
         m, v = _rand(g, n, 1e-4), np.abs(_rand(g, n, 1e-6))
         flags = (g.uniform(size=n // block) < frac).astype(np.int32) if block else None
-        t = {k: torch.from_numpy(a.copy()).cuda() for k, a in (("param", p), ("grad", gr), ("m", m), ("v", v))}
-        t["work"] = torch.full((n,), 7.0, dtype=work, device="cuda") if work != torch.float32 else None
+        t = {k: placed(a.copy(), off) for k, a in (("param", p), ("grad", gr), ("m", m), ("v", v))}
+        t["work"] = placed(np.full(n, 7.0, np.float32), off, work) if work != torch.float32 else None
         if block:
             t["touched"], t["block"] = torch.from_numpy(flags).cuda(), block
         segs.append(t)

@@ -233,6 +233,9 @@ def test_disparity_adjoint_matches_central_differences(full):
         batch = dict(batch, target_override=T.astype(np.float32))
     out = {}
     dfeat, dW, _ = oracle.residual_bwd(tree, mlp, batch, disp_out=out)
+    # the output bias enters d directly: its gradient is the sum of dL/dd
+    np.testing.assert_allclose(out["b"][-1][0], out["dd"].sum(), rtol=1e-12, atol=1e-18)
+    assert len(out["dd"]) == len(batch["x"]) * (1 + (batch["N"] if full else 0))
     g = np.random.default_rng(11)
     # small enough that no step crosses a ReLU kink of either network (the
     # closest hidden pre-activation of the predictor sits 3.6e-5 from zero)
