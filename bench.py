@@ -41,6 +41,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 step and render forwards")
+    ap.add_argument("--no-paper", action="store_true",
+                    help="skip the legs of the paper's interpolation and configuration (shorter profiled runs)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -215,6 +217,7 @@ def main():
         del fp32
         torch.cuda.empty_cache()
         extra["render"] = render_bench(torch, binding, synth, args)
+    if not args.no_extra and not args.no_paper:
         # the paper's interpolation (8-cell trilinear blend over barycentric
         # vertex maps) on the same tree, batch and decoder
         del mixed

@@ -174,6 +174,7 @@ int check_mlp(const oo_mlp* m, int LC, MlpArgs& A) {
   A.K0 = K0;
   A.E = K0 - LC;
   A.H = H;
+  A.n_out = 3;
   for (int i = 0; i < OO_MAX_LAYERS; ++i) {
     A.W[i] = i < m->n_layers ? m->W[i] : nullptr;
     A.b[i] = i < m->n_layers ? m->b[i] : nullptr;
@@ -272,7 +273,8 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Workspace {
   size_t Lq, lossp, seeds, nidx, uv, pos, dh, wt[OO_MAX_LAYERS], dwp, order, rank, scount, stotal, sstart, gpad, total;
-  size_t wdir, dd, gdwp;  // the disparity predictor's: lookup directions, dLoss/d disparity, parameter partials
+  size_t wdir, dd, gdwp, dsp;  // the disparity predictor's: lookup directions, dLoss/d disparity,
+                               // parameter partials, disparity of every query
   int ggrid;
   int K;  // node indices stored per level and backward query: 1, or 8 corners in the paper's scheme
   int64_t pad_off[OO_MAX_LEVELS];  // float offset of each level's pair buffer in gpad, or -1
@@ -342,6 +344,8 @@ Workspace workspace_layout(const MlpArgs& M, oo_dtype md, const oo_residual_batc
   o = align256(o + (shift ? (size_t)Qb * sizeof(float4) : 0));
   w.dd = o;
   o = align256(o + (shift ? (size_t)Qb * sizeof(float) : 0));
+  w.dsp = o;  // [Qf], sorted order
+  o = align256(o + (shift ? (size_t)Qf * sizeof(float) : 0));
   w.gdwp = o;
   if (shift) {
     const oo_disparity* p = tree->disparity;
@@ -647,8 +651,14 @@ int oo_radiosity_residual_fwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   sorted.n = Q;
   {
     ProfScope ps(OO_PROF_QUERY, stream);
-    const QueryOut O{nidx, reinterpret_cast<float2*>(ws + w.uv), reinterpret_cast<float4*>(ws + w.pos),
-                     G.n_levels ? reinterpret_cast<float4*>(ws + w.wdir) : nullptr, w.Qb};
+    QueryOut O{nidx, reinterpret_cast<float2*>(ws + w.uv), reinterpret_cast<float4*>(ws + w.pos),
+               G.n_levels ? reinterpret_cast<float4*>(ws + w.wdir) : nullptr, w.Qb};
+    if (G.n_levels) {  // every query's disparity first, on the matrix cores
+      float* dsp = reinterpret_cast<float*>(ws + w.dsp);
+      e = launch_disparity_fwd(G, sorted, Q, dsp, stream);
+      if (e != hipSuccess) return hip_status(e, "disparity launch");
+      O.disp = dsp;
+    }
     e = launch_query(T, tree->feat_dtype, M, mlp->dtype, sorted, Q, Lq, O, G, stream);
   }
   if (e != hipSuccess) return hip_status(e, "residual query launch");

@@ -581,52 +581,16 @@ __global__ __launch_bounds__(256) void dw_reduce_kernel(const float* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// BSDF weight (same formula as the forward residual assembly).
+// BSDF weight of sample (b, k), as the forward residual assembly forms it.
 // ---------------------------------------------------------------------------
-__device__ inline void unit3(const float* p, float v[3]) {
-  v[0] = p[0];
-  v[1] = p[1];
-  v[2] = p[2];
-  const float l = sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-  if (l > 0.0f) {
-    v[0] /= l;
-    v[1] /= l;
-    v[2] /= l;
-  }
-}
-
 __device__ inline void bsdf_weight_b(const ResidualArgs& A, int64_t b, int k, float w[3]) {
   const int64_t bk = b * A.N + k;
   float n[3], wo[3], wi[3];
-  unit3(A.n + 3 * b, n);
-  unit3(A.wo + 3 * b, wo);
-  unit3(A.wi + 3 * bk, wi);
-  const float alpha = A.rough[b];
-  const float pdf = A.pdf ? A.pdf[bk] : 1.0f;
-  const float ci = n[0] * wi[0] + n[1] * wi[1] + n[2] * wi[2];
-  const float co = n[0] * wo[0] + n[1] * wo[1] + n[2] * wo[2];
-  if (!(ci > 0.0f) || !(co > 0.0f)) {
-    w[0] = w[1] = w[2] = 0.0f;
-    return;
-  }
-  float h[3] = {wi[0] + wo[0], wi[1] + wo[1], wi[2] + wo[2]};
-  const float hl = sqrtf(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
-  h[0] /= hl;
-  h[1] /= hl;
-  h[2] /= hl;
-  const float nh = n[0] * h[0] + n[1] * h[1] + n[2] * h[2];
-  const float cx = n[1] * h[2] - n[2] * h[1], cy = n[2] * h[0] - n[0] * h[2], cz = n[0] * h[1] - n[1] * h[0];
-  const float a2 = alpha * alpha;
-  const float den = a2 * nh * nh + (cx * cx + cy * cy + cz * cz);
-  const float Dm = a2 / (3.14159265358979f * den * den);
-  const float g1i = 2.0f * ci / (ci + sqrtf(a2 + (1.0f - a2) * ci * ci));
-  const float g1o = 2.0f * co / (co + sqrtf(a2 + (1.0f - a2) * co * co));
-  const float vh = 1.0f - (wi[0] * h[0] + wi[1] * h[1] + wi[2] * h[2]);
-  const float vh2 = vh * vh;
-  const float F = A.F0 + (1.0f - A.F0) * (vh2 * vh2 * vh);
-  const float spec = Dm * g1i * g1o * F / (4.0f * ci * co);
-  const float sc = ci / pdf;
-  for (int c = 0; c < 3; ++c) w[c] = (A.albedo[3 * b + c] * (1.0f / 3.14159265358979f) + spec) * sc;
+  load_unit(A.n + 3 * b, n);
+  load_unit(A.wo + 3 * b, wo);
+  load_unit(A.wi + 3 * bk, wi);
+  const float alb[3] = {A.albedo[3 * b], A.albedo[3 * b + 1], A.albedo[3 * b + 2]};
+  bsdf_weight(n, wo, wi, alb, A.rough[b], A.F0, A.pdf ? A.pdf[bk] : 1.0f, w);
 }
 
 // ---------------------------------------------------------------------------

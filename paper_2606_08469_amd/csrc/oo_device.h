@@ -49,6 +49,7 @@ struct MlpArgs {
   int32_t K0;        // input width: levels * C features, then E surface attributes
   int32_t E;
   int32_t H;
+  int32_t n_out;     // output width: 3 (RGB) for the decoder
   const void* W[kMaxLayers];  // [out][in] row-major, MT
   const float* b[kMaxLayers];
 };
@@ -304,11 +305,10 @@ __device__ inline void descend(const TreeArgs& T, bool valid, const float x[3], 
 // unfolded coordinates, (s, t) = (u + 1) / 2. sign(0) = +1.
 __device__ inline void octa(const float d[3], float& s, float& t) {
   const float S = fabsf(d[0]) + fabsf(d[1]) + fabsf(d[2]);
-  float ux = 0.0f, uy = 0.0f;
-  if (S > 0.0f) {
-    ux = d[0] / S;
-    uy = d[1] / S;
-  }
+  // one division for both coordinates (the rounded reciprocal can put a
+  // coordinate a unit past +-1; the clamp keeps the fold's 1 - |u| >= 0)
+  const float iS = S > 0.0f ? 1.0f / S : 0.0f;
+  float ux = fminf(fmaxf(d[0] * iS, -1.0f), 1.0f), uy = fminf(fmaxf(d[1] * iS, -1.0f), 1.0f);
   if (d[2] < 0.0f) {
     const float fx = (1.0f - fabsf(uy)) * (ux < 0.0f ? -1.0f : 1.0f);
     const float fy = (1.0f - fabsf(ux)) * (uy < 0.0f ? -1.0f : 1.0f);
@@ -1048,6 +1048,52 @@ __device__ inline TileRange xcd_tiles(int64_t n_tiles, int workers_per_wg, int w
   r.end = hi;
   r.stride = (int64_t)per * workers_per_wg;
   return r;
+}
+
+// ---------------------------------------------------------------------------
+// BSDF sample weight of the residual's Monte-Carlo target (forward and the
+// backward's full-mode seeds use the same one)
+// ---------------------------------------------------------------------------
+// GGX + Lambert sample weight f |n.wi| / pdf for unit n, wo, wi. The GGX
+// denominator (n.h)^2 (a^2 - 1) + 1 is evaluated as a^2 (n.h)^2 + |n x h|^2,
+// which avoids the cancellation near the specular peak. Smith's separable
+// G_1(c) = 2c / (c + sqrt(a^2 + (1 - a^2) c^2)) cancels against the
+// 4 cos_i cos_o of the microfacet term, leaving D F / ((ci + si)(co + so)).
+__device__ __forceinline__ void bsdf_weight(const float n[3], const float wo[3], const float wi[3], const float alb[3],
+                                   float alpha, float F0, float pdf, float w[3]) {
+  const float ci = n[0] * wi[0] + n[1] * wi[1] + n[2] * wi[2];
+  const float co = n[0] * wo[0] + n[1] * wo[1] + n[2] * wo[2];
+  if (!(ci > 0.0f) || !(co > 0.0f)) {
+    w[0] = w[1] = w[2] = 0.0f;
+    return;
+  }
+  float h[3] = {wi[0] + wo[0], wi[1] + wo[1], wi[2] + wo[2]};
+  const float ihl = 1.0f / sqrtf(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) h[a] *= ihl;
+  const float nh = n[0] * h[0] + n[1] * h[1] + n[2] * h[2];
+  const float cx = n[1] * h[2] - n[2] * h[1], cy = n[2] * h[0] - n[0] * h[2], cz = n[0] * h[1] - n[1] * h[0];
+  const float a2 = alpha * alpha;
+  const float den = a2 * nh * nh + (cx * cx + cy * cy + cz * cz);
+  const float vh = 1.0f - (wi[0] * h[0] + wi[1] * h[1] + wi[2] * h[2]);
+  const float vh2 = vh * vh;
+  const float F = F0 + (1.0f - F0) * (vh2 * vh2 * vh);
+  const float gi = ci + sqrtf(a2 + (1.0f - a2) * ci * ci), go = co + sqrtf(a2 + (1.0f - a2) * co * co);
+  const float spec = a2 * F / (3.14159265358979f * den * den * gi * go);
+  const float sc = ci / pdf;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) w[c] = (alb[c] * (1.0f / 3.14159265358979f) + spec) * sc;
+}
+
+__device__ __forceinline__ void load_unit(const float* p, float v[3]) {
+  v[0] = p[0];
+  v[1] = p[1];
+  v[2] = p[2];
+  const float l2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  const float il = l2 > 0.0f ? 1.0f / sqrtf(l2) : 1.0f;
+  v[0] *= il;
+  v[1] *= il;
+  v[2] *= il;
 }
 
 }  // namespace oo

@@ -106,7 +106,7 @@ struct WFrag {
       return *reinterpret_cast<const typename FragT<MT>::type*>(lds + ((base + m * KB + kb) * kWave + lane) * 8);
     } else {
       const int n_in = layer == 0 ? M.K0 : M.H;
-      const int n_out = layer == M.n_layers - 1 ? 3 : M.H;
+      const int n_out = layer == M.n_layers - 1 ? M.n_out : M.H;
       return wfrag_global<MT>(launder_ptr(reinterpret_cast<const MT*>(M.W[layer])), n_out, n_in, n_in, m, kb, lane);
     }
   }
@@ -173,7 +173,7 @@ __device__ inline void mlp_forward_tiles(const MlpArgs& M, const WSrc& W, const 
   }
   // output layer H -> 3
   const int lo = M.n_layers - 1;
-  const f32x4 bt = bias_tile(M.b[lo], 3, 0, lane);
+  const f32x4 bt = bias_tile(M.b[lo], M.n_out, 0, lane);
 #pragma unroll
   for (int t = 0; t < NT; ++t) out[t] = bt;
 #pragma unroll
@@ -239,8 +239,10 @@ __device__ inline void store_rgb(const f32x4 out[NT], int t0, int64_t q_base, in
 // In the paper's scheme the stored indices are the eight corner cells'
 // nodes per level ([L][8][n_idx]) and the query's position is kept too
 // (pos_out, [n_idx]); the backward recomputes the trilinear weights from it.
-// MODE as for encode_kernel; with the shift the query's predicted
-// disparity goes to pos_out's w and its unit lookup direction to wdir_out.
+// MODE as for encode_kernel, and 3: the shift with each query's disparity
+// read from O.disp (predicted beforehand by disparity_fwd_kernel); with the
+// shift the query's disparity goes to pos_out's w and its unit lookup
+// direction to wdir_out.
 template <class TT, class MT, int C, int H, bool WLDS, int MODE>
 __global__ __launch_bounds__(512) void query_kernel(const TreeArgs T, const MlpArgs M, const QuerySrc src,
                                                     int64_t Q, float* __restrict__ rgb, const QueryOut O,
@@ -276,13 +278,16 @@ __global__ __launch_bounds__(512) void query_kernel(const TreeArgs T, const MlpA
     if (keep) uv_out[q] = make_float2(s, t);
     if constexpr (MODE > 0) {
       float u[3] = {0.f, 0.f, 0.f}, disp = 0.0f;
-      if constexpr (MODE == 2) {
+      if constexpr (MODE >= 2) {
         unit_dir3(d, u);
-        disp = predict_disparity(G, x, u);
+        if constexpr (MODE == 2)
+          disp = predict_disparity(G, x, u);
+        else
+          disp = valid ? O.disp[q] : 0.0f;
         if (keep) O.wdir[q] = make_float4(u[0], u[1], u[2], 0.0f);
       }
       if (keep) pos_out[q] = make_float4(x[0], x[1], x[2], disp);
-      encode_paper<TT, C, MODE == 2>(T, valid, x, s, t, [&](int l, const float (&h)[C], const int (&node)[8]) {
+      encode_paper<TT, C, MODE >= 2>(T, valid, x, s, t, [&](int l, const float (&h)[C], const int (&node)[8]) {
 #pragma unroll
         for (int c = 0; c < C; c += 4) htile_put4<MT>(htile, KB0, lane, l * C + c, &h[c]);
         if (keep)
@@ -357,51 +362,54 @@ __global__ __launch_bounds__(512) void mlp_kernel(const MlpArgs M, const MT* __r
 }
 
 // ---------------------------------------------------------------------------
+// Disparity predictor on the matrix cores: each wave encodes 64 queries'
+// positions (hash grid) and lookup directions into its FP32 activation tile
+// and runs the predictor's MLP on it like the decoder's (16x16x4 FP32
+// MFMA), writing d per query.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void disparity_fwd_kernel(const DispArgs G, const MlpArgs P, const QuerySrc src,
+                                                            int64_t Q, float* __restrict__ d_out) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  constexpr int NT = 2;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63, waves = blockDim.x >> 6;
+  const int KB0 = (P.K0 + 31) / 32;
+  float* htile = reinterpret_cast<float*>(smem) + wave * (4 * KB0 * kWave * 8);
+  {  // zero the K padding of this lane's row once
+    const float z[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int k = P.K0; k < 32 * KB0; k += 4) htile_put4<float>(htile, KB0, lane, k, z);
+  }
+  const WFrag<float, false> W{nullptr, KB0};
+  const int64_t n_tiles = (Q + 63) / 64;
+  const TileRange tr = xcd_tiles(n_tiles, waves, wave);
+  for (int64_t tile = tr.first; tile < tr.end; tile += tr.stride) {
+    const int64_t q = tile * 64 + lane;
+    float x[3] = {0.f, 0.f, 0.f}, d[3] = {0.f, 0.f, 1.f}, u[3];
+    if (q < Q) load_query(src, q, x, d);
+    unit_dir3(d, u);
+    float a[kDispK];
+    disparity_input(G, x, u, a);
+#pragma unroll
+    for (int k = 0; k < kDispK; k += 4) htile_put4<float>(htile, KB0, lane, k, &a[k]);
+    wave_lds_sync();
+#pragma unroll
+    for (int t0 = 0; t0 < 4; t0 += NT) {
+      f32x4 out[NT];
+      mlp_forward_tiles<float, kDispH, NT>(P, W, htile, KB0, t0, lane, out);
+      if (lane < 16) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const int64_t qq = tile * 64 + 16 * (t0 + t) + lane;
+          if (qq < Q) d_out[qq] = out[t][0];
+        }
+      }
+    }
+    wave_lds_sync();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Residual assembly (rendering-equation RHS) and loss partials.
 // ---------------------------------------------------------------------------
-
-// GGX + Lambert sample weight f |n.wi| / pdf for unit n, wo, wi. The GGX
-// denominator (n.h)^2 (a^2 - 1) + 1 is evaluated as a^2 (n.h)^2 + |n x h|^2,
-// which avoids the cancellation near the specular peak.
-__device__ inline void bsdf_weight(const float n[3], const float wo[3], const float wi[3], const float alb[3],
-                                   float alpha, float F0, float pdf, float w[3]) {
-  const float ci = n[0] * wi[0] + n[1] * wi[1] + n[2] * wi[2];
-  const float co = n[0] * wo[0] + n[1] * wo[1] + n[2] * wo[2];
-  if (!(ci > 0.0f) || !(co > 0.0f)) {
-    w[0] = w[1] = w[2] = 0.0f;
-    return;
-  }
-  float h[3] = {wi[0] + wo[0], wi[1] + wo[1], wi[2] + wo[2]};
-  const float hl = sqrtf(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) h[a] /= hl;
-  const float nh = n[0] * h[0] + n[1] * h[1] + n[2] * h[2];
-  const float cx = n[1] * h[2] - n[2] * h[1], cy = n[2] * h[0] - n[0] * h[2], cz = n[0] * h[1] - n[1] * h[0];
-  const float a2 = alpha * alpha;
-  const float den = a2 * nh * nh + (cx * cx + cy * cy + cz * cz);
-  const float Dm = a2 / (3.14159265358979f * den * den);
-  const float g1i = 2.0f * ci / (ci + sqrtf(a2 + (1.0f - a2) * ci * ci));
-  const float g1o = 2.0f * co / (co + sqrtf(a2 + (1.0f - a2) * co * co));
-  const float vh = 1.0f - (wi[0] * h[0] + wi[1] * h[1] + wi[2] * h[2]);
-  const float vh2 = vh * vh;
-  const float F = F0 + (1.0f - F0) * (vh2 * vh2 * vh);
-  const float spec = Dm * g1i * g1o * F / (4.0f * ci * co);
-  const float sc = ci / pdf;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) w[c] = (alb[c] * (1.0f / 3.14159265358979f) + spec) * sc;
-}
-
-__device__ inline void load_unit(const float* p, float v[3]) {
-  v[0] = p[0];
-  v[1] = p[1];
-  v[2] = p[2];
-  const float l = sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-  if (l > 0.0f) {
-    v[0] /= l;
-    v[1] /= l;
-    v[2] /= l;
-  }
-}
 
 // One group of G lanes per LHS point (G = N rounded up to a power of two,
 // at most 64): lane k of the group weighs secondary sample k (and k + G, ...)
@@ -412,7 +420,7 @@ __device__ inline void load_unit(const float* p, float v[3]) {
 __global__ __launch_bounds__(256) void combine_kernel(const ResidualArgs A, int G, const float* __restrict__ Lq,
                                                       const int32_t* __restrict__ rank, float* __restrict__ lhs_out, float* __restrict__ rhs_out,
                                                       float* __restrict__ resid_out, double* __restrict__ partials) {
-  __shared__ double red[256];
+  __shared__ double red[4];
   const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
   const int64_t b = gid / G;
   const int k0 = (int)(gid % G);
@@ -464,13 +472,11 @@ __global__ __launch_bounds__(256) void combine_kernel(const ResidualArgs A, int 
       acc += rr * rr;
     }
   }
-  red[threadIdx.x] = acc;
+  // fixed order: within each wave by shuffles, then the four waves in turn
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // Fixed-order sum of the block partials: loss = sum / (3B).
@@ -652,12 +658,12 @@ static hipError_t launch_query_p(const TreeArgs& T, const MlpArgs& M, const Quer
   int waves, grid;
   size_t lds;
   tile_launch_shape<MT>(M, Q, wlds, waves, lds, grid);
-  if (wlds && MODE == 2) {  // the predictor's registers: keep one variant
+  if (wlds && MODE >= 2) {  // the shifted variants: keep one of each
     wlds = false;
     tile_launch_shape_plain<MT>(M, Q, waves, lds, grid);
   }
   if (wlds) {
-    auto k = query_kernel<TT, MT, C, H, true, MODE == 2 ? 1 : MODE>;
+    auto k = query_kernel<TT, MT, C, H, true, MODE >= 2 ? 1 : MODE>;
     hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, st, T, M, src, Q, rgb, O, G);
   } else {
@@ -672,8 +678,9 @@ template <class TT, class MT, int C, int H>
 static hipError_t launch_query_t(const TreeArgs& T, const MlpArgs& M, const QuerySrc& src, int64_t Q, float* rgb,
                                  const QueryOut& O, const DispArgs& G, hipStream_t st) {
   if (T.interp != OO_INTERP_PAPER) return launch_query_p<TT, MT, C, H, 0>(T, M, src, Q, rgb, O, G, st);
-  return G.n_levels == 0 ? launch_query_p<TT, MT, C, H, 1>(T, M, src, Q, rgb, O, G, st)
-                         : launch_query_p<TT, MT, C, H, 2>(T, M, src, Q, rgb, O, G, st);
+  if (G.n_levels == 0) return launch_query_p<TT, MT, C, H, 1>(T, M, src, Q, rgb, O, G, st);
+  return O.disp ? launch_query_p<TT, MT, C, H, 3>(T, M, src, Q, rgb, O, G, st)
+                : launch_query_p<TT, MT, C, H, 2>(T, M, src, Q, rgb, O, G, st);
 }
 
 template <class TT, class MT, int C>
@@ -761,6 +768,31 @@ hipError_t launch_cast(const float* src, void* dst, oo_dtype dt, int64_t n, hipS
     hipLaunchKernelGGL(cast_kernel<f16>, dim3((unsigned)blocks), dim3(256), 0, st, src, (f16*)dst, n);
   else
     hipLaunchKernelGGL(cast_kernel<bf16>, dim3((unsigned)blocks), dim3(256), 0, st, src, (bf16*)dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_disparity_fwd(const DispArgs& G, const QuerySrc& src, int64_t Q, float* d_out, hipStream_t st) {
+  if (Q == 0) return hipSuccess;
+  MlpArgs P{};
+  P.n_layers = G.n_layers;
+  P.K0 = kDispK;
+  P.E = 0;
+  P.H = kDispH;
+  P.n_out = 1;
+  for (int i = 0; i < kMaxLayers; ++i) {
+    P.W[i] = i < G.n_layers ? G.W[i] : nullptr;
+    P.b[i] = i < G.n_layers ? G.b[i] : nullptr;
+  }
+  int waves, grid;
+  size_t lds;
+  tile_launch_shape_plain<float>(P, Q, waves, lds, grid);
+  if (waves > 4) {  // the kernel's workgroups have at most 4 waves
+    waves = 4;
+    lds = (size_t)4 * 4 * ((P.K0 + 31) / 32) * kWave * 8 * sizeof(float);
+    grid = tile_grid(Q, waves, lds);
+  }
+  hipFuncSetAttribute((const void*)disparity_fwd_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(disparity_fwd_kernel, dim3(grid), dim3(64 * waves), lds, st, G, P, src, Q, d_out);
   return hipGetLastError();
 }
 

@@ -64,7 +64,10 @@ struct QueryOut {
   float4* pos;
   float4* wdir;
   int64_t n_idx;
+  const float* disp = nullptr;  // per-query disparity, when already predicted
 };
+// The predictor's d for Q queries (matrix cores), into d_out [Q].
+hipError_t launch_disparity_fwd(const DispArgs& G, const QuerySrc& src, int64_t Q, float* d_out, hipStream_t st);
 hipError_t launch_query(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, const QuerySrc& src,
                         int64_t Q, float* rgb, const QueryOut& O, const DispArgs& G, hipStream_t st);
 
