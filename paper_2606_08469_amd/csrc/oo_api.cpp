@@ -273,9 +273,11 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Workspace {
   size_t Lq, lossp, seeds, nidx, uv, pos, dh, wt[OO_MAX_LAYERS], dwp, order, rank, scount, stotal, sstart, gpad, total;
-  size_t wdir, dd, gdwp, dsp;  // the disparity predictor's: lookup directions, dLoss/d disparity,
-                               // parameter partials, disparity of every query
+  size_t wdir, dd, gdwp, dsp, drows, hrows;  // the disparity predictor's: lookup directions, dLoss/d
+                                             // disparity, parameter partials, disparity of every query,
+                                             // backward rows, decoder input rows
   int ggrid;
+  int64_t dcap;  // queries per pass of the predictor's backward
   int K;  // node indices stored per level and backward query: 1, or 8 corners in the paper's scheme
   int64_t pad_off[OO_MAX_LEVELS];  // float offset of each level's pair buffer in gpad, or -1
   int64_t pad_total;               // floats in gpad
@@ -346,6 +348,8 @@ Workspace workspace_layout(const MlpArgs& M, oo_dtype md, const oo_residual_batc
   o = align256(o + (shift ? (size_t)Qb * sizeof(float) : 0));
   w.dsp = o;  // [Qf], sorted order
   o = align256(o + (shift ? (size_t)Qf * sizeof(float) : 0));
+  w.hrows = o;  // decoder input rows of the shifted encode, [Qf][K0] in the MLP's dtype
+  o = align256(o + (shift ? (size_t)Qf * M.K0 * (md == OO_F32 ? 4 : 2) : 0));
   w.gdwp = o;
   if (shift) {
     const oo_disparity* p = tree->disparity;
@@ -354,6 +358,9 @@ Workspace workspace_layout(const MlpArgs& M, oo_dtype md, const oo_residual_batc
     if (p->n_layers == 3) P += (size_t)p->dims[2] * p->dims[1] + p->dims[2];
     o = align256(o + (size_t)w.ggrid * P * sizeof(float));
   }
+  w.dcap = shift ? disparity_rows_cap(Qb) : 0;
+  w.drows = o;
+  o = align256(o + (size_t)disparity_rows_floats(w.dcap) * sizeof(float));
   const size_t esz = md == OO_F32 ? 4 : 2;
   for (int i = 0; i < M.n_layers; ++i) {
     w.wt[i] = o;
@@ -653,13 +660,20 @@ int oo_radiosity_residual_fwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
     ProfScope ps(OO_PROF_QUERY, stream);
     QueryOut O{nidx, reinterpret_cast<float2*>(ws + w.uv), reinterpret_cast<float4*>(ws + w.pos),
                G.n_levels ? reinterpret_cast<float4*>(ws + w.wdir) : nullptr, w.Qb};
-    if (G.n_levels) {  // every query's disparity first, on the matrix cores
+    if (G.n_levels) {
+      // every query's disparity on the matrix cores, the shifted encode into
+      // decoder input rows, then the decoder over the rows
       float* dsp = reinterpret_cast<float*>(ws + w.dsp);
       e = launch_disparity_fwd(G, sorted, Q, dsp, stream);
       if (e != hipSuccess) return hip_status(e, "disparity launch");
       O.disp = dsp;
+      void* hrows = ws + w.hrows;
+      e = launch_encode_rows(T, tree->feat_dtype, M, sorted, Q, hrows, O, stream);
+      if (e != hipSuccess) return hip_status(e, "shifted encode launch");
+      e = launch_mlp(M, mlp->dtype, hrows, Q, Lq, stream);
+    } else {
+      e = launch_query(T, tree->feat_dtype, M, mlp->dtype, sorted, Q, Lq, O, G, stream);
     }
-    e = launch_query(T, tree->feat_dtype, M, mlp->dtype, sorted, Q, Lq, O, G, stream);
   }
   if (e != hipSuccess) return hip_status(e, "residual query launch");
   ProfScope ps(OO_PROF_COMBINE, stream);
@@ -796,8 +810,8 @@ int oo_radiosity_residual_bwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
   src.idx = order;
   src.n = A.B * (1 + A.N);
   float* gpart = reinterpret_cast<float*>(ws + w.gdwp);
-  if ((e = launch_disparity_bwd(G, src, Qb, reinterpret_cast<const float*>(ws + w.dd), gp->dtables, gpart, w.ggrid,
-                                stream)) != hipSuccess)
+  if ((e = launch_disparity_bwd(G, src, Qb, reinterpret_cast<const float*>(ws + w.dd), gp->dtables,
+                                reinterpret_cast<float*>(ws + w.drows), w.dcap, gpart, w.ggrid, stream)) != hipSuccess)
     return hip_status(e, "disparity backward launch");
   ParamLayout GL;
   ReduceDst GD;

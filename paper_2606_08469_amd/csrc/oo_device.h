@@ -186,18 +186,31 @@ __device__ __forceinline__ void disparity_input(const DispArgs& G, const float x
 // the wave, so the weights come through the scalar cache.
 constexpr int kDispChunk = 16;
 
+// Weights read at wave-uniform addresses through the constant address
+// space: the loads go through the scalar cache (scalar registers) even in
+// kernels that store to global memory, where a plain pointer's loads could
+// be clobbered and become vector loads. The weights are read-only while the
+// predictor's kernels run.
+typedef const __attribute__((address_space(4))) float* cfloat_ptr;
+__device__ __forceinline__ cfloat_ptr uniform_ptr(const float* p) {
+  asm volatile("" : "+s"(p));
+  return (cfloat_ptr)p;
+}
+
 // Units c .. c + kDispChunk - 1 of the first hidden layer, ReLU'd:
 // b_0[o] + sum_k W_0[o][k] a[k] (W: the first layer's weights, rows of
 // kDispK).
 __device__ __forceinline__ void disp_chunk0(const DispArgs& G, const float* W, int c, const float (&a)[kDispK],
                                             float (&h)[kDispChunk]) {
+  const cfloat_ptr Wc = uniform_ptr(W + c * kDispK);
+  const cfloat_ptr bc = uniform_ptr(G.b[0] + c);
 #pragma unroll
   for (int j = 0; j < kDispChunk; ++j) {
-    const int o = c + j;
-    float z = G.b[0][o];
+    float z = bc[j];
 #pragma unroll
-    for (int k = 0; k < kDispK; ++k) z += W[o * kDispK + k] * a[k];
+    for (int k = 0; k < kDispK; ++k) z += Wc[j * kDispK + k] * a[k];
     h[j] = fmaxf(z, 0.0f);
+    if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bound the weights in flight
   }
 }
 
@@ -214,10 +227,11 @@ __device__ __forceinline__ void disp_hidden2(const DispArgs& G, const float* W0,
     float h1[kDispChunk];
     disp_chunk0(G, W0, c, a, h1);
     h1_out(c, h1);
+    const cfloat_ptr W1c = uniform_ptr(W1 + c);
 #pragma unroll
     for (int o = 0; o < kDispH; ++o) {
 #pragma unroll
-      for (int j = 0; j < kDispChunk; ++j) z2[o] += W1[o * kDispH + c + j] * h1[j];
+      for (int j = 0; j < kDispChunk; ++j) z2[o] += W1c[o * kDispH + j] * h1[j];
       // a few units' weights in flight at a time: the scheduler would
       // otherwise hoist all of them into scalar registers and spill
       if ((o & 3) == 3) __builtin_amdgcn_sched_barrier(0);
@@ -303,11 +317,19 @@ __device__ inline void descend(const TreeArgs& T, bool valid, const float x[3], 
 
 // u = (dx, dy) / (|dx| + |dy| + |dz|), lower hemisphere folded from the
 // unfolded coordinates, (s, t) = (u + 1) / 2. sign(0) = +1.
+// 1 / x for x > 0: the hardware reciprocal (about 1 ulp) refined by one
+// Newton-Raphson step r' = r + r (1 - x r), a few instructions in place of
+// the IEEE division sequence.
+__device__ __forceinline__ float rcp_refined(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
 __device__ inline void octa(const float d[3], float& s, float& t) {
   const float S = fabsf(d[0]) + fabsf(d[1]) + fabsf(d[2]);
-  // one division for both coordinates (the rounded reciprocal can put a
-  // coordinate a unit past +-1; the clamp keeps the fold's 1 - |u| >= 0)
-  const float iS = S > 0.0f ? 1.0f / S : 0.0f;
+  // one reciprocal for both coordinates (its rounding can put a coordinate
+  // a unit past +-1; the clamp keeps the fold's 1 - |u| >= 0)
+  const float iS = S > 0.0f ? rcp_refined(S) : 0.0f;
   float ux = fminf(fmaxf(d[0] * iS, -1.0f), 1.0f), uy = fminf(fmaxf(d[1] * iS, -1.0f), 1.0f);
   if (d[2] < 0.0f) {
     const float fx = (1.0f - fabsf(uy)) * (ux < 0.0f ? -1.0f : 1.0f);
@@ -624,7 +646,7 @@ __device__ inline void corner_weights(const float f[3], const int node[8], float
     w[d] = node[d] >= 0 ? wx * wy * wz : 0.0f;
     sum += w[d];
   }
-  const float inv = sum > 0.0f ? 1.0f / sum : 0.0f;
+  const float inv = sum > 0.0f ? rcp_refined(sum) : 0.0f;
 #pragma unroll
   for (int d = 0; d < 8; ++d) w[d] *= inv;
 }
@@ -634,9 +656,10 @@ __device__ inline void corner_weights(const float f[3], const int node[8], float
 // themselves with t mirrored, t = 0 and t = 1 with s mirrored, corners the
 // -z pole) uses the slot of the one with the lower index along the edge.
 __device__ inline int vertex_slot(int i, int j, int R) {
-  if (i == 0 || i == R) j = min(j, R - j);
-  if (j == 0 || j == R) i = min(i, R - i);
-  return j * (R + 1) + i;
+  // i in [0, R]: i is 0 or R exactly when i - 1 wraps past R - 2 unsigned
+  j = (unsigned)(i - 1) >= (unsigned)(R - 1) ? min(j, R - j) : j;
+  i = (unsigned)(j - 1) >= (unsigned)(R - 1) ? min(i, R - i) : i;
+  return (int)__umul24((unsigned)j, (unsigned)(R + 1)) + i;  // R < 2^23
 }
 
 // Barycentric lookup at (s, t) in [0, 1]^2 on a map of R x R grid cells:
@@ -651,35 +674,32 @@ __device__ __forceinline__ void bary_t(float s, float t, int R, int slot[3], flo
   const int i = min(max((int)floorf(pu), 0), R - 1), j = min(max((int)floorf(pv), 0), R - 1);
   const float fu = pu - (float)i, fv = pv - (float)j;
   const bool same = (2 * i >= R) == (2 * j >= R);
-  int i0, j0, i1, j1, i2, j2;
-  float du[3], dv[3];
-  if (same) {
-    if (fu + fv <= 1.0f) {
-      i0 = i; j0 = j; w[0] = 1.0f - fu - fv; du[0] = -1.0f; dv[0] = -1.0f;
-      i1 = i + 1; j1 = j; w[1] = fu; du[1] = 1.0f; dv[1] = 0.0f;
-      i2 = i; j2 = j + 1; w[2] = fv; du[2] = 0.0f; dv[2] = 1.0f;
-    } else {
-      i0 = i + 1; j0 = j + 1; w[0] = fu + fv - 1.0f; du[0] = 1.0f; dv[0] = 1.0f;
-      i1 = i; j1 = j + 1; w[1] = 1.0f - fu; du[1] = -1.0f; dv[1] = 0.0f;
-      i2 = i + 1; j2 = j; w[2] = 1.0f - fv; du[2] = 0.0f; dv[2] = -1.0f;
-    }
-  } else {
-    if (fu >= fv) {
-      i0 = i; j0 = j; w[0] = 1.0f - fu; du[0] = -1.0f; dv[0] = 0.0f;
-      i1 = i + 1; j1 = j; w[1] = fu - fv; du[1] = 1.0f; dv[1] = -1.0f;
-      i2 = i + 1; j2 = j + 1; w[2] = fv; du[2] = 0.0f; dv[2] = 1.0f;
-    } else {
-      i0 = i; j0 = j; w[0] = 1.0f - fv; du[0] = 0.0f; dv[0] = -1.0f;
-      i1 = i; j1 = j + 1; w[1] = fv - fu; du[1] = -1.0f; dv[1] = 1.0f;
-      i2 = i + 1; j2 = j + 1; w[2] = fu; du[2] = 1.0f; dv[2] = 0.0f;
-    }
-  }
+  // up: the triangle of the cell's far half (above the anti-diagonal when
+  // the cell is split along it, above the main diagonal otherwise). The four
+  // cases, as selects (lanes of a wave take different ones):
+  //   same, lower: (i, j) 1 - fu - fv, (i+1, j) fu,     (i, j+1) fv
+  //   same, upper: (i+1, j+1) fu + fv - 1, (i, j+1) 1 - fu, (i+1, j) 1 - fv
+  //   split, lower: (i, j) 1 - fu, (i+1, j) fu - fv, (i+1, j+1) fv
+  //   split, upper: (i, j) 1 - fv, (i, j+1) fv - fu, (i+1, j+1) fu
+  // every candidate first, so that the selects pick values (arms holding
+  // arithmetic are turned into branches)
+  const float sum = fu + fv, ou = 1.0f - fu, ov = 1.0f - fv;
+  const float lo = ou - fv, hi = sum - 1.0f, duv = fu - fv, dvu = fv - fu;
+  const bool up = (same && sum > 1.0f) || (!same && fu < fv);
+  w[0] = same ? (up ? hi : lo) : (up ? ov : ou);
+  w[1] = same ? (up ? ou : fu) : (up ? dvu : duv);
+  w[2] = same ? (up ? ov : fv) : (up ? fu : fv);
+  const int o0 = same && up ? 1 : 0;
+  const int i0 = i + o0, j0 = j + o0;
+  const int i1 = up ? i : i + 1, j1 = up ? j + 1 : j;
+  const int i2 = same ? (up ? i + 1 : i) : i + 1, j2 = same ? (up ? j : j + 1) : j + 1;
   if constexpr (GRAD) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      gu[k] = du[k];
-      gv[k] = dv[k];
-    }
+    gu[0] = same ? (up ? 1.0f : -1.0f) : (up ? 0.0f : -1.0f);
+    gv[0] = same ? (up ? 1.0f : -1.0f) : (up ? -1.0f : 0.0f);
+    gu[1] = up ? -1.0f : 1.0f;
+    gv[1] = same ? 0.0f : (up ? 1.0f : -1.0f);
+    gu[2] = same ? 0.0f : (up ? 1.0f : 0.0f);
+    gv[2] = same ? (up ? -1.0f : 1.0f) : (up ? 0.0f : 1.0f);
   }
   slot[0] = vertex_slot(i0, j0, R);
   slot[1] = vertex_slot(i1, j1, R);
@@ -694,7 +714,7 @@ __device__ __forceinline__ void bary(float s, float t, int R, int slot[3], float
 __device__ __forceinline__ void octa_jacobian(const float v[3], float J[2][3]) {
   const float S = fabsf(v[0]) + fabsf(v[1]) + fabsf(v[2]);
   float du[2][3];
-  const float iS = S > 0.0f ? 1.0f / S : 0.0f;
+  const float iS = S > 0.0f ? rcp_refined(S) : 0.0f;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -719,7 +739,7 @@ __device__ __forceinline__ void octa_jacobian(const float v[3], float J[2][3]) {
 // x is clamped to the cube as for the cells.
 __device__ __forceinline__ void shifted_dir(const float x[3], int l, const int base[3], int d, float disp, const float u[3],
                                    float v[3], float dv[3]) {
-  const float inv = 1.0f / (float)(1u << l);
+  const float inv = ldexpf(1.0f, -l);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const int bit = (d >> a) & 1;
@@ -729,18 +749,54 @@ __device__ __forceinline__ void shifted_dir(const float x[3], int l, const int b
   }
 }
 
+// The eight corners' shifted directions share their per-axis terms: axis a
+// of corner d is v[(d >> a) & 1][a] (the same arithmetic as shifted_dir).
+struct ShiftAxes {
+  float v[2][3];
+};
+__device__ __forceinline__ void shift_axes(const float x[3], int l, const int base[3], float disp, const float u[3],
+                                           ShiftAxes& A) {
+  const float inv = ldexpf(1.0f, -l);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float xc = fminf(fmaxf(x[a], 0.0f), 1.0f);
+#pragma unroll
+    for (int bit = 0; bit < 2; ++bit) A.v[bit][a] = (xc - ((float)(base[a] + bit) + 0.5f) * inv) * disp + u[a];
+  }
+}
+
+// Byte address of node `node` (a global index, or < 0 for none) of level
+// l's map table; a missing node reads the level's first map. A map holds
+// (R+1)^2 C entries, so offsets inside it fit 32 bits.
+template <class TT, int C>
+struct LevelMaps {
+  const char* tab;
+  int32_t off;
+  uint32_t node_bytes;
+  int R;
+  __device__ __forceinline__ LevelMaps(const TreeArgs& T, int l)
+      : tab(reinterpret_cast<const char*>(T.feat[l])), off((int32_t)T.off[l]), R(T.res[l]) {
+    node_bytes = (uint32_t)((R + 1) * (R + 1)) * (uint32_t)(C * sizeof(TT));
+  }
+  __device__ __forceinline__ const char* map(int node) const {
+    const uint32_t n = node >= 0 ? (uint32_t)(node - off) : 0u;
+    return tab + (uint64_t)n * node_bytes;
+  }
+  __device__ __forceinline__ static const TT* entry(const char* m, int slot) {
+    return reinterpret_cast<const TT*>(m + (uint32_t)slot * (uint32_t)(C * sizeof(TT)));
+  }
+};
+
 // Level feature of the paper's scheme: sum over the corners and the three
 // vertices of w_corner * w_vertex * T[node][slot]. Loads go out a batch of
 // corners at a time (12 entries of 16 bytes, or 6 of 32 bytes); corners
-// without a node read entry 0 of the level with weight 0.
+// without a node read the level's first map with weight 0.
 template <class TT, int C>
 __device__ inline void gather_paper_level(const TreeArgs& T, int l, const int node[8], const float wc[8],
                                           const int slot[3], const float wv[3], float* h) {
   typedef typename Texel<TT, C>::raw Raw;
   constexpr int CB = sizeof(TT) * C > 16 ? 2 : 4;  // corners per batch
-  const int R = T.res[l];
-  const int64_t E = (int64_t)(R + 1) * (R + 1);
-  const TT* base = reinterpret_cast<const TT*>(T.feat[l]);
+  const LevelMaps<TT, C> M(T, l);
 #pragma unroll
   for (int c = 0; c < C; ++c) h[c] = 0.0f;
 #pragma unroll
@@ -748,11 +804,9 @@ __device__ inline void gather_paper_level(const TreeArgs& T, int l, const int no
     Raw r[CB][3];
 #pragma unroll
     for (int dd = 0; dd < CB; ++dd) {
-      const int d = b0 + dd;
-      const bool ok = node[d] >= 0;
-      const int64_t nb = ok ? ((int64_t)node[d] - T.off[l]) * E : 0;
+      const char* m = M.map(node[b0 + dd]);
 #pragma unroll
-      for (int k = 0; k < 3; ++k) Texel<TT, C>::load(base + (ok ? (nb + slot[k]) * C : 0), r[dd][k]);
+      for (int k = 0; k < 3; ++k) Texel<TT, C>::load(M.entry(m, slot[k]), r[dd][k]);
     }
 #pragma unroll
     for (int dd = 0; dd < CB; ++dd)
@@ -770,9 +824,9 @@ __device__ __forceinline__ void gather_paper_level_shift(const TreeArgs& T, int 
                                                 float* h) {
   typedef typename Texel<TT, C>::raw Raw;
   constexpr int CB = sizeof(TT) * C > 16 ? 2 : 4;  // corners per batch
-  const int R = T.res[l];
-  const int64_t E = (int64_t)(R + 1) * (R + 1);
-  const TT* tab = reinterpret_cast<const TT*>(T.feat[l]);
+  const LevelMaps<TT, C> M(T, l);
+  ShiftAxes A;
+  shift_axes(x, l, base, disp, u, A);
 #pragma unroll
   for (int c = 0; c < C; ++c) h[c] = 0.0f;
 #pragma unroll
@@ -782,15 +836,14 @@ __device__ __forceinline__ void gather_paper_level_shift(const TreeArgs& T, int 
 #pragma unroll
     for (int dd = 0; dd < CB; ++dd) {
       const int d = b0 + dd;
-      float v[3], dv[3], s, t;
-      shifted_dir(x, l, base, d, disp, u, v, dv);
+      const float v[3] = {A.v[d & 1][0], A.v[(d >> 1) & 1][1], A.v[d >> 2][2]};
+      float s, t;
       octa(v, s, t);
       int slot[3];
-      bary(s, t, R, slot, wv[dd]);
-      const bool ok = node[d] >= 0;
-      const int64_t nb = ok ? ((int64_t)node[d] - T.off[l]) * E : 0;
+      bary(s, t, M.R, slot, wv[dd]);
+      const char* m = M.map(node[d]);
 #pragma unroll
-      for (int k = 0; k < 3; ++k) Texel<TT, C>::load(tab + (ok ? (nb + slot[k]) * C : 0), r[dd][k]);
+      for (int k = 0; k < 3; ++k) Texel<TT, C>::load(M.entry(m, slot[k]), r[dd][k]);
     }
 #pragma unroll
     for (int dd = 0; dd < CB; ++dd)

@@ -239,10 +239,8 @@ __device__ inline void store_rgb(const f32x4 out[NT], int t0, int64_t q_base, in
 // In the paper's scheme the stored indices are the eight corner cells'
 // nodes per level ([L][8][n_idx]) and the query's position is kept too
 // (pos_out, [n_idx]); the backward recomputes the trilinear weights from it.
-// MODE as for encode_kernel, and 3: the shift with each query's disparity
-// read from O.disp (predicted beforehand by disparity_fwd_kernel); with the
-// shift the query's disparity goes to pos_out's w and its unit lookup
-// direction to wdir_out.
+// MODE as for encode_kernel; with the shift the query's disparity goes to
+// pos_out's w and its unit lookup direction to wdir_out.
 template <class TT, class MT, int C, int H, bool WLDS, int MODE>
 __global__ __launch_bounds__(512) void query_kernel(const TreeArgs T, const MlpArgs M, const QuerySrc src,
                                                     int64_t Q, float* __restrict__ rgb, const QueryOut O,
@@ -280,10 +278,7 @@ __global__ __launch_bounds__(512) void query_kernel(const TreeArgs T, const MlpA
       float u[3] = {0.f, 0.f, 0.f}, disp = 0.0f;
       if constexpr (MODE >= 2) {
         unit_dir3(d, u);
-        if constexpr (MODE == 2)
-          disp = predict_disparity(G, x, u);
-        else
-          disp = valid ? O.disp[q] : 0.0f;
+        disp = predict_disparity(G, x, u);
         if (keep) O.wdir[q] = make_float4(u[0], u[1], u[2], 0.0f);
       }
       if (keep) pos_out[q] = make_float4(x[0], x[1], x[2], disp);
@@ -342,12 +337,16 @@ __global__ __launch_bounds__(512) void mlp_kernel(const MlpArgs M, const MT* __r
   const TileRange tr = xcd_tiles(n_tiles, waves, wave);
   for (int64_t tile = tr.first; tile < tr.end; tile += tr.stride) {
     const int64_t q = tile * 64 + lane;
-    const MT* row = h + q * (int64_t)M.K0;
+    // rows of K0 (a multiple of 4) entries: four entries per load
+    typedef MT v4 __attribute__((ext_vector_type(4)));
+    const v4* row = reinterpret_cast<const v4*>(h + (q < Q ? q : 0) * (int64_t)M.K0);
     for (int k = 0; k < M.K0; k += 4) {
       float v[4] = {0.f, 0.f, 0.f, 0.f};
-      if (q < Q)
+      if (q < Q) {
+        const v4 r = row[k >> 2];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) v[c] = to_f32(row[k + c]);
+        for (int c = 0; c < 4; ++c) v[c] = to_f32(r[c]);
+      }
       htile_put4<MT>(htile, KB0, lane, k, v);
     }
     wave_lds_sync();
@@ -358,6 +357,60 @@ __global__ __launch_bounds__(512) void mlp_kernel(const MlpArgs M, const MT* __r
       store_rgb<MT, NT>(out, t0, tile * 64, Q, lane, rgb);
     }
     wave_lds_sync();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Shifted encode of the residual's sorted queries into decoder input rows:
+// one thread per query (the paper's scheme with the disparity shift, each
+// query's disparity read from O.disp). Row q of h_rows (K0 = L C + E
+// entries of MT) holds the level features, then the surface attributes;
+// queries q < n_idx also leave what the backward reads (corner nodes,
+// octahedral coordinates, position and disparity, lookup direction), as
+// the fused query does. Without the decoder's registers the encode runs at
+// several more waves per SIMD, which its dependent gathers need; the
+// standalone decoder then reads the rows.
+// ---------------------------------------------------------------------------
+template <class TT, class MT, int C>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C == 4 ? 4 : 3))) void encode_rows_kernel(const TreeArgs T, const QuerySrc src, int64_t Q, int K0,
+                                                          int E, MT* __restrict__ h_rows, const QueryOut O) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = q < Q;
+  float x[3] = {0.f, 0.f, 0.f}, d[3] = {0.f, 0.f, 1.f};
+  if (valid) load_query(src, q, x, d);
+  float s, t;
+  octa(d, s, t);
+  float u[3];
+  unit_dir3(d, u);
+  const float disp = valid ? O.disp[q] : 0.0f;
+  const bool keep = q < O.n_idx;
+  if (keep) {
+    O.uv[q] = make_float2(s, t);
+    O.wdir[q] = make_float4(u[0], u[1], u[2], 0.0f);
+    O.pos[q] = make_float4(x[0], x[1], x[2], disp);
+  }
+  typedef MT vC __attribute__((ext_vector_type(C)));
+  MT* const row = h_rows + (valid ? q : 0) * (int64_t)K0;
+  encode_paper<TT, C, true>(T, valid, x, s, t, [&](int l, const float (&h)[C], const int (&node)[8]) {
+    if (valid) {
+      vC v;
+#pragma unroll
+      for (int c = 0; c < C; ++c) v[c] = from_f32<MT>(h[c]);
+      *reinterpret_cast<vC*>(row + l * C) = v;
+    }
+    if (keep)
+#pragma unroll
+      for (int dd = 0; dd < 8; ++dd) O.idx[(l * 8 + dd) * O.n_idx + q] = node[dd];  // coalesced across lanes
+  }, disp, u);
+  if (!valid) return;
+  typedef MT v4 __attribute__((ext_vector_type(4)));
+  for (int k = 0; k < E; k += 4) {
+    float g4[4];
+    load_attr4(src, q, k, g4);
+    v4 v;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c] = from_f32<MT>(g4[c]);
+    *reinterpret_cast<v4*>(row + K0 - E + k) = v;
   }
 }
 
@@ -679,8 +732,7 @@ static hipError_t launch_query_t(const TreeArgs& T, const MlpArgs& M, const Quer
                                  const QueryOut& O, const DispArgs& G, hipStream_t st) {
   if (T.interp != OO_INTERP_PAPER) return launch_query_p<TT, MT, C, H, 0>(T, M, src, Q, rgb, O, G, st);
   if (G.n_levels == 0) return launch_query_p<TT, MT, C, H, 1>(T, M, src, Q, rgb, O, G, st);
-  return O.disp ? launch_query_p<TT, MT, C, H, 3>(T, M, src, Q, rgb, O, G, st)
-                : launch_query_p<TT, MT, C, H, 2>(T, M, src, Q, rgb, O, G, st);
+  return launch_query_p<TT, MT, C, H, 2>(T, M, src, Q, rgb, O, G, st);
 }
 
 template <class TT, class MT, int C>
@@ -768,6 +820,29 @@ hipError_t launch_cast(const float* src, void* dst, oo_dtype dt, int64_t n, hipS
     hipLaunchKernelGGL(cast_kernel<f16>, dim3((unsigned)blocks), dim3(256), 0, st, src, (f16*)dst, n);
   else
     hipLaunchKernelGGL(cast_kernel<bf16>, dim3((unsigned)blocks), dim3(256), 0, st, src, (bf16*)dst, n);
+  return hipGetLastError();
+}
+
+template <class TT, class MT, int C>
+static void launch_encode_rows_t(const TreeArgs& T, const QuerySrc& src, int64_t Q, int K0, int E, void* h_rows,
+                                 const QueryOut& O, hipStream_t st) {
+  hipLaunchKernelGGL((encode_rows_kernel<TT, MT, C>), dim3((unsigned)((Q + 255) / 256)), dim3(256), 0, st, T, src, Q,
+                     K0, E, reinterpret_cast<MT*>(h_rows), O);
+}
+
+hipError_t launch_encode_rows(const TreeArgs& T, oo_dtype td, const MlpArgs& M, const QuerySrc& src, int64_t Q,
+                              void* h_rows, const QueryOut& O, hipStream_t st) {
+  if (Q == 0) return hipSuccess;
+  // the tables and the decoder share one dtype in the product paths
+  if (td == OO_F32)
+    T.C == 4 ? launch_encode_rows_t<float, float, 4>(T, src, Q, M.K0, M.E, h_rows, O, st)
+             : launch_encode_rows_t<float, float, 8>(T, src, Q, M.K0, M.E, h_rows, O, st);
+  else if (td == OO_F16)
+    T.C == 4 ? launch_encode_rows_t<f16, f16, 4>(T, src, Q, M.K0, M.E, h_rows, O, st)
+             : launch_encode_rows_t<f16, f16, 8>(T, src, Q, M.K0, M.E, h_rows, O, st);
+  else
+    T.C == 4 ? launch_encode_rows_t<bf16, bf16, 4>(T, src, Q, M.K0, M.E, h_rows, O, st)
+             : launch_encode_rows_t<bf16, bf16, 8>(T, src, Q, M.K0, M.E, h_rows, O, st);
   return hipGetLastError();
 }
 

@@ -64,10 +64,15 @@ struct QueryOut {
   float4* pos;
   float4* wdir;
   int64_t n_idx;
-  const float* disp = nullptr;  // per-query disparity, when already predicted
+  const float* disp = nullptr;  // per-query disparity, read by the shifted encode into rows
 };
 // The predictor's d for Q queries (matrix cores), into d_out [Q].
 hipError_t launch_disparity_fwd(const DispArgs& G, const QuerySrc& src, int64_t Q, float* d_out, hipStream_t st);
+// The shifted encode of the Q sorted queries (disparity from O.disp) into
+// decoder input rows h_rows [Q][M.K0] of the tables' dtype (level features,
+// then the M.E surface attributes), with the backward's outputs in O.
+hipError_t launch_encode_rows(const TreeArgs& T, oo_dtype td, const MlpArgs& M, const QuerySrc& src, int64_t Q,
+                              void* h_rows, const QueryOut& O, hipStream_t st);
 hipError_t launch_query(const TreeArgs& T, oo_dtype td, const MlpArgs& M, oo_dtype md, const QuerySrc& src,
                         int64_t Q, float* rgb, const QueryOut& O, const DispArgs& G, hipStream_t st);
 
@@ -137,13 +142,18 @@ hipError_t launch_scatter(const TreeArgs& T, oo_dtype td, int64_t Q, const int32
                           const float2* uv, const float4* pos, const float* dh, float post_scale, const GradArgs& G,
                           const ShiftArgs& S, hipStream_t st);
 // Disparity predictor backward over the Q sorted backward queries (x, dir
-// from src; dd[q] = dLoss/d disparity): hash-table gradients added into
-// dtables, MLP parameter sums per workgroup into partials [grid][P] with
-// P = disparity_params(G) (flat W_0, b_0, (W_1, b_1,) W_out, b_out).
+// from src; dd[q] = dLoss/d disparity), at most `cap` queries per pass
+// through the row buffer `rows` (disparity_rows_floats(cap) floats):
+// hash-table gradients added into dtables, MLP parameter sums per
+// workgroup into partials [grid][P] with P = disparity_params(G) (flat W_0,
+// b_0, (W_1, b_1,) W_out, b_out).
+constexpr int64_t kDispRowsMax = 262144;
 int disparity_bwd_grid(int64_t Q);
+int64_t disparity_rows_cap(int64_t Q);
+int64_t disparity_rows_floats(int64_t cap);
 int32_t disparity_params(const DispArgs& G);
 hipError_t launch_disparity_bwd(const DispArgs& G, const QuerySrc& src, int64_t Q, const float* dd, float* dtables,
-                                float* partials, int grid, hipStream_t st);
+                                float* rows, int64_t cap, float* partials, int grid, hipStream_t st);
 hipError_t launch_dw_reduce(const float* partials, int grid, const ParamLayout& PL, const ReduceDst& D, float scale,
                             hipStream_t st);
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t st);
