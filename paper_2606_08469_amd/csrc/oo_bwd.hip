@@ -104,24 +104,64 @@ __host__ __device__ constexpr int bwd_waves() {
   return sizeof(MT) == 4 ? 16 : 8;
 }
 
+// With 16-bit operands a K-chunk's operand reads all go out before its
+// MFMAs (a scheduling barrier keeps them there; otherwise each read is
+// waited on next to its MFMA). FP32 fragments take 8 registers each and its
+// 16-wave workgroups hide the latency; there the batching measured slower,
+// so FP32 keeps the compiler's interleaved schedule.
+template <class MT>
+__host__ __device__ constexpr bool batch_reads() {
+  return sizeof(MT) == 2;
+}
+
 // dW tiles of one layer owned by this wave: tile tau = wave + NW u.
 template <class MT, int NW, int U>
 __device__ inline void dw_layer(f32x4 (&acc)[U], const MT* dT, const MT* act, int n_out, int n_in, int wave, int lane) {
   const int MM = (n_out + 15) / 16, NK = (n_in + 15) / 16;
   const int r16 = lane & 15, g = lane >> 4;
+  if constexpr (!batch_reads<MT>()) {
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int tau = wave + NW * u;
-    if (tau < MM * NK) {
-      const int mm = tau / NK, nk = tau % NK;
+    for (int u = 0; u < U; ++u) {
+      const int tau = wave + NW * u;
+      if (tau < MM * NK) {
+        const int mm = tau / NK, nk = tau % NK;
 #pragma unroll
-      for (int kk = 0; kk < 2; ++kk) {
-        const auto a = tq_frag<MT>(dT, 16 * mm + r16, 4 * kk + g);
-        const auto b = tq_frag<MT>(act, 16 * nk + r16, 4 * kk + g);
-        acc[u] = mma(a, b, acc[u]);
+        for (int kk = 0; kk < 2; ++kk) {
+          const auto a = tq_frag<MT>(dT, 16 * mm + r16, 4 * kk + g);
+          const auto b = tq_frag<MT>(act, 16 * nk + r16, 4 * kk + g);
+          acc[u] = mma(a, b, acc[u]);
+        }
+      }
+      // keep the scheduler from hoisting every tile's LDS reads at once
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    return;
+  }
+  // two tiles at a time: their eight operand reads go out before the four
+  // MFMAs (all tiles' reads at once would hold too many registers)
+#pragma unroll
+  for (int u0 = 0; u0 < U; u0 += 2) {
+    typename FragT<MT>::type a[2][2], b[2][2];
+#pragma unroll
+    for (int du = 0; du < 2; ++du) {
+      const int tau = wave + NW * (u0 + du);
+      if (u0 + du < U && tau < MM * NK) {
+        const int mm = tau / NK, nk = tau % NK;
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+          a[du][kk] = tq_frag<MT>(dT, 16 * mm + r16, 4 * kk + g);
+          b[du][kk] = tq_frag<MT>(act, 16 * nk + r16, 4 * kk + g);
+        }
       }
     }
-    // keep the scheduler from hoisting every tile's LDS reads at once
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int du = 0; du < 2; ++du) {
+      const int tau = wave + NW * (u0 + du);
+      if (u0 + du < U && tau < MM * NK)
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) acc[u0 + du] = mma(a[du][kk], b[du][kk], acc[u0 + du]);
+    }
     __builtin_amdgcn_sched_barrier(0);
   }
 }
@@ -350,13 +390,27 @@ __global__ __launch_bounds__(64 * bwd_waves<MT>()) void bwd_kernel(const TreeArg
       for (int mi = 0; mi < MH2; ++mi)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[mi][j] = b0[16 * (mh * MH2 + mi) + 4 * g + j];
+      // per K-chunk, every operand read goes out before the chunk's MFMAs
+      // (the scheduler would otherwise wait on each read next to its MFMA)
       for (int kb = 0; kb < KB0; ++kb) {
         const frag b = tq_bfrag<MT>(act0, kb, g, col, K0);
+        if constexpr (batch_reads<MT>()) {
+          frag a[MH2];
 #pragma unroll
-        for (int mi = 0; mi < MH2; ++mi) {
-          const int m = mh * MH2 + mi;
-          acc[mi] = mma(WL ? lds_frag<MT>(w0p, KB0, m, kb, lane) : wfrag_global<MT>(W0, H, K0, K0, m, kb, lane), b,
-                        acc[mi]);
+          for (int mi = 0; mi < MH2; ++mi) {
+            const int m = mh * MH2 + mi;
+            a[mi] = WL ? lds_frag<MT>(w0p, KB0, m, kb, lane) : wfrag_global<MT>(W0, H, K0, K0, m, kb, lane);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int mi = 0; mi < MH2; ++mi) acc[mi] = mma(a[mi], b, acc[mi]);
+        } else {
+#pragma unroll
+          for (int mi = 0; mi < MH2; ++mi) {
+            const int m = mh * MH2 + mi;
+            acc[mi] = mma(WL ? lds_frag<MT>(w0p, KB0, m, kb, lane) : wfrag_global<MT>(W0, H, K0, K0, m, kb, lane), b,
+                          acc[mi]);
+          }
         }
       }
       store_tq<MT, MH2>(act(1), acc, mh * MH2, MH, H, nt, lane, true);
@@ -373,11 +427,23 @@ __global__ __launch_bounds__(64 * bwd_waves<MT>()) void bwd_kernel(const TreeArg
 #pragma unroll
         for (int kb = 0; kb < H / 32; ++kb) {
           const frag b = tq_bfrag<MT>(a, kb, g, col, H);
+          if constexpr (batch_reads<MT>()) {
+            frag wa[MH2];
 #pragma unroll
-          for (int mi = 0; mi < MH2; ++mi) {
-            const int m = mh * MH2 + mi;
-            acc[mi] = mma(WL ? lds_frag<MT>(Wp, H / 32, m, kb, lane) : wfrag_global<MT>(Wl, H, H, H, m, kb, lane), b,
-                          acc[mi]);
+            for (int mi = 0; mi < MH2; ++mi) {
+              const int m = mh * MH2 + mi;
+              wa[mi] = WL ? lds_frag<MT>(Wp, H / 32, m, kb, lane) : wfrag_global<MT>(Wl, H, H, H, m, kb, lane);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int mi = 0; mi < MH2; ++mi) acc[mi] = mma(wa[mi], b, acc[mi]);
+          } else {
+#pragma unroll
+            for (int mi = 0; mi < MH2; ++mi) {
+              const int m = mh * MH2 + mi;
+              acc[mi] = mma(WL ? lds_frag<MT>(Wp, H / 32, m, kb, lane) : wfrag_global<MT>(Wl, H, H, H, m, kb, lane), b,
+                            acc[mi]);
+            }
           }
         }
         store_tq<MT, MH2>(act(layer + 1), acc, mh * MH2, MH, H, nt, lane, true);
@@ -434,11 +500,23 @@ __global__ __launch_bounds__(64 * bwd_waves<MT>()) void bwd_kernel(const TreeArg
         const MT* Wp = hw + (size_t)(2 * (i - 1) + 1) * H * H;
         for (int kb = 0; kb < KBo; ++kb) {
           const frag b = tq_bfrag<MT>(dT, kb, gs, cs, n_out);
+          if constexpr (batch_reads<MT>()) {
+            frag wa[MH2];
 #pragma unroll
-          for (int mi = 0; mi < MH2; ++mi) {
-            const int m = mh * MH2 + mi;
-            dacc[mi] = mma(hid ? lds_frag<MT>(Wp, H / 32, m, kb, ln) : wfrag_global<MT>(Wt, H, n_out, ldt, m, kb, ln), b,
-                           dacc[mi]);
+            for (int mi = 0; mi < MH2; ++mi) {
+              const int m = mh * MH2 + mi;
+              wa[mi] = hid ? lds_frag<MT>(Wp, H / 32, m, kb, ln) : wfrag_global<MT>(Wt, H, n_out, ldt, m, kb, ln);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int mi = 0; mi < MH2; ++mi) dacc[mi] = mma(wa[mi], b, dacc[mi]);
+          } else {
+#pragma unroll
+            for (int mi = 0; mi < MH2; ++mi) {
+              const int m = mh * MH2 + mi;
+              dacc[mi] = mma(hid ? lds_frag<MT>(Wp, H / 32, m, kb, ln) : wfrag_global<MT>(Wt, H, n_out, ldt, m, kb, ln),
+                             b, dacc[mi]);
+            }
           }
         }
         // ReLU'(z) = 1 where the layer-i input activation is positive
@@ -462,13 +540,27 @@ __global__ __launch_bounds__(64 * bwd_waves<MT>()) void bwd_kernel(const TreeArg
         for (int mi = 0; mi < MK2; ++mi) dacc[mi] = z4;
         for (int kb = 0; kb < KBo; ++kb) {
           const frag b = tq_bfrag<MT>(dT, kb, gs, cs, n_out);
+          if constexpr (batch_reads<MT>()) {
+            frag wa[MK2];
 #pragma unroll
-          for (int mi = 0; mi < MK2; ++mi)
-            if (mh * MK2 + mi < MK) {
+            for (int mi = 0; mi < MK2; ++mi) {
               const int m = mh * MK2 + mi;
-              dacc[mi] = mma(WL ? lds_frag<MT>(wt0, H / 32, m, kb, ln) : wfrag_global<MT>(Wt, K0, n_out, ldt, m, kb, ln),
-                             b, dacc[mi]);
+              if (m < MK)
+                wa[mi] = WL ? lds_frag<MT>(wt0, H / 32, m, kb, ln) : wfrag_global<MT>(Wt, K0, n_out, ldt, m, kb, ln);
             }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int mi = 0; mi < MK2; ++mi)
+              if (mh * MK2 + mi < MK) dacc[mi] = mma(wa[mi], b, dacc[mi]);
+          } else {
+#pragma unroll
+            for (int mi = 0; mi < MK2; ++mi)
+              if (mh * MK2 + mi < MK) {
+                const int m = mh * MK2 + mi;
+                dacc[mi] = mma(WL ? lds_frag<MT>(wt0, H / 32, m, kb, ln) : wfrag_global<MT>(Wt, K0, n_out, ldt, m, kb, ln),
+                               b, dacc[mi]);
+              }
+          }
         }
         // dh of query column cs, rows 16m + 4g .. +3: one 16-byte store each
         const int64_t q = qbase + cs;

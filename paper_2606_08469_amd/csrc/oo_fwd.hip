@@ -138,16 +138,19 @@ __device__ inline void mlp_forward_tiles(const MlpArgs& M, const WSrc& W, const 
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[m][t] = bt;
   }
+  // Each K-chunk's weight fragments are all read before its MFMAs, so their
+  // LDS latency overlaps instead of stalling every pair of MFMAs.
   for (int kb = 0; kb < KB0; ++kb) {
-    frag bf[NT];
+    frag bf[NT], a[MH];
 #pragma unroll
     for (int t = 0; t < NT; ++t) bf[t] = htile_get<MT>(htile, KB0, t0 + t, kb, lane);
 #pragma unroll
-    for (int m = 0; m < MH; ++m) {
-      const frag a = W.get(M, 0, m, kb, lane);
+    for (int m = 0; m < MH; ++m) a[m] = W.get(M, 0, m, kb, lane);
+    __builtin_amdgcn_sched_barrier(0);  // (the scheduler would sink each read to its MFMAs)
 #pragma unroll
-      for (int t = 0; t < NT; ++t) acc[m][t] = mma(a, bf[t], acc[m][t]);
-    }
+    for (int m = 0; m < MH; ++m)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[m][t] = mma(a[m], bf[t], acc[m][t]);
   }
   // hidden layers H -> H
   for (int layer = 1; layer < M.n_layers - 1; ++layer) {
@@ -163,13 +166,16 @@ __device__ inline void mlp_forward_tiles(const MlpArgs& M, const WSrc& W, const 
       for (int t = 0; t < NT; ++t) acc[m][t] = bt;
     }
 #pragma unroll
-    for (int kb = 0; kb < KH; ++kb)
+    for (int kb = 0; kb < KH; ++kb) {
+      frag a[MH];
 #pragma unroll
-      for (int m = 0; m < MH; ++m) {
-        const frag a = W.get(M, layer, m, kb, lane);
+      for (int m = 0; m < MH; ++m) a[m] = W.get(M, layer, m, kb, lane);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[m][t] = mma(a, bf[kb][t], acc[m][t]);
-      }
+      for (int m = 0; m < MH; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = mma(a[m], bf[kb][t], acc[m][t]);
+    }
   }
   // output layer H -> 3
   const int lo = M.n_layers - 1;
