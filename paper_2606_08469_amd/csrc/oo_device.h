@@ -325,6 +325,15 @@ __device__ __forceinline__ float rcp_refined(float x) {
   return fmaf(r, fmaf(-x, r, 1.0f), r);
 }
 
+// 1 / sqrt(x) and sqrt(x) for normal x > 0: the hardware reciprocal square
+// root refined by one Newton-Raphson step, y' = y + y (1 - x y^2) / 2, and
+// sqrt(x) = x y' (a few ulp, in place of the correctly rounded sequences).
+__device__ __forceinline__ float rsqrt_refined(float x) {
+  const float y = __builtin_amdgcn_rsqf(x);
+  return fmaf(0.5f * y, fmaf(-x * y, y, 1.0f), y);
+}
+__device__ __forceinline__ float sqrt_refined(float x) { return x > 0.0f ? x * rsqrt_refined(x) : 0.0f; }
+
 __device__ inline void octa(const float d[3], float& s, float& t) {
   const float S = fabsf(d[0]) + fabsf(d[1]) + fabsf(d[2]);
   // one reciprocal for both coordinates (its rounding can put a coordinate
@@ -1121,7 +1130,7 @@ __device__ __forceinline__ void bsdf_weight(const float n[3], const float wo[3],
     return;
   }
   float h[3] = {wi[0] + wo[0], wi[1] + wo[1], wi[2] + wo[2]};
-  const float ihl = 1.0f / sqrtf(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
+  const float ihl = rsqrt_refined(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
 #pragma unroll
   for (int a = 0; a < 3; ++a) h[a] *= ihl;
   const float nh = n[0] * h[0] + n[1] * h[1] + n[2] * h[2];
@@ -1131,19 +1140,18 @@ __device__ __forceinline__ void bsdf_weight(const float n[3], const float wo[3],
   const float vh = 1.0f - (wi[0] * h[0] + wi[1] * h[1] + wi[2] * h[2]);
   const float vh2 = vh * vh;
   const float F = F0 + (1.0f - F0) * (vh2 * vh2 * vh);
-  const float gi = ci + sqrtf(a2 + (1.0f - a2) * ci * ci), go = co + sqrtf(a2 + (1.0f - a2) * co * co);
-  const float spec = a2 * F / (3.14159265358979f * den * den * gi * go);
-  const float sc = ci / pdf;
+  const float gi = ci + sqrt_refined(a2 + (1.0f - a2) * ci * ci), go = co + sqrt_refined(a2 + (1.0f - a2) * co * co);
+  const float spec = a2 * F * rcp_refined(3.14159265358979f * den * den * gi * go);
+  const float sc = ci * rcp_refined(pdf);
 #pragma unroll
   for (int c = 0; c < 3; ++c) w[c] = (alb[c] * (1.0f / 3.14159265358979f) + spec) * sc;
 }
-
 __device__ __forceinline__ void load_unit(const float* p, float v[3]) {
   v[0] = p[0];
   v[1] = p[1];
   v[2] = p[2];
   const float l2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-  const float il = l2 > 0.0f ? 1.0f / sqrtf(l2) : 1.0f;
+  const float il = l2 > 0.0f ? rsqrt_refined(l2) : 1.0f;
   v[0] *= il;
   v[1] *= il;
   v[2] *= il;
