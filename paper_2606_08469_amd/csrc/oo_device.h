@@ -774,38 +774,18 @@ __device__ __forceinline__ void shift_axes(const float x[3], int l, const int ba
   }
 }
 
-// Byte address of node `node` (a global index, or < 0 for none) of level
-// l's map table; a missing node reads the level's first map. A map holds
-// (R+1)^2 C entries, so offsets inside it fit 32 bits.
-template <class TT, int C>
-struct LevelMaps {
-  const char* tab;
-  int32_t off;
-  uint32_t node_bytes;
-  int R;
-  __device__ __forceinline__ LevelMaps(const TreeArgs& T, int l)
-      : tab(reinterpret_cast<const char*>(T.feat[l])), off((int32_t)T.off[l]), R(T.res[l]) {
-    node_bytes = (uint32_t)((R + 1) * (R + 1)) * (uint32_t)(C * sizeof(TT));
-  }
-  __device__ __forceinline__ const char* map(int node) const {
-    const uint32_t n = node >= 0 ? (uint32_t)(node - off) : 0u;
-    return tab + (uint64_t)n * node_bytes;
-  }
-  __device__ __forceinline__ static const TT* entry(const char* m, int slot) {
-    return reinterpret_cast<const TT*>(m + (uint32_t)slot * (uint32_t)(C * sizeof(TT)));
-  }
-};
-
 // Level feature of the paper's scheme: sum over the corners and the three
 // vertices of w_corner * w_vertex * T[node][slot]. Loads go out a batch of
 // corners at a time (12 entries of 16 bytes, or 6 of 32 bytes); corners
-// without a node read the level's first map with weight 0.
+// without a node read entry 0 of the level with weight 0.
 template <class TT, int C>
 __device__ inline void gather_paper_level(const TreeArgs& T, int l, const int node[8], const float wc[8],
                                           const int slot[3], const float wv[3], float* h) {
   typedef typename Texel<TT, C>::raw Raw;
   constexpr int CB = sizeof(TT) * C > 16 ? 2 : 4;  // corners per batch
-  const LevelMaps<TT, C> M(T, l);
+  const int R = T.res[l];
+  const int64_t E = (int64_t)(R + 1) * (R + 1);
+  const TT* base = reinterpret_cast<const TT*>(T.feat[l]);
 #pragma unroll
   for (int c = 0; c < C; ++c) h[c] = 0.0f;
 #pragma unroll
@@ -813,9 +793,11 @@ __device__ inline void gather_paper_level(const TreeArgs& T, int l, const int no
     Raw r[CB][3];
 #pragma unroll
     for (int dd = 0; dd < CB; ++dd) {
-      const char* m = M.map(node[b0 + dd]);
+      const int d = b0 + dd;
+      const bool ok = node[d] >= 0;
+      const int64_t nb = ok ? ((int64_t)node[d] - T.off[l]) * E : 0;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) Texel<TT, C>::load(M.entry(m, slot[k]), r[dd][k]);
+      for (int k = 0; k < 3; ++k) Texel<TT, C>::load(base + (ok ? (nb + slot[k]) * C : 0), r[dd][k]);
     }
 #pragma unroll
     for (int dd = 0; dd < CB; ++dd)
@@ -833,7 +815,10 @@ __device__ __forceinline__ void gather_paper_level_shift(const TreeArgs& T, int 
                                                 float* h) {
   typedef typename Texel<TT, C>::raw Raw;
   constexpr int CB = sizeof(TT) * C > 16 ? 2 : 4;  // corners per batch
-  const LevelMaps<TT, C> M(T, l);
+  const int R = T.res[l];
+  const int64_t E = (int64_t)(R + 1) * (R + 1);
+  const int64_t off = T.off[l];
+  const TT* tab = reinterpret_cast<const TT*>(T.feat[l]);
   ShiftAxes A;
   shift_axes(x, l, base, disp, u, A);
 #pragma unroll
@@ -849,10 +834,11 @@ __device__ __forceinline__ void gather_paper_level_shift(const TreeArgs& T, int 
       float s, t;
       octa(v, s, t);
       int slot[3];
-      bary(s, t, M.R, slot, wv[dd]);
-      const char* m = M.map(node[d]);
+      bary(s, t, R, slot, wv[dd]);
+      const bool ok = node[d] >= 0;
+      const int64_t nb = ok ? ((int64_t)node[d] - off) * E : 0;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) Texel<TT, C>::load(M.entry(m, slot[k]), r[dd][k]);
+      for (int k = 0; k < 3; ++k) Texel<TT, C>::load(tab + (ok ? (nb + slot[k]) * C : 0), r[dd][k]);
     }
 #pragma unroll
     for (int dd = 0; dd < CB; ++dd)
