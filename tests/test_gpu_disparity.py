@@ -259,3 +259,21 @@ def test_shifted_paper_config_fp16():
     assert max(e1, e2, el) <= MIX_TOL
     compare_disp_grads("shifted paper config fp16", gd, otree, omlp, bt, cos=MIX_COS)
     compare_grads("shifted paper config fp16", got, otree, omlp, bt, cos=MIX_COS)
+
+
+def test_predictor_backward_two_row_passes():
+    """The predictor's backward runs at most 262,144 queries per pass through
+    its row buffer. With the gradient through the target, 8,192 points x 32
+    samples give 270,336 backward queries: two passes, the second starting
+    at sorted position 262,144 and adding its parameter sums to the first's.
+    Every predictor gradient group against the oracle at cosine >= 0.9999
+    (FP32, no kink filter: a pass that overwrote instead of adding, or read
+    another pass's rows, would lose about 3% of the queries' share)."""
+    B, N = 8192, 32
+    assert B * (1 + N) > 262144, "two passes of the predictor's row buffer"
+    bt = dict(batch(B, N), grad_through_rhs=1)
+    gpu, otree, omlp = models()
+    print(f"[case] predictor backward two row passes B={B} N={N} full", flush=True)
+    run_residual(gpu, bt)
+    gd = disp_grads_of(gpu)
+    compare_disp_grads("predictor two row passes", gd, otree, omlp, bt, cos=0.9999)
