@@ -342,18 +342,42 @@ __global__ __launch_bounds__(512) void mlp_kernel(const MlpArgs M, const MT* __r
   const int64_t n_tiles = (Q + 63) / 64;
   const TileRange tr = xcd_tiles(n_tiles, waves, wave);
   for (int64_t tile = tr.first; tile < tr.end; tile += tr.stride) {
-    const int64_t q = tile * 64 + lane;
-    // rows of K0 (a multiple of 4) entries: four entries per load
-    typedef MT v4 __attribute__((ext_vector_type(4)));
-    const v4* row = reinterpret_cast<const v4*>(h + (q < Q ? q : 0) * (int64_t)M.K0);
-    for (int k = 0; k < M.K0; k += 4) {
-      float v[4] = {0.f, 0.f, 0.f, 0.f};
-      if (q < Q) {
-        const v4 r = row[k >> 2];
+    // The tile's 64 rows are contiguous: the wave reads them as 16-byte
+    // pieces in order (coalesced; EP entries each, K0 a multiple of EP),
+    // else each lane reads its own row four entries at a time.
+    constexpr int EP = 16 / sizeof(MT);
+    const int64_t q0 = tile * 64;
+    const int nrow = Q - q0 < 64 ? (int)(Q - q0) : 64;
+    if (M.K0 % EP == 0) {
+      typedef MT vP __attribute__((ext_vector_type(EP)));
+      const int P = M.K0 / EP;
+      const vP* src = reinterpret_cast<const vP*>(h + q0 * (int64_t)M.K0);
+      for (int p = lane; p < 64 * P; p += 64) {
+        const int r = p / P, k0 = (p - r * P) * EP;
+        float v[EP];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) v[c] = to_f32(r[c]);
+        for (int c = 0; c < EP; ++c) v[c] = 0.0f;
+        if (r < nrow) {
+          const vP x = src[p];
+#pragma unroll
+          for (int c = 0; c < EP; ++c) v[c] = to_f32(x[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < EP; c += 4) htile_put4<MT>(htile, KB0, r, k0 + c, &v[c]);
       }
-      htile_put4<MT>(htile, KB0, lane, k, v);
+    } else {
+      typedef MT v4 __attribute__((ext_vector_type(4)));
+      const int64_t q = q0 + lane;
+      const v4* row = reinterpret_cast<const v4*>(h + (q < Q ? q : 0) * (int64_t)M.K0);
+      for (int k = 0; k < M.K0; k += 4) {
+        float v[4] = {0.f, 0.f, 0.f, 0.f};
+        if (q < Q) {
+          const v4 r = row[k >> 2];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) v[c] = to_f32(r[c]);
+        }
+        htile_put4<MT>(htile, KB0, lane, k, v);
+      }
     }
     wave_lds_sync();
 #pragma unroll
