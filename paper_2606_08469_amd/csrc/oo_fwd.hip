@@ -326,7 +326,10 @@ template <class MT, int H, bool WLDS>
 __global__ __launch_bounds__(512) void mlp_kernel(const MlpArgs M, const MT* __restrict__ h, int64_t Q,
                                                   float* __restrict__ rgb) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  constexpr int NT = 2;
+  // N-tiles per pass: with 16-bit operands and the weights in LDS all
+  // four, so that each weight fragment read serves four MFMAs (the other
+  // variants would spill)
+  constexpr int NT = sizeof(MT) == 2 && WLDS ? 4 : 2;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63, waves = blockDim.x >> 6;
   const int KB0 = (M.K0 + 31) / 32;
   const int wl_elems = WLDS ? packed_weight_elems<MT>(M.n_layers, M.K0, M.H) : 0;
