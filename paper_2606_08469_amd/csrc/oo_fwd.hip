@@ -256,7 +256,10 @@ __global__ __launch_bounds__(512) void query_kernel(const TreeArgs T, const MlpA
   float4* __restrict__ pos_out = O.pos;
   const int64_t n_idx = O.n_idx;
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  constexpr int NT = 2;
+  // N-tiles per decoder pass: all four with 16-bit operands, LDS weights
+  // and 64-wide layers (each weight fragment read then serves four MFMAs;
+  // at width 128 the accumulators would spill)
+  constexpr int NT = sizeof(MT) == 2 && WLDS && H == 64 ? 4 : 2;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63, waves = blockDim.x >> 6;
   const int KB0 = (M.K0 + 31) / 32;
   const int wl_elems = WLDS ? packed_weight_elems<MT>(M.n_layers, M.K0, M.H) : 0;
