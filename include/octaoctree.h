@@ -29,9 +29,11 @@
  *    parallel to its quadrant's equator segment, so triangles follow the
  *    octahedron's faces. Border vertices that are one direction share one
  *    slot (the lower index along the edge; the four corners use slot 0).
- *    All eight cells use the same direction: there is no disparity
- *    predictor.
- *  - The decoder reads h only.
+ *    Without a disparity predictor (oo_tree.disparity = NULL) all eight
+ *    cells use the lookup direction; with one, each cell is read along
+ *    its own disparity-shifted direction (oo_disparity below).
+ *  - The decoder reads h, followed by the query's surface attributes when
+ *    its input is wider than h (oo_mlp, oo_residual_batch).
  *  - The BSDF is Lambert plus GGX.
  *
  * Conventions for every entry point:
