@@ -664,7 +664,7 @@ int oo_radiosity_residual_fwd(const oo_tree* tree, const oo_mlp* mlp, const oo_r
       // every query's disparity on the matrix cores, the shifted encode into
       // decoder input rows, then the decoder over the rows
       float* dsp = reinterpret_cast<float*>(ws + w.dsp);
-      e = launch_disparity_fwd(G, sorted, Q, dsp, stream);
+      e = launch_disparity_fwd(G, mlp->dtype, sorted, Q, dsp, stream);
       if (e != hipSuccess) return hip_status(e, "disparity launch");
       O.disp = dsp;
       void* hrows = ws + w.hrows;

@@ -454,21 +454,163 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C == 4 ? 4 
 // ---------------------------------------------------------------------------
 // Disparity predictor on the matrix cores: each wave encodes 64 queries'
 // positions (hash grid) and lookup directions into its FP32 activation tile
-// and runs the predictor's MLP on it like the decoder's (16x16x4 FP32
-// MFMA), writing d per query.
+// and runs the predictor's MLP on it like the decoder's, writing d per
+// query. FP32 path: 16x16x4 FP32 MFMA, weights from L2. 16-bit path
+// (SPLIT): every operand is split into two BF16 parts, x = hi + lo with
+// hi = bf16(x) and lo = bf16(x - hi) (about 16 significant bits, FP32's
+// exponent range), and each product is hi hi + hi lo + lo hi on 16x16x32
+// BF16 MFMA with FP32 accumulation: three MFMAs of 16 cycles for each
+// eight FP32 ones of 32. The weights are split once per workgroup into LDS.
+// (A plain 16-bit predictor moves shifted lookups across triangle edges
+// often enough to break its gradients' agreement; the split keeps d within
+// about 1e-5 of FP32.)
 // ---------------------------------------------------------------------------
+
+// Packs the predictor's FP32 weights into LDS in fragment order, split into
+// BF16 hi (at hi) and lo (at hi + the packed size) parts.
+__device__ inline void pack_weights_split(const MlpArgs& M, bf16* hi, int total_elems) {
+  int offset = 0;
+  for (int layer = 0; layer < M.n_layers; ++layer) {
+    const int n_in = layer == 0 ? M.K0 : M.H;
+    const int n_out = layer == M.n_layers - 1 ? M.n_out : M.H;
+    const int KB = (n_in + 31) / 32;
+    const int total = ((n_out + 15) / 16) * KB * kWave * 8;
+    const float* src = static_cast<const float*>(M.W[layer]);
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+      const int i = e & 7, lane = (e >> 3) & 63, frag = e >> 9;
+      const int kb = frag % KB, m = frag / KB;
+      const int row = 16 * m + (lane & 15), col = nu(kb, lane >> 4, i);
+      const float w = (row < n_out && col < n_in) ? src[(int64_t)row * n_in + col] : 0.0f;
+      const bf16 h = from_f32<bf16>(w);
+      hi[offset + e] = h;
+      hi[total_elems + offset + e] = from_f32<bf16>(w - to_f32(h));
+    }
+    offset += total;
+  }
+}
+
+__device__ __forceinline__ void split8(const float (&v)[8], bf16x8& h, bf16x8& l) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const bf16 a = from_f32<bf16>(v[i]);
+    h[i] = a;
+    l[i] = from_f32<bf16>(v[i] - to_f32(a));
+  }
+}
+
+// acc += A B with A, B split: hi hi + hi lo + lo hi.
+__device__ __forceinline__ f32x4 mma_split(const bf16x8& ah, const bf16x8& al, const bf16x8& bh, const bf16x8& bl,
+                                           f32x4 c) {
+  c = mma(ah, bh, c);
+  c = mma(ah, bl, c);
+  return mma(al, bh, c);
+}
+
+// The predictor's MLP (width 64) on N-tiles t0 .. t0+NT-1 of the FP32 tile
+// with split operands; out[t] rows 0.. = d in lanes 0..15.
+template <int NT>
+__device__ inline void disp_mlp_split(const MlpArgs& M, const WFrag<bf16, true>& Wh, const WFrag<bf16, true>& Wl,
+                                      const float* htile, int KB0, int t0, int lane, f32x4 out[NT]) {
+  constexpr int MH = kDispH / 16, KH = kDispH / 32;
+  f32x4 acc[MH][NT];
+#pragma unroll
+  for (int m = 0; m < MH; ++m) {
+    const f32x4 bt = bias_tile(M.b[0], kDispH, m, lane);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = bt;
+  }
+  for (int kb = 0; kb < KB0; ++kb) {
+    bf16x8 bh[NT], bl[NT], ah[MH], al[MH];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const f32x8 x = htile_get<float>(htile, KB0, t0 + t, kb, lane);
+      float v[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = x[i];
+      split8(v, bh[t], bl[t]);
+    }
+#pragma unroll
+    for (int m = 0; m < MH; ++m) {
+      ah[m] = Wh.get(M, 0, m, kb, lane);
+      al[m] = Wl.get(M, 0, m, kb, lane);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int m = 0; m < MH; ++m)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[m][t] = mma_split(ah[m], al[m], bh[t], bl[t], acc[m][t]);
+  }
+  // ReLU'd outputs of tiles (2kb, 2kb+1) are the next layer's chunk kb
+  auto chain = [&](int kb, int t, bf16x8& h, bf16x8& l) {
+    float v[8];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      v[j] = fmaxf(acc[2 * kb][t][j], 0.0f);
+      v[4 + j] = fmaxf(acc[2 * kb + 1][t][j], 0.0f);
+    }
+    split8(v, h, l);
+  };
+  for (int layer = 1; layer < M.n_layers - 1; ++layer) {
+    bf16x8 bh[KH][NT], bl[KH][NT];
+#pragma unroll
+    for (int kb = 0; kb < KH; ++kb)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) chain(kb, t, bh[kb][t], bl[kb][t]);
+#pragma unroll
+    for (int m = 0; m < MH; ++m) {
+      const f32x4 bt = bias_tile(M.b[layer], kDispH, m, lane);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[m][t] = bt;
+    }
+#pragma unroll
+    for (int kb = 0; kb < KH; ++kb) {
+      bf16x8 ah[MH], al[MH];
+#pragma unroll
+      for (int m = 0; m < MH; ++m) {
+        ah[m] = Wh.get(M, layer, m, kb, lane);
+        al[m] = Wl.get(M, layer, m, kb, lane);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int m = 0; m < MH; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = mma_split(ah[m], al[m], bh[kb][t], bl[kb][t], acc[m][t]);
+    }
+  }
+  const int lo = M.n_layers - 1;
+  const f32x4 bo = bias_tile(M.b[lo], M.n_out, 0, lane);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) out[t] = bo;
+#pragma unroll
+  for (int kb = 0; kb < KH; ++kb) {
+    const bf16x8 ah = Wh.get(M, lo, 0, kb, lane), al = Wl.get(M, lo, 0, kb, lane);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      bf16x8 bh, bl;
+      chain(kb, t, bh, bl);
+      out[t] = mma_split(ah, al, bh, bl, out[t]);
+    }
+  }
+}
+
+template <bool SPLIT>
 __global__ __launch_bounds__(256) void disparity_fwd_kernel(const DispArgs G, const MlpArgs P, const QuerySrc src,
                                                             int64_t Q, float* __restrict__ d_out) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   constexpr int NT = 2;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63, waves = blockDim.x >> 6;
   const int KB0 = (P.K0 + 31) / 32;
-  float* htile = reinterpret_cast<float*>(smem) + wave * (4 * KB0 * kWave * 8);
+  const int wl_elems = SPLIT ? packed_weight_elems<bf16>(P.n_layers, P.K0, P.H) : 0;
+  bf16* const wl = reinterpret_cast<bf16*>(smem);
+  float* const htile = reinterpret_cast<float*>(wl + 2 * wl_elems) + wave * (4 * KB0 * kWave * 8);
+  if (SPLIT) pack_weights_split(P, wl, wl_elems);
   {  // zero the K padding of this lane's row once
     const float z[4] = {0.f, 0.f, 0.f, 0.f};
     for (int k = P.K0; k < 32 * KB0; k += 4) htile_put4<float>(htile, KB0, lane, k, z);
   }
+  if (SPLIT) __syncthreads();
   const WFrag<float, false> W{nullptr, KB0};
+  const WFrag<bf16, true> Wh{wl, KB0}, Wlo{wl + wl_elems, KB0};
   const int64_t n_tiles = (Q + 63) / 64;
   const TileRange tr = xcd_tiles(n_tiles, waves, wave);
   for (int64_t tile = tr.first; tile < tr.end; tile += tr.stride) {
@@ -484,7 +626,10 @@ __global__ __launch_bounds__(256) void disparity_fwd_kernel(const DispArgs G, co
 #pragma unroll
     for (int t0 = 0; t0 < 4; t0 += NT) {
       f32x4 out[NT];
-      mlp_forward_tiles<float, kDispH, NT>(P, W, htile, KB0, t0, lane, out);
+      if constexpr (SPLIT)
+        disp_mlp_split<NT>(P, Wh, Wlo, htile, KB0, t0, lane, out);
+      else
+        mlp_forward_tiles<float, kDispH, NT>(P, W, htile, KB0, t0, lane, out);
       if (lane < 16) {
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
@@ -883,7 +1028,8 @@ hipError_t launch_encode_rows(const TreeArgs& T, oo_dtype td, const MlpArgs& M, 
   return hipGetLastError();
 }
 
-hipError_t launch_disparity_fwd(const DispArgs& G, const QuerySrc& src, int64_t Q, float* d_out, hipStream_t st) {
+hipError_t launch_disparity_fwd(const DispArgs& G, oo_dtype md, const QuerySrc& src, int64_t Q, float* d_out,
+                                hipStream_t st) {
   if (Q == 0) return hipSuccess;
   MlpArgs P{};
   P.n_layers = G.n_layers;
@@ -895,16 +1041,20 @@ hipError_t launch_disparity_fwd(const DispArgs& G, const QuerySrc& src, int64_t 
     P.W[i] = i < G.n_layers ? G.W[i] : nullptr;
     P.b[i] = i < G.n_layers ? G.b[i] : nullptr;
   }
-  int waves, grid;
-  size_t lds;
-  tile_launch_shape_plain<float>(P, Q, waves, lds, grid);
-  if (waves > 4) {  // the kernel's workgroups have at most 4 waves
-    waves = 4;
-    lds = (size_t)4 * 4 * ((P.K0 + 31) / 32) * kWave * 8 * sizeof(float);
-    grid = tile_grid(Q, waves, lds);
+  // four-wave workgroups; the split variant adds the hi and lo weight copies
+  // (2 x 18 KiB) to the four 16 KiB FP32 tiles
+  const bool split = md != OO_F32;
+  constexpr int waves = 4;
+  const size_t wbytes = split ? (size_t)2 * packed_weight_elems<bf16>(P.n_layers, P.K0, P.H) * sizeof(bf16) : 0;
+  const size_t lds = wbytes + (size_t)waves * 4 * ((P.K0 + 31) / 32) * kWave * 8 * sizeof(float);
+  const int grid = tile_grid(Q, waves, lds);
+  if (split) {
+    hipFuncSetAttribute((const void*)disparity_fwd_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(disparity_fwd_kernel<true>, dim3(grid), dim3(64 * waves), lds, st, G, P, src, Q, d_out);
+  } else {
+    hipFuncSetAttribute((const void*)disparity_fwd_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(disparity_fwd_kernel<false>, dim3(grid), dim3(64 * waves), lds, st, G, P, src, Q, d_out);
   }
-  hipFuncSetAttribute((const void*)disparity_fwd_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(disparity_fwd_kernel, dim3(grid), dim3(64 * waves), lds, st, G, P, src, Q, d_out);
   return hipGetLastError();
 }
 

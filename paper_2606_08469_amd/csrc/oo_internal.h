@@ -66,8 +66,10 @@ struct QueryOut {
   int64_t n_idx;
   const float* disp = nullptr;  // per-query disparity, read by the shifted encode into rows
 };
-// The predictor's d for Q queries (matrix cores), into d_out [Q].
-hipError_t launch_disparity_fwd(const DispArgs& G, const QuerySrc& src, int64_t Q, float* d_out, hipStream_t st);
+// The predictor's d for Q queries (matrix cores), into d_out [Q]: FP32 for
+// an FP32 model, split BF16 operands (hi + lo) for a 16-bit one.
+hipError_t launch_disparity_fwd(const DispArgs& G, oo_dtype md, const QuerySrc& src, int64_t Q, float* d_out,
+                                hipStream_t st);
 // The shifted encode of the Q sorted queries (disparity from O.disp) into
 // decoder input rows h_rows [Q][M.K0] of the tables' dtype (level features,
 // then the M.E surface attributes), with the backward's outputs in O.
