@@ -288,7 +288,8 @@ def paper_config_bench(torch, binding, synth, args, timed, grad_bufs):
     """The paper's network and loss on its batch schedule: 8 levels x 4 FP16
     channels on vertex maps (257^2 .. 3^2), eight-cell blend along the
     disparity-shifted directions (hash-grid predictor, 16 levels x 2, MLP
-    36-64-64-1 in FP32), the 13 surface attributes (+3 zero columns), four
+    36-64-64-1 with FP32 parameters, its forward on split BF16 operands),
+    the 13 surface attributes (+3 zero columns), four
     hidden layers of width 128, relative L2, mirror-direction lookup. One
     timed training step (forward and backward, the predictor's included) per
     schedule stage (B LHS points x M samples), and the first stage without
@@ -304,7 +305,7 @@ def paper_config_bench(torch, binding, synth, args, timed, grad_bufs):
                                interp=binding.INTERP_PAPER, disparity=disp)
     out = {"workload": "paper network and loss: depth-7 octree (%d nodes), 8 levels x 4 FP16 channels on "
                        "(R+1)^2 vertex maps R = 256..2 read along disparity-shifted directions (hash grid "
-                       "16 x 2^19 x 2 + MLP 36-64-64-1, FP32), 13 surface attributes (+3 zero), decoder "
+                       "16 x 2^19 x 2 + MLP 36-64-64-1, FP32 parameters, split-BF16 forward), 13 surface attributes (+3 zero), decoder "
                        "48-128-128-128-128-3 FP16 MFMA, relative L2, detached target" % len(nodes),
            "stages": []}
     log(f"paper config: tree built in {time.time() - t0:.1f}s, nodes={len(nodes)} levels={counts.tolist()}")
