@@ -327,7 +327,7 @@ def paper_config_bench(torch, binding, synth, args, timed, grad_bufs):
         log(f"paper config B={B} M={N}: {msc:.3f} ms/step (fwd {fc:.3f}, bwd {bc:.3f}), "
             f"{Q / (msc * 1e-3) / 1e6:.1f} Mqueries/s")
         if (B, N) == synth.PAPER_SCHEDULE[0]:
-            # the same stage without the shift (the "no direction offset" lookup)
+            # the same stage without the shift (every cell reads the unshifted direction)
             plain = binding.OctaOctree(nodes, lo, list(cfg.res), cfg.C, feat, W, b, dtype=torch.float16,
                                        interp=binding.INTERP_PAPER)
             grad_bufs.clear()

@@ -123,6 +123,10 @@ typedef enum { OO_F32 = 0, OO_F16 = 1, OO_BF16 = 2 } oo_dtype;
  *    has two), W[i] row-major [dims[i+1]][dims[i]] FP32, b[i] [dims[i+1]];
  *    dims[0] = 36, dims[n_layers] = 1 (the disparity d, linear output).
  *    ReLU between. Other shapes are refused with OO_EUNSUPPORTED.
+ *  - Arithmetic: FP32, except that the residual forward of a 16-bit decoder
+ *    (oo_mlp dtype FP16/BF16) runs the MLP on split BF16 operands (each
+ *    FP32 value as hi + lo, three BF16 products per FP32 one, FP32
+ *    accumulation; about 16 significant bits).
  *  - dtables, dW, db: gradient accumulators (same shapes) that the residual
  *    backward adds the predictor's gradients into (+=); NULL for calls
  *    that do not differentiate.
@@ -157,8 +161,8 @@ typedef struct {
   const void* feat[OO_MAX_LEVELS];
   int32_t interp;
   /* OO_INTERP_PAPER only: the disparity predictor shifting each cell's
-   * lookup direction, or NULL for the lookup along w_r (the "no direction
-   * offset" ablation of Sec. 4.4). */
+   * lookup direction, or NULL for the lookup along w_r (Sec. 4.4's ablation
+   * without a direction offset). */
   const oo_disparity* disparity;
 } oo_tree;
 

@@ -45,7 +45,8 @@ class _Disparity(C.Structure):
 class _Tree(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("C", C.c_int32), ("res", C.c_int32 * MAX_LEVELS),
                 ("level_offset", C.c_int64 * (MAX_LEVELS + 1)), ("nodes", C.c_void_p),
-                ("feat_dtype", C.c_int32), ("feat", C.c_void_p * MAX_LEVELS), ("interp", C.c_int32), ("disparity", C.POINTER(_Disparity))]
+                ("feat_dtype", C.c_int32), ("feat", C.c_void_p * MAX_LEVELS), ("interp", C.c_int32),
+                ("disparity", C.POINTER(_Disparity))]
 
 
 # Level-feature interpolation schemes (oo_tree.interp).
