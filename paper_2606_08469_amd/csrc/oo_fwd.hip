@@ -506,11 +506,16 @@ __device__ __forceinline__ f32x4 mma_split(const bf16x8& ah, const bf16x8& al, c
   return mma(al, bh, c);
 }
 
-// The predictor's MLP (width 64) on N-tiles t0 .. t0+NT-1 of the FP32 tile
-// with split operands; out[t] rows 0.. = d in lanes 0..15.
+// The predictor's MLP (width 64) on N-tiles t0 .. t0+NT-1 with split
+// operands; out[t] rows 0.. = d in lanes 0..15. The input's first K-chunk
+// (the 32 hash features) comes from the wave's one-chunk FP32 tile; the
+// second holds only the unit direction (inputs 32..34, input 35 zero),
+// which the lanes of group 0 take from the lane that owns the query, so the
+// tile needs half the LDS.
+static_assert(kDispK == 36, "the predictor's input is 32 hash features, the unit direction and a zero");
 template <int NT>
 __device__ inline void disp_mlp_split(const MlpArgs& M, const WFrag<bf16, true>& Wh, const WFrag<bf16, true>& Wl,
-                                      const float* htile, int KB0, int t0, int lane, f32x4 out[NT]) {
+                                      const float* htile, const float u[3], int t0, int lane, f32x4 out[NT]) {
   constexpr int MH = kDispH / 16, KH = kDispH / 32;
   f32x4 acc[MH][NT];
 #pragma unroll
@@ -519,14 +524,27 @@ __device__ inline void disp_mlp_split(const MlpArgs& M, const WFrag<bf16, true>&
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[m][t] = bt;
   }
-  for (int kb = 0; kb < KB0; ++kb) {
+#pragma unroll
+  for (int kb = 0; kb < 2; ++kb) {
     bf16x8 bh[NT], bl[NT], ah[MH], al[MH];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      const f32x8 x = htile_get<float>(htile, KB0, t0 + t, kb, lane);
       float v[8];
+      if (kb == 0) {
+        const f32x8 x = htile_get<float>(htile, 1, t0 + t, 0, lane);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) v[i] = x[i];
+        for (int i = 0; i < 8; ++i) v[i] = x[i];
+      } else {
+        // slot i < 4 of group g holds input 32 + 4g + i; the rest are >= 48
+        const int src = 16 * (t0 + t) + (lane & 15);
+        const float s0 = __shfl(u[0], src), s1 = __shfl(u[1], src), s2 = __shfl(u[2], src);
+        const bool g0 = (lane >> 4) == 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = 0.0f;
+        v[0] = g0 ? s0 : 0.0f;
+        v[1] = g0 ? s1 : 0.0f;
+        v[2] = g0 ? s2 : 0.0f;
+      }
       split8(v, bh[t], bl[t]);
     }
 #pragma unroll
@@ -600,13 +618,14 @@ __global__ __launch_bounds__(256) void disparity_fwd_kernel(const DispArgs G, co
   constexpr int NT = 2;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63, waves = blockDim.x >> 6;
   const int KB0 = (P.K0 + 31) / 32;
+  const int KBT = SPLIT ? 1 : KB0;  // K-chunks the FP32 tile holds
   const int wl_elems = SPLIT ? packed_weight_elems<bf16>(P.n_layers, P.K0, P.H) : 0;
   bf16* const wl = reinterpret_cast<bf16*>(smem);
-  float* const htile = reinterpret_cast<float*>(wl + 2 * wl_elems) + wave * (4 * KB0 * kWave * 8);
+  float* const htile = reinterpret_cast<float*>(wl + 2 * wl_elems) + wave * (4 * KBT * kWave * 8);
   if (SPLIT) pack_weights_split(P, wl, wl_elems);
   {  // zero the K padding of this lane's row once
     const float z[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int k = P.K0; k < 32 * KB0; k += 4) htile_put4<float>(htile, KB0, lane, k, z);
+    for (int k = P.K0; k < 32 * KBT; k += 4) htile_put4<float>(htile, KBT, lane, k, z);
   }
   if (SPLIT) __syncthreads();
   const WFrag<float, false> W{nullptr, KB0};
@@ -621,13 +640,13 @@ __global__ __launch_bounds__(256) void disparity_fwd_kernel(const DispArgs G, co
     float a[kDispK];
     disparity_input(G, x, u, a);
 #pragma unroll
-    for (int k = 0; k < kDispK; k += 4) htile_put4<float>(htile, KB0, lane, k, &a[k]);
+    for (int k = 0; k < (SPLIT ? 32 : kDispK); k += 4) htile_put4<float>(htile, KBT, lane, k, &a[k]);
     wave_lds_sync();
 #pragma unroll
     for (int t0 = 0; t0 < 4; t0 += NT) {
       f32x4 out[NT];
       if constexpr (SPLIT)
-        disp_mlp_split<NT>(P, Wh, Wlo, htile, KB0, t0, lane, out);
+        disp_mlp_split<NT>(P, Wh, Wlo, htile, u, t0, lane, out);
       else
         mlp_forward_tiles<float, kDispH, NT>(P, W, htile, KB0, t0, lane, out);
       if (lane < 16) {
@@ -1041,12 +1060,14 @@ hipError_t launch_disparity_fwd(const DispArgs& G, oo_dtype md, const QuerySrc& 
     P.W[i] = i < G.n_layers ? G.W[i] : nullptr;
     P.b[i] = i < G.n_layers ? G.b[i] : nullptr;
   }
-  // four-wave workgroups; the split variant adds the hi and lo weight copies
-  // (2 x 18 KiB) to the four 16 KiB FP32 tiles
+  // four-wave workgroups, two per CU: four 16 KiB FP32 tiles, or for the
+  // split variant the hi and lo weight copies (2 x 18 KiB) and four 8 KiB
+  // one-chunk tiles
   const bool split = md != OO_F32;
   constexpr int waves = 4;
   const size_t wbytes = split ? (size_t)2 * packed_weight_elems<bf16>(P.n_layers, P.K0, P.H) * sizeof(bf16) : 0;
-  const size_t lds = wbytes + (size_t)waves * 4 * ((P.K0 + 31) / 32) * kWave * 8 * sizeof(float);
+  const int kbt = split ? 1 : (P.K0 + 31) / 32;
+  const size_t lds = wbytes + (size_t)waves * 4 * kbt * kWave * 8 * sizeof(float);
   const int grid = tile_grid(Q, waves, lds);
   if (split) {
     hipFuncSetAttribute((const void*)disparity_fwd_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
