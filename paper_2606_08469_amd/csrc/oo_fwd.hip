@@ -461,9 +461,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C == 4 ? 4 
 // exponent range), and each product is hi hi + hi lo + lo hi on 16x16x32
 // BF16 MFMA with FP32 accumulation: three MFMAs of 16 cycles for each
 // eight FP32 ones of 32. The weights are split once per workgroup into LDS.
-// (A plain 16-bit predictor moves shifted lookups across triangle edges
-// often enough to break its gradients' agreement; the split keeps d within
-// about 1e-5 of FP32.)
+// hi + lo holds x to 2^-16 relative (each part rounds to 8 significant
+// bits) and the dropped lo lo term is below 2^-16 of the product, so each
+// product carries at most about 3 * 2^-16 relative error. (A plain 16-bit
+// predictor moves shifted lookups across triangle edges often enough to
+// break its gradients' agreement.)
 // ---------------------------------------------------------------------------
 
 // Packs the predictor's FP32 weights into LDS in fragment order, split into
