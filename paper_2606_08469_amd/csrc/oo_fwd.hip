@@ -350,27 +350,40 @@ __global__ __launch_bounds__(512) void mlp_kernel(const MlpArgs M, const MT* __r
   for (int64_t tile = tr.first; tile < tr.end; tile += tr.stride) {
     // With 16-bit rows the wave reads the tile's 64 contiguous rows as
     // 16-byte pieces in order (coalesced; EP entries each, K0 a multiple of
-    // EP). Otherwise each lane reads its own row four entries at a time
-    // (FP32 measured faster that way).
+    // EP), eight of a lane's pieces (at most 16, K0 <= 128) loaded before
+    // any of them is stored, so their latencies overlap; the pieces go to
+    // their fragment slots unconverted. Otherwise each lane reads its own
+    // row four entries at a time (FP32 measured faster that way).
     constexpr int EP = 16 / sizeof(MT);
     const int64_t q0 = tile * 64;
     const int nrow = Q - q0 < 64 ? (int)(Q - q0) : 64;
     if (sizeof(MT) == 2 && M.K0 % EP == 0) {
       typedef MT vP __attribute__((ext_vector_type(EP)));
+      typedef MT v4 __attribute__((ext_vector_type(4)));
+      constexpr int kMaxPieces = 128 / EP, kBatch = 8;
       const int P = M.K0 / EP;
       const vP* src = reinterpret_cast<const vP*>(h + q0 * (int64_t)M.K0);
-      for (int p = lane; p < 64 * P; p += 64) {
-        const int r = p / P, k0 = (p - r * P) * EP;
-        float v[EP];
+#pragma unroll 1
+      for (int i0 = 0; i0 < kMaxPieces; i0 += kBatch) {
+        vP xs[kBatch];
 #pragma unroll
-        for (int c = 0; c < EP; ++c) v[c] = 0.0f;
-        if (r < nrow) {
-          const vP x = src[p];
-#pragma unroll
-          for (int c = 0; c < EP; ++c) v[c] = to_f32(x[c]);
+        for (int j = 0; j < kBatch; ++j) {
+          const int i = i0 + j, p = lane + 64 * i;  // piece p: row p / P, entries (p % P) EP ..
+          xs[j] = vP{};
+          if (i < P && p / P < nrow) xs[j] = src[p];
         }
 #pragma unroll
-        for (int c = 0; c < EP; c += 4) htile_put4<MT>(htile, KB0, r, k0 + c, &v[c]);
+        for (int j = 0; j < kBatch; ++j) {
+          const int i = i0 + j;
+          if (i < P) {
+            const int p = lane + 64 * i, r = p / P, k0 = (p - r * P) * EP;
+#pragma unroll
+            for (int c = 0; c < EP; c += 4) {
+              const v4 x4 = {xs[j][c], xs[j][c + 1], xs[j][c + 2], xs[j][c + 3]};
+              *reinterpret_cast<v4*>(htile + htile_index<MT>(r, k0 + c, KB0)) = x4;
+            }
+          }
+        }
       }
     } else {
       typedef MT v4 __attribute__((ext_vector_type(4)));
