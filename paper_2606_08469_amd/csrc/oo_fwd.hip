@@ -347,6 +347,13 @@ __global__ __launch_bounds__(512) void mlp_kernel(const MlpArgs M, const MT* __r
   const WFrag<MT, WLDS> W{wl, KB0};
   const int64_t n_tiles = (Q + 63) / 64;
   const TileRange tr = xcd_tiles(n_tiles, waves, wave);
+  // 16-bit rows: a tile's rows are P pieces of 16 bytes each; this lane
+  // reads pieces lane + 64 i, i = 0 .. P-1, walked by row and position
+  // without a division per piece
+  constexpr int EP = 16 / sizeof(MT);
+  const int P = M.K0 / EP > 0 ? M.K0 / EP : 1;
+  const int step_r = 64 / P, step_m = 64 % P;
+  const int lane_r = lane / P, lane_m = lane % P;
   for (int64_t tile = tr.first; tile < tr.end; tile += tr.stride) {
     // With 16-bit rows the wave reads the tile's 64 contiguous rows as
     // 16-byte pieces in order (coalesced; EP entries each, K0 a multiple of
@@ -354,33 +361,39 @@ __global__ __launch_bounds__(512) void mlp_kernel(const MlpArgs M, const MT* __r
     // any of them is stored, so their latencies overlap; the pieces go to
     // their fragment slots unconverted. Otherwise each lane reads its own
     // row four entries at a time (FP32 measured faster that way).
-    constexpr int EP = 16 / sizeof(MT);
     const int64_t q0 = tile * 64;
     const int nrow = Q - q0 < 64 ? (int)(Q - q0) : 64;
     if (sizeof(MT) == 2 && M.K0 % EP == 0) {
       typedef MT vP __attribute__((ext_vector_type(EP)));
       typedef MT v4 __attribute__((ext_vector_type(4)));
       constexpr int kMaxPieces = 128 / EP, kBatch = 8;
-      const int P = M.K0 / EP;
       const vP* src = reinterpret_cast<const vP*>(h + q0 * (int64_t)M.K0);
+      int r = lane_r, m = lane_m;  // row and position of piece lane + 64 i
 #pragma unroll 1
       for (int i0 = 0; i0 < kMaxPieces; i0 += kBatch) {
         vP xs[kBatch];
-#pragma unroll
-        for (int j = 0; j < kBatch; ++j) {
-          const int i = i0 + j, p = lane + 64 * i;  // piece p: row p / P, entries (p % P) EP ..
-          xs[j] = vP{};
-          if (i < P && p / P < nrow) xs[j] = src[p];
-        }
+        int rs[kBatch], ms[kBatch];
 #pragma unroll
         for (int j = 0; j < kBatch; ++j) {
           const int i = i0 + j;
-          if (i < P) {
-            const int p = lane + 64 * i, r = p / P, k0 = (p - r * P) * EP;
+          rs[j] = r;
+          ms[j] = m;
+          xs[j] = vP{};
+          if (i < P && r < nrow) xs[j] = src[lane + 64 * i];
+          m += step_m;
+          r += step_r;
+          if (m >= P) {
+            m -= P;
+            ++r;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+          if (i0 + j < P) {
 #pragma unroll
             for (int c = 0; c < EP; c += 4) {
               const v4 x4 = {xs[j][c], xs[j][c + 1], xs[j][c + 2], xs[j][c + 3]};
-              *reinterpret_cast<v4*>(htile + htile_index<MT>(r, k0 + c, KB0)) = x4;
+              *reinterpret_cast<v4*>(htile + htile_index<MT>(rs[j], ms[j] * EP + c, KB0)) = x4;
             }
           }
         }

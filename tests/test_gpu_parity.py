@@ -106,6 +106,28 @@ def test_mlp_fwd(ci, dtype, tol):
     assert err <= tol
 
 
+@pytest.mark.parametrize("ci,dtype", [(2, torch.float16), (4, torch.bfloat16)])
+@pytest.mark.parametrize("B", [1, 63, 65, 1000, 4099])
+def test_mlp_fwd_rows_ragged(ci, dtype, B):
+    """The 16-bit decoder on batches that end inside a 64-row tile (input
+    widths 72 and 88: 9 and 11 sixteen-byte pieces per row), checked row by
+    row against the oracle on the same 16-bit h: every output within 5% of
+    its own magnitude plus the batch's RMS, so a row read from the wrong
+    place in the tile fails on its own."""
+    x, d = queries(ci)
+    x, d = x[:B], d[:B]
+    model = gpu_models(ci, dtype)
+    print(f"[case] mlp_fwd rows cfg{ci} {dtype} B={B}", flush=True)
+    h, _ = binding.encode_query(model.tree, dev(x), dev(d), dtype, feat=model.work_feat)
+    rgb = to_np(binding.mlp_fwd(model.mlp, h, W=model.work_W))
+    _, omlp = oracle_models(ci)
+    want = oracle.mlp_fwd(omlp, to_np(h).astype(np.float64))
+    rms = float(np.sqrt(np.mean(want ** 2)))
+    worst = float(np.max(np.abs(rgb - want) / (np.abs(want) + rms)))
+    report(f"mlp_fwd rows cfg{ci} {dtype} B={B}", worst_row_rel=worst)
+    assert rgb.shape == want.shape and worst <= 0.05
+
+
 @pytest.mark.parametrize("ci,dtype,tol,n_oracle", [(1, torch.float32, FP32_TOL, None),
                                                     (2, torch.float32, FP32_TOL, None),
                                                     (2, torch.float16, MIX_TOL, None),
